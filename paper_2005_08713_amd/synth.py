@@ -1,0 +1,149 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+The paper benchmarks on histopathology scans (RGB, 8-9 bits per channel) and
+on radiology images (CR/DX/MG, 12-16 bit single channel) whose datasets are
+not available here (Sec. 5).  These generators produce stand-ins with the
+same shapes, value ranges and spatial structure:
+
+* ``he_like``  -- H&E-stained tissue on a bright background, RGB uint8.
+* ``rad_like`` -- a smooth radial gradient with blob structures and Poisson
+  counting noise, single channel uint16 with 12 significant bits.
+* ``tile_batch`` -- a batch of RGB tiles of uneven size (square 512/256/128
+  tiles plus ragged edge tiles), with per-tile wavelet levels and
+  lossless/quantised mode, as produced when a slide is cut into tiles.
+
+This module holds none of the codec's arithmetic; it only draws numbers.
+Both the GPU library and the CPU oracle are fed the arrays it returns.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PINK = np.array([232.0, 150.0, 190.0])
+PURPLE = np.array([130.0, 70.0, 160.0])
+
+
+def _blob_field(rng, w, h, nblobs, sig_lo, sig_hi, amp_lo, amp_hi):
+    """Sum of separable isotropic Gaussian blobs evaluated on a w x h grid."""
+    xs = np.arange(w, dtype=np.float64)
+    ys = np.arange(h, dtype=np.float64)
+    field = np.zeros((h, w), dtype=np.float64)
+    for _ in range(nblobs):
+        cx = rng.uniform(0, w)
+        cy = rng.uniform(0, h)
+        sig = rng.uniform(sig_lo, sig_hi)
+        amp = rng.uniform(amp_lo, amp_hi)
+        gx = np.exp(-((xs - cx) ** 2) / (2.0 * sig * sig))
+        gy = np.exp(-((ys - cy) ** 2) / (2.0 * sig * sig))
+        field += amp * np.outer(gy, gx)
+    return field
+
+
+def he_like(width: int, height: int, seed: int, sigma=(20.0, 60.0),
+            tissue: float = 0.40) -> np.ndarray:
+    """H&E-like RGB uint8 image, shape (height, width, 3).
+
+    Background ~U{230..245} per pixel and channel; tissue where an 8-blob
+    field exceeds its (1-tissue) quantile, coloured by a second 8-blob field
+    mixing pink and purple stain colours; additive N(0, 2^2) noise.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    img = rng.integers(230, 246, size=(height, width, 3)).astype(np.float64)
+    f = _blob_field(rng, width, height, 8, sigma[0], sigma[1], 0.5, 1.0)
+    thr = np.quantile(f, 1.0 - tissue)
+    mask = f > thr
+    hfield = _blob_field(rng, width, height, 8, sigma[0], sigma[1], 0.5, 1.0)
+    lo, hi = hfield.min(), hfield.max()
+    hmix = (hfield - lo) / (hi - lo) if hi > lo else np.zeros_like(hfield)
+    colour = np.rint((1.0 - hmix)[..., None] * PINK + hmix[..., None] * PURPLE)
+    img[mask] = colour[mask]
+    img += rng.normal(0.0, 2.0, size=img.shape)
+    return np.clip(np.rint(img), 0, 255).astype(np.uint8)
+
+
+def rad_like(width: int, height: int, seed: int) -> np.ndarray:
+    """Radiology-like uint16 image (12 significant bits), shape (height, width).
+
+    lambda = 2000 + 300 (1 - 2 r / r_max) plus 20 Gaussian blobs with
+    amplitude ~U(-600, 1200) and sigma ~U(50, 800) px (scaled down for
+    images smaller than 8192 px), clipped to [1, 4000]; Poisson counts
+    clipped to [0, 4095].
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ys, xs = np.mgrid[0:height, 0:width].astype(np.float64)
+    cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
+    r = np.hypot(xs - cx, ys - cy)
+    rmax = max(r.max(), 1.0)
+    lam = 2000.0 + 300.0 * (1.0 - 2.0 * r / rmax)
+    del xs, ys, r
+    scale = min(1.0, max(width, height) / 8192.0)
+    lam += _blob_field(rng, width, height, 20, 50.0 * scale + 1.0,
+                       800.0 * scale + 2.0, -600.0, 1200.0)
+    lam = np.clip(lam, 1.0, 4000.0)
+    counts = rng.poisson(lam)
+    return np.clip(counts, 0, 4095).astype(np.uint16)
+
+
+def random_image(width: int, height: int, channels: int, bits: int,
+                 seed: int, kind: str = "uniform") -> np.ndarray:
+    """Adversarial / generic test images of any bit depth.
+
+    kind: 'uniform' (iid uniform over [0, 2^bits)), 'const', 'max'
+    (all samples 2^bits-1), 'checker' (alternating 0 / max), 'ramp',
+    'sparse' (mostly zero with a few random samples).
+    Returns uint8 for bits <= 8 else uint16, shape (h, w, c).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    top = (1 << bits) - 1
+    dt = np.uint8 if bits <= 8 else np.uint16
+    shape = (height, width, channels)
+    if kind == "uniform":
+        a = rng.integers(0, top + 1, size=shape)
+    elif kind == "const":
+        a = np.full(shape, rng.integers(0, top + 1))
+    elif kind == "max":
+        a = np.full(shape, top)
+    elif kind == "checker":
+        yy, xx = np.mgrid[0:height, 0:width]
+        a = np.repeat((((yy + xx) & 1) * top)[..., None], channels, axis=2)
+    elif kind == "ramp":
+        yy, xx = np.mgrid[0:height, 0:width]
+        a = np.repeat(((yy * 7 + xx * 3) % (top + 1))[..., None], channels, axis=2)
+    elif kind == "sparse":
+        a = np.zeros(shape, dtype=np.int64)
+        n = max(1, (height * width * channels) // 50)
+        idx = rng.integers(0, height * width * channels, size=n)
+        a.reshape(-1)[idx] = rng.integers(0, top + 1, size=n)
+    else:
+        raise ValueError(kind)
+    return a.astype(dt)
+
+
+def tile_batch(n_tiles: int, seed: int, content_seed_base: int,
+               sides=(512, 256, 128), edge_frac: float = 0.15,
+               levels=(3, 4, 5), qstep: int = 4, max_side: int = 511):
+    """Mixed batch of RGB uint8 tiles as cut from a slide.
+
+    Returns a list of dicts {pixels, levels, qstep}.  85% of tiles are
+    square with side drawn uniformly from ``sides``; the rest are edge tiles
+    with width and height ~U{1..max_side}.  Levels ~U(levels); mode is
+    lossless (qstep 1) or quantised (``qstep``) with probability 1/2.  Tile i
+    has content seed ``content_seed_base + i`` and blob sigma scaled by
+    side/256.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_tiles):
+        if rng.uniform() < edge_frac:
+            w = int(rng.integers(1, max_side + 1))
+            h = int(rng.integers(1, max_side + 1))
+        else:
+            s = int(sides[int(rng.integers(0, len(sides)))])
+            w = h = s
+        lv = int(levels[int(rng.integers(0, len(levels)))])
+        q = 1 if rng.uniform() < 0.5 else int(qstep)
+        sc = max(w, h) / 256.0
+        px = he_like(w, h, content_seed_base + i,
+                     sigma=(max(1.0, 20.0 * sc), max(2.0, 60.0 * sc)))
+        out.append({"pixels": px, "levels": lv, "qstep": q})
+    return out
