@@ -1,0 +1,175 @@
+/*
+ * isx.h -- C ABI of the MI355X (gfx950) codec library libisx.so.
+ *
+ * The codec is the one of "Fast Compression Method for Medical Images on the
+ * Web" (Hulsken, 2020): reversible colour transform, recursive 2-D 5/3 integer
+ * lifting wavelet (Sec. 4), quantisation of the high-pass bands (Sec. 3),
+ * 128x128 coefficient blocks coded as signed-magnitude bitplanes of 4x2 areas
+ * (Sec. 4 Eq. 1, Eq. 2) with empty-plane masks, zero runs (Eq. 3) and a
+ * per-block Huffman code, packed as in the block layout of Fig. 3.
+ *
+ * Conventions for every entry point:
+ *  - "d_" pointers are device (HBM) pointers on the current HIP device, "h_"
+ *    pointers are host pointers.  The caller owns every buffer and keeps it
+ *    alive until the work queued on `stream` has completed.
+ *  - Calls are asynchronous and stream ordered: they validate their host
+ *    arguments, enqueue kernels (and, for the convenience entry points, one
+ *    small host-to-device copy of the plan) on `stream` and return without
+ *    synchronising.  The library never allocates or frees device memory.
+ *  - The return value is ISX_OK or a negative status for errors detected on
+ *    the host before anything was enqueued.  Errors only the device can see
+ *    (corrupt streams, full output buffer) are written per tile or per job
+ *    into d_status, readable after the stream has been synchronised.
+ *  - Entry points are thread safe; the library keeps no mutable global state.
+ */
+#ifndef ISX_H
+#define ISX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define ISX_OK 0
+#define ISX_E_INVALID_ARG (-1)   /* bad descriptor, null pointer, size out of range    */
+#define ISX_E_CAPACITY (-2)      /* (device status) output arena too small for a tile   */
+#define ISX_E_CORRUPT (-3)       /* (device status) malformed encoded stream            */
+#define ISX_E_TRUNCATED (-4)     /* (device status) encoded stream shorter than needed  */
+#define ISX_E_UNSUPPORTED (-5)   /* parameters outside what this build implements       */
+#define ISX_E_WORKSPACE (-6)     /* workspace smaller than the *_workspace_bytes figure */
+#define ISX_E_HIP (-7)           /* a HIP runtime call failed                           */
+#define ISX_E_PENDING 1          /* (device status) initial value before completion     */
+
+#define ISX_CT_NONE 0
+#define ISX_CT_RCT 1  /* reversible colour transform (Y, Cb, Cr), channels == 3 */
+
+/* One tile (image) to encode, or the parameters of an encoded tile.
+ * Limits: 1 <= width, height <= 65535; 1 <= channels <= 8; bytes_per_sample
+ * 1 (uint8) or 2 (uint16, little endian); 1 <= bits <= 8*bytes_per_sample and
+ * every sample < 2^bits; 0 <= levels <= 15; qstep >= 1 (1 = lossless).
+ * Pixels are interleaved: sample (x, y, c) is at byte
+ *   pixel_offset + y*row_stride_bytes + (x*channels + c)*bytes_per_sample. */
+typedef struct {
+    uint64_t pixel_offset;     /* byte offset of the tile in the pixel arena       */
+    uint32_t width, height;
+    uint32_t row_stride_bytes; /* >= width*channels*bytes_per_sample               */
+    uint8_t channels;
+    uint8_t bytes_per_sample;
+    uint8_t bits;
+    uint8_t levels;
+    uint8_t colour_transform;  /* ISX_CT_NONE or ISX_CT_RCT                         */
+    uint8_t reserved0[3];
+    uint16_t qstep;            /* dead-zone quantiser step on HL/LH/HH (Sec. 3)     */
+    uint16_t reserved1;
+} isx_tile_desc;               /* 32 bytes */
+
+/* One decode job: reconstruct an encoded tile at resolution level
+ * target_level (0 = full size; z gives the ceil(W/2^z) x ceil(H/2^z) image
+ * built from the coarser blocks only, Sec. 4 "discarding the high-pass
+ * coefficients").  `tile` repeats the encoded tile's parameters (the host
+ * plans the workspace from them; the device checks them against the stream
+ * header and reports ISX_E_CORRUPT on mismatch); tile.pixel_offset and
+ * tile.row_stride_bytes are ignored. */
+typedef struct {
+    isx_tile_desc tile;
+    uint64_t in_offset;            /* byte offset of the encoded tile in d_encoded    */
+    uint64_t in_bytes;             /* bytes available for it                           */
+    uint64_t out_offset;           /* byte offset of the output image in d_pixels_out  */
+    uint32_t out_row_stride_bytes; /* >= out_width*channels*bytes_per_sample           */
+    uint8_t target_level;          /* 0 .. tile.levels                                 */
+    uint8_t drop_bitplanes;        /* must be 0 (quality-progressive decode not built) */
+    uint16_t reserved;
+} isx_decode_job;                  /* 64 bytes */
+
+/* ---- sizes (host, pure) -------------------------------------------------- */
+
+/* Upper bound of the encoded size of every tile, summed, including the
+ * 256-byte alignment of tile starts in the output arena. 0 on invalid input. */
+uint64_t isx_max_encoded_bytes(const isx_tile_desc *h_descs, int32_t n_tiles);
+
+/* Device workspace needed by isx_encode_tiles for these tiles (bytes). */
+uint64_t isx_encode_workspace_bytes(const isx_tile_desc *h_descs, int32_t n_tiles);
+
+/* Device workspace needed by isx_decode_tiles for these jobs (bytes). */
+uint64_t isx_decode_workspace_bytes(const isx_decode_job *h_jobs, int32_t n_jobs);
+
+/* Number of coefficient blocks of a tile (Sec. 4: 128x128 blocks; LL blocks
+ * plus one multiplexed LH/HL/HH block per non-empty grid cell per level). */
+int64_t isx_tile_block_count(const isx_tile_desc *h_desc);
+
+/* ---- encode ---------------------------------------------------------------- */
+
+/* Encode n_tiles tiles read from the device pixel arena d_pixels.
+ * Output: tile i is written to d_out[d_tile_offsets[i] .. + d_tile_sizes[i])
+ * (offsets are 256-byte aligned, assigned in tile order); each tile is a
+ * self-contained stream: a 24-byte little-endian header ("ISX1", version,
+ * colour transform, channels, bits, bytes/sample, levels, qstep, width,
+ * height, block count), the per-block byte sizes (u32 each) and the blocks,
+ * each byte aligned.  d_tile_offsets, d_tile_sizes (uint64 x n_tiles) and
+ * d_status (int32 x n_tiles) are device arrays written by the kernels;
+ * d_status[i] is ISX_OK or ISX_E_CAPACITY (nothing of tile i written).
+ * d_workspace must hold isx_encode_workspace_bytes(h_descs, n_tiles) bytes.
+ * Output is bit-identical for any batch composition and any run. */
+int32_t isx_encode_tiles(const isx_tile_desc *h_descs, int32_t n_tiles,
+                         const void *d_pixels, void *d_out, uint64_t out_capacity,
+                         uint64_t *d_tile_offsets, uint64_t *d_tile_sizes, int32_t *d_status,
+                         void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* ---- decode ---------------------------------------------------------------- */
+
+/* Decode n_jobs jobs from the device arena d_encoded (as written by
+ * isx_encode_tiles) into the device pixel arena d_pixels_out (interleaved,
+ * same sample type as the source).  d_status[j] (int32, device) receives
+ * ISX_OK, ISX_E_CORRUPT or ISX_E_TRUNCATED.  On error the job's output
+ * region holds unspecified pixels; the call never reads or writes outside
+ * the regions the jobs name.  Lossless tiles decode bit-exactly; lossy
+ * tiles and reduced-resolution outputs are clamped to [0, 2^bits-1]. */
+int32_t isx_decode_tiles(const void *d_encoded, const isx_decode_job *h_jobs, int32_t n_jobs,
+                         void *d_pixels_out, int32_t *d_status,
+                         void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* ---- plans (for callers that replay the same shapes, e.g. in a HIP graph) --
+ * isx_*_plan_bytes gives the size of a host plan; isx_*_plan_build fills it;
+ * the caller copies it to device memory once and calls isx_*_run with the
+ * device copy: the run entry points enqueue kernels only (no copies), so
+ * they may be captured into a HIP graph. */
+uint64_t isx_encode_plan_bytes(const isx_tile_desc *h_descs, int32_t n_tiles);
+int32_t isx_encode_plan_build(const isx_tile_desc *h_descs, int32_t n_tiles, void *h_plan,
+                              uint64_t plan_bytes);
+int32_t isx_encode_run(const void *h_plan, const void *d_plan, const void *d_pixels, void *d_out,
+                       uint64_t out_capacity, uint64_t *d_tile_offsets, uint64_t *d_tile_sizes,
+                       int32_t *d_status, void *d_workspace, uint64_t workspace_bytes,
+                       void *stream);
+
+uint64_t isx_decode_plan_bytes(const isx_decode_job *h_jobs, int32_t n_jobs);
+int32_t isx_decode_plan_build(const isx_decode_job *h_jobs, int32_t n_jobs, void *h_plan,
+                              uint64_t plan_bytes);
+int32_t isx_decode_run(const void *h_plan, const void *d_plan, const void *d_encoded,
+                       void *d_pixels_out, int32_t *d_status, void *d_workspace,
+                       uint64_t workspace_bytes, void *stream);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+
+/* Human-readable text of a status code (static storage). */
+const char *isx_status_string(int32_t code);
+
+/* Debug: forward transform only.  Writes, for each channel c, the quantised
+ * coefficient bands LL_L then (HL_l, LH_l, HH_l) for l = L..1, each dense
+ * row-major int32, into d_coeffs (device), in that order (the same order as
+ * the tile's block groups).  Workspace as for isx_encode_tiles. */
+int32_t isx_debug_forward(const isx_tile_desc *h_desc, const void *d_pixels, int32_t *d_coeffs,
+                          void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* Debug: Huffman code lengths as built on the device for a 256-bin
+ * frequency table (d_freq: uint32 x 256, device); limit 0 = unlimited
+ * two-queue construction, 14 = the length-limited fallback.  d_len:
+ * uint8 x 256 (device). */
+int32_t isx_debug_huffman(const uint32_t *d_freq, int32_t limit, uint8_t *d_len, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISX_H */

@@ -1,0 +1,507 @@
+// isx_api.hip -- host side of libisx: argument validation, planning
+// (geometry, workspace layout, work lists) and the C ABI of include/isx.h.
+#include <string.h>
+
+#include <vector>
+
+#include "isx.h"
+#include "isx_common.h"
+
+using namespace isx;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr uint64_t kPlanRegion = 1ull << 20;  // plan copy kept at the start of the workspace (convenience API)
+
+uint64_t al(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
+
+int validate_desc(const isx_tile_desc &d)
+{
+    if (d.width < 1 || d.height < 1 || d.width > 65535 || d.height > 65535) return ISX_E_INVALID_ARG;
+    if (d.channels < 1 || d.channels > kMaxChannels) return ISX_E_INVALID_ARG;
+    if (d.bytes_per_sample != 1 && d.bytes_per_sample != 2) return ISX_E_INVALID_ARG;
+    if (d.bits < 1 || d.bits > 8 * d.bytes_per_sample) return ISX_E_INVALID_ARG;
+    if (d.levels > kMaxLevels) return ISX_E_INVALID_ARG;
+    if (d.colour_transform > 1) return ISX_E_INVALID_ARG;
+    if (d.colour_transform == ISX_CT_RCT && d.channels != 3) return ISX_E_INVALID_ARG;
+    if (d.qstep < 1) return ISX_E_INVALID_ARG;
+    return ISX_OK;
+}
+
+// Upper bound of the number of bitplanes d of any block (1 + bit length of
+// the largest coefficient magnitude).  With M0 = 2^bits - 1 bounding every
+// colour-transformed sample: the integer LL of level l stays within
+// 1.72^2 M0 (L1 norm of the iterated 2-D 5/3 low-pass, < 1.7157^2 for every
+// depth) plus an accumulated rounding error e_l <= 2.25 e_{l-1} + 2.5; a
+// level's high-pass outputs are at most 4 A + 2 for inputs bounded by A.
+uint32_t dmax_bound(uint32_t bits, uint32_t levels)
+{
+    double M0 = (double)((1u << bits) - 1);
+    double A = M0, e = 0.0, mx = M0;
+    for (uint32_t l = 1; l <= levels; l++) {
+        double h = 4.0 * A + 2.0;
+        if (h > mx) mx = h;
+        e = 2.25 * e + 2.5;
+        A = 2.9584 * M0 + e;
+        if (A > mx) mx = A;
+    }
+    uint64_t m = (uint64_t)mx + 1;
+    uint32_t d = 1;
+    while (m) { d++; m >>= 1; }
+    if (d > (uint32_t)kMaxPlanes) d = kMaxPlanes;
+    return d;
+}
+
+struct TileBuild {
+    TileGeo g;
+    uint64_t arena_elems = 0, tmp_elems[2] = {0, 0}, sym_bytes = 0;
+};
+
+// Geometry of one tile; offsets are relative (filled in later).
+void tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb)
+{
+    TileGeo &T = tb.g;
+    memset(&T, 0, sizeof(T));
+    T.pix_offset = d.pixel_offset;
+    T.pix_stride = d.row_stride_bytes;
+    T.width = d.width; T.height = d.height;
+    T.channels = d.channels; T.bps = d.bytes_per_sample; T.bits = d.bits; T.levels = d.levels;
+    T.ct = d.colour_transform; T.target_level = (uint8_t)target_level; T.qstep = d.qstep;
+    T.dmax = (uint8_t)dmax_bound(d.bits, d.levels);
+    T.first_level = (uint8_t)(target_level + 1);
+    uint32_t w = d.width, h = d.height;
+    for (uint32_t l = 1; l <= d.levels; l++) {
+        T.lv[l].w = w; T.lv[l].h = h;
+        w = (w + 1) / 2; h = (h + 1) / 2;
+    }
+    T.ll_w = w; T.ll_h = h;
+    T.ll_gx = div_up(w, kBlock); T.ll_gy = div_up(h, kBlock);
+    uint32_t start = T.ll_gx * T.ll_gy * d.channels;
+    uint32_t prefix_needed = start;  // blocks needed for target level
+    for (uint32_t l = d.levels; l >= 1; l--) {
+        LevelGeo &G = T.lv[l];
+        uint32_t gw = (G.w + 1) / 2, gh = (G.h + 1) / 2, hw = G.w / 2, hh = G.h / 2;
+        G.gx = div_up(gw, kBlock); G.gy = div_up(gh, kBlock);
+        uint32_t bx = G.gx - 1, by = G.gy - 1;
+        G.corner_empty = ((int64_t)hw - (int64_t)bx * kBlock <= 0) && ((int64_t)hh - (int64_t)by * kBlock <= 0);
+        G.blocks_per_chan = G.gx * G.gy - G.corner_empty;
+        G.group_start = start;
+        start += G.blocks_per_chan * d.channels;
+        if ((int)l > target_level) prefix_needed = start;
+    }
+    T.nblocks_stream = start;
+    T.nblocks = prefix_needed;
+    // per-channel arena layout (int32 elements)
+    uint64_t off = 0;
+    T.ll_pitch = round4(T.ll_w);
+    T.ll_off = off;
+    off = al(off + (uint64_t)T.ll_pitch * T.ll_h, 64);
+    for (uint32_t l = 1; l <= d.levels; l++) {
+        LevelGeo &G = T.lv[l];
+        uint32_t bw[3] = {(G.w + 1) / 2, G.w / 2, G.w / 2};
+        uint32_t bh[3] = {G.h / 2, (G.h + 1) / 2, G.h / 2};
+        for (int t = 0; t < 3; t++) {
+            G.pitch[t] = round4(bw[t] ? bw[t] : 1);
+            G.off[t] = off;
+            off = al(off + (uint64_t)G.pitch[t] * bh[t], 64);
+        }
+    }
+    T.chan_elems = al(off, 64);
+    tb.arena_elems = T.chan_elems * d.channels;
+    // LL ping-pong: odd levels (LL_1 largest), even levels (LL_2 largest)
+    if (d.levels >= 2) {
+        T.tmp_pitch[0] = round4(T.lv[2].w);
+        T.tmp_chan[0] = al((uint64_t)T.tmp_pitch[0] * T.lv[2].h, 64);
+        tb.tmp_elems[0] = T.tmp_chan[0] * d.channels;
+    }
+    if (d.levels >= 3) {
+        T.tmp_pitch[1] = round4(T.lv[3].w);
+        T.tmp_chan[1] = al((uint64_t)T.tmp_pitch[1] * T.lv[3].h, 64);
+        tb.tmp_elems[1] = T.tmp_chan[1] * d.channels;
+    }
+    // symbols
+    uint64_t sb = 0;
+    for (uint32_t i = 0; i < T.nblocks; i++) {
+        BlockDesc B;
+        block_geometry(T, i, B);
+        sb += ((uint64_t)B.p * B.wb * B.hb / 8 * T.dmax + 15) & ~15ull;
+    }
+    tb.sym_bytes = sb;
+}
+
+struct Plan {
+    std::vector<uint8_t> bytes;
+    PlanHdr H;
+};
+
+int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs, int32_t n, Plan &P)
+{
+    if (n < 1) return ISX_E_INVALID_ARG;
+    std::vector<TileBuild> tb((size_t)n);
+    PlanHdr &H = P.H;
+    memset(&H, 0, sizeof(H));
+    H.magic = kPlanMagic;
+    H.mode = (uint32_t)mode;
+    H.n_tiles = (uint32_t)n;
+    uint64_t total_blocks = 0, total_slots = 0;
+    for (int32_t i = 0; i < n; i++) {
+        const isx_tile_desc &d = mode == MODE_ENCODE ? descs[i] : jobs[i].tile;
+        int rc = validate_desc(d);
+        if (rc) return rc;
+        int z = 0;
+        if (mode == MODE_DECODE) {
+            const isx_decode_job &j = jobs[i];
+            if (j.target_level > d.levels) return ISX_E_INVALID_ARG;
+            if (j.drop_bitplanes != 0) return ISX_E_UNSUPPORTED;
+            z = j.target_level;
+        } else if (d.row_stride_bytes < (uint64_t)d.width * d.channels * d.bytes_per_sample) {
+            return ISX_E_INVALID_ARG;
+        }
+        tile_geometry(d, z, tb[i]);
+        TileGeo &T = tb[i].g;
+        if (mode == MODE_DECODE) {
+            const isx_decode_job &j = jobs[i];
+            uint32_t ow = T.width, oh = T.height;
+            for (int k = 0; k < z; k++) { ow = (ow + 1) / 2; oh = (oh + 1) / 2; }
+            if (j.out_row_stride_bytes < (uint64_t)ow * T.channels * T.bps) return ISX_E_INVALID_ARG;
+            T.pix_offset = j.out_offset;
+            T.pix_stride = j.out_row_stride_bytes;
+            T.enc_offset = j.in_offset;
+            T.enc_bytes = j.in_bytes;
+        }
+        T.block_base = (uint32_t)total_blocks;
+        T.slot_base = (uint32_t)total_slots;
+        total_blocks += T.nblocks;
+        total_slots += (uint64_t)T.nblocks * T.dmax;
+        if (total_blocks > 0x7fffffffull || total_slots > 0x7fffffffull) return ISX_E_UNSUPPORTED;
+        if (T.levels > H.max_levels) H.max_levels = T.levels;
+        if (T.nblocks > H.max_nblocks) H.max_nblocks = T.nblocks;
+    }
+    H.total_blocks = (uint32_t)total_blocks;
+    H.total_slots = (uint32_t)total_slots;
+    // workspace: global regions, then per-tile arenas
+    uint64_t o = kPlanRegion;
+    H.ws_blockdesc = o; o = al(o + total_blocks * sizeof(BlockDesc));
+    H.ws_acc = o; o = al(o + total_blocks * sizeof(BlkAcc));
+    H.ws_blkstat = o; o = al(o + total_blocks * sizeof(BlkStat));
+    H.ws_blkplan = o; o = al(o + total_blocks * sizeof(BlkPlan));
+    if (mode == MODE_ENCODE) {
+        H.ws_seghist = o; o = al(o + total_slots * 256 * sizeof(uint16_t));
+        H.ws_segstat = o; o = al(o + total_slots * sizeof(SegStat));
+    }
+    H.ws_tileout = o; o = al(o + (uint64_t)n * sizeof(TileOut));
+    if (mode == MODE_DECODE) { H.ws_lut = o; o = al(o + total_blocks * kLutBytes); }
+    for (int32_t i = 0; i < n; i++) {
+        TileGeo &T = tb[i].g;
+        uint64_t base = o / 4;  // int32 elements
+        T.ll_off += base;
+        for (uint32_t l = 1; l <= T.levels; l++)
+            for (int t = 0; t < 3; t++) T.lv[l].off[t] += base;
+        o = al(o + tb[i].arena_elems * 4);
+        T.tmp_off[0] = o / 4; o = al(o + tb[i].tmp_elems[0] * 4);
+        T.tmp_off[1] = o / 4; o = al(o + tb[i].tmp_elems[1] * 4);
+        T.sym_base = o; o = al(o + tb[i].sym_bytes);
+    }
+    H.ws_bytes = o;
+    // work lists
+    std::vector<WorkItem> items;
+    auto add_level = [&](int lvl, bool inverse) {
+        H.lvl_first[lvl] = (uint32_t)items.size();
+        uint32_t wg = 0;
+        for (int32_t i = 0; i < n; i++) {
+            const TileGeo &T = tb[i].g;
+            uint32_t w, h;
+            if (lvl == 0) {
+                if (inverse || T.levels != 0) continue;
+                w = T.width; h = T.height;
+            } else {
+                if (T.levels < lvl) continue;
+                if (inverse && lvl < (int)T.target_level + 2) continue;
+                w = T.lv[lvl].w; h = T.lv[lvl].h;
+            }
+            WorkItem it;
+            memset(&it, 0, sizeof(it));
+            it.tile = (uint32_t)i;
+            it.wg_start = wg;
+            it.ntx = div_up(w, 64); it.nty = div_up(h, 64);
+            it.nch = T.channels;
+            wg += it.ntx * it.nty * it.nch;
+            items.push_back(it);
+        }
+        H.lvl_count[lvl] = (uint32_t)items.size() - H.lvl_first[lvl];
+        H.lvl_wgs[lvl] = wg;
+    };
+    if (mode == MODE_ENCODE) {
+        for (int l = 0; l <= (int)H.max_levels; l++) add_level(l, false);
+    } else {
+        for (int l = 1; l <= (int)H.max_levels; l++) add_level(l, true);
+        H.fin_first = (uint32_t)items.size();
+        uint32_t wg = 0;
+        for (int32_t i = 0; i < n; i++) {
+            const TileGeo &T = tb[i].g;
+            uint32_t w, h;
+            if (T.target_level < T.levels) { w = T.lv[T.target_level + 1].w; h = T.lv[T.target_level + 1].h; }
+            else { w = T.ll_w; h = T.ll_h; }
+            WorkItem it;
+            memset(&it, 0, sizeof(it));
+            it.tile = (uint32_t)i;
+            it.wg_start = wg;
+            it.ntx = div_up(w, 64); it.nty = div_up(h, 64);
+            it.nch = T.ct ? 1 : div_up(T.channels, 3);
+            wg += it.ntx * it.nty * it.nch;
+            items.push_back(it);
+        }
+        H.fin_count = (uint32_t)items.size() - H.fin_first;
+        H.fin_wgs = wg;
+    }
+    H.tiles_off = al(sizeof(PlanHdr), 64);
+    H.work_off = al(H.tiles_off + (uint64_t)n * sizeof(TileGeo), 64);
+    H.plan_bytes = H.work_off + items.size() * sizeof(WorkItem);
+    if (H.plan_bytes > kPlanRegion) {
+        // large batches keep the plan after the workspace regions
+        uint64_t extra = al(H.plan_bytes);
+        H.ws_bytes += extra;
+    }
+    P.bytes.assign(H.plan_bytes, 0);
+    memcpy(P.bytes.data(), &H, sizeof(H));
+    for (int32_t i = 0; i < n; i++) memcpy(P.bytes.data() + H.tiles_off + (uint64_t)i * sizeof(TileGeo), &tb[i].g, sizeof(TileGeo));
+    if (!items.empty()) memcpy(P.bytes.data() + H.work_off, items.data(), items.size() * sizeof(WorkItem));
+    return ISX_OK;
+}
+
+// Device address of the plan copy inside the workspace (convenience API).
+uint64_t plan_ws_offset(const PlanHdr &H)
+{
+    if (H.plan_bytes <= kPlanRegion) return 0;
+    return H.ws_bytes - al(H.plan_bytes);
+}
+
+int upload_plan(const Plan &P, uint8_t *d_ws, hipStream_t stream, uint8_t **d_plan)
+{
+    *d_plan = d_ws + plan_ws_offset(P.H);
+    // A pageable source is staged by the runtime before hipMemcpyAsync returns.
+    hipError_t e = hipMemcpyAsync(*d_plan, P.bytes.data(), P.bytes.size(), hipMemcpyHostToDevice, stream);
+    return e == hipSuccess ? ISX_OK : ISX_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *isx_status_string(int32_t code)
+{
+    switch (code) {
+    case ISX_OK: return "ok";
+    case ISX_E_INVALID_ARG: return "invalid argument";
+    case ISX_E_CAPACITY: return "output capacity exceeded";
+    case ISX_E_CORRUPT: return "corrupt stream";
+    case ISX_E_TRUNCATED: return "truncated stream";
+    case ISX_E_UNSUPPORTED: return "unsupported parameters";
+    case ISX_E_WORKSPACE: return "workspace too small";
+    case ISX_E_HIP: return "HIP runtime error";
+    case ISX_E_PENDING: return "pending";
+    default: return "unknown status";
+    }
+}
+
+int64_t isx_tile_block_count(const isx_tile_desc *h_desc)
+{
+    if (!h_desc || validate_desc(*h_desc)) return ISX_E_INVALID_ARG;
+    TileBuild tb;
+    tile_geometry(*h_desc, 0, tb);
+    return tb.g.nblocks_stream;
+}
+
+uint64_t isx_max_encoded_bytes(const isx_tile_desc *h_descs, int32_t n_tiles)
+{
+    if (!h_descs || n_tiles < 1) return 0;
+    uint64_t total = 0;
+    for (int32_t i = 0; i < n_tiles; i++) {
+        if (validate_desc(h_descs[i])) return 0;
+        TileBuild tb;
+        tile_geometry(h_descs[i], 0, tb);
+        const TileGeo &T = tb.g;
+        uint64_t t = 24 + 4ull * T.nblocks_stream;
+        for (uint32_t b = 0; b < T.nblocks_stream; b++) {
+            BlockDesc B;
+            block_geometry(T, b, B);
+            uint64_t S = (uint64_t)B.p * B.wb * B.hb / 8 * T.dmax;  // symbols
+            // header <= 3200 bits; payload <= 8 bits per token + wz (<= 13)
+            // per C_zr token (< S/2 + S/256 of them): < 15 S bits
+            t += 400 + (15 * S + 7) / 8;
+        }
+        total += al(t);
+    }
+    return total;
+}
+
+uint64_t isx_encode_workspace_bytes(const isx_tile_desc *h_descs, int32_t n_tiles)
+{
+    Plan P;
+    if (!h_descs || build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P)) return 0;
+    return P.H.ws_bytes;
+}
+
+uint64_t isx_decode_workspace_bytes(const isx_decode_job *h_jobs, int32_t n_jobs)
+{
+    Plan P;
+    if (!h_jobs || build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P)) return 0;
+    return P.H.ws_bytes;
+}
+
+uint64_t isx_encode_plan_bytes(const isx_tile_desc *h_descs, int32_t n_tiles)
+{
+    Plan P;
+    if (!h_descs || build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P)) return 0;
+    return P.H.plan_bytes;
+}
+
+int32_t isx_encode_plan_build(const isx_tile_desc *h_descs, int32_t n_tiles, void *h_plan, uint64_t plan_bytes)
+{
+    Plan P;
+    if (!h_descs || !h_plan) return ISX_E_INVALID_ARG;
+    int rc = build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P);
+    if (rc) return rc;
+    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
+    memcpy(h_plan, P.bytes.data(), P.bytes.size());
+    return ISX_OK;
+}
+
+uint64_t isx_decode_plan_bytes(const isx_decode_job *h_jobs, int32_t n_jobs)
+{
+    Plan P;
+    if (!h_jobs || build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P)) return 0;
+    return P.H.plan_bytes;
+}
+
+int32_t isx_decode_plan_build(const isx_decode_job *h_jobs, int32_t n_jobs, void *h_plan, uint64_t plan_bytes)
+{
+    Plan P;
+    if (!h_jobs || !h_plan) return ISX_E_INVALID_ARG;
+    int rc = build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P);
+    if (rc) return rc;
+    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
+    memcpy(h_plan, P.bytes.data(), P.bytes.size());
+    return ISX_OK;
+}
+
+static int check_plan(const void *h_plan, int mode)
+{
+    if (!h_plan) return ISX_E_INVALID_ARG;
+    const PlanHdr *H = (const PlanHdr *)h_plan;
+    if (H->magic != kPlanMagic || H->mode != (uint32_t)mode) return ISX_E_INVALID_ARG;
+    return ISX_OK;
+}
+
+int32_t isx_encode_run(const void *h_plan, const void *d_plan, const void *d_pixels, void *d_out,
+                       uint64_t out_capacity, uint64_t *d_tile_offsets, uint64_t *d_tile_sizes,
+                       int32_t *d_status, void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    int rc = check_plan(h_plan, MODE_ENCODE);
+    if (rc) return rc;
+    const PlanHdr &H = *(const PlanHdr *)h_plan;
+    if (!d_plan || !d_pixels || !d_out || !d_tile_offsets || !d_tile_sizes || !d_status || !d_workspace)
+        return ISX_E_INVALID_ARG;
+    if (workspace_bytes < H.ws_bytes) return ISX_E_WORKSPACE;
+    hipError_t e = launch_encode(H, (const uint8_t *)d_plan, (const uint8_t *)d_pixels, (uint8_t *)d_out,
+                                 out_capacity, d_tile_offsets, d_tile_sizes, d_status, (uint8_t *)d_workspace,
+                                 (hipStream_t)stream);
+    return e == hipSuccess ? ISX_OK : ISX_E_HIP;
+}
+
+int32_t isx_decode_run(const void *h_plan, const void *d_plan, const void *d_encoded, void *d_pixels_out,
+                       int32_t *d_status, void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    int rc = check_plan(h_plan, MODE_DECODE);
+    if (rc) return rc;
+    const PlanHdr &H = *(const PlanHdr *)h_plan;
+    if (!d_plan || !d_encoded || !d_pixels_out || !d_status || !d_workspace) return ISX_E_INVALID_ARG;
+    if (workspace_bytes < H.ws_bytes) return ISX_E_WORKSPACE;
+    hipError_t e = launch_decode(H, (const uint8_t *)d_plan, (const uint8_t *)d_encoded, (uint8_t *)d_pixels_out,
+                                 d_status, (uint8_t *)d_workspace, (hipStream_t)stream);
+    return e == hipSuccess ? ISX_OK : ISX_E_HIP;
+}
+
+int32_t isx_encode_tiles(const isx_tile_desc *h_descs, int32_t n_tiles, const void *d_pixels, void *d_out,
+                         uint64_t out_capacity, uint64_t *d_tile_offsets, uint64_t *d_tile_sizes,
+                         int32_t *d_status, void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!h_descs) return ISX_E_INVALID_ARG;
+    Plan P;
+    int rc = build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P);
+    if (rc) return rc;
+    if (!d_pixels || !d_out || !d_tile_offsets || !d_tile_sizes || !d_status || !d_workspace)
+        return ISX_E_INVALID_ARG;
+    if (workspace_bytes < P.H.ws_bytes) return ISX_E_WORKSPACE;
+    uint8_t *d_plan;
+    rc = upload_plan(P, (uint8_t *)d_workspace, (hipStream_t)stream, &d_plan);
+    if (rc) return rc;
+    return isx_encode_run(P.bytes.data(), d_plan, d_pixels, d_out, out_capacity, d_tile_offsets, d_tile_sizes,
+                          d_status, d_workspace, workspace_bytes, stream);
+}
+
+int32_t isx_decode_tiles(const void *d_encoded, const isx_decode_job *h_jobs, int32_t n_jobs, void *d_pixels_out,
+                         int32_t *d_status, void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!h_jobs) return ISX_E_INVALID_ARG;
+    Plan P;
+    int rc = build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P);
+    if (rc) return rc;
+    if (!d_encoded || !d_pixels_out || !d_status || !d_workspace) return ISX_E_INVALID_ARG;
+    if (workspace_bytes < P.H.ws_bytes) return ISX_E_WORKSPACE;
+    uint8_t *d_plan;
+    rc = upload_plan(P, (uint8_t *)d_workspace, (hipStream_t)stream, &d_plan);
+    if (rc) return rc;
+    return isx_decode_run(P.bytes.data(), d_plan, d_encoded, d_pixels_out, d_status, d_workspace,
+                          workspace_bytes, stream);
+}
+
+int32_t isx_debug_forward(const isx_tile_desc *h_desc, const void *d_pixels, int32_t *d_coeffs,
+                          void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!h_desc || !d_pixels || !d_coeffs || !d_workspace) return ISX_E_INVALID_ARG;
+    Plan P;
+    int rc = build_plan(MODE_ENCODE, h_desc, nullptr, 1, P);
+    if (rc) return rc;
+    if (workspace_bytes < P.H.ws_bytes) return ISX_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *d_plan;
+    rc = upload_plan(P, (uint8_t *)d_workspace, s, &d_plan);
+    if (rc) return rc;
+    if (launch_forward_only(P.H, d_plan, (const uint8_t *)d_pixels, (uint8_t *)d_workspace, s) != hipSuccess)
+        return ISX_E_HIP;
+    const TileGeo &T = *(const TileGeo *)(P.bytes.data() + P.H.tiles_off);
+    const int32_t *wsi = (const int32_t *)d_workspace;
+    uint64_t k = 0;
+    for (uint32_t c = 0; c < T.channels; c++) {
+        struct BandRef { uint64_t off; uint32_t pitch, w, h; };
+        std::vector<BandRef> list;
+        list.push_back({T.ll_off + c * T.chan_elems, T.ll_pitch, T.ll_w, T.ll_h});
+        for (uint32_t l = T.levels; l >= 1; l--) {
+            const LevelGeo &G = T.lv[l];
+            // HL, LH, HH
+            list.push_back({G.off[1] + c * T.chan_elems, G.pitch[1], G.w / 2, (G.h + 1) / 2});
+            list.push_back({G.off[0] + c * T.chan_elems, G.pitch[0], (G.w + 1) / 2, G.h / 2});
+            list.push_back({G.off[2] + c * T.chan_elems, G.pitch[2], G.w / 2, G.h / 2});
+        }
+        for (const BandRef &b : list) {
+            if (b.w && b.h) {
+                hipError_t e = hipMemcpy2DAsync(d_coeffs + k, (size_t)b.w * 4, wsi + b.off, (size_t)b.pitch * 4,
+                                                (size_t)b.w * 4, b.h, hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) return ISX_E_HIP;
+            }
+            k += (uint64_t)b.w * b.h;
+        }
+    }
+    return ISX_OK;
+}
+
+int32_t isx_debug_huffman(const uint32_t *d_freq, int32_t limit, uint8_t *d_len, void *stream)
+{
+    if (!d_freq || !d_len) return ISX_E_INVALID_ARG;
+    if (limit != 0 && (limit < 8 || limit > 15)) return ISX_E_INVALID_ARG;
+    return launch_debug_huffman(d_freq, limit, d_len, (hipStream_t)stream) == hipSuccess ? ISX_OK : ISX_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,857 @@
+// k_encode.hip -- per-block entropy coder of the codec (Sec. 4, Eq. 1-3,
+// Fig. 3) for gfx950: symbols, statistics, code construction, offsets and the
+// bit packer.
+//
+// Per block (one workgroup each):
+//  k_enc_symbols  d from the OR of the magnitudes (collected by the forward
+//                 transform), the 4x2-area symbols of every kept bitplane
+//                 (Eq. 1 order: 4-row bands, 4-column groups, upper area then
+//                 lower area; Eq. 2 bit weights), a 256-bin histogram per
+//                 segment, and the maximal zero runs of each segment via a
+//                 workgroup prefix-max scan of "last non-zero position".
+//  k_enc_code     C_zr = least frequent symbol (smallest on ties), a
+//                 provisional Huffman code to get l, the counter width wz
+//                 minimising Eq. 3, the final Huffman code (two-queue merge,
+//                 (f, symbol) order, leaf first on ties), canonical codes,
+//                 exact segment lengths (seek table), header and block sizes.
+//  k_enc_pack     one workgroup per block header and per segment: token bit
+//                 lengths, a prefix sum to bit offsets, MSB-first packing into
+//                 an LDS window, written once to the final position in HBM.
+// Per tile: block offsets (scan), tile offsets (scan), tile header.
+#include "isx_common.h"
+
+namespace isx {
+
+#define ISX_STATUS_OK 0
+#define ISX_STATUS_CAPACITY (-2)
+#define ISX_STATUS_CORRUPT (-3)
+#define ISX_STATUS_TRUNC (-4)
+#define ISX_STATUS_UNSUP (-5)
+
+// ---------------------------------------------------------------- scans
+template <int NT>
+__device__ inline uint64_t block_excl_sum_u64(uint64_t v, uint64_t *sh /* NT/64 + 1 */, uint64_t *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+    for (int w = 0; w < NT / 64; w++) {
+        if (w < wave) base += sh[w];
+        tot += sh[w];
+    }
+    __syncthreads();
+    if (total) *total = tot;
+    return base + x - v;
+}
+
+template <int NT>
+__device__ inline int32_t block_excl_max_i32(int32_t v, int32_t *sh)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x = max(x, y);
+    }
+    int32_t ex = __shfl_up(x, 1, 64);
+    if (lane == 0) ex = -1;
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    int32_t base = -1;
+    for (int w = 0; w < wave; w++) base = max(base, sh[w]);
+    __syncthreads();
+    return max(base, ex);
+}
+
+// Digits of L in bijective base B = 2^w - 1.
+__device__ inline uint32_t bij_digits(uint32_t L, uint32_t B)
+{
+    uint32_t m = 1, t = B, p = B;
+    while (L > t) { p *= B; t += p; m++; }
+    return m;
+}
+
+// ---------------------------------------------------------------- prep
+// Per tile: block descriptors, symbol-area offsets, zeroed accumulators.
+__global__ void __launch_bounds__(256) k_prep_blocks(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                     uint8_t *__restrict__ ws)
+{
+    __shared__ uint64_t sh[8];
+    const TileGeo &T = ((const TileGeo *)(plan + H.tiles_off))[blockIdx.x];
+    BlockDesc *descs = (BlockDesc *)(ws + H.ws_blockdesc);
+    BlkAcc *acc = (BlkAcc *)(ws + H.ws_acc);
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < T.nblocks; base += 256) {
+        uint32_t local = base + threadIdx.x;
+        BlockDesc B;
+        uint64_t sz = 0;
+        if (local < T.nblocks) {
+            block_geometry(T, local, B);
+            sz = ((uint64_t)B.p * B.wb * B.hb / 8 * T.dmax + 15) & ~15ull;
+        }
+        uint64_t tot;
+        uint64_t ex = block_excl_sum_u64<256>(sz, sh, &tot);
+        if (local < T.nblocks) {
+            B.tile = blockIdx.x;
+            B.sym_off = T.sym_base + carry + ex;
+            B.slot = T.slot_base + local * T.dmax;
+            B.dmax = T.dmax;
+            B.byte_off = 0;
+            B.byte_len = 0;
+            descs[T.block_base + local] = B;
+            BlkAcc z = {{0, 0, 0}, 0};
+            acc[T.block_base + local] = z;
+        }
+        carry += tot;
+    }
+}
+
+// ---------------------------------------------------------------- symbols
+constexpr int kSymNT = 1024;
+constexpr int kCellsPT = 3;  // 3 x 1024 cells = one 128x128 H-block (3 types)
+
+__global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                        uint8_t *__restrict__ ws)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ int32_t wsh[kSymNT / 64];
+    __shared__ uint32_t s_zir, s_dig[kNumWz], s_F[16], s_nruns, s_zero;
+    const uint32_t blk = blockIdx.x;
+    const BlockDesc B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+    const BlkAcc A = ((const BlkAcc *)(ws + H.ws_acc))[blk];
+    BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
+    BlkStat &S = ((BlkStat *)(ws + H.ws_blkstat))[blk];
+    uint16_t *seghist = (uint16_t *)(ws + H.ws_seghist);
+    SegStat *segstat = (SegStat *)(ws + H.ws_segstat);
+    const int32_t *wsi = (const int32_t *)ws;
+    const uint32_t p = B.p, wb = B.wb, hb = B.hb, n = wb * hb / 8, cpt = n / 2, wq = wb / 4;
+    const uint32_t tid = threadIdx.x;
+
+    uint32_t orall = A.or_mag[0] | A.or_mag[1] | A.or_mag[2];
+    uint32_t d = 1 + bitlen32(orall);
+    uint32_t err = 0;
+    if (d > B.dmax) { err = 1; d = B.dmax; }
+    uint32_t pres[3];
+    for (int t = 0; t < 3; t++)
+        pres[t] = (t < (int)p) ? ((A.or_mag[t] & ((1u << (d - 1)) - 1u)) | (((A.neg >> t) & 1u) << (d - 1))) : 0u;
+
+    // load own cells (16 magnitudes + sign bits each)
+    uint32_t mag[kCellsPT][16];
+    uint32_t sgn[kCellsPT];
+    uint32_t ctype[kCellsPT], cci[kCellsPT];
+    const uint32_t ncell = p * cpt;
+    for (int k = 0; k < kCellsPT; k++) {
+        uint32_t cell = tid * kCellsPT + k;
+        sgn[k] = 0;
+        ctype[k] = 3;
+        cci[k] = 0;
+#pragma unroll
+        for (int i = 0; i < 16; i++) mag[k][i] = 0;
+        if (cell >= ncell) continue;
+        uint32_t t = cell / cpt, ci = cell % cpt;
+        ctype[k] = t;
+        cci[k] = ci;
+        uint32_t band = ci / wq, cg = ci % wq;
+        uint32_t r0 = 4 * band, c0 = 4 * cg;
+        const uint32_t tw = B.tw[t], th = B.th[t];
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            uint32_t row = r0 + rr;
+            if (row >= th || c0 >= tw) continue;
+            const int32_t *src = wsi + B.off[t] + (uint64_t)row * B.pitch[t] + c0;
+            int32_t v[4];
+            if (c0 + 3 < tw) {
+                int4 q = *(const int4 *)src;
+                v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < 4; cc++) v[cc] = (c0 + cc < tw) ? src[cc] : 0;
+            }
+#pragma unroll
+            for (int cc = 0; cc < 4; cc++) {
+                int32_t x = v[cc];
+                mag[k][rr * 4 + cc] = (uint32_t)(x < 0 ? -x : x);
+                sgn[k] |= (x < 0 ? 1u : 0u) << (rr * 4 + cc);
+            }
+        }
+    }
+
+    if (tid < 256) hist[tid] = 0;
+    if (tid < kNumWz) s_dig[tid] = 0;
+    if (tid < 16) s_F[tid] = 0;
+    if (tid == 0) { s_zir = 0; s_nruns = 0; s_zero = 0; }
+    __syncthreads();
+
+    uint32_t nseg = 0;
+    for (int b = (int)d - 1; b >= 0; b--) {
+        uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
+        if (!pm) continue;
+        uint32_t M = n * __popc(pm);
+        uint8_t *segp = ws + B.sym_off + (uint64_t)b * p * n;
+        // symbols of own cells
+        uint32_t sy[kCellsPT], pos[kCellsPT];
+        int32_t lastnz = -1;
+        uint32_t zeros = 0;
+        for (int k = 0; k < kCellsPT; k++) {
+            sy[k] = 0;
+            pos[k] = 0xffffffffu;
+            uint32_t t = ctype[k];
+            if (t > 2 || !((pm >> t) & 1u)) continue;
+            uint32_t v = 0;
+            if ((uint32_t)b == d - 1) v = sgn[k];
+            else {
+#pragma unroll
+                for (int i = 0; i < 16; i++) v |= ((mag[k][i] >> b) & 1u) << i;
+            }
+            uint32_t rank = __popc(pm & ((1u << t) - 1u));
+            uint32_t ps = rank * n + 2 * cci[k];
+            pos[k] = ps;
+            sy[k] = v;
+            *(uint16_t *)(segp + ps) = (uint16_t)v;
+            uint32_t top = v & 0xffu, bot = v >> 8;
+            if (top) { atomicAdd(&hist[top], 1u); lastnz = (int32_t)ps; } else zeros++;
+            if (bot) { atomicAdd(&hist[bot], 1u); lastnz = (int32_t)ps + 1; } else zeros++;
+        }
+        // zeros: one atomic per wave
+        for (int o = 32; o >= 1; o >>= 1) zeros += __shfl_xor(zeros, o, 64);
+        if ((tid & 63) == 0 && zeros) atomicAdd(&s_zero, zeros);
+        int32_t prev = block_excl_max_i32<kSymNT>(lastnz, wsh);
+        // runs terminated inside this thread (by a non-zero symbol or the segment end)
+        int32_t cur = prev;
+        for (int k = 0; k < kCellsPT; k++) {
+            if (pos[k] == 0xffffffffu) continue;
+            for (int h = 0; h < 2; h++) {
+                uint32_t s = h ? (sy[k] >> 8) : (sy[k] & 0xffu);
+                int32_t ps = (int32_t)pos[k] + h;
+                bool endseg = (uint32_t)ps == M - 1;
+                if (s || endseg) {
+                    int32_t L = s ? (ps - cur - 1) : (ps - cur);
+                    if (L >= 2) {
+                        atomicAdd(&s_F[bitlen32((uint32_t)L)], 1u);
+                        atomicAdd(&s_zir, (uint32_t)L);
+                        atomicAdd(&s_nruns, 1u);
+                        for (int i = 0; i < kNumWz; i++) {
+                            uint32_t Bb = (1u << (i + 2)) - 1u;
+                            atomicAdd(&s_dig[i], bij_digits((uint32_t)L, Bb));
+                        }
+                    }
+                    if (s) cur = ps;
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t slot = B.slot + (uint32_t)b;
+        if (tid < 256) {
+            uint32_t hv = hist[tid];
+            if (tid == 0) hv = s_zero;
+            seghist[(uint64_t)slot * 256 + tid] = (uint16_t)hv;
+            hist[tid] = 0;
+        }
+        if (tid < kNumWz) { segstat[slot].dig[tid] = s_dig[tid]; }
+        if (tid == 0) {
+            segstat[slot].zir = s_zir;
+            P.seg_plane[nseg] = (uint8_t)b;
+            P.seg_M[nseg] = M;
+        }
+        __syncthreads();
+        if (tid < kNumWz) s_dig[tid] = 0;
+        if (tid == 0) { s_zir = 0; s_zero = 0; }
+        nseg++;
+        __syncthreads();
+    }
+    if (tid < 16) S.F[tid] = s_F[tid];
+    if (tid == 0) {
+        S.nruns = s_nruns;
+        S.err = err;
+        P.d = d;
+        P.nseg = nseg;
+        P.p = p;
+        P.n = n;
+        P.err = err;
+        for (uint32_t t = 0; t < 3; t++) P.masks[t] = (t < p) ? (~pres[t] & ((1u << d) - 1u)) : 0u;
+    }
+}
+
+// ---------------------------------------------------------------- Huffman
+// Code lengths of the per-block Huffman code (Sec. 3 / Sec. 4): leaves with
+// f > 0 sorted by (f, symbol); two-queue merge taking the leaf on equal
+// weight; length = depth.  256 threads; the merge itself is sequential.
+struct HuffScratch {
+    uint32_t w[512];
+    uint16_t par[512];
+    uint16_t srt[256];
+    uint32_t m;
+};
+
+__device__ void huff_lengths(const uint32_t *f, uint8_t *len, HuffScratch &S)
+{
+    const uint32_t v = threadIdx.x;
+    uint32_t fv = f[v];
+    uint32_t m = __syncthreads_count(fv > 0);
+    len[v] = 0;
+    if (m <= 1) { __syncthreads(); return; }
+    if (fv > 0) {
+        uint32_t r = 0;
+        for (uint32_t u = 0; u < 256; u++) {
+            uint32_t fu = f[u];
+            r += (fu > 0) && (fu < fv || (fu == fv && u < v));
+        }
+        S.srt[r] = (uint16_t)v;
+        S.w[r] = fv;
+    }
+    __syncthreads();
+    if (v == 0) {
+        uint32_t qa = 0, qb = m, qe = m;
+        uint32_t wa = S.w[0];
+        for (uint32_t step = 0; step + 1 < m; step++) {
+            uint32_t pick[2], pw[2];
+            for (int t = 0; t < 2; t++) {
+                bool leaf;
+                if (qa >= m) leaf = false;
+                else if (qb >= qe) leaf = true;
+                else leaf = wa <= S.w[qb];
+                if (leaf) { pick[t] = qa; pw[t] = wa; qa++; wa = (qa < m) ? S.w[qa] : 0; }
+                else { pick[t] = qb; pw[t] = S.w[qb]; qb++; }
+            }
+            S.w[qe] = pw[0] + pw[1];
+            S.par[pick[0]] = (uint16_t)qe;
+            S.par[pick[1]] = (uint16_t)qe;
+            qe++;
+        }
+        S.par[qe - 1] = 0xffff;
+    }
+    __syncthreads();
+    if (v < m) {
+        uint32_t dpt = 0, x = v;
+        while (S.par[x] != 0xffff) { x = S.par[x]; dpt++; }
+        len[S.srt[v]] = (uint8_t)dpt;
+    }
+    __syncthreads();
+}
+
+// Length-limited optimal code by package-merge (fallback when a seek-table
+// entry of t bits cannot hold a segment length).  Thread 0 runs it; lengths
+// are added level by level while backtracking the chosen items.
+struct PMScratch {
+    uint32_t wa[512], wb[512];
+    uint32_t flag[16][16];  // per level: bit i = item i is a package
+};
+
+__device__ void package_merge_lengths(const uint32_t *f, int limit, uint8_t *len, HuffScratch &S,
+                                      PMScratch &Q)
+{
+    const uint32_t v = threadIdx.x;
+    uint32_t fv = f[v];
+    uint32_t m = __syncthreads_count(fv > 0);
+    len[v] = 0;
+    if (m <= 1) { __syncthreads(); return; }
+    if (fv > 0) {
+        uint32_t r = 0;
+        for (uint32_t u = 0; u < 256; u++) {
+            uint32_t fu = f[u];
+            r += (fu > 0) && (fu < fv || (fu == fv && u < v));
+        }
+        S.srt[r] = (uint16_t)v;
+        S.w[r] = fv;
+    }
+    __syncthreads();
+    if (v == 0) {
+        uint32_t *prev = Q.wa, *cur = Q.wb;
+        for (uint32_t i = 0; i < m; i++) prev[i] = S.w[i];
+        uint32_t nprev = m;
+        for (int lvl = 0; lvl < 16; lvl++)
+            for (int i = 0; i < 16; i++) Q.flag[lvl][i] = 0;
+        // level index j = limit (finest) ... 1; flags stored for j = 1..limit-1
+        for (int j = limit - 1; j >= 1; j--) {
+            uint32_t npk = nprev / 2, a = 0, b = 0, nc = 0;
+            while (a < m || b < npk) {
+                bool coin;
+                uint32_t wpk = (b < npk) ? prev[2 * b] + prev[2 * b + 1] : 0;
+                if (a >= m) coin = false;
+                else if (b >= npk) coin = true;
+                else coin = S.w[a] <= wpk;
+                if (coin) { cur[nc] = S.w[a]; a++; }
+                else { cur[nc] = wpk; Q.flag[j][nc >> 5] |= 1u << (nc & 31); b++; }
+                nc++;
+            }
+            uint32_t *t = prev; prev = cur; cur = t; nprev = nc;
+        }
+        // backtrack from level 1: choose the first 2(m-1) items
+        uint32_t take = 2 * (m - 1);
+        for (int j = 1; j <= limit; j++) {
+            uint32_t leaves = 0, pk = 0;
+            for (uint32_t i = 0; i < take; i++) {
+                bool isp = (j < limit) && ((Q.flag[j][i >> 5] >> (i & 31)) & 1u);
+                if (isp) pk++; else leaves++;
+            }
+            for (uint32_t i = 0; i < leaves; i++) len[S.srt[i]]++;
+            take = 2 * pk;
+            if (!take) break;
+        }
+    }
+    __syncthreads();
+}
+
+// Canonical codes (sort by (length, symbol), count up) and the leaf order.
+__device__ void canonical(const uint8_t *len, uint32_t *code, uint8_t *order, uint32_t *s_cnt,
+                          uint32_t *s_first, uint32_t *s_below)
+{
+    const uint32_t v = threadIdx.x;
+    if (v < 40) s_cnt[v] = 0;
+    __syncthreads();
+    uint32_t lv = len[v];
+    if (lv) atomicAdd(&s_cnt[lv], 1u);
+    __syncthreads();
+    if (v == 0) {
+        uint32_t c = 0, below = 0;
+        s_first[0] = 0;
+        s_below[0] = 0;
+        for (int b = 1; b < 40; b++) {
+            c = (c + (b >= 2 ? s_cnt[b - 1] : 0)) << 1;
+            s_first[b] = c;
+            s_below[b] = below;
+            below += s_cnt[b];
+        }
+    }
+    __syncthreads();
+    if (lv) {
+        uint32_t idx = 0;
+        for (uint32_t u = 0; u < v; u++) idx += len[u] == lv;
+        code[v] = s_first[lv] + idx;
+        order[s_below[lv] + idx] = (uint8_t)v;
+    } else {
+        code[v] = 0;
+    }
+    __syncthreads();
+}
+
+struct CodeShared {
+    uint16_t sh_hist[kMaxPlanes][256];
+    uint32_t f[256];
+    uint32_t lit[256];
+    uint8_t len[256];
+    uint32_t code[256];
+    uint8_t order[256];
+    uint32_t segbits[32];
+    uint32_t cnt[40], first[40], below[40];
+    uint32_t scal[16];
+    uint64_t red[4];
+    HuffScratch hs;
+};
+
+__device__ void seg_lengths(CodeShared &C, const SegStat *segstat, uint32_t slot0, const BlkPlan &Pr,
+                            uint32_t nseg, uint32_t czr, uint32_t wz)
+{
+    const uint32_t v = threadIdx.x;
+    if (v < 32) C.segbits[v] = 0;
+    __syncthreads();
+    uint32_t cost = C.len[v] + (v == czr ? wz : 0u);
+    for (uint32_t s = 0; s < nseg; s++) {
+        uint32_t cnt = C.sh_hist[s][v];
+        if (v == 0) cnt -= segstat[slot0 + Pr.seg_plane[s]].zir;
+        uint32_t add = cnt * cost;
+        if (v == 0) add += segstat[slot0 + Pr.seg_plane[s]].dig[wz - 2] * (C.len[czr] + wz);
+        if (add) atomicAdd(&C.segbits[s], add);
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict__ ws)
+{
+    __shared__ CodeShared C;
+    __shared__ PMScratch Q;
+    const uint32_t blk = blockIdx.x, v = threadIdx.x;
+    const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+    BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
+    const BlkStat &S = ((const BlkStat *)(ws + H.ws_blkstat))[blk];
+    const uint16_t *seghist = (const uint16_t *)(ws + H.ws_seghist);
+    const SegStat *segstat = (const SegStat *)(ws + H.ws_segstat);
+    const uint32_t nseg = P.nseg, d = P.d, p = P.p, n = P.n;
+    const uint32_t tb = bitlen32(p * n) - 1 + 5;  // t = floor(log2(p w h / 8)) + 5
+    if (nseg == 0) {
+        if (v == 0) {
+            P.czr = 0; P.wz = 0; P.m = 0; P.tbits = tb; P.limited = 0;
+            P.hdr_bits = 5 + p * d;
+            P.bytes = (P.hdr_bits + 7) / 8;
+        }
+        return;
+    }
+    // per-segment histograms into LDS, block histogram
+    uint32_t h = 0;
+    for (uint32_t s = 0; s < nseg; s++) {
+        uint16_t x = seghist[(uint64_t)(B.slot + P.seg_plane[s]) * 256 + v];
+        C.sh_hist[s][v] = x;
+        h += x;
+    }
+    if (v == 0) {
+        uint32_t Z = 0;
+        for (uint32_t s = 0; s < nseg; s++) Z += segstat[B.slot + P.seg_plane[s]].zir;
+        C.scal[0] = Z;
+    }
+    // C_zr: least frequent symbol, smallest value on ties (Sec. 4)
+    uint64_t key = ((uint64_t)h << 8) | v;
+    for (int o = 32; o >= 1; o >>= 1) { uint64_t y = __shfl_xor(key, o, 64); key = y < key ? y : key; }
+    if ((v & 63) == 0) C.red[v >> 6] = key;
+    __syncthreads();
+    uint64_t kmin = C.red[0];
+    for (int i = 1; i < 4; i++) kmin = C.red[i] < kmin ? C.red[i] : kmin;
+    const uint32_t czr = (uint32_t)(kmin & 0xff);
+    uint32_t lit = h - (v == 0 ? C.scal[0] : 0u);
+    C.lit[v] = lit;
+    C.f[v] = lit + (v == czr ? S.nruns : 0u);
+    __syncthreads();
+    // provisional code (each run one C_zr token) -> l
+    huff_lengths(C.f, C.len, C.hs);
+    const uint32_t l = C.len[czr];
+    // counter width: Eq. 3 as read, minimised over [2, max(2, beta)]
+    const uint32_t beta = bitlen32(p * n - 1);
+    const uint32_t wzhi = beta > 2 ? beta : 2;
+    if (v == 0) {
+        uint64_t best = ~0ull;
+        uint32_t bw = 2;
+        for (uint32_t w = 2; w <= wzhi; w++) {
+            uint64_t cost = 0;
+            for (uint32_t i = 1; i < 16; i++) cost += (uint64_t)S.F[i] * ((i + w - 1) / w) * (w + l);
+            if (cost < best) { best = cost; bw = w; }
+        }
+        uint32_t D = 0;
+        for (uint32_t s = 0; s < nseg; s++) D += segstat[B.slot + P.seg_plane[s]].dig[bw - 2];
+        C.scal[1] = bw;
+        C.scal[2] = D;
+    }
+    __syncthreads();
+    const uint32_t wz = C.scal[1];
+    C.f[v] = C.lit[v] + (v == czr ? C.scal[2] : 0u);
+    __syncthreads();
+    huff_lengths(C.f, C.len, C.hs);
+    seg_lengths(C, segstat, B.slot, P, nseg, czr, wz);
+    // seek-table overflow -> length-limited fallback
+    uint32_t limited = 0;
+    {
+        uint32_t ov = (v < nseg) && (C.segbits[v] >= (1u << tb));
+        if (__syncthreads_or(ov)) {
+            package_merge_lengths(C.f, 14, C.len, C.hs, Q);
+            seg_lengths(C, segstat, B.slot, P, nseg, czr, wz);
+            limited = 1;
+        }
+    }
+    canonical(C.len, C.code, C.order, C.cnt, C.first, C.below);
+    uint32_t m = __syncthreads_count(C.f[v] > 0);
+    if (m == 1 && C.f[v] > 0) C.order[0] = (uint8_t)v;  // single leaf: code length 0
+    __syncthreads();
+    P.code[v] = C.code[v];
+    P.len[v] = C.len[v];
+    P.order[v] = C.order[v];
+    if (v < nseg) P.seg_bits[v] = C.segbits[v];
+    if (v == 0) {
+        uint32_t over = 0, sum = 0;
+        for (uint32_t s = 0; s < nseg; s++) { sum += C.segbits[s]; over |= C.segbits[s] >= (1u << tb); }
+        P.czr = czr; P.wz = wz; P.m = m; P.tbits = tb; P.limited = limited;
+        P.hdr_bits = 5 + p * d + 8 + 4 + (10 * m - 1) + nseg * tb;
+        P.bytes = (P.hdr_bits + sum + 7) / 8;
+        if (over) P.err = 2;
+    }
+}
+
+// ---------------------------------------------------------------- offsets
+__global__ void __launch_bounds__(256) k_enc_block_offsets(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                           uint8_t *__restrict__ ws)
+{
+    __shared__ uint64_t sh[8];
+    const TileGeo &T = ((const TileGeo *)(plan + H.tiles_off))[blockIdx.x];
+    BlkPlan *plans = (BlkPlan *)(ws + H.ws_blkplan);
+    TileOut *to = (TileOut *)(ws + H.ws_tileout);
+    uint64_t carry = 24 + 4ull * T.nblocks_stream;
+    uint32_t err = 0;
+    for (uint32_t base = 0; base < T.nblocks; base += 256) {
+        uint32_t local = base + threadIdx.x;
+        uint64_t sz = 0;
+        if (local < T.nblocks) {
+            sz = plans[T.block_base + local].bytes;
+            err |= plans[T.block_base + local].err;
+        }
+        uint64_t tot;
+        uint64_t ex = block_excl_sum_u64<256>(sz, sh, &tot);
+        if (local < T.nblocks) plans[T.block_base + local].byte_off = carry + ex;
+        carry += tot;
+    }
+    err = __syncthreads_or(err);
+    if (threadIdx.x == 0) {
+        to[blockIdx.x].size = carry;
+        to[blockIdx.x].status = err ? ISX_STATUS_UNSUP : ISX_STATUS_OK;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_enc_tile_offsets(PlanHdr H, uint8_t *__restrict__ ws,
+                                                           uint64_t capacity,
+                                                           uint64_t *__restrict__ d_off,
+                                                           uint64_t *__restrict__ d_size,
+                                                           int32_t *__restrict__ d_status)
+{
+    __shared__ uint64_t sh[16];
+    TileOut *to = (TileOut *)(ws + H.ws_tileout);
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < H.n_tiles; base += 1024) {
+        uint32_t i = base + threadIdx.x;
+        uint64_t sz = 0;
+        if (i < H.n_tiles) sz = (to[i].size + 255) & ~255ull;
+        uint64_t tot;
+        uint64_t ex = block_excl_sum_u64<1024>(sz, sh, &tot);
+        if (i < H.n_tiles) {
+            uint64_t off = carry + ex;
+            int32_t st = to[i].status;
+            if (st == ISX_STATUS_OK && off + ((to[i].size + 3) & ~3ull) > capacity) st = ISX_STATUS_CAPACITY;
+            to[i].offset = off;
+            to[i].status = st;
+            d_off[i] = off;
+            d_size[i] = to[i].size;
+            d_status[i] = st;
+        }
+        carry += tot;
+    }
+}
+
+// Tile header (little endian) + block size table; zero the payload words so
+// the packers can OR the words shared by neighbouring blocks/segments.
+__global__ void __launch_bounds__(256) k_enc_tile_finish(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                         const uint8_t *__restrict__ ws,
+                                                         uint8_t *__restrict__ out)
+{
+    const TileGeo &T = ((const TileGeo *)(plan + H.tiles_off))[blockIdx.x];
+    const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[blockIdx.x];
+    if (O.status != ISX_STATUS_OK) return;
+    const BlkPlan *plans = (const BlkPlan *)(ws + H.ws_blkplan);
+    uint32_t *w = (uint32_t *)(out + O.offset);
+    uint32_t nw = (uint32_t)((O.size + 3) / 4);
+    uint32_t hdrw = 6 + T.nblocks_stream;
+    for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
+        uint32_t x = 0;
+        if (i == 0) x = 0x31585349u;  // "ISX1"
+        else if (i == 1) x = 1u | ((uint32_t)T.ct << 8) | ((uint32_t)T.channels << 16) | ((uint32_t)T.bits << 24);
+        else if (i == 2) x = (uint32_t)T.bps | ((uint32_t)T.levels << 8) | ((uint32_t)T.qstep << 16);
+        else if (i == 3) x = T.width;
+        else if (i == 4) x = T.height;
+        else if (i == 5) x = T.nblocks_stream;
+        else if (i < hdrw) x = plans[T.block_base + (i - 6)].bytes;
+        w[i] = x;
+    }
+}
+
+// ---------------------------------------------------------------- pack
+constexpr int kStageWords = 4160;  // > (2^17 + 64) / 32
+
+__device__ inline void put_bits(uint32_t *st, uint32_t pos, uint32_t val, uint32_t nb)
+{
+    if (!nb) return;
+    if (nb < 32) val &= (1u << nb) - 1u;
+    uint32_t wi = pos >> 5, o = pos & 31u;
+    uint64_t x = (uint64_t)val << (64u - nb - o);
+    uint32_t hi = (uint32_t)(x >> 32), lo = (uint32_t)x;
+    if (hi) atomicOr(&st[wi], hi);
+    if (lo) atomicOr(&st[wi + 1], lo);
+}
+
+__device__ inline void flush_bits(const uint32_t *st, uint64_t abs_bit, uint32_t nbits, uint32_t *outw)
+{
+    uint32_t o = (uint32_t)(abs_bit & 31u);
+    uint64_t w0 = abs_bit >> 5;
+    uint32_t nw = (o + nbits + 31) >> 5;
+    for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
+        uint32_t v = st[i];
+        bool partial = (i == 0 && o != 0) || (i == nw - 1 && ((o + nbits) & 31u) != 0);
+        if (partial) { if (v) atomicOr(&outw[w0 + i], __builtin_bswap32(v)); }
+        else outw[w0 + i] = __builtin_bswap32(v);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__restrict__ ws_c,
+                                                  uint8_t *__restrict__ out)
+{
+    __shared__ uint32_t st[kStageWords];
+    __shared__ uint32_t s_code[256];
+    __shared__ uint8_t s_len[256];
+    __shared__ uint64_t sh[4];
+    __shared__ int32_t shi[4];
+    const uint8_t *ws = ws_c;
+    const uint32_t blk = blockIdx.x, y = blockIdx.y, tid = threadIdx.x;
+    const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+    const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
+    const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[B.tile];
+    if (O.status != ISX_STATUS_OK) return;
+    const uint32_t nseg = P.nseg;
+    if (y > nseg) return;
+    uint32_t *outw = (uint32_t *)out;
+    const uint64_t bit0 = (O.offset + P.byte_off) * 8;
+    if (y == 0) {
+        // header: d | masks | C_zr | wz | tree | seek table (Fig. 3)
+        const uint32_t nbits = P.hdr_bits;
+        const uint32_t o = (uint32_t)(bit0 & 31u);
+        const uint32_t nw = (o + nbits + 31) >> 5;
+        for (uint32_t i = tid; i < nw + 1; i += blockDim.x) st[i] = 0;
+        __syncthreads();
+        const uint32_t d = P.d, p = P.p;
+        if (tid == 0) {
+            put_bits(st, o, d, 5);
+            for (uint32_t t = 0; t < p; t++) put_bits(st, o + 5 + t * d, P.masks[t], d);
+            if (nseg) {
+                put_bits(st, o + 5 + p * d, P.czr, 8);
+                put_bits(st, o + 13 + p * d, P.wz, 4);
+            }
+        }
+        if (nseg) {
+            const uint32_t tree0 = o + 17 + p * d;
+            const uint32_t m = P.m;
+            uint32_t zj = 0, sym = 0;
+            if (tid < m) {
+                sym = P.order[tid];
+                uint32_t lj = P.len[sym];
+                if (tid == 0) zj = lj;
+                else {
+                    uint32_t ps = P.order[tid - 1];
+                    uint32_t lp = P.len[ps], cp = P.code[ps];
+                    zj = lj - lp + (uint32_t)__builtin_ctz(~cp);  // trailing ones of the previous code
+                }
+            }
+            uint64_t ex = block_excl_sum_u64<256>(tid < m ? (uint64_t)(zj + 9) : 0ull, sh, nullptr);
+            if (tid < m) put_bits(st, tree0 + (uint32_t)ex + zj, 0x100u | sym, 9);
+            const uint32_t seek0 = tree0 + 10 * m - 1;
+            if (tid < nseg) put_bits(st, seek0 + tid * P.tbits, P.seg_bits[tid], P.tbits);
+        }
+        __syncthreads();
+        flush_bits(st, bit0, nbits, outw);
+        return;
+    }
+    // segment y-1: tokens of the plane's symbols
+    const uint32_t s = y - 1;
+    uint32_t start = P.hdr_bits;
+    for (uint32_t i = 0; i < s; i++) start += P.seg_bits[i];
+    const uint32_t nbits = P.seg_bits[s];
+    const uint64_t abit = bit0 + start;
+    const uint32_t o = (uint32_t)(abit & 31u);
+    const uint32_t nw = (o + nbits + 31) >> 5;
+    for (uint32_t i = tid; i < nw + 1; i += blockDim.x) st[i] = 0;
+    s_code[tid] = P.code[tid];
+    s_len[tid] = P.len[tid];
+    __syncthreads();
+    const uint32_t M = P.seg_M[s];
+    const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * P.p * P.n;
+    const uint32_t czr = P.czr, wz = P.wz, Bb = (1u << wz) - 1u;
+    const uint32_t lz = s_len[czr];
+    const uint32_t chunk = (M + 255) / 256;
+    const uint32_t lo = tid * chunk;
+    uint32_t hi = lo + chunk;
+    if (hi > M) hi = M;
+    uint8_t loc[32];
+    int32_t lastnz = -1;
+    for (uint32_t i = 0; i < 32; i++) {
+        uint32_t ps = lo + i;
+        loc[i] = (ps < hi) ? syms[ps] : 0;
+        if (ps < hi && loc[i]) lastnz = (int32_t)ps;
+    }
+    int32_t prev = block_excl_max_i32<256>(lastnz, shi);
+    // pass 1: bit count
+    uint32_t bits = 0;
+    {
+        int32_t cur = prev;
+        for (uint32_t i = 0; i < 32 && lo + i < hi; i++) {
+            uint32_t v = loc[i];
+            int32_t ps = (int32_t)(lo + i);
+            bool endseg = (uint32_t)ps == M - 1;
+            if (v || endseg) {
+                int32_t L = v ? (ps - cur - 1) : (ps - cur);
+                if (L == 1) bits += s_len[0] + (czr == 0 ? wz : 0u);
+                else if (L >= 2) bits += bij_digits((uint32_t)L, Bb) * (lz + wz);
+                if (v) { bits += s_len[v] + (v == czr ? wz : 0u); cur = ps; }
+            }
+        }
+    }
+    uint64_t off = block_excl_sum_u64<256>(bits, sh, nullptr);
+    // pass 2: write
+    {
+        uint32_t bp = o + (uint32_t)off;
+        int32_t cur = prev;
+        for (uint32_t i = 0; i < 32 && lo + i < hi; i++) {
+            uint32_t v = loc[i];
+            int32_t ps = (int32_t)(lo + i);
+            bool endseg = (uint32_t)ps == M - 1;
+            if (v || endseg) {
+                int32_t L = v ? (ps - cur - 1) : (ps - cur);
+                if (L == 1) {
+                    put_bits(st, bp, s_code[0], s_len[0]); bp += s_len[0];
+                    if (czr == 0) bp += wz;  // literal C_zr: counter 0
+                } else if (L >= 2) {
+                    // bijective base-(2^wz - 1) digits, most significant first
+                    uint32_t dg[16], nd = 0, x = (uint32_t)L;
+                    while (x > 0) { uint32_t q = (x - 1) / Bb; dg[nd++] = x - q * Bb; x = q; }
+                    for (int k = (int)nd - 1; k >= 0; k--) {
+                        put_bits(st, bp, s_code[czr], lz); bp += lz;
+                        put_bits(st, bp, dg[k], wz); bp += wz;
+                    }
+                }
+                if (v) {
+                    put_bits(st, bp, s_code[v], s_len[v]); bp += s_len[v];
+                    if (v == czr) bp += wz;
+                    cur = ps;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    flush_bits(st, abit, nbits, outw);
+}
+
+// ---------------------------------------------------------------- launch
+hipError_t launch_forward_levels(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
+                                 uint8_t *d_ws, hipStream_t stream);
+
+hipError_t launch_forward_only(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
+                               uint8_t *d_ws, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_prep_blocks, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
+    return launch_forward_levels(H, d_plan, d_pixels, d_ws, stream);
+}
+
+hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
+                         uint8_t *d_out, uint64_t out_capacity, uint64_t *d_tile_offsets,
+                         uint64_t *d_tile_sizes, int32_t *d_status, uint8_t *d_ws,
+                         hipStream_t stream)
+{
+    hipError_t e = launch_forward_only(H, d_plan, d_pixels, d_ws, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_enc_symbols, dim3(H.total_blocks), dim3(kSymNT), 0, stream, H, d_plan, d_ws);
+    hipLaunchKernelGGL(k_enc_code, dim3(H.total_blocks), dim3(256), 0, stream, H, d_ws);
+    hipLaunchKernelGGL(k_enc_block_offsets, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
+    hipLaunchKernelGGL(k_enc_tile_offsets, dim3(1), dim3(1024), 0, stream, H, d_ws, out_capacity,
+                       d_tile_offsets, d_tile_sizes, d_status);
+    hipLaunchKernelGGL(k_enc_tile_finish, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws, d_out);
+    hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, 32), dim3(256), 0, stream, H, d_ws, d_out);
+    return hipGetLastError();
+}
+
+// Debug: Huffman lengths of one frequency table, as the block coder builds them.
+__global__ void __launch_bounds__(256) k_debug_huffman(const uint32_t *freq, int limit, uint8_t *out)
+{
+    __shared__ uint32_t f[256];
+    __shared__ uint8_t len[256];
+    __shared__ HuffScratch hs;
+    __shared__ PMScratch q;
+    f[threadIdx.x] = freq[threadIdx.x];
+    __syncthreads();
+    if (limit <= 0) huff_lengths(f, len, hs);
+    else package_merge_lengths(f, limit, len, hs, q);
+    out[threadIdx.x] = len[threadIdx.x];
+}
+
+hipError_t launch_debug_huffman(const uint32_t *d_freq, int limit, uint8_t *d_len, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_debug_huffman, dim3(1), dim3(256), 0, stream, d_freq, limit, d_len);
+    return hipGetLastError();
+}
+
+}  // namespace isx

@@ -1,0 +1,68 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and its pure host entry points validate and size correctly
+(no device calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2005_08713_amd import isx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "isx.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(isx_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = isx.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(isx.EXPORTS) == names
+
+
+def test_status_strings():
+    assert isx.status_string(0) == "ok"
+    assert "corrupt" in isx.status_string(-3)
+
+
+def test_block_counts_match_oracle_geometry():
+    import oracle
+    for (w, h, c, lv) in [(1, 1, 1, 0), (256, 256, 3, 3), (257, 129, 3, 5), (4096, 4096, 3, 5),
+                          (8192, 8192, 1, 6), (1, 300, 1, 6), (511, 3, 3, 4)]:
+        d = isx.tile_desc(w, h, c, 1, 8, lv)
+        assert isx.block_count(d) == oracle.lib().oracle_count_blocks(w, h, c, lv)
+
+
+def test_host_validation_rejects_bad_descriptors():
+    L = isx.lib()
+    bad = [isx.tile_desc(0, 5, 1, 1, 8, 1), isx.tile_desc(5, 5, 9, 1, 8, 1),
+           isx.tile_desc(5, 5, 1, 1, 9, 1), isx.tile_desc(5, 5, 1, 3, 8, 1),
+           isx.tile_desc(5, 5, 1, 1, 8, 16), isx.tile_desc(5, 5, 2, 1, 8, 1, ct=1),
+           isx.tile_desc(5, 5, 1, 1, 8, 1, qstep=0)]
+    for d in bad:
+        assert L.isx_encode_workspace_bytes(ctypes.byref(d), 1) == 0
+        assert L.isx_max_encoded_bytes(ctypes.byref(d), 1) == 0
+    d = isx.tile_desc(64, 64, 3, 1, 8, 3)
+    assert L.isx_encode_workspace_bytes(ctypes.byref(d), 1) > 64 * 64 * 3 * 4
+    # a call with a null device pointer fails on the host before any launch
+    rc = L.isx_encode_tiles(ctypes.byref(d), 1, None, None, 0, None, None, None, None, 0, None)
+    assert rc == isx.E_INVALID_ARG
+
+
+def test_max_encoded_bytes_covers_oracle_output():
+    import numpy as np
+    import oracle
+    from paper_2005_08713_amd import synth
+    for (w, h, c, bits, lv, kind) in [(64, 64, 3, 8, 3, "uniform"), (33, 17, 1, 16, 6, "uniform"),
+                                      (40, 9, 3, 8, 4, "checker")]:
+        img = synth.random_image(w, h, c, bits, 3, kind)
+        blob = oracle.encode_tile(img, lv, bits=bits)
+        d = isx.tile_desc(w, h, c, img.itemsize, bits, lv)
+        assert isx.lib().isx_max_encoded_bytes(ctypes.byref(d), 1) >= len(blob)

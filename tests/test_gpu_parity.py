@@ -1,0 +1,120 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Integer codec: every comparison is exact (coefficients, code lengths,
+bitstream bytes, decoded pixels).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_08713_amd import isx, synth
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [
+    # (w, h, c, bits, levels, qstep, kind)
+    (1, 1, 1, 8, 0, 1, "uniform"), (4, 4, 1, 8, 0, 1, "uniform"), (5, 3, 1, 8, 2, 1, "uniform"),
+    (37, 23, 3, 8, 3, 1, "uniform"), (64, 64, 1, 12, 2, 1, "uniform"),
+    (130, 257, 3, 8, 5, 1, "ramp"), (33, 17, 1, 16, 6, 1, "uniform"), (50, 50, 3, 8, 3, 4, "uniform"),
+    (40, 9, 3, 8, 4, 3, "checker"), (16, 16, 1, 1, 2, 1, "sparse"), (129, 3, 1, 10, 3, 1, "max"),
+    (200, 150, 3, 8, 4, 1, "sparse"), (1, 40, 3, 8, 6, 2, "uniform"), (257, 257, 1, 8, 1, 1, "uniform"),
+    (300, 260, 3, 8, 4, 1, "const"), (140, 131, 3, 16, 3, 1, "uniform"), (2, 2, 1, 8, 1, 1, "uniform"),
+    (511, 7, 3, 8, 5, 4, "uniform"), (3, 511, 3, 8, 5, 1, "ramp"), (128, 128, 3, 8, 15, 1, "uniform"),
+]
+
+
+def _img(case, seed=0):
+    w, h, c, bits, lv, q, kind = case
+    return synth.random_image(w, h, c, bits, seed=w * 7 + h + seed, kind=kind)
+
+
+def _ct(c):
+    return 1 if c == 3 else 0
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "x".join(map(str, c)))
+def test_forward_coefficients_match_oracle(case):
+    w, h, c, bits, lv, q, kind = case
+    img = _img(case)
+    print("forward", case, flush=True)
+    got = isx.debug_forward(img, lv, bits=bits, ct=_ct(c), qstep=q)
+    ref = oracle.forward_dump(img, lv, bits=bits, ct=_ct(c), qstep=q)
+    for ch in range(c):
+        assert np.array_equal(got[ch]["LL"], ref[ch]["LL"]), (ch, "LL")
+        for l in range(1, lv + 1):
+            for nm in ("HL", "LH", "HH"):
+                assert np.array_equal(got[ch][nm][l], ref[ch][nm][l]), (ch, nm, l)
+
+
+def test_huffman_lengths_match_oracle():
+    rng = np.random.default_rng(4)
+    for trial in range(60):
+        m = int(rng.integers(1, 257))
+        f = np.zeros(256, dtype=np.uint64)
+        idx = rng.choice(256, size=m, replace=False)
+        f[idx] = rng.integers(1, [2, 10, 1000, 100000][trial % 4], size=m)
+        got = isx.debug_huffman(f, 0)
+        assert np.array_equal(got, oracle.huffman_lengths(f)), trial
+    # length-limited fallback (package-merge) on Fibonacci weights
+    f = np.zeros(256, dtype=np.uint64)
+    a, b = 1, 1
+    for s in range(30):
+        f[s * 7 % 256] = a
+        a, b = b, a + b
+    for lim in (14, 12, 10):
+        assert np.array_equal(isx.debug_huffman(f, lim), oracle.huffman_lengths(f, limit=lim))
+    for trial in range(20):
+        f = rng.integers(0, 5000, size=256).astype(np.uint64)
+        f[rng.random(256) < 0.3] = 0
+        assert np.array_equal(isx.debug_huffman(f, 14), oracle.huffman_lengths(f, limit=14))
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "x".join(map(str, c)))
+def test_encode_bitstream_matches_oracle(case):
+    w, h, c, bits, lv, q, kind = case
+    img = _img(case, 1)
+    print("encode", case, flush=True)
+    got = isx.encode_image(img, lv, bits=bits, ct=_ct(c), qstep=q)
+    ref = oracle.encode_tile(img, lv, bits=bits, ct=_ct(c), qstep=q)
+    assert len(got) == len(ref)
+    assert got == ref
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "x".join(map(str, c)))
+def test_decode_matches_oracle_at_every_level(case):
+    w, h, c, bits, lv, q, kind = case
+    img = _img(case, 2)
+    print("decode", case, flush=True)
+    blob = oracle.encode_tile(img, lv, bits=bits, ct=_ct(c), qstep=q)
+    levels = list(range(lv + 1))
+    got = isx.decode_streams([blob] * len(levels), levels=levels)
+    for z, g in zip(levels, got):
+        assert np.array_equal(g, oracle.decode_tile(blob, z)), z
+    if q == 1:
+        assert np.array_equal(got[0], img.reshape(got[0].shape))
+
+
+def test_c1_workload_seeds():
+    for seed in (101, 102, 103):
+        img = synth.he_like(256, 256, seed)
+        print("C1 seed", seed, flush=True)
+        got = isx.encode_image(img, 3)
+        assert got == oracle.encode_tile(img, 3)
+        dec = isx.decode_streams([got])[0]
+        assert np.array_equal(dec, img)
+
+
+def test_batch_of_uneven_tiles_matches_per_tile_oracle():
+    tiles = synth.tile_batch(24, seed=7, content_seed_base=7000, sides=(128, 64, 32), max_side=200)
+    imgs = [t["pixels"] for t in tiles]
+    levels = [t["levels"] for t in tiles]
+    qs = [t["qstep"] for t in tiles]
+    print("batch encode", flush=True)
+    got = isx.encode_images(imgs, levels, qs)
+    for i, t in enumerate(tiles):
+        assert got[i] == oracle.encode_tile(t["pixels"], t["levels"], qstep=t["qstep"]), i
+    zs = [i % (t["levels"] + 1) for i, t in enumerate(tiles)]
+    print("batch decode", flush=True)
+    dec = isx.decode_streams(got, levels=zs)
+    for i, t in enumerate(tiles):
+        assert np.array_equal(dec[i], oracle.decode_tile(got[i], zs[i])), i
