@@ -151,6 +151,24 @@ int32_t isx_decode_run(const void *h_plan, const void *d_plan, const void *d_enc
                        void *d_pixels_out, int32_t *d_status, void *d_workspace,
                        uint64_t workspace_bytes, void *stream);
 
+/* ---- stage-wise runs (profiling) -------------------------------------------
+ * The encode and decode runs are fixed sequences of kernel stages; these
+ * entry points enqueue stages [first, first + count) of the full sequence
+ * (isx_*_run == all stages), so a caller can bracket each stage with events
+ * on `stream`.  Stages without work for the plan enqueue nothing.  Running
+ * every stage once, in order, is equivalent to one isx_*_run call.
+ * mode: 0 = encode, 1 = decode.  isx_stage_count returns the number of
+ * stages (or ISX_E_INVALID_ARG); isx_stage_name a static name ("" if none). */
+int32_t isx_stage_count(int32_t mode);
+const char *isx_stage_name(int32_t mode, int32_t stage);
+int32_t isx_encode_run_stages(const void *h_plan, const void *d_plan, const void *d_pixels, void *d_out,
+                              uint64_t out_capacity, uint64_t *d_tile_offsets, uint64_t *d_tile_sizes,
+                              int32_t *d_status, void *d_workspace, uint64_t workspace_bytes,
+                              void *stream, int32_t first, int32_t count);
+int32_t isx_decode_run_stages(const void *h_plan, const void *d_plan, const void *d_encoded,
+                              void *d_pixels_out, int32_t *d_status, void *d_workspace,
+                              uint64_t workspace_bytes, void *stream, int32_t first, int32_t count);
+
 /* ---- diagnostics ----------------------------------------------------------- */
 
 /* Human-readable text of a status code (static storage). */

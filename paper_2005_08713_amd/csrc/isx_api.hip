@@ -406,7 +406,7 @@ int32_t isx_encode_run(const void *h_plan, const void *d_plan, const void *d_pix
     if (workspace_bytes < H.ws_bytes) return ISX_E_WORKSPACE;
     hipError_t e = launch_encode(H, (const uint8_t *)d_plan, (const uint8_t *)d_pixels, (uint8_t *)d_out,
                                  out_capacity, d_tile_offsets, d_tile_sizes, d_status, (uint8_t *)d_workspace,
-                                 (hipStream_t)stream);
+                                 (hipStream_t)stream, 0, ENC_NSTAGES - 1);
     return e == hipSuccess ? ISX_OK : ISX_E_HIP;
 }
 
@@ -419,7 +419,76 @@ int32_t isx_decode_run(const void *h_plan, const void *d_plan, const void *d_enc
     if (!d_plan || !d_encoded || !d_pixels_out || !d_status || !d_workspace) return ISX_E_INVALID_ARG;
     if (workspace_bytes < H.ws_bytes) return ISX_E_WORKSPACE;
     hipError_t e = launch_decode(H, (const uint8_t *)d_plan, (const uint8_t *)d_encoded, (uint8_t *)d_pixels_out,
-                                 d_status, (uint8_t *)d_workspace, (hipStream_t)stream);
+                                 d_status, (uint8_t *)d_workspace, (hipStream_t)stream, 0, DEC_NSTAGES - 1);
+    return e == hipSuccess ? ISX_OK : ISX_E_HIP;
+}
+
+int32_t isx_stage_count(int32_t mode)
+{
+    return mode == 0 ? (int32_t)ENC_NSTAGES : (mode == 1 ? (int32_t)DEC_NSTAGES : ISX_E_INVALID_ARG);
+}
+
+const char *isx_stage_name(int32_t mode, int32_t stage)
+{
+    static const char *fwd[16] = {"forward_l0", "forward_l1", "forward_l2", "forward_l3", "forward_l4",
+                                  "forward_l5", "forward_l6", "forward_l7", "forward_l8", "forward_l9",
+                                  "forward_l10", "forward_l11", "forward_l12", "forward_l13", "forward_l14",
+                                  "forward_l15"};
+    static const char *inv[16] = {"inverse_final", "inverse_l1", "inverse_l2", "inverse_l3", "inverse_l4",
+                                  "inverse_l5", "inverse_l6", "inverse_l7", "inverse_l8", "inverse_l9",
+                                  "inverse_l10", "inverse_l11", "inverse_l12", "inverse_l13", "inverse_l14",
+                                  "inverse_l15"};
+    if (mode == 0) {
+        if (stage == ENC_PREP) return "enc_prep";
+        if (stage >= ENC_FWD0 && stage <= ENC_FWD0 + kMaxLevels) return fwd[stage - ENC_FWD0];
+        if (stage == ENC_SYM) return "enc_symbols";
+        if (stage == ENC_CODE) return "enc_code";
+        if (stage == ENC_BOFF) return "enc_block_offsets";
+        if (stage == ENC_TOFF) return "enc_tile_offsets";
+        if (stage == ENC_FIN) return "enc_tile_finish";
+        if (stage == ENC_PACK) return "enc_pack";
+    } else if (mode == 1) {
+        if (stage == DEC_PREP) return "dec_prep";
+        if (stage == DEC_HDR) return "dec_header";
+        if (stage == DEC_SEG) return "dec_segments";
+        if (stage == DEC_REASM) return "dec_reassemble";
+        if (stage >= DEC_INV15 && stage <= DEC_FINAL) return inv[DEC_FINAL - stage];
+    }
+    return "";
+}
+
+int32_t isx_encode_run_stages(const void *h_plan, const void *d_plan, const void *d_pixels, void *d_out,
+                              uint64_t out_capacity, uint64_t *d_tile_offsets, uint64_t *d_tile_sizes,
+                              int32_t *d_status, void *d_workspace, uint64_t workspace_bytes, void *stream,
+                              int32_t first, int32_t count)
+{
+    int rc = check_plan(h_plan, MODE_ENCODE);
+    if (rc) return rc;
+    const PlanHdr &H = *(const PlanHdr *)h_plan;
+    if (!d_plan || !d_pixels || !d_out || !d_tile_offsets || !d_tile_sizes || !d_status || !d_workspace)
+        return ISX_E_INVALID_ARG;
+    if (first < 0 || count < 0 || first + count > (int32_t)ENC_NSTAGES) return ISX_E_INVALID_ARG;
+    if (workspace_bytes < H.ws_bytes) return ISX_E_WORKSPACE;
+    if (!count) return ISX_OK;
+    hipError_t e = launch_encode(H, (const uint8_t *)d_plan, (const uint8_t *)d_pixels, (uint8_t *)d_out,
+                                 out_capacity, d_tile_offsets, d_tile_sizes, d_status, (uint8_t *)d_workspace,
+                                 (hipStream_t)stream, first, first + count - 1);
+    return e == hipSuccess ? ISX_OK : ISX_E_HIP;
+}
+
+int32_t isx_decode_run_stages(const void *h_plan, const void *d_plan, const void *d_encoded, void *d_pixels_out,
+                              int32_t *d_status, void *d_workspace, uint64_t workspace_bytes, void *stream,
+                              int32_t first, int32_t count)
+{
+    int rc = check_plan(h_plan, MODE_DECODE);
+    if (rc) return rc;
+    const PlanHdr &H = *(const PlanHdr *)h_plan;
+    if (!d_plan || !d_encoded || !d_pixels_out || !d_status || !d_workspace) return ISX_E_INVALID_ARG;
+    if (first < 0 || count < 0 || first + count > (int32_t)DEC_NSTAGES) return ISX_E_INVALID_ARG;
+    if (workspace_bytes < H.ws_bytes) return ISX_E_WORKSPACE;
+    if (!count) return ISX_OK;
+    hipError_t e = launch_decode(H, (const uint8_t *)d_plan, (const uint8_t *)d_encoded, (uint8_t *)d_pixels_out,
+                                 d_status, (uint8_t *)d_workspace, (hipStream_t)stream, first, first + count - 1);
     return e == hipSuccess ? ISX_OK : ISX_E_HIP;
 }
 

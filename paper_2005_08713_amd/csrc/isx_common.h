@@ -218,17 +218,39 @@ __host__ __device__ inline int reflect_idx(int i, int n)
     return i >= n ? per - i : i;
 }
 
+// ---------------------------------------------------------------- stages
+enum EncStage {
+    ENC_PREP = 0,
+    ENC_FWD0 = 1,  // forward level l is stage ENC_FWD0 + l (l = 0..15)
+    ENC_SYM = ENC_FWD0 + kMaxLevels + 1,
+    ENC_CODE,
+    ENC_BOFF,
+    ENC_TOFF,
+    ENC_FIN,
+    ENC_PACK,
+    ENC_NSTAGES
+};
+enum DecStage {
+    DEC_PREP = 0,
+    DEC_HDR,
+    DEC_SEG,
+    DEC_REASM,
+    DEC_INV15,                     // inverse of level 15 .. level 2 (intermediate outputs)
+    DEC_FINAL = DEC_INV15 + kMaxLevels,  // inverse of level z+1 fused with the output stage
+    DEC_NSTAGES
+};
+
 // ---------------------------------------------------------------- launchers
 // (defined in the .hip files; all asynchronous on `stream`)
 hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
                          uint8_t *d_out, uint64_t out_capacity, uint64_t *d_tile_offsets,
                          uint64_t *d_tile_sizes, int32_t *d_status, uint8_t *d_ws,
-                         hipStream_t stream);
+                         hipStream_t stream, int first, int last);
 hipError_t launch_forward_only(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
                                uint8_t *d_ws, hipStream_t stream);
 hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_encoded,
                          uint8_t *d_pixels_out, int32_t *d_status, uint8_t *d_ws,
-                         hipStream_t stream);
+                         hipStream_t stream, int first, int last);
 hipError_t launch_debug_huffman(const uint32_t *d_freq, int limit, uint8_t *d_len,
                                 hipStream_t stream);
 

@@ -125,11 +125,36 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
 }
 
 // ------------------------------------------------------------------ header
+// Bits of the block header staged in LDS, read through a 64-bit window.
+struct LdsBits {
+    const uint32_t *w;  // big-endian words
+    uint32_t nwords;
+    uint64_t pos;       // next bit
+    uint64_t win;       // bits [wpos, wpos + 64)
+    uint64_t wpos;
+    __device__ inline uint32_t word(uint64_t i) const { return i < nwords ? w[i] : 0u; }
+    __device__ inline void seek(uint64_t p)
+    {
+        pos = p;
+        wpos = p & ~31ull;
+        win = ((uint64_t)word(wpos >> 5) << 32) | word((wpos >> 5) + 1);
+    }
+    __device__ inline uint32_t get(uint32_t n)  // n <= 32
+    {
+        if (!n) return 0;
+        while (pos - wpos > 32) { wpos += 32; win = (win << 32) | word((wpos >> 5) + 1); }
+        uint32_t off = (uint32_t)(pos - wpos);
+        uint64_t v = (win << off) >> (64 - n);
+        pos += n;
+        return (uint32_t)v;
+    }
+};
+
 __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__restrict__ enc,
                                                    uint8_t *__restrict__ ws,
                                                    int32_t *__restrict__ status)
 {
-    __shared__ uint8_t hb[512];
+    __shared__ uint32_t hw[132];
     __shared__ uint32_t s_info[8];
     __shared__ uint32_t s_acode[256];
     __shared__ uint8_t s_len[256], s_sym[256];
@@ -144,28 +169,26 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
     }
     const uint8_t *src = enc + B.byte_off;
     const uint32_t blen = B.byte_len;
-    for (uint32_t i = lane; i < 512; i += 64) hb[i] = (uint8_t)rd_byte(src, blen, i);
+    // stage the first 512 bytes (the largest header is ~400 bytes)
+    for (uint32_t i = lane; i < 128; i += 64) {
+        uint32_t x = 0;
+        for (int k = 0; k < 4; k++) x = (x << 8) | rd_byte(src, blen, 4 * i + k);
+        hw[i] = x;
+    }
+    if (lane < 4) hw[128 + lane] = 0;
     __syncthreads();
     const uint32_t p = B.p, n = (uint32_t)B.wb * B.hb / 8;
     if (lane == 0) {
-        uint64_t pos = 0;
-        const uint64_t lim = (uint64_t)blen * 8;
+        const uint64_t lim = (uint64_t)(blen < 512 ? blen : 512) * 8;
+        LdsBits r;
+        r.w = hw; r.nwords = 130;
+        r.seek(0);
         int32_t err = 0;
-        auto get = [&](uint32_t nb) -> uint32_t {
-            uint32_t v = 0;
-            for (uint32_t i = 0; i < nb; i++) {
-                uint32_t bit = 0;
-                if (pos < lim && pos < 4096) bit = (hb[pos >> 3] >> (7 - (pos & 7))) & 1u;
-                else err = D_TRUNC;
-                v = (v << 1) | bit;
-                pos++;
-            }
-            return v;
-        };
-        uint32_t d = get(5);
+        uint32_t d = r.get(5);
         uint32_t masks[3] = {0, 0, 0};
-        for (uint32_t t = 0; t < p; t++) masks[t] = get(d);
-        if (!err && (d < 1 || d > B.dmax)) err = D_CORRUPT;
+        if (d >= 1 && d <= B.dmax)
+            for (uint32_t t = 0; t < p; t++) masks[t] = r.get(d);
+        else err = D_CORRUPT;
         uint32_t nseg = 0;
         if (!err) {
             for (int b = (int)d - 1; b >= 0; b--) {
@@ -180,56 +203,55 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         }
         uint32_t czr = 0, wz = 0, m = 0, single = 0;
         if (!err && nseg) {
-            czr = get(8);
-            wz = get(4);
+            czr = r.get(8);
+            wz = r.get(4);
             uint32_t beta = bitlen32(p * n - 1), wzhi = beta > 2 ? beta : 2;
             if (wz < 2 || wz > wzhi) err = D_CORRUPT;
-            // recursive tree, pre-order; explicit stack of pending right children
-            uint32_t stk_code[33], stk_len[33];
-            int sp = 0;
-            uint32_t code = 0, len = 0, nodes = 0;
+            // pre-order tree: a node is 0 (internal) or 1 + 8-bit symbol (leaf).
+            // Walk with the left-aligned code A and depth of the current node;
+            // after a leaf the next node is at A + 2^(32-depth), depth 32 - ctz.
+            uint64_t A = 0;
+            uint32_t depth = 0, nodes = 0;
             uint32_t seen[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             while (!err) {
-                if (++nodes > 511) { err = D_CORRUPT; break; }
-                uint32_t bit = get(1);
-                if (err) break;
-                if (!bit) {
-                    if (len >= 32) { err = D_CORRUPT; break; }
-                    stk_code[sp] = (code << 1) | 1u;
-                    stk_len[sp] = len + 1;
-                    sp++;
-                    code <<= 1;
-                    len++;
-                } else {
-                    uint32_t s = get(8);
-                    if (err) break;
-                    if ((seen[s >> 5] >> (s & 31)) & 1u) { err = D_CORRUPT; break; }
-                    seen[s >> 5] |= 1u << (s & 31);
-                    s_acode[m] = len ? (code << (32 - len)) : 0u;
-                    s_len[m] = (uint8_t)len;
-                    s_sym[m] = (uint8_t)s;
-                    m++;
-                    if (sp == 0) break;
-                    sp--;
-                    code = stk_code[sp];
-                    len = stk_len[sp];
+                if (++nodes > 511 || r.pos + 1 > lim) { err = D_CORRUPT; break; }
+                uint32_t peek = r.get(1);
+                if (!peek) {
+                    if (depth >= 32) { err = D_CORRUPT; break; }
+                    depth++;
+                    continue;
                 }
+                if (r.pos + 8 > lim) { err = D_CORRUPT; break; }
+                uint32_t sym = r.get(8);
+                if ((seen[sym >> 5] >> (sym & 31)) & 1u) { err = D_CORRUPT; break; }
+                seen[sym >> 5] |= 1u << (sym & 31);
+                s_acode[m] = (uint32_t)A;
+                s_len[m] = (uint8_t)depth;
+                s_sym[m] = (uint8_t)sym;
+                m++;
+                if (depth == 0) break;  // a lone leaf is the whole tree
+                A += 1ull << (32 - depth);
+                if (A >= (1ull << 32)) break;  // the rightmost leaf closes the tree
+                depth = 32 - (uint32_t)__builtin_ctzll(A);
             }
             single = (m == 1);
             const uint32_t tb = bitlen32(p * n) - 1 + 5;
             uint64_t acc = 0;
             for (uint32_t s = 0; s < nseg && !err; s++) {
-                P.seg_bits[s] = get(tb);
+                if (r.pos + tb > lim) { err = D_TRUNC; break; }
+                P.seg_bits[s] = r.get(tb);
                 acc += P.seg_bits[s];
             }
             if (!err) {
-                uint64_t start = (uint64_t)B.byte_off * 8 + pos;
-                if (pos + acc > lim) err = D_TRUNC;
+                uint64_t start = (uint64_t)B.byte_off * 8 + r.pos;
+                if (r.pos + acc > (uint64_t)blen * 8) err = D_TRUNC;
                 for (uint32_t s = 0; s < nseg; s++) {
                     P.seg_bitpos[s] = start;
                     start += P.seg_bits[s];
                 }
             }
+        } else if (!err && r.pos > (uint64_t)blen * 8) {
+            err = D_TRUNC;
         }
         P.d = d; P.nseg = err ? 0 : nseg; P.czr = czr; P.wz = wz; P.m = m; P.p = p; P.n = n;
         for (uint32_t t = 0; t < 3; t++) P.masks[t] = masks[t];
@@ -242,137 +264,289 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
     __syncthreads();
     const uint32_t nseg = s_info[0], m = s_info[1];
     if (!nseg) return;
-    // prefix table: entry = sym | len << 8, or kLutLong for codes longer than K
     for (uint32_t j = lane; j < m; j += 64) {
         LV->acode[j] = s_acode[j];
         LV->len[j] = s_len[j];
         LV->sym[j] = s_sym[j];
-        uint32_t L = s_len[j];
-        uint32_t a = s_acode[j] >> (32 - kLutK);
-        if (L <= (uint32_t)kLutK) {
-            uint32_t cnt = 1u << (kLutK - L);
-            uint16_t e = (uint16_t)(s_sym[j] | (L << 8));
-            for (uint32_t k = 0; k < cnt; k++) lut[a + k] = e;
-        } else {
-            lut[a] = kLutLong;
-        }
     }
     if (lane == 0) { LV->m = m; LV->single = s_info[2]; }
+    // prefix table: entry e belongs to the last leaf whose left-aligned code
+    // is <= e << (32 - K); sym | len << 8, or kLutLong for codes longer than K
+    const uint32_t per = (1u << kLutK) / 64;
+    uint32_t e0 = lane * per;
+    uint32_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (s_acode[mid] <= (e0 << (32 - kLutK))) lo = mid; else hi = mid;
+    }
+    uint32_t j = lo;
+    for (uint32_t e = e0; e < e0 + per; e++) {
+        uint32_t key = e << (32 - kLutK);
+        while (j + 1 < m && s_acode[j + 1] <= key) j++;
+        uint32_t L = s_len[j];
+        lut[e] = (L <= (uint32_t)kLutK) ? (uint16_t)(s_sym[j] | (L << 8)) : kLutLong;
+    }
 }
 
 // ------------------------------------------------------------------ segments
-// Bounded MSB-first bit reader over one block.
-struct BitRd {
-    const uint8_t *base;  // stream start (d_encoded)
-    uint64_t lo, hi;      // allowed byte range [lo, hi)
-    uint64_t bytepos;     // next byte to load
-    uint64_t buf;         // MSB aligned
-    uint32_t nb;          // valid bits in buf
-    __device__ inline void init(const uint8_t *b, uint64_t lo_, uint64_t hi_, uint64_t bitpos)
+// Window over the stream (MSB-first), loads bounded to [lo, hi) bytes.
+struct BitWin {
+    const uint8_t *base;
+    uint64_t lo, hi;
+    uint64_t wpos;  // bit position of win's MSB (multiple of 32)
+    uint64_t win;
+    uint32_t nxt;
+    __device__ inline uint32_t load(uint64_t wi) const
     {
-        base = b; lo = lo_; hi = hi_;
-        bytepos = bitpos >> 3;
-        buf = 0; nb = 0;
-        refill();
-        uint32_t skip = (uint32_t)(bitpos & 7);
-        buf <<= skip;
-        nb -= skip;
+        uint64_t b = wi * 4;
+        if (b >= lo && b + 4 <= hi) return __builtin_bswap32(*(const uint32_t *)(base + b));
+        uint32_t x = 0;
+        for (int k = 0; k < 4; k++) x = (x << 8) | ((b + k >= lo && b + k < hi) ? base[b + k] : 0u);
+        return x;
     }
-    __device__ inline void refill()
+    __device__ inline void seek(uint64_t pos)
     {
-        while (nb <= 56) {
-            uint64_t v = (bytepos >= lo && bytepos < hi) ? base[bytepos] : 0;
-            buf |= v << (56 - nb);
-            nb += 8;
-            bytepos++;
+        wpos = pos & ~31ull;
+        uint64_t wi = wpos >> 5;
+        win = ((uint64_t)load(wi) << 32) | load(wi + 1);
+        nxt = load(wi + 2);
+    }
+    __device__ inline uint32_t peek(uint64_t pos)
+    {
+        while (pos - wpos >= 32) {
+            win = (win << 32) | nxt;
+            wpos += 32;
+            nxt = load((wpos >> 5) + 2);
         }
+        return (uint32_t)((win << (pos - wpos)) >> 32);
     }
-    __device__ inline uint32_t peek32() { return (uint32_t)(buf >> 32); }
-    __device__ inline void skip(uint32_t k) { buf <<= k; nb -= k; if (nb <= 56) refill(); }
 };
 
-__global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
-                                                     uint8_t *__restrict__ ws,
-                                                     int32_t *__restrict__ status)
+// Run-length bookkeeping of a token range as an affine map on (pos, R):
+// pos = output position, R = value of the pending run of C_zr digits.
+constexpr uint32_t kSat = 1u << 30;
+__device__ inline uint32_t smul(uint32_t a, uint32_t b) { uint64_t r = (uint64_t)a * b; return r > kSat ? kSat : (uint32_t)r; }
+__device__ inline uint32_t sadd(uint32_t a, uint32_t b) { uint32_t r = a + b; return r > kSat ? kSat : r; }
+struct RunXf {
+    uint32_t lit;  // the range holds a literal symbol
+    uint32_t P0;   // B^(digits before the first literal)
+    uint32_t V0;   // value of those digits
+    uint32_t mid;  // output symbols from the first literal up to the trailing digits
+    uint32_t V1;   // value of the trailing digits (pending run)
+};
+__device__ inline RunXf xf_combine(const RunXf &a, const RunXf &b)
+{
+    RunXf r;
+    if (!a.lit) {
+        r.lit = b.lit; r.P0 = smul(a.P0, b.P0); r.V0 = sadd(smul(a.V0, b.P0), b.V0);
+        r.mid = b.mid; r.V1 = b.V1;
+    } else if (!b.lit) {
+        r.lit = 1; r.P0 = a.P0; r.V0 = a.V0; r.mid = a.mid; r.V1 = sadd(smul(a.V1, b.P0), b.V0);
+    } else {
+        r.lit = 1; r.P0 = a.P0; r.V0 = a.V0;
+        r.mid = sadd(sadd(a.mid, sadd(smul(a.V1, b.P0), b.V0)), b.mid);
+        r.V1 = b.V1;
+    }
+    return r;
+}
+
+struct SegCtx {
+    const uint16_t *lut;
+    const uint32_t *acode;
+    const uint8_t *llen, *lsym;
+    uint32_t m, czr, wz, single;
+};
+
+// One token at bit `pos`: returns the symbol, advances pos; *cnt = counter
+// (valid when the symbol is C_zr).
+__device__ inline uint32_t next_token(const SegCtx &C, BitWin &R, uint64_t &pos, uint32_t *cnt)
+{
+    uint32_t v, L;
+    if (C.single) { v = C.lsym[0]; L = 0; }
+    else {
+        uint32_t pk = R.peek(pos);
+        uint16_t e = C.lut[pk >> (32 - kLutK)];
+        if (!(e & kLutLong)) { v = e & 0xffu; L = (e >> 8) & 0x3fu; }
+        else {
+            uint32_t lo = 0, hi = C.m;
+            while (hi - lo > 1) { uint32_t mid = (lo + hi) >> 1; if (C.acode[mid] <= pk) lo = mid; else hi = mid; }
+            v = C.lsym[lo]; L = C.llen[lo];
+        }
+    }
+    pos += L;
+    *cnt = 0;
+    if (v == C.czr) {
+        *cnt = R.peek(pos) >> (32 - C.wz);
+        pos += C.wz;
+    }
+    return v;
+}
+
+constexpr int kSyncBits = 128;  // token starts remembered per chunk (re-sync window)
+
+// Segments of one block: one wave per segment, the segment's bits split into
+// 64 chunks.  Phase 1: every lane decodes its chunk from the chunk start
+// (speculatively, for lanes > 0) and remembers its token starts in the first
+// kSyncBits bits.  Phase 2: a lane whose start differs from its left
+// neighbour's exit re-decodes from that exit until it reaches a remembered
+// token start (then its old exit stands) or its chunk end; repeated until no
+// lane changes (Huffman codes resynchronise within a few tokens).  Phase 3:
+// per-chunk run maps, a wave scan gives each lane its output position and
+// pending run.  Phase 4: decode again and write the non-zero symbols (the
+// plane was zeroed first, so runs write nothing).
+__global__ void __launch_bounds__(256) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
+                                                      uint8_t *__restrict__ ws,
+                                                      int32_t *__restrict__ status)
 {
     __shared__ uint16_t lut[1 << kLutK];
     __shared__ uint32_t acode[256];
     __shared__ uint8_t llen[256], lsym[256];
-    const uint32_t blk = blockIdx.x, lane = threadIdx.x;
+    __shared__ uint32_t vis[4][64][kSyncBits / 32];
+    const uint32_t blk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
     const uint32_t nseg = P.nseg;
     if (!nseg || status[B.tile] != D_OK) return;
     const uint16_t *glut = (const uint16_t *)(ws + H.ws_lut + (uint64_t)blk * kLutBytes);
     const DecLeaves *LV = (const DecLeaves *)((const uint8_t *)glut + (1u << kLutK) * 2);
-    for (uint32_t i = lane; i < (1u << kLutK); i += 64) lut[i] = glut[i];
     const uint32_t m = LV->m;
-    for (uint32_t j = lane; j < m; j += 64) { acode[j] = LV->acode[j]; llen[j] = LV->len[j]; lsym[j] = LV->sym[j]; }
-    // zero the symbol planes of the present segments
+    for (uint32_t i = tid; i < (1u << kLutK) / 2; i += blockDim.x)
+        ((uint32_t *)lut)[i] = ((const uint32_t *)glut)[i];
+    for (uint32_t j = tid; j < m; j += blockDim.x) { acode[j] = LV->acode[j]; llen[j] = LV->len[j]; lsym[j] = LV->sym[j]; }
     const uint32_t pn = P.p * P.n;
+    // zero the kept planes (runs and literal zeros are then not written)
     for (uint32_t s = 0; s < nseg; s++) {
-        uint32_t *dst = (uint32_t *)(ws + B.sym_off + (uint64_t)P.seg_plane[s] * pn);
-        uint32_t nw = (P.seg_M[s] + 3) / 4;
+        uint8_t *dst = ws + B.sym_off + (uint64_t)P.seg_plane[s] * pn;
+        uint32_t M = P.seg_M[s];
         if ((((uintptr_t)dst) & 3u) == 0) {
-            for (uint32_t i = lane; i < nw; i += 64) dst[i] = 0;
+            for (uint32_t i = tid; i < M / 4; i += blockDim.x) ((uint32_t *)dst)[i] = 0;
+            for (uint32_t i = (M / 4) * 4 + tid; i < M; i += blockDim.x) dst[i] = 0;
         } else {
-            uint8_t *db = (uint8_t *)dst;
-            for (uint32_t i = lane; i < P.seg_M[s]; i += 64) db[i] = 0;
+            for (uint32_t i = tid; i < M; i += blockDim.x) dst[i] = 0;
         }
     }
     __syncthreads();
-    if (lane >= nseg) return;
-    const uint32_t s = lane;
-    const uint32_t M = P.seg_M[s];
-    uint8_t *out = ws + B.sym_off + (uint64_t)P.seg_plane[s] * pn;
-    const uint64_t start = P.seg_bitpos[s], end = start + P.seg_bits[s];
-    BitRd r;
-    r.init(enc, B.byte_off, B.byte_off + B.byte_len, start);
-    uint64_t pos = start;
-    const uint32_t czr = P.czr, wz = P.wz, Bb = (1u << wz) - 1u;
-    const bool single = (m == 1);
-    uint32_t k = 0, run = 0;
-    bool in_run = false;
+    SegCtx C;
+    C.lut = lut; C.acode = acode; C.llen = llen; C.lsym = lsym; C.m = m;
+    C.czr = P.czr; C.wz = P.wz; C.single = (m == 1);
+    const uint32_t Bb = (1u << P.wz) - 1u;
+    BitWin R;
+    R.base = enc; R.lo = B.byte_off; R.hi = B.byte_off + B.byte_len;
     int32_t err = 0;
-    while (k + run < M) {
-        uint32_t v, L;
-        if (single) { v = lsym[0]; L = 0; }
-        else {
-            uint32_t pk = r.peek32();
-            uint16_t e = lut[pk >> (32 - kLutK)];
-            if (!(e & kLutLong)) { v = e & 0xffu; L = (e >> 8) & 0x3fu; }
-            else {
-                uint32_t lo = 0, hi = m;  // last leaf with acode <= pk
-                while (hi - lo > 1) { uint32_t mid = (lo + hi) >> 1; if (acode[mid] <= pk) lo = mid; else hi = mid; }
-                v = lsym[lo]; L = llen[lo];
+    for (uint32_t s = wave; s < nseg; s += 4) {
+        const uint32_t M = P.seg_M[s];
+        uint8_t *out = ws + B.sym_off + (uint64_t)P.seg_plane[s] * pn;
+        const uint64_t S0 = P.seg_bitpos[s], N = P.seg_bits[s], SE = S0 + N;
+        if (C.single && lsym[0] != C.czr) {
+            // zero-length codewords: the segment is M copies of the leaf
+            if (N != 0) err = D_CORRUPT;
+            else if (lsym[0]) for (uint32_t i = lane; i < M; i += 64) out[i] = lsym[0];
+            continue;
+        }
+        uint64_t chunk = (N + 63) / 64;
+        chunk = (chunk + 31) & ~31ull;
+        if (chunk < 32) chunk = 32;
+        const uint64_t cs = S0 + lane * chunk;
+        const bool active = cs < SE;
+        const uint64_t ce = active ? (cs + chunk < SE ? cs + chunk : SE) : cs;
+        // phase 1
+        uint32_t *mv = vis[wave][lane];
+        for (int k = 0; k < kSyncBits / 32; k++) mv[k] = 0;
+        uint64_t start = cs, exit1 = cs;
+        if (active) {
+            uint64_t pos = cs;
+            R.seek(pos);
+            while (pos < ce) {
+                uint64_t rel = pos - cs;
+                if (rel < kSyncBits) mv[rel >> 5] |= 1u << (rel & 31);
+                uint32_t c;
+                next_token(C, R, pos, &c);
+            }
+            exit1 = pos;
+        }
+        uint64_t exitc = exit1;
+        // phase 2
+        for (int it = 0; it < 64; it++) {
+            uint64_t left = __shfl_up(exitc, 1, 64);
+            uint64_t want = (lane == 0) ? S0 : left;
+            bool chg = active && want != start;
+            if (!__any(chg)) break;
+            if (chg) {
+                start = want;
+                uint64_t pos = want;
+                bool synced = false;
+                if (pos < ce) R.seek(pos);
+                while (pos < ce) {
+                    if (pos >= cs) {
+                        uint64_t rel = pos - cs;
+                        if (rel < kSyncBits && ((mv[rel >> 5] >> (rel & 31)) & 1u)) { synced = true; break; }
+                    }
+                    uint32_t c;
+                    next_token(C, R, pos, &c);
+                }
+                exitc = synced ? exit1 : pos;
             }
         }
-        if (pos + L > end) { err = D_CORRUPT; break; }
-        r.skip(L); pos += L;
-        if (v == czr) {
-            if (pos + wz > end) { err = D_CORRUPT; break; }
-            uint32_t c = r.peek32() >> (32 - wz);
-            r.skip(wz); pos += wz;
-            if (c) {
-                run = run * Bb + c;
-                in_run = true;
-                if (k + run > M) { err = D_CORRUPT; break; }
-                continue;
+        // phase 3: run maps and their scan
+        RunXf f = {0, 1, 0, 0, 0};
+        if (active && start < ce) {
+            uint64_t pos = start;
+            R.seek(pos);
+            while (pos < ce) {
+                uint32_t c;
+                uint32_t v = next_token(C, R, pos, &c);
+                if (v == C.czr && c) {
+                    if (!f.lit) { f.V0 = sadd(smul(f.V0, Bb), c); f.P0 = smul(f.P0, Bb); }
+                    else f.V1 = sadd(smul(f.V1, Bb), c);
+                } else {
+                    if (!f.lit) { f.lit = 1; f.mid = 1; }
+                    else { f.mid = sadd(f.mid, sadd(f.V1, 1)); f.V1 = 0; }
+                }
             }
         }
-        if (in_run) {
-            if (run < 2) { err = D_CORRUPT; break; }
-            k += run; run = 0; in_run = false;
+        RunXf x = f;
+        for (int o = 1; o < 64; o <<= 1) {
+            RunXf y;
+            y.lit = __shfl_up(x.lit, o, 64); y.P0 = __shfl_up(x.P0, o, 64); y.V0 = __shfl_up(x.V0, o, 64);
+            y.mid = __shfl_up(x.mid, o, 64); y.V1 = __shfl_up(x.V1, o, 64);
+            if ((int)lane >= o) x = xf_combine(y, x);
         }
-        if (k >= M) { err = D_CORRUPT; break; }
-        if (v) out[k] = (uint8_t)v;
-        k++;
+        RunXf ex;
+        ex.lit = __shfl_up(x.lit, 1, 64); ex.P0 = __shfl_up(x.P0, 1, 64); ex.V0 = __shfl_up(x.V0, 1, 64);
+        ex.mid = __shfl_up(x.mid, 1, 64); ex.V1 = __shfl_up(x.V1, 1, 64);
+        if (lane == 0) { ex.lit = 0; ex.P0 = 1; ex.V0 = 0; ex.mid = 0; ex.V1 = 0; }
+        uint32_t opos, orun;
+        if (ex.lit) { opos = sadd(ex.V0, ex.mid); orun = ex.V1; }
+        else { opos = 0; orun = ex.V0; }
+        // phase 4: write
+        const bool last = active && (lane == 63 || cs + chunk >= SE);
+        if (active) {
+            uint64_t pos = start;
+            uint32_t op = opos, run = orun;
+            if (pos < ce) R.seek(pos);
+            while (pos < ce) {
+                uint32_t c;
+                uint32_t v = next_token(C, R, pos, &c);
+                if (v == C.czr && c) { run = sadd(smul(run, Bb), c); continue; }
+                if (run) {
+                    if (run < 2) { err = D_CORRUPT; break; }
+                    op = sadd(op, run);
+                    run = 0;
+                }
+                if (op >= M) { err = D_CORRUPT; break; }
+                if (v) out[op] = (uint8_t)v;
+                op++;
+            }
+            if (last && !err) {
+                if (run) {
+                    if (run < 2) err = D_CORRUPT;
+                    op = sadd(op, run);
+                }
+                if (pos != SE || op != M) err = D_CORRUPT;
+            }
+        }
+        if (N == 0 && lane == 0 && M != 0) err = D_CORRUPT;
     }
-    if (!err && in_run) {
-        if (run < 2) err = D_CORRUPT;
-        else k += run;
-    }
-    if (!err && (k != M || pos != end)) err = D_CORRUPT;
     if (err) atomicMin(&status[B.tile], err);
 }
 
@@ -428,20 +602,35 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
 }
 
 // ------------------------------------------------------------------ launch
-hipError_t launch_inverse_levels(const PlanHdr &H, const uint8_t *d_plan, uint8_t *d_ws,
-                                 uint8_t *d_pixels_out, const int32_t *d_status, hipStream_t stream);
+hipError_t launch_inverse_level(const PlanHdr &H, const uint8_t *d_plan, uint8_t *d_ws,
+                                uint8_t *d_pixels_out, const int32_t *d_status, int level,
+                                hipStream_t stream);
 
+// Stages (in order): prep, block headers, segments, reassembly, inverse
+// levels 15..1 (intermediate outputs), final output stage.
 hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_encoded,
                          uint8_t *d_pixels_out, int32_t *d_status, uint8_t *d_ws,
-                         hipStream_t stream)
+                         hipStream_t stream, int first, int last)
 {
-    hipLaunchKernelGGL(k_dec_prep, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_encoded, d_ws, d_status);
-    if (H.total_blocks) {
-        hipLaunchKernelGGL(k_dec_header, dim3(H.total_blocks), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
-        hipLaunchKernelGGL(k_dec_segments, dim3(H.total_blocks), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
-        hipLaunchKernelGGL(k_dec_reasm, dim3(H.total_blocks), dim3(1024), 0, stream, H, d_plan, d_ws, d_status);
+    for (int st = first; st <= last; st++) {
+        if (st == DEC_PREP) {
+            hipLaunchKernelGGL(k_dec_prep, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_encoded, d_ws, d_status);
+        } else if (st == DEC_HDR) {
+            if (H.total_blocks)
+                hipLaunchKernelGGL(k_dec_header, dim3(H.total_blocks), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
+        } else if (st == DEC_SEG) {
+            if (H.total_blocks)
+                hipLaunchKernelGGL(k_dec_segments, dim3(H.total_blocks), dim3(256), 0, stream, H, d_encoded, d_ws, d_status);
+        } else if (st == DEC_REASM) {
+            if (H.total_blocks)
+                hipLaunchKernelGGL(k_dec_reasm, dim3(H.total_blocks), dim3(1024), 0, stream, H, d_plan, d_ws, d_status);
+        } else if (st >= DEC_INV15 && st <= DEC_FINAL) {
+            int level = DEC_FINAL - st;  // 15..1, then 0 = final stage
+            hipError_t e = launch_inverse_level(H, d_plan, d_ws, d_pixels_out, d_status, level, stream);
+            if (e != hipSuccess) return e;
+        }
     }
-    return launch_inverse_levels(H, d_plan, d_ws, d_pixels_out, d_status, stream);
+    return hipGetLastError();
 }
 
 }  // namespace isx

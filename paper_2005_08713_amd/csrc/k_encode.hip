@@ -617,8 +617,10 @@ __global__ void __launch_bounds__(1024) k_enc_tile_offsets(PlanHdr H, uint8_t *_
     }
 }
 
-// Tile header (little endian) + block size table; zero the payload words so
-// the packers can OR the words shared by neighbouring blocks/segments.
+// Tile header (little endian) + block size table, and zero the words that the
+// packers OR into: the first and last word of every block header and every
+// segment (neighbouring regions share those words; all other words are
+// written whole by exactly one packer).
 __global__ void __launch_bounds__(256) k_enc_tile_finish(PlanHdr H, const uint8_t *__restrict__ plan,
                                                          const uint8_t *__restrict__ ws,
                                                          uint8_t *__restrict__ out)
@@ -628,9 +630,8 @@ __global__ void __launch_bounds__(256) k_enc_tile_finish(PlanHdr H, const uint8_
     if (O.status != ISX_STATUS_OK) return;
     const BlkPlan *plans = (const BlkPlan *)(ws + H.ws_blkplan);
     uint32_t *w = (uint32_t *)(out + O.offset);
-    uint32_t nw = (uint32_t)((O.size + 3) / 4);
     uint32_t hdrw = 6 + T.nblocks_stream;
-    for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
+    for (uint32_t i = threadIdx.x; i < hdrw; i += blockDim.x) {
         uint32_t x = 0;
         if (i == 0) x = 0x31585349u;  // "ISX1"
         else if (i == 1) x = 1u | ((uint32_t)T.ct << 8) | ((uint32_t)T.channels << 16) | ((uint32_t)T.bits << 24);
@@ -638,8 +639,26 @@ __global__ void __launch_bounds__(256) k_enc_tile_finish(PlanHdr H, const uint8_
         else if (i == 3) x = T.width;
         else if (i == 4) x = T.height;
         else if (i == 5) x = T.nblocks_stream;
-        else if (i < hdrw) x = plans[T.block_base + (i - 6)].bytes;
+        else x = plans[T.block_base + (i - 6)].bytes;
         w[i] = x;
+    }
+    for (uint32_t b = threadIdx.x; b < T.nblocks; b += blockDim.x) {
+        const BlkPlan &P = plans[T.block_base + b];
+        uint64_t a = P.byte_off * 8;
+        uint64_t e = a + P.hdr_bits;
+        w[a >> 5] = 0;
+        w[(e - 1) >> 5] = 0;
+        for (uint32_t s = 0; s < P.nseg; s++) {
+            uint32_t nb = P.seg_bits[s];
+            if (nb) {
+                w[e >> 5] = 0;
+                w[(e + nb - 1) >> 5] = 0;
+            }
+            e += nb;
+        }
+        // the byte padding after the last region
+        uint64_t end = (P.byte_off + P.bytes) * 8;
+        if (end > e) w[(end - 1) >> 5] = 0;
     }
 }
 
@@ -807,30 +826,46 @@ __global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__re
 }
 
 // ---------------------------------------------------------------- launch
-hipError_t launch_forward_levels(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
-                                 uint8_t *d_ws, hipStream_t stream);
+hipError_t launch_forward_level(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
+                                uint8_t *d_ws, int level, hipStream_t stream);
 
 hipError_t launch_forward_only(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
                                uint8_t *d_ws, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_prep_blocks, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
-    return launch_forward_levels(H, d_plan, d_pixels, d_ws, stream);
+    return launch_encode(H, d_plan, d_pixels, nullptr, 0, nullptr, nullptr, nullptr, d_ws, stream,
+                         ENC_PREP, ENC_FWD0 + kMaxLevels);
 }
 
+// Stages (in order): prep, forward levels 0..15, symbols, code, block
+// offsets, tile offsets, tile finish, pack.  Stages without work launch nothing.
 hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
                          uint8_t *d_out, uint64_t out_capacity, uint64_t *d_tile_offsets,
                          uint64_t *d_tile_sizes, int32_t *d_status, uint8_t *d_ws,
-                         hipStream_t stream)
+                         hipStream_t stream, int first, int last)
 {
-    hipError_t e = launch_forward_only(H, d_plan, d_pixels, d_ws, stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_enc_symbols, dim3(H.total_blocks), dim3(kSymNT), 0, stream, H, d_plan, d_ws);
-    hipLaunchKernelGGL(k_enc_code, dim3(H.total_blocks), dim3(256), 0, stream, H, d_ws);
-    hipLaunchKernelGGL(k_enc_block_offsets, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
-    hipLaunchKernelGGL(k_enc_tile_offsets, dim3(1), dim3(1024), 0, stream, H, d_ws, out_capacity,
-                       d_tile_offsets, d_tile_sizes, d_status);
-    hipLaunchKernelGGL(k_enc_tile_finish, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws, d_out);
-    hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, 32), dim3(256), 0, stream, H, d_ws, d_out);
+    for (int st = first; st <= last; st++) {
+        if (st == ENC_PREP) {
+            hipLaunchKernelGGL(k_prep_blocks, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
+        } else if (st >= ENC_FWD0 && st <= ENC_FWD0 + kMaxLevels) {
+            hipError_t e = launch_forward_level(H, d_plan, d_pixels, d_ws, st - ENC_FWD0, stream);
+            if (e != hipSuccess) return e;
+        } else if (st == ENC_SYM) {
+            if (H.total_blocks)
+                hipLaunchKernelGGL(k_enc_symbols, dim3(H.total_blocks), dim3(kSymNT), 0, stream, H, d_plan, d_ws);
+        } else if (st == ENC_CODE) {
+            if (H.total_blocks) hipLaunchKernelGGL(k_enc_code, dim3(H.total_blocks), dim3(256), 0, stream, H, d_ws);
+        } else if (st == ENC_BOFF) {
+            hipLaunchKernelGGL(k_enc_block_offsets, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
+        } else if (st == ENC_TOFF) {
+            hipLaunchKernelGGL(k_enc_tile_offsets, dim3(1), dim3(1024), 0, stream, H, d_ws, out_capacity,
+                               d_tile_offsets, d_tile_sizes, d_status);
+        } else if (st == ENC_FIN) {
+            hipLaunchKernelGGL(k_enc_tile_finish, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws, d_out);
+        } else if (st == ENC_PACK) {
+            if (H.total_blocks)
+                hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, 32), dim3(256), 0, stream, H, d_ws, d_out);
+        }
+    }
     return hipGetLastError();
 }
 

@@ -392,27 +392,27 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
 }
 
 // ------------------------------------------------------------------ launch
-hipError_t launch_forward_levels(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
-                                 uint8_t *d_ws, hipStream_t stream)
+hipError_t launch_forward_level(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
+                                uint8_t *d_ws, int level, hipStream_t stream)
 {
-    if (H.lvl_wgs[0])
+    if (level > (int)H.max_levels || !H.lvl_wgs[level]) return hipSuccess;
+    if (level == 0)
         hipLaunchKernelGGL(k_fwd_level0, dim3(H.lvl_wgs[0]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws);
-    for (uint32_t l = 1; l <= H.max_levels; l++) {
-        if (!H.lvl_wgs[l]) continue;
-        hipLaunchKernelGGL(k_fwd_level, dim3(H.lvl_wgs[l]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws, (int)l);
-    }
+    else
+        hipLaunchKernelGGL(k_fwd_level, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws, level);
     return hipGetLastError();
 }
 
-hipError_t launch_inverse_levels(const PlanHdr &H, const uint8_t *d_plan, uint8_t *d_ws,
-                                 uint8_t *d_pixels_out, const int32_t *d_status, hipStream_t stream)
+hipError_t launch_inverse_level(const PlanHdr &H, const uint8_t *d_plan, uint8_t *d_ws,
+                                uint8_t *d_pixels_out, const int32_t *d_status, int level,
+                                hipStream_t stream)
 {
-    for (int l = (int)H.max_levels; l >= 1; l--) {
-        if (!H.lvl_wgs[l]) continue;
-        hipLaunchKernelGGL(k_inv_level, dim3(H.lvl_wgs[l]), dim3(256), 0, stream, H, d_plan, d_ws, l);
+    if (level == 0) {
+        if (H.fin_wgs)
+            hipLaunchKernelGGL(k_inv_final, dim3(H.fin_wgs), dim3(256), 0, stream, H, d_plan, d_ws, d_pixels_out, d_status);
+    } else if (level <= (int)H.max_levels && H.lvl_wgs[level]) {
+        hipLaunchKernelGGL(k_inv_level, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_ws, level);
     }
-    if (H.fin_wgs)
-        hipLaunchKernelGGL(k_inv_final, dim3(H.fin_wgs), dim3(256), 0, stream, H, d_plan, d_ws, d_pixels_out, d_status);
     return hipGetLastError();
 }
 

@@ -70,6 +70,10 @@ def lib():
             "isx_status_string": (ctypes.c_char_p, [i32]),
             "isx_debug_forward": (i32, [P, P, P, P, u64, P]),
             "isx_debug_huffman": (i32, [P, i32, P, P]),
+            "isx_stage_count": (i32, [i32]),
+            "isx_stage_name": (ctypes.c_char_p, [i32, i32]),
+            "isx_encode_run_stages": (i32, [P, P, P, P, u64, P, P, P, P, u64, P, i32, i32]),
+            "isx_decode_run_stages": (i32, [P, P, P, P, P, P, u64, P, i32, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -83,7 +87,8 @@ EXPORTS = ["isx_max_encoded_bytes", "isx_encode_workspace_bytes", "isx_decode_wo
            "isx_tile_block_count", "isx_encode_tiles", "isx_decode_tiles", "isx_encode_plan_bytes",
            "isx_encode_plan_build", "isx_encode_run", "isx_decode_plan_bytes",
            "isx_decode_plan_build", "isx_decode_run", "isx_status_string", "isx_debug_forward",
-           "isx_debug_huffman"]
+           "isx_debug_huffman", "isx_stage_count", "isx_stage_name", "isx_encode_run_stages",
+           "isx_decode_run_stages"]
 
 
 def status_string(code: int) -> str:
@@ -164,6 +169,13 @@ class Encoder:
                                   _stream_ptr(stream))
         _check(rc, "isx_encode_run")
 
+    def run_stages(self, d_pixels, first, count, stream=None):
+        rc = lib().isx_encode_run_stages(self.h_plan, _ptr(self.d_plan), _ptr(d_pixels),
+                                         _ptr(self.out), self.capacity, _ptr(self.offsets),
+                                         _ptr(self.sizes), _ptr(self.status), _ptr(self.ws),
+                                         self.ws_bytes, _stream_ptr(stream), first, count)
+        _check(rc, "isx_encode_run_stages")
+
     def streams(self):
         """Host copies of the encoded tiles (after the stream has completed)."""
         st = self.status.cpu().numpy()
@@ -205,6 +217,17 @@ class Decoder:
                                   _ptr(self.status), _ptr(self.ws), self.ws_bytes,
                                   _stream_ptr(stream))
         _check(rc, "isx_decode_run")
+
+    def run_stages(self, d_encoded, first, count, stream=None):
+        rc = lib().isx_decode_run_stages(self.h_plan, _ptr(self.d_plan), _ptr(d_encoded),
+                                         _ptr(self.out), _ptr(self.status), _ptr(self.ws),
+                                         self.ws_bytes, _stream_ptr(stream), first, count)
+        _check(rc, "isx_decode_run_stages")
+
+
+def stage_names(mode):
+    L = lib()
+    return [L.isx_stage_name(mode, i).decode() for i in range(L.isx_stage_count(mode))]
 
 
 def out_size(w, h, level):
