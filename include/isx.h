@@ -151,6 +151,26 @@ int32_t isx_decode_run(const void *h_plan, const void *d_plan, const void *d_enc
                        void *d_pixels_out, int32_t *d_status, void *d_workspace,
                        uint64_t workspace_bytes, void *stream);
 
+/* Launch parameters of a plan.  They change speed only: the encoded bytes and
+ * decoded pixels are identical for every setting.
+ *  transform_tile: quads per side of a lifting tile staged in LDS, 16 or 32
+ *                  (0 = 32); 32 stages 68x68-sample windows, 16 stages 36x36.
+ *  blocks_per_cu:  0 = one workgroup per coefficient block for the per-block
+ *                  kernels; k > 0 = a persistent grid of k workgroups per
+ *                  compute unit that loops over the blocks (1..64). */
+typedef struct {
+    int32_t transform_tile;
+    int32_t blocks_per_cu;
+    int32_t reserved[6];
+} isx_tuning;
+
+/* As isx_*_plan_build, with explicit launch parameters (NULL = defaults).
+ * Returns ISX_E_INVALID_ARG for values outside the ranges above. */
+int32_t isx_encode_plan_build_tuned(const isx_tile_desc *h_descs, int32_t n_tiles,
+                                    const isx_tuning *tuning, void *h_plan, uint64_t plan_bytes);
+int32_t isx_decode_plan_build_tuned(const isx_decode_job *h_jobs, int32_t n_jobs,
+                                    const isx_tuning *tuning, void *h_plan, uint64_t plan_bytes);
+
 /* ---- stage-wise runs (profiling) -------------------------------------------
  * The encode and decode runs are fixed sequences of kernel stages; these
  * entry points enqueue stages [first, first + count) of the full sequence

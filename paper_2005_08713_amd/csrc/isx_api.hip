@@ -135,7 +135,16 @@ struct Plan {
     PlanHdr H;
 };
 
-int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs, int32_t n, Plan &P)
+int device_cus()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) return 256;
+    return v;
+}
+
+int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs, int32_t n, Plan &P,
+               const isx_tuning *tune = nullptr)
 {
     if (n < 1) return ISX_E_INVALID_ARG;
     std::vector<TileBuild> tb((size_t)n);
@@ -144,6 +153,16 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     H.magic = kPlanMagic;
     H.mode = (uint32_t)mode;
     H.n_tiles = (uint32_t)n;
+    H.tq = 32;
+    H.blocks_per_cu = 0;
+    if (tune) {
+        if (tune->transform_tile != 0 && tune->transform_tile != 16 && tune->transform_tile != 32)
+            return ISX_E_INVALID_ARG;
+        if (tune->blocks_per_cu < 0 || tune->blocks_per_cu > 64) return ISX_E_INVALID_ARG;
+        if (tune->transform_tile) H.tq = (uint32_t)tune->transform_tile;
+        H.blocks_per_cu = (uint32_t)tune->blocks_per_cu;
+    }
+    H.num_cus = (uint32_t)device_cus();
     uint64_t total_blocks = 0, total_slots = 0;
     for (int32_t i = 0; i < n; i++) {
         const isx_tile_desc &d = mode == MODE_ENCODE ? descs[i] : jobs[i].tile;
@@ -157,6 +176,8 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
             z = j.target_level;
         } else if (d.row_stride_bytes < (uint64_t)d.width * d.channels * d.bytes_per_sample) {
             return ISX_E_INVALID_ARG;
+        } else if (d.bytes_per_sample == 2 && ((d.pixel_offset | d.row_stride_bytes) & 1u)) {
+            return ISX_E_INVALID_ARG;  // 16-bit samples are read as aligned uint16
         }
         tile_geometry(d, z, tb[i]);
         TileGeo &T = tb[i].g;
@@ -180,6 +201,11 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     }
     H.total_blocks = (uint32_t)total_blocks;
     H.total_slots = (uint32_t)total_slots;
+    H.blk_grid = H.total_blocks;
+    if (H.blocks_per_cu) {
+        uint64_t g = (uint64_t)H.num_cus * H.blocks_per_cu;
+        if (g < H.blk_grid) H.blk_grid = (uint32_t)g;
+    }
     // workspace: global regions, then per-tile arenas
     uint64_t o = kPlanRegion;
     H.ws_blockdesc = o; o = al(o + total_blocks * sizeof(BlockDesc));
@@ -224,7 +250,8 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
             memset(&it, 0, sizeof(it));
             it.tile = (uint32_t)i;
             it.wg_start = wg;
-            it.ntx = div_up(w, 64); it.nty = div_up(h, 64);
+            uint32_t span = lvl == 0 ? 64u : 2u * H.tq;  // level-0 copies use 64x64 tiles
+            it.ntx = div_up(w, span); it.nty = div_up(h, span);
             it.nch = T.channels;
             wg += it.ntx * it.nty * it.nch;
             items.push_back(it);
@@ -247,7 +274,7 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
             memset(&it, 0, sizeof(it));
             it.tile = (uint32_t)i;
             it.wg_start = wg;
-            it.ntx = div_up(w, 64); it.nty = div_up(h, 64);
+            it.ntx = div_up(w, 2 * H.tq); it.nty = div_up(h, 2 * H.tq);
             it.nch = T.ct ? 1 : div_up(T.channels, 3);
             wg += it.ntx * it.nty * it.nch;
             items.push_back(it);
@@ -362,6 +389,30 @@ int32_t isx_encode_plan_build(const isx_tile_desc *h_descs, int32_t n_tiles, voi
     Plan P;
     if (!h_descs || !h_plan) return ISX_E_INVALID_ARG;
     int rc = build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P);
+    if (rc) return rc;
+    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
+    memcpy(h_plan, P.bytes.data(), P.bytes.size());
+    return ISX_OK;
+}
+
+int32_t isx_encode_plan_build_tuned(const isx_tile_desc *h_descs, int32_t n_tiles, const isx_tuning *tuning,
+                                    void *h_plan, uint64_t plan_bytes)
+{
+    Plan P;
+    if (!h_descs || !h_plan) return ISX_E_INVALID_ARG;
+    int rc = build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P, tuning);
+    if (rc) return rc;
+    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
+    memcpy(h_plan, P.bytes.data(), P.bytes.size());
+    return ISX_OK;
+}
+
+int32_t isx_decode_plan_build_tuned(const isx_decode_job *h_jobs, int32_t n_jobs, const isx_tuning *tuning,
+                                    void *h_plan, uint64_t plan_bytes)
+{
+    Plan P;
+    if (!h_jobs || !h_plan) return ISX_E_INVALID_ARG;
+    int rc = build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P, tuning);
     if (rc) return rc;
     if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
     memcpy(h_plan, P.bytes.data(), P.bytes.size());

@@ -14,9 +14,6 @@ constexpr int kBlock = 128;        // Sec. 4: wavelet data partitioned in 128x12
 constexpr int kMaxLevels = 15;
 constexpr int kMaxChannels = 8;
 constexpr int kMaxPlanes = 31;     // d is a 5-bit field; magnitudes < 2^30
-constexpr int kTQ = 32;            // transform tile: 32x32 quads (64x64 samples)
-constexpr int kWin = 2 * kTQ + 4;  // LDS window (samples) per axis incl. halo
-constexpr int kWinPitch = kWin + 1;
 constexpr int kNumWz = 14;         // counter widths 2..15 tracked per segment
 constexpr uint32_t kPlanMagic = 0x4e4c5058u;  // "XPLN"
 
@@ -79,6 +76,9 @@ struct PlanHdr {
     uint32_t lvl_count[kMaxLevels + 2];  // per level: number of WorkItems
     uint32_t lvl_wgs[kMaxLevels + 2];    // per level: total workgroups
     uint32_t fin_first, fin_count, fin_wgs, pad1;  // decode: final-output work list
+    uint32_t tq;        // transform tile: quads per side (16 or 32)
+    uint32_t blk_grid;  // workgroups of the per-block kernels (== total_blocks unless persistent)
+    uint32_t num_cus, blocks_per_cu;
 };
 
 struct BlockDesc {

@@ -158,14 +158,16 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
     __shared__ uint32_t s_info[8];
     __shared__ uint32_t s_acode[256];
     __shared__ uint8_t s_len[256], s_sym[256];
-    const uint32_t blk = blockIdx.x, lane = threadIdx.x;
+    const uint32_t lane = threadIdx.x;
+    for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
+    __syncthreads();
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
     uint16_t *lut = (uint16_t *)(ws + H.ws_lut + (uint64_t)blk * kLutBytes);
     DecLeaves *LV = (DecLeaves *)((uint8_t *)lut + (1u << kLutK) * 2);
     if (status[B.tile] != D_OK || B.byte_len == 0) {
         if (lane == 0) { P.nseg = 0; P.err = 1; P.d = 1; }
-        return;
+        continue;
     }
     const uint8_t *src = enc + B.byte_off;
     const uint32_t blen = B.byte_len;
@@ -263,7 +265,7 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
     }
     __syncthreads();
     const uint32_t nseg = s_info[0], m = s_info[1];
-    if (!nseg) return;
+    if (!nseg) continue;
     for (uint32_t j = lane; j < m; j += 64) {
         LV->acode[j] = s_acode[j];
         LV->len[j] = s_len[j];
@@ -285,6 +287,7 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         while (j + 1 < m && s_acode[j + 1] <= key) j++;
         uint32_t L = s_len[j];
         lut[e] = (L <= (uint32_t)kLutK) ? (uint16_t)(s_sym[j] | (L << 8)) : kLutLong;
+    }
     }
 }
 
@@ -402,11 +405,13 @@ __global__ void __launch_bounds__(256) k_dec_segments(PlanHdr H, const uint8_t *
     __shared__ uint32_t acode[256];
     __shared__ uint8_t llen[256], lsym[256];
     __shared__ uint32_t vis[4][64][kSyncBits / 32];
-    const uint32_t blk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
     const uint32_t nseg = P.nseg;
-    if (!nseg || status[B.tile] != D_OK) return;
+    if (!nseg || status[B.tile] != D_OK) continue;
+    __syncthreads();
     const uint16_t *glut = (const uint16_t *)(ws + H.ws_lut + (uint64_t)blk * kLutBytes);
     const DecLeaves *LV = (const DecLeaves *)((const uint8_t *)glut + (1u << kLutK) * 2);
     const uint32_t m = LV->m;
@@ -548,6 +553,7 @@ __global__ void __launch_bounds__(256) k_dec_segments(PlanHdr H, const uint8_t *
         if (N == 0 && lane == 0 && M != 0) err = D_CORRUPT;
     }
     if (err) atomicMin(&status[B.tile], err);
+    }
 }
 
 // ------------------------------------------------------------------ reassembly
@@ -555,10 +561,11 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
                                                     uint8_t *__restrict__ ws,
                                                     const int32_t *__restrict__ status)
 {
-    const uint32_t blk = blockIdx.x, tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
-    if (status[B.tile] != D_OK) return;
+    if (status[B.tile] != D_OK) continue;
     const TileGeo &T = ((const TileGeo *)(plan + H.tiles_off))[B.tile];
     const uint32_t p = B.p, wb = B.wb, hb = B.hb, n = wb * hb / 8, cpt = n / 2, wq = wb / 4;
     const uint32_t d = P.d, nseg = P.nseg;
@@ -599,6 +606,7 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
             }
         }
     }
+    }
 }
 
 // ------------------------------------------------------------------ launch
@@ -617,13 +625,13 @@ hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             hipLaunchKernelGGL(k_dec_prep, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_encoded, d_ws, d_status);
         } else if (st == DEC_HDR) {
             if (H.total_blocks)
-                hipLaunchKernelGGL(k_dec_header, dim3(H.total_blocks), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
+                hipLaunchKernelGGL(k_dec_header, dim3(H.blk_grid), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
         } else if (st == DEC_SEG) {
             if (H.total_blocks)
-                hipLaunchKernelGGL(k_dec_segments, dim3(H.total_blocks), dim3(256), 0, stream, H, d_encoded, d_ws, d_status);
+                hipLaunchKernelGGL(k_dec_segments, dim3(H.blk_grid), dim3(256), 0, stream, H, d_encoded, d_ws, d_status);
         } else if (st == DEC_REASM) {
             if (H.total_blocks)
-                hipLaunchKernelGGL(k_dec_reasm, dim3(H.total_blocks), dim3(1024), 0, stream, H, d_plan, d_ws, d_status);
+                hipLaunchKernelGGL(k_dec_reasm, dim3(H.blk_grid), dim3(1024), 0, stream, H, d_plan, d_ws, d_status);
         } else if (st >= DEC_INV15 && st <= DEC_FINAL) {
             int level = DEC_FINAL - st;  // 15..1, then 0 = final stage
             hipError_t e = launch_inverse_level(H, d_plan, d_ws, d_pixels_out, d_status, level, stream);

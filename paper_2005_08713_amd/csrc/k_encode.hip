@@ -122,7 +122,8 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
     __shared__ uint32_t hist[256];
     __shared__ int32_t wsh[kSymNT / 64];
     __shared__ uint32_t s_zir, s_dig[kNumWz], s_F[16], s_nruns, s_zero;
-    const uint32_t blk = blockIdx.x;
+    for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
+    __syncthreads();
     const BlockDesc B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkAcc A = ((const BlkAcc *)(ws + H.ws_acc))[blk];
     BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
@@ -275,6 +276,7 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
         P.n = n;
         P.err = err;
         for (uint32_t t = 0; t < 3; t++) P.masks[t] = (t < p) ? (~pres[t] & ((1u << d) - 1u)) : 0u;
+    }
     }
 }
 
@@ -466,7 +468,9 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
 {
     __shared__ CodeShared C;
     __shared__ PMScratch Q;
-    const uint32_t blk = blockIdx.x, v = threadIdx.x;
+    for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
+    __syncthreads();
+    const uint32_t v = threadIdx.x;
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
     const BlkStat &S = ((const BlkStat *)(ws + H.ws_blkstat))[blk];
@@ -480,7 +484,7 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
             P.hdr_bits = 5 + p * d;
             P.bytes = (P.hdr_bits + 7) / 8;
         }
-        return;
+        continue;
     }
     // per-segment histograms into LDS, block histogram
     uint32_t h = 0;
@@ -556,6 +560,7 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
         P.hdr_bits = 5 + p * d + 8 + 4 + (10 * m - 1) + nseg * tb;
         P.bytes = (P.hdr_bits + sum + 7) / 8;
         if (over) P.err = 2;
+    }
     }
 }
 
@@ -698,13 +703,17 @@ __global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__re
     __shared__ uint64_t sh[4];
     __shared__ int32_t shi[4];
     const uint8_t *ws = ws_c;
-    const uint32_t blk = blockIdx.x, y = blockIdx.y, tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nitems = (uint64_t)H.total_blocks * 33;
+    for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const uint32_t blk = (uint32_t)(item / 33), y = (uint32_t)(item % 33);
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
     const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[B.tile];
-    if (O.status != ISX_STATUS_OK) return;
+    if (O.status != ISX_STATUS_OK) continue;
     const uint32_t nseg = P.nseg;
-    if (y > nseg) return;
+    if (y > nseg) continue;
+    __syncthreads();
     uint32_t *outw = (uint32_t *)out;
     const uint64_t bit0 = (O.offset + P.byte_off) * 8;
     if (y == 0) {
@@ -744,7 +753,7 @@ __global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__re
         }
         __syncthreads();
         flush_bits(st, bit0, nbits, outw);
-        return;
+        continue;
     }
     // segment y-1: tokens of the plane's symbols
     const uint32_t s = y - 1;
@@ -823,6 +832,7 @@ __global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__re
     }
     __syncthreads();
     flush_bits(st, abit, nbits, outw);
+    }
 }
 
 // ---------------------------------------------------------------- launch
@@ -851,9 +861,9 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             if (e != hipSuccess) return e;
         } else if (st == ENC_SYM) {
             if (H.total_blocks)
-                hipLaunchKernelGGL(k_enc_symbols, dim3(H.total_blocks), dim3(kSymNT), 0, stream, H, d_plan, d_ws);
+                hipLaunchKernelGGL(k_enc_symbols, dim3(H.blk_grid), dim3(kSymNT), 0, stream, H, d_plan, d_ws);
         } else if (st == ENC_CODE) {
-            if (H.total_blocks) hipLaunchKernelGGL(k_enc_code, dim3(H.total_blocks), dim3(256), 0, stream, H, d_ws);
+            if (H.total_blocks) hipLaunchKernelGGL(k_enc_code, dim3(H.blk_grid), dim3(256), 0, stream, H, d_ws);
         } else if (st == ENC_BOFF) {
             hipLaunchKernelGGL(k_enc_block_offsets, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
         } else if (st == ENC_TOFF) {
@@ -863,7 +873,8 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             hipLaunchKernelGGL(k_enc_tile_finish, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws, d_out);
         } else if (st == ENC_PACK) {
             if (H.total_blocks)
-                hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, 32), dim3(256), 0, stream, H, d_ws, d_out);
+                hipLaunchKernelGGL(k_enc_pack, dim3(H.blocks_per_cu ? H.blk_grid : H.total_blocks * 33), dim3(256), 0,
+                                   stream, H, d_ws, d_out);
         }
     }
     return hipGetLastError();

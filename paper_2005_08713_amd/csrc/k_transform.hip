@@ -64,62 +64,84 @@ __device__ inline uint32_t wave_or(uint32_t v)
     return v;
 }
 
-// One forward 2-D level over a 32x32-quad tile, one channel per workgroup.
+// One forward 2-D level over a TQ x TQ-quad tile, one channel per workgroup
+// (the channels of a tile are adjacent workgroups, so the pixels they share
+// are served from L2).  LDS window: (2TQ + 4)^2 samples.
+template <int TQ>
 __global__ void __launch_bounds__(256) k_fwd_level(PlanHdr H, const uint8_t *__restrict__ plan,
                                                    const uint8_t *__restrict__ pix,
                                                    uint8_t *__restrict__ ws, int level)
 {
-    __shared__ int32_t win[kWin * kWinPitch];
+    constexpr int WN = 2 * TQ + 4, WP = WN + 1, T2 = 2 * TQ;
+    __shared__ int32_t win[WN * WP];
+    __shared__ int32_t rmap[WN], cmap[WN];
     const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
     const WorkItem *items = (const WorkItem *)(plan + H.work_off);
     const WorkItem &W = find_item(items, H.lvl_first[level], H.lvl_count[level], blockIdx.x);
     const TileGeo &T = tiles[W.tile];
     uint32_t r = blockIdx.x - W.wg_start;
-    uint32_t nsp = W.ntx * W.nty;
-    int c = (int)(r / nsp);
-    uint32_t sp = r % nsp;
-    int qx0 = (int)(sp % W.ntx) * kTQ, qy0 = (int)(sp / W.ntx) * kTQ;
+    int c = (int)(r % W.nch);
+    uint32_t sp = r / W.nch;
+    int qx0 = (int)(sp % W.ntx) * TQ, qy0 = (int)(sp / W.ntx) * TQ;
     const LevelGeo &G = T.lv[level];
     int w = (int)G.w, h = (int)G.h;
     int32_t *wsi = (int32_t *)ws;
-    // source LL_{level-1}
-    const int32_t *src = nullptr;
-    uint32_t spitch = 0;
-    if (level > 1) {
+    if (threadIdx.x < WN) rmap[threadIdx.x] = reflect_idx(2 * qy0 - 2 + (int)threadIdx.x, h);
+    else if (threadIdx.x < 2 * WN) cmap[threadIdx.x - WN] = reflect_idx(2 * qx0 - 2 + (int)threadIdx.x - WN, w);
+    __syncthreads();
+    // stage window rows [2qy0-2, 2qy0+2TQ+1], same columns (reflected)
+    if (level == 1) {
+        const uint32_t C = T.channels, bps = T.bps;
+        for (int i = threadIdx.x; i < WN * WN; i += blockDim.x) {
+            int lr = i / WN, lc = i % WN;
+            const uint8_t *px = pix + T.pix_offset + (uint64_t)rmap[lr] * T.pix_stride + (uint32_t)cmap[lc] * C * bps;
+            int32_t v;
+            if (bps == 1) {
+                if (T.ct) {
+                    int32_t R = px[0], Gc = px[1], Bc = px[2];
+                    v = c == 0 ? ((R + 2 * Gc + Bc) >> 2) : (c == 1 ? Bc - Gc : R - Gc);
+                } else v = px[c];
+            } else {
+                const uint16_t *p16 = (const uint16_t *)px;
+                if (T.ct) {
+                    int32_t R = p16[0], Gc = p16[1], Bc = p16[2];
+                    v = c == 0 ? ((R + 2 * Gc + Bc) >> 2) : (c == 1 ? Bc - Gc : R - Gc);
+                } else v = p16[c];
+            }
+            win[lr * WP + lc] = v;
+        }
+    } else {
         int k = level - 1, which = (k & 1) ? 0 : 1;
-        src = wsi + T.tmp_off[which] + (uint64_t)c * T.tmp_chan[which];
-        spitch = T.tmp_pitch[which];
-    }
-    // stage window rows [2qy0-2, 2qy0+65], cols [2qx0-2, 2qx0+65] (reflected)
-    for (int i = threadIdx.x; i < kWin * kWin; i += blockDim.x) {
-        int lr = i / kWin, lc = i % kWin;
-        int gy = reflect_idx(2 * qy0 - 2 + lr, h), gx = reflect_idx(2 * qx0 - 2 + lc, w);
-        int32_t v = (level == 1) ? load_colour(pix, T, gx, gy, c) : src[(uint64_t)gy * spitch + gx];
-        win[lr * kWinPitch + lc] = v;
+        const int32_t *src = wsi + T.tmp_off[which] + (uint64_t)c * T.tmp_chan[which];
+        const uint32_t spitch = T.tmp_pitch[which];
+        for (int i = threadIdx.x; i < WN * WN; i += blockDim.x) {
+            int lr = i / WN, lc = i % WN;
+            win[lr * WP + lc] = src[(uint64_t)rmap[lr] * spitch + cmap[lc]];
+        }
     }
     __syncthreads();
-    // rows: predict at odd columns 1..65, update at even columns 2..64 (all 68 rows)
-    for (int i = threadIdx.x; i < kWin * 33; i += blockDim.x) {
-        int lr = i / 33, lc = 1 + 2 * (i % 33);
-        int32_t *row = win + lr * kWinPitch;
+    // rows: predict at odd columns 1..2TQ+1, update at even columns 2..2TQ (all rows)
+    for (int i = threadIdx.x; i < WN * (TQ + 1); i += blockDim.x) {
+        int lr = i / (TQ + 1), lc = 1 + 2 * (i % (TQ + 1));
+        int32_t *row = win + lr * WP;
         row[lc] -= floor_half(row[lc - 1] + row[lc + 1]);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kWin * 32; i += blockDim.x) {
-        int lr = i / 32, lc = 2 + 2 * (i % 32);
-        int32_t *row = win + lr * kWinPitch;
+    for (int i = threadIdx.x; i < WN * TQ; i += blockDim.x) {
+        int lr = i / TQ, lc = 2 + 2 * (i % TQ);
+        int32_t *row = win + lr * WP;
         row[lc] += floor_quarter_r(row[lc - 1] + row[lc + 1]);
     }
     __syncthreads();
-    // columns 2..65: predict at odd rows 1..65, update at even rows 2..64
-    for (int i = threadIdx.x; i < 33 * 64; i += blockDim.x) {
-        int lc = 2 + (i % 64), lr = 1 + 2 * (i / 64);
-        win[lr * kWinPitch + lc] -= floor_half(win[(lr - 1) * kWinPitch + lc] + win[(lr + 1) * kWinPitch + lc]);
+    // columns 2..2TQ+1: predict at odd rows 1..2TQ+1, update at even rows 2..2TQ
+    for (int i = threadIdx.x; i < (TQ + 1) * T2; i += blockDim.x) {
+        int lc = 2 + (i % T2), lr = 1 + 2 * (i / T2);
+        win[lr * WP + lc] -= floor_half(win[(lr - 1) * WP + lc] + win[(lr + 1) * WP + lc]);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 32 * 64; i += blockDim.x) {
-        int lc = 2 + (i % 64), lr = 2 + 2 * (i / 64);
-        win[lr * kWinPitch + lc] += floor_quarter_r(win[(lr - 1) * kWinPitch + lc] + win[(lr + 1) * kWinPitch + lc]);
+    for (int i = threadIdx.x; i < TQ * T2; i += blockDim.x) {
+        int lc = 2 + (i % T2), lr = 2 + 2 * (i / T2);
+        win[lr * WP + lc] += floor_quarter_r(win[(lr - 1) * WP + lc] + win[(lr + 1) * WP + lc]);
     }
     __syncthreads();
     // outputs
@@ -140,13 +162,13 @@ __global__ void __launch_bounds__(256) k_fwd_level(PlanHdr H, const uint8_t *__r
     int32_t *hhb = wsi + G.off[2] + (uint64_t)c * T.chan_elems;
     uint32_t step = T.qstep;
     uint32_t orm[3] = {0, 0, 0}, neg = 0, llor = 0;
-    for (int i = threadIdx.x; i < kTQ * kTQ; i += blockDim.x) {
-        int ii = i % kTQ, jj = i / kTQ;
+    for (int i = threadIdx.x; i < TQ * TQ; i += blockDim.x) {
+        int ii = i % TQ, jj = i / TQ;
         int qx = qx0 + ii, qy = qy0 + jj;
-        int32_t vLL = win[(2 + 2 * jj) * kWinPitch + 2 + 2 * ii];
-        int32_t vHL = win[(2 + 2 * jj) * kWinPitch + 3 + 2 * ii];
-        int32_t vLH = win[(3 + 2 * jj) * kWinPitch + 2 + 2 * ii];
-        int32_t vHH = win[(3 + 2 * jj) * kWinPitch + 3 + 2 * ii];
+        int32_t vLL = win[(2 + 2 * jj) * WP + 2 + 2 * ii];
+        int32_t vHL = win[(2 + 2 * jj) * WP + 3 + 2 * ii];
+        int32_t vLH = win[(3 + 2 * jj) * WP + 2 + 2 * ii];
+        int32_t vHH = win[(3 + 2 * jj) * WP + 3 + 2 * ii];
         if (step > 1) {
             vHL = vHL < 0 ? -(int32_t)((uint32_t)(-vHL) / step) : (int32_t)((uint32_t)vHL / step);
             vLH = vLH < 0 ? -(int32_t)((uint32_t)(-vLH) / step) : (int32_t)((uint32_t)vLH / step);
@@ -169,7 +191,7 @@ __global__ void __launch_bounds__(256) k_fwd_level(PlanHdr H, const uint8_t *__r
             orm[2] |= (uint32_t)(vHH < 0 ? -vHH : vHH); neg |= (vHH < 0) ? 4u : 0u;
         }
     }
-    // per-block accumulation (the whole 32x32-quad tile lies in one 128 cell)
+    // per-block accumulation (the whole quad tile lies in one 128 cell)
     orm[0] = wave_or(orm[0]); orm[1] = wave_or(orm[1]); orm[2] = wave_or(orm[2]);
     neg = wave_or(neg); llor = wave_or(llor);
     if ((threadIdx.x & 63) == 0) {
@@ -231,11 +253,13 @@ __global__ void __launch_bounds__(256) k_fwd_level0(PlanHdr H, const uint8_t *__
 // ------------------------------------------------------------------ inverse
 // Stage the interleaved window of level `level` for channel c: position
 // (gy, gx) of LL_{level-1}, reflected, maps to LL/HL/LH/HH by parity.
-__device__ inline void stage_inverse(const TileGeo &T, int level, int c, int qx0, int qy0,
-                                     const int32_t *wsi, int32_t *win)
+// rmap/cmap hold the reflected coordinates of the window rows/columns.
+template <int TQ>
+__device__ inline void stage_inverse(const TileGeo &T, int level, int c, const int32_t *rmap,
+                                     const int32_t *cmap, const int32_t *wsi, int32_t *win)
 {
+    constexpr int WN = 2 * TQ + 4, WP = WN + 1;
     const LevelGeo &G = T.lv[level];
-    int w = (int)G.w, h = (int)G.h;
     const int32_t *ll;
     uint32_t llp;
     if (level == T.levels) { ll = wsi + T.ll_off + (uint64_t)c * T.chan_elems; llp = T.ll_pitch; }
@@ -247,145 +271,185 @@ __device__ inline void stage_inverse(const TileGeo &T, int level, int c, int qx0
     const int32_t *lh = wsi + G.off[0] + (uint64_t)c * T.chan_elems;
     const int32_t *hl = wsi + G.off[1] + (uint64_t)c * T.chan_elems;
     const int32_t *hh = wsi + G.off[2] + (uint64_t)c * T.chan_elems;
-    for (int i = threadIdx.x; i < kWin * kWin; i += blockDim.x) {
-        int lr = i / kWin, lc = i % kWin;
-        int gy = reflect_idx(2 * qy0 - 2 + lr, h), gx = reflect_idx(2 * qx0 - 2 + lc, w);
-        int32_t v;
-        if (h == 1) gy = 0;
-        if (w == 1) gx = 0;
+    for (int i = threadIdx.x; i < WN * WN; i += blockDim.x) {
+        int lr = i / WN, lc = i % WN;
+        int gy = rmap[lr], gx = cmap[lc];
         int py = gy & 1, px = gx & 1;
-        if (!py && !px) v = ll[(uint64_t)(gy >> 1) * llp + (gx >> 1)];
-        else if (!py && px) v = hl[(uint64_t)(gy >> 1) * G.pitch[1] + (gx >> 1)];
-        else if (py && !px) v = lh[(uint64_t)(gy >> 1) * G.pitch[0] + (gx >> 1)];
-        else v = hh[(uint64_t)(gy >> 1) * G.pitch[2] + (gx >> 1)];
-        win[lr * kWinPitch + lc] = v;
+        uint64_t ry = (uint64_t)(gy >> 1);
+        int32_t v;
+        if (!py) v = !px ? ll[ry * llp + (gx >> 1)] : hl[ry * G.pitch[1] + (gx >> 1)];
+        else v = !px ? lh[ry * G.pitch[0] + (gx >> 1)] : hh[ry * G.pitch[2] + (gx >> 1)];
+        win[lr * WP + lc] = v;
     }
 }
 
 // Undo the lifting in the window: columns (unless the level has one row),
-// then rows (unless it has one column).  Valid output: [2, 66) x [2, 66).
+// then rows (unless it has one column).  Valid output: [2, 2TQ+2)^2.
+template <int TQ>
 __device__ inline void inverse_window(int32_t *win, bool do_cols, bool do_rows)
 {
+    constexpr int WN = 2 * TQ + 4, WP = WN + 1, T2 = 2 * TQ, NC = WN - 1;
     if (do_cols) {
-        // undo update at even rows 2..66, columns 1..67
-        for (int i = threadIdx.x; i < 33 * 67; i += blockDim.x) {
-            int lc = 1 + (i % 67), lr = 2 + 2 * (i / 67);
-            win[lr * kWinPitch + lc] -= floor_quarter_r(win[(lr - 1) * kWinPitch + lc] + win[(lr + 1) * kWinPitch + lc]);
+        // undo update at even rows 2..2TQ+2, columns 1..2TQ+3
+        for (int i = threadIdx.x; i < (TQ + 1) * NC; i += blockDim.x) {
+            int lc = 1 + (i % NC), lr = 2 + 2 * (i / NC);
+            win[lr * WP + lc] -= floor_quarter_r(win[(lr - 1) * WP + lc] + win[(lr + 1) * WP + lc]);
         }
         __syncthreads();
-        // undo predict at odd rows 3..65
-        for (int i = threadIdx.x; i < 32 * 67; i += blockDim.x) {
-            int lc = 1 + (i % 67), lr = 3 + 2 * (i / 67);
-            win[lr * kWinPitch + lc] += floor_half(win[(lr - 1) * kWinPitch + lc] + win[(lr + 1) * kWinPitch + lc]);
+        // undo predict at odd rows 3..2TQ+1
+        for (int i = threadIdx.x; i < TQ * NC; i += blockDim.x) {
+            int lc = 1 + (i % NC), lr = 3 + 2 * (i / NC);
+            win[lr * WP + lc] += floor_half(win[(lr - 1) * WP + lc] + win[(lr + 1) * WP + lc]);
         }
         __syncthreads();
     }
     if (do_rows) {
-        for (int i = threadIdx.x; i < 64 * 33; i += blockDim.x) {
-            int lr = 2 + (i / 33), lc = 2 + 2 * (i % 33);
-            int32_t *row = win + lr * kWinPitch;
+        for (int i = threadIdx.x; i < T2 * (TQ + 1); i += blockDim.x) {
+            int lr = 2 + (i / (TQ + 1)), lc = 2 + 2 * (i % (TQ + 1));
+            int32_t *row = win + lr * WP;
             row[lc] -= floor_quarter_r(row[lc - 1] + row[lc + 1]);
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < 64 * 32; i += blockDim.x) {
-            int lr = 2 + (i / 32), lc = 3 + 2 * (i % 32);
-            int32_t *row = win + lr * kWinPitch;
+        for (int i = threadIdx.x; i < T2 * TQ; i += blockDim.x) {
+            int lr = 2 + (i / TQ), lc = 3 + 2 * (i % TQ);
+            int32_t *row = win + lr * WP;
             row[lc] += floor_half(row[lc - 1] + row[lc + 1]);
         }
         __syncthreads();
     }
 }
 
+template <int TQ>
+__device__ inline void fill_maps(int32_t *rmap, int32_t *cmap, int qx0, int qy0, int w, int h)
+{
+    constexpr int WN = 2 * TQ + 4;
+    if (threadIdx.x < WN) rmap[threadIdx.x] = reflect_idx(2 * qy0 - 2 + (int)threadIdx.x, h);
+    else if (threadIdx.x < 2 * WN) cmap[threadIdx.x - WN] = reflect_idx(2 * qx0 - 2 + (int)threadIdx.x - WN, w);
+}
+
 // Inverse of level `level` into LL_{level-1} (an intermediate level).
+template <int TQ>
 __global__ void __launch_bounds__(256) k_inv_level(PlanHdr H, const uint8_t *__restrict__ plan,
                                                    uint8_t *__restrict__ ws, int level)
 {
-    __shared__ int32_t win[kWin * kWinPitch];
+    constexpr int WN = 2 * TQ + 4, WP = WN + 1, T2 = 2 * TQ;
+    __shared__ int32_t win[WN * WP];
+    __shared__ int32_t rmap[WN], cmap[WN];
     const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
     const WorkItem *items = (const WorkItem *)(plan + H.work_off);
     const WorkItem &W = find_item(items, H.lvl_first[level], H.lvl_count[level], blockIdx.x);
     const TileGeo &T = tiles[W.tile];
     uint32_t r = blockIdx.x - W.wg_start;
-    uint32_t nsp = W.ntx * W.nty;
-    int c = (int)(r / nsp);
-    uint32_t sp = r % nsp;
-    int qx0 = (int)(sp % W.ntx) * kTQ, qy0 = (int)(sp / W.ntx) * kTQ;
+    int c = (int)(r % W.nch);
+    uint32_t sp = r / W.nch;
+    int qx0 = (int)(sp % W.ntx) * TQ, qy0 = (int)(sp / W.ntx) * TQ;
     int32_t *wsi = (int32_t *)ws;
     const LevelGeo &G = T.lv[level];
-    stage_inverse(T, level, c, qx0, qy0, wsi, win);
+    fill_maps<TQ>(rmap, cmap, qx0, qy0, (int)G.w, (int)G.h);
     __syncthreads();
-    inverse_window(win, G.h > 1, G.w > 1);
+    stage_inverse<TQ>(T, level, c, rmap, cmap, wsi, win);
+    __syncthreads();
+    inverse_window<TQ>(win, G.h > 1, G.w > 1);
     int k = level - 1, which = (k & 1) ? 0 : 1;
     int32_t *dst = wsi + T.tmp_off[which] + (uint64_t)c * T.tmp_chan[which];
     uint32_t dp = T.tmp_pitch[which];
-    for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
-        int x = 2 * qx0 + (i % 64), y = 2 * qy0 + (i / 64);
-        if (x < (int)G.w && y < (int)G.h) dst[(uint64_t)y * dp + x] = win[(2 + i / 64) * kWinPitch + 2 + (i % 64)];
+    for (int i = threadIdx.x; i < T2 * T2; i += blockDim.x) {
+        int x = 2 * qx0 + (i % T2), y = 2 * qy0 + (i / T2);
+        if (x < (int)G.w && y < (int)G.h) dst[(uint64_t)y * dp + x] = win[(2 + i / T2) * WP + 2 + (i % T2)];
     }
-}
-
-__device__ inline void store_pixel(uint8_t *pix, const TileGeo &T, int x, int y, int c, int32_t v)
-{
-    int32_t top = (1 << T.bits) - 1;
-    v = v < 0 ? 0 : (v > top ? top : v);
-    uint8_t *row = pix + T.pix_offset + (uint64_t)y * T.pix_stride;
-    uint32_t e = ((uint32_t)x * T.channels + c) * T.bps;
-    row[e] = (uint8_t)(v & 0xff);
-    if (T.bps == 2) row[e + 1] = (uint8_t)(v >> 8);
 }
 
 // Final stage of a decode job: LL_z (z = target level) -> inverse colour
 // transform -> clamp -> interleaved pixels.  If z < levels this fuses the
-// inverse of level z+1; all channels are handled by one workgroup.
+// inverse of level z+1.  The channels of a group (3 with the colour
+// transform) go through one LDS window in turn; each thread keeps its output
+// samples per channel in registers, then converts and stores 4 horizontally
+// adjacent pixels at a time.
+template <int TQ>
 __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__restrict__ plan,
                                                    uint8_t *__restrict__ ws,
                                                    uint8_t *__restrict__ pix,
                                                    const int32_t *__restrict__ status)
 {
-    __shared__ int32_t win[3][kWin * kWinPitch];
+    constexpr int WN = 2 * TQ + 4, WP = WN + 1, T2 = 2 * TQ;
+    constexpr int TPR = T2 / 4;          // threads per output row (4 pixels each)
+    constexpr int RSTEP = 256 / TPR;     // rows between a thread's rows
+    constexpr int NR = T2 / RSTEP;       // rows per thread
+    __shared__ int32_t win[WN * WP];
+    __shared__ int32_t rmap[WN], cmap[WN];
     const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
     const WorkItem *items = (const WorkItem *)(plan + H.work_off);
     const WorkItem &W = find_item(items, H.fin_first, H.fin_count, blockIdx.x);
     const TileGeo &T = tiles[W.tile];
     uint32_t r = blockIdx.x - W.wg_start;
-    uint32_t nsp = W.ntx * W.nty;
-    int cg = (int)(r / nsp);
-    uint32_t sp = r % nsp;
-    int qx0 = (int)(sp % W.ntx) * kTQ, qy0 = (int)(sp / W.ntx) * kTQ;
+    int cg = (int)(r % W.nch);
+    uint32_t sp = r / W.nch;
+    int qx0 = (int)(sp % W.ntx) * TQ, qy0 = (int)(sp / W.ntx) * TQ;
     int32_t *wsi = (int32_t *)ws;
     int z = T.target_level;
     int c0 = cg * 3, nc = (int)T.channels - c0;
     if (nc > 3) nc = 3;
     int ow, oh;
-    if (z < T.levels) {
-        const LevelGeo &G = T.lv[z + 1];
-        ow = (int)G.w; oh = (int)G.h;
-        for (int k = 0; k < nc; k++) stage_inverse(T, z + 1, c0 + k, qx0, qy0, wsi, win[k]);
+    const bool fused = z < T.levels;
+    if (fused) { ow = (int)T.lv[z + 1].w; oh = (int)T.lv[z + 1].h; }
+    else { ow = (int)T.ll_w; oh = (int)T.ll_h; }
+    if (fused) fill_maps<TQ>(rmap, cmap, qx0, qy0, ow, oh);
+    const int tx = (threadIdx.x % TPR) * 4, ty = threadIdx.x / TPR;
+    int32_t v[3][NR][4];
+    for (int k = 0; k < nc; k++) {
         __syncthreads();
-        for (int k = 0; k < nc; k++) inverse_window(win[k], G.h > 1, G.w > 1);
-    } else {
-        ow = (int)T.ll_w; oh = (int)T.ll_h;
-        for (int k = 0; k < nc; k++) {
-            const int32_t *ll = wsi + T.ll_off + (uint64_t)(c0 + k) * T.chan_elems;
-            for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
-                int x = 2 * qx0 + (i % 64), y = 2 * qy0 + (i / 64);
-                if (x < ow && y < oh) win[k][(2 + i / 64) * kWinPitch + 2 + (i % 64)] = ll[(uint64_t)y * T.ll_pitch + x];
-            }
-        }
-        __syncthreads();
-    }
-    for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
-        int x = 2 * qx0 + (i % 64), y = 2 * qy0 + (i / 64);
-        if (x >= ow || y >= oh) continue;
-        int li = (2 + i / 64) * kWinPitch + 2 + (i % 64);
-        if (T.ct == 1) {
-            int32_t Y = win[0][li], cb = win[1][li], cr = win[2][li];
-            int32_t g = Y - ((cb + cr) >> 2);
-            store_pixel(pix, T, x, y, 0, cr + g);
-            store_pixel(pix, T, x, y, 1, g);
-            store_pixel(pix, T, x, y, 2, cb + g);
+        if (fused) {
+            stage_inverse<TQ>(T, z + 1, c0 + k, rmap, cmap, wsi, win);
+            __syncthreads();
+            inverse_window<TQ>(win, oh > 1, ow > 1);
         } else {
-            for (int k = 0; k < nc; k++) store_pixel(pix, T, x, y, c0 + k, win[k][li]);
+            const int32_t *ll = wsi + T.ll_off + (uint64_t)(c0 + k) * T.chan_elems;
+            for (int i = threadIdx.x; i < T2 * T2; i += blockDim.x) {
+                int x = 2 * qx0 + (i % T2), y = 2 * qy0 + (i / T2);
+                if (x < ow && y < oh) win[(2 + i / T2) * WP + 2 + (i % T2)] = ll[(uint64_t)y * T.ll_pitch + x];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++)
+#pragma unroll
+            for (int xx = 0; xx < 4; xx++) v[k][rr][xx] = win[(2 + ty + RSTEP * rr) * WP + 2 + tx + xx];
+    }
+    const int32_t top = (1 << T.bits) - 1;
+    const uint32_t C = T.channels, bps = T.bps;
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) {
+        int y = 2 * qy0 + ty + RSTEP * rr;
+        if (y >= oh) continue;
+        int x0 = 2 * qx0 + tx;
+        int32_t o[3][4];
+#pragma unroll
+        for (int xx = 0; xx < 4; xx++) {
+            if (T.ct == 1) {
+                int32_t Y = v[0][rr][xx], cb = v[1][rr][xx], cr = v[2][rr][xx];
+                int32_t g = Y - ((cb + cr) >> 2);
+                o[0][xx] = cr + g; o[1][xx] = g; o[2][xx] = cb + g;
+            } else {
+                for (int k = 0; k < 3; k++) o[k][xx] = v[k][rr][xx];
+            }
+            for (int k = 0; k < 3; k++) o[k][xx] = o[k][xx] < 0 ? 0 : (o[k][xx] > top ? top : o[k][xx]);
+        }
+        uint8_t *row = pix + T.pix_offset + (uint64_t)y * T.pix_stride;
+        if (bps == 1 && C == 3 && x0 + 3 < ow && ((((uintptr_t)(row + (uint32_t)x0 * 3)) & 3u) == 0)) {
+            uint32_t *d = (uint32_t *)(row + (uint32_t)x0 * 3);
+            d[0] = (uint32_t)o[0][0] | ((uint32_t)o[1][0] << 8) | ((uint32_t)o[2][0] << 16) | ((uint32_t)o[0][1] << 24);
+            d[1] = (uint32_t)o[1][1] | ((uint32_t)o[2][1] << 8) | ((uint32_t)o[0][2] << 16) | ((uint32_t)o[1][2] << 24);
+            d[2] = (uint32_t)o[2][2] | ((uint32_t)o[0][3] << 8) | ((uint32_t)o[1][3] << 16) | ((uint32_t)o[2][3] << 24);
+        } else {
+            for (int xx = 0; xx < 4; xx++) {
+                int x = x0 + xx;
+                if (x >= ow) break;
+                for (int k = 0; k < nc; k++) {
+                    uint32_t e = ((uint32_t)x * C + c0 + k) * bps;
+                    row[e] = (uint8_t)(o[k][xx] & 0xff);
+                    if (bps == 2) row[e + 1] = (uint8_t)(o[k][xx] >> 8);
+                }
+            }
         }
     }
     (void)status;
@@ -398,8 +462,10 @@ hipError_t launch_forward_level(const PlanHdr &H, const uint8_t *d_plan, const u
     if (level > (int)H.max_levels || !H.lvl_wgs[level]) return hipSuccess;
     if (level == 0)
         hipLaunchKernelGGL(k_fwd_level0, dim3(H.lvl_wgs[0]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws);
+    else if (H.tq == 16)
+        hipLaunchKernelGGL(k_fwd_level<16>, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws, level);
     else
-        hipLaunchKernelGGL(k_fwd_level, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws, level);
+        hipLaunchKernelGGL(k_fwd_level<32>, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws, level);
     return hipGetLastError();
 }
 
@@ -408,10 +474,16 @@ hipError_t launch_inverse_level(const PlanHdr &H, const uint8_t *d_plan, uint8_t
                                 hipStream_t stream)
 {
     if (level == 0) {
-        if (H.fin_wgs)
-            hipLaunchKernelGGL(k_inv_final, dim3(H.fin_wgs), dim3(256), 0, stream, H, d_plan, d_ws, d_pixels_out, d_status);
+        if (!H.fin_wgs) return hipSuccess;
+        if (H.tq == 16)
+            hipLaunchKernelGGL(k_inv_final<16>, dim3(H.fin_wgs), dim3(256), 0, stream, H, d_plan, d_ws, d_pixels_out, d_status);
+        else
+            hipLaunchKernelGGL(k_inv_final<32>, dim3(H.fin_wgs), dim3(256), 0, stream, H, d_plan, d_ws, d_pixels_out, d_status);
     } else if (level <= (int)H.max_levels && H.lvl_wgs[level]) {
-        hipLaunchKernelGGL(k_inv_level, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_ws, level);
+        if (H.tq == 16)
+            hipLaunchKernelGGL(k_inv_level<16>, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_ws, level);
+        else
+            hipLaunchKernelGGL(k_inv_level<32>, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_ws, level);
     }
     return hipGetLastError();
 }

@@ -36,6 +36,17 @@ class DecodeJob(ctypes.Structure):
                 ("reserved", ctypes.c_uint16)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("transform_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+def tuning(transform_tile=0, blocks_per_cu=0) -> Tuning:
+    t = Tuning()
+    t.transform_tile, t.blocks_per_cu = int(transform_tile), int(blocks_per_cu)
+    return t
+
+
 assert ctypes.sizeof(TileDesc) == 32 and ctypes.sizeof(DecodeJob) == 64
 
 _lib = None
@@ -74,6 +85,8 @@ def lib():
             "isx_stage_name": (ctypes.c_char_p, [i32, i32]),
             "isx_encode_run_stages": (i32, [P, P, P, P, u64, P, P, P, P, u64, P, i32, i32]),
             "isx_decode_run_stages": (i32, [P, P, P, P, P, P, u64, P, i32, i32]),
+            "isx_encode_plan_build_tuned": (i32, [P, i32, P, P, u64]),
+            "isx_decode_plan_build_tuned": (i32, [P, i32, P, P, u64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -88,7 +101,7 @@ EXPORTS = ["isx_max_encoded_bytes", "isx_encode_workspace_bytes", "isx_decode_wo
            "isx_encode_plan_build", "isx_encode_run", "isx_decode_plan_bytes",
            "isx_decode_plan_build", "isx_decode_run", "isx_status_string", "isx_debug_forward",
            "isx_debug_huffman", "isx_stage_count", "isx_stage_name", "isx_encode_run_stages",
-           "isx_decode_run_stages"]
+           "isx_decode_run_stages", "isx_encode_plan_build_tuned", "isx_decode_plan_build_tuned"]
 
 
 def status_string(code: int) -> str:
@@ -142,7 +155,7 @@ class Encoder:
     """Encoder for a fixed batch of tile shapes: plan built and uploaded once,
     workspace and output arena allocated once (torch, on `device`)."""
 
-    def __init__(self, descs, device="cuda"):
+    def __init__(self, descs, device="cuda", tune=None):
         torch = _torch()
         L = lib()
         self.n = len(descs)
@@ -151,7 +164,10 @@ class Encoder:
         if pb == 0:
             raise IsxError(E_INVALID_ARG, "encode plan")
         self.h_plan = (ctypes.c_uint8 * pb)()
-        _check(L.isx_encode_plan_build(self.descs, self.n, self.h_plan, pb), "encode plan")
+        self.tune = tune if tune is not None else tuning()
+        _check(L.isx_encode_plan_build_tuned(self.descs, self.n, ctypes.byref(self.tune), self.h_plan,
+                                             pb), "encode plan")
+        self.graph = None
         self.d_plan = torch.frombuffer(bytearray(self.h_plan), dtype=torch.uint8).to(device)
         self.ws_bytes = int(L.isx_encode_workspace_bytes(self.descs, self.n))
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
@@ -176,6 +192,13 @@ class Encoder:
                                          self.ws_bytes, _stream_ptr(stream), first, count)
         _check(rc, "isx_encode_run_stages")
 
+    def capture(self, d_pixels):
+        """Capture one full encode of d_pixels into a HIP graph (replayed by replay())."""
+        self.graph = _capture(lambda: self.run(d_pixels))
+
+    def replay(self):
+        self.graph.replay()
+
     def streams(self):
         """Host copies of the encoded tiles (after the stream has completed)."""
         st = self.status.cpu().numpy()
@@ -194,7 +217,7 @@ class Encoder:
 class Decoder:
     """Decoder for a fixed list of jobs (plan uploaded once)."""
 
-    def __init__(self, jobs, out_bytes, device="cuda"):
+    def __init__(self, jobs, out_bytes, device="cuda", tune=None, out=None):
         torch = _torch()
         L = lib()
         self.n = len(jobs)
@@ -205,11 +228,15 @@ class Decoder:
         if pb == 0:
             raise IsxError(E_INVALID_ARG, "decode plan")
         self.h_plan = (ctypes.c_uint8 * pb)()
-        _check(L.isx_decode_plan_build(self.jobs, self.n, self.h_plan, pb), "decode plan")
+        self.tune = tune if tune is not None else tuning()
+        _check(L.isx_decode_plan_build_tuned(self.jobs, self.n, ctypes.byref(self.tune), self.h_plan,
+                                             pb), "decode plan")
+        self.graph = None
         self.d_plan = torch.frombuffer(bytearray(self.h_plan), dtype=torch.uint8).to(device)
         self.ws_bytes = int(L.isx_decode_workspace_bytes(self.jobs, self.n))
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
-        self.out = torch.zeros(max(1, out_bytes), dtype=torch.uint8, device=device)
+        self.out = out if out is not None else torch.zeros(max(1, out_bytes), dtype=torch.uint8,
+                                                           device=device)
         self.status = torch.full((self.n,), 1, dtype=torch.int32, device=device)
 
     def run(self, d_encoded, stream=None):
@@ -223,6 +250,29 @@ class Decoder:
                                          _ptr(self.out), _ptr(self.status), _ptr(self.ws),
                                          self.ws_bytes, _stream_ptr(stream), first, count)
         _check(rc, "isx_decode_run_stages")
+
+    def capture(self, d_encoded):
+        """Capture one full decode of d_encoded into a HIP graph."""
+        self.graph = _capture(lambda: self.run(d_encoded))
+
+    def replay(self):
+        self.graph.replay()
+
+
+def _capture(fn):
+    """Record the kernels `fn` enqueues into a torch CUDA(HIP) graph.  The
+    library enqueues kernels only (no copies, no memsets) on the current
+    stream, which torch points at its capture stream."""
+    torch = _torch()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()  # warm-up outside the graph
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
 
 
 def stage_names(mode):

@@ -119,9 +119,14 @@ def random_image(width: int, height: int, channels: int, bits: int,
     return a.astype(dt)
 
 
+def _he_tile(args):
+    w, h, seed, sc = args
+    return he_like(w, h, seed, sigma=(max(1.0, 20.0 * sc), max(2.0, 60.0 * sc)))
+
+
 def tile_batch(n_tiles: int, seed: int, content_seed_base: int,
                sides=(512, 256, 128), edge_frac: float = 0.15,
-               levels=(3, 4, 5), qstep: int = 4, max_side: int = 511):
+               levels=(3, 4, 5), qstep: int = 4, max_side: int = 511, workers: int = 1):
     """Mixed batch of RGB uint8 tiles as cut from a slide.
 
     Returns a list of dicts {pixels, levels, qstep}.  85% of tiles are
@@ -132,7 +137,7 @@ def tile_batch(n_tiles: int, seed: int, content_seed_base: int,
     side/256.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
-    out = []
+    specs = []
     for i in range(n_tiles):
         if rng.uniform() < edge_frac:
             w = int(rng.integers(1, max_side + 1))
@@ -142,8 +147,13 @@ def tile_batch(n_tiles: int, seed: int, content_seed_base: int,
             w = h = s
         lv = int(levels[int(rng.integers(0, len(levels)))])
         q = 1 if rng.uniform() < 0.5 else int(qstep)
-        sc = max(w, h) / 256.0
-        px = he_like(w, h, content_seed_base + i,
-                     sigma=(max(1.0, 20.0 * sc), max(2.0, 60.0 * sc)))
-        out.append({"pixels": px, "levels": lv, "qstep": q})
-    return out
+        specs.append((w, h, lv, q))
+    jobs = [(w, h, content_seed_base + i, max(w, h) / 256.0) for i, (w, h, _, _) in enumerate(specs)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            pixels = pool.map(_he_tile, jobs, chunksize=8)
+    else:
+        pixels = [_he_tile(j) for j in jobs]
+    return [{"pixels": px, "levels": lv, "qstep": q}
+            for px, (w, h, lv, q) in zip(pixels, specs)]
