@@ -323,6 +323,22 @@ def bench_batch(args):
             raise SystemExit(f"lossless tile {i} did not round-trip")
         o += n
     sbytes = sum(len(s) for s in streams)
+    # one stage-by-stage pass with events, for the per-stage breakdown
+    for kind, obj, src, names in (("enc", enc, d_pix, isx.stage_names(0)), ("dec", dec, enc.out, isx.stage_names(1))):
+        evs = []
+        for st in range(len(names)):
+            e = torch.cuda.Event(enable_timing=True)
+            e.record()
+            evs.append(e)
+            obj.run_stages(src, st, 1)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        evs.append(e)
+        torch.cuda.synchronize()
+        for st in range(len(names)):
+            t = evs[st].elapsed_time(evs[st + 1])
+            if t > 0.02:
+                log(f"[stage] {kind} {names[st]:>20s} {t * 1e3:9.1f} us")
     out = {"metric": "bit-exact encode+decode megapixels/s per GPU (batched, graph-captured)",
            "value": round(px / 1e6 / (ms * 1e-3), 2), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",

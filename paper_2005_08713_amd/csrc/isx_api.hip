@@ -282,9 +282,23 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         H.fin_count = (uint32_t)items.size() - H.fin_first;
         H.fin_wgs = wg;
     }
+    // block lists by size class (symbol kernel launch shape)
+    std::vector<uint32_t> big, small;
+    for (int32_t i = 0; i < n; i++) {
+        const TileGeo &T = tb[i].g;
+        for (uint32_t b = 0; b < T.nblocks; b++) {
+            BlockDesc B;
+            block_geometry(T, b, B);
+            uint32_t cells = (uint32_t)B.p * B.wb * B.hb / 16;
+            (cells > 768 ? big : small).push_back(T.block_base + b);
+        }
+    }
+    H.n_big = (uint32_t)big.size();
+    H.n_small = (uint32_t)small.size();
     H.tiles_off = al(sizeof(PlanHdr), 64);
     H.work_off = al(H.tiles_off + (uint64_t)n * sizeof(TileGeo), 64);
-    H.plan_bytes = H.work_off + items.size() * sizeof(WorkItem);
+    H.list_off = al(H.work_off + items.size() * sizeof(WorkItem), 64);
+    H.plan_bytes = H.list_off + (big.size() + small.size()) * sizeof(uint32_t);
     if (H.plan_bytes > kPlanRegion) {
         // large batches keep the plan after the workspace regions
         uint64_t extra = al(H.plan_bytes);
@@ -294,6 +308,9 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     memcpy(P.bytes.data(), &H, sizeof(H));
     for (int32_t i = 0; i < n; i++) memcpy(P.bytes.data() + H.tiles_off + (uint64_t)i * sizeof(TileGeo), &tb[i].g, sizeof(TileGeo));
     if (!items.empty()) memcpy(P.bytes.data() + H.work_off, items.data(), items.size() * sizeof(WorkItem));
+    if (!big.empty()) memcpy(P.bytes.data() + H.list_off, big.data(), big.size() * sizeof(uint32_t));
+    if (!small.empty())
+        memcpy(P.bytes.data() + H.list_off + big.size() * sizeof(uint32_t), small.data(), small.size() * sizeof(uint32_t));
     return ISX_OK;
 }
 

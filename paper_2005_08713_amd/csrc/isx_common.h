@@ -79,6 +79,8 @@ struct PlanHdr {
     uint32_t tq;        // transform tile: quads per side (16 or 32)
     uint32_t blk_grid;  // workgroups of the per-block kernels (== total_blocks unless persistent)
     uint32_t num_cus, blocks_per_cu;
+    uint64_t list_off;      // plan offset of the block list (u32): large blocks, then small ones
+    uint32_t n_big, n_small;  // blocks with > 768 4x4 cells / with <= 768
 };
 
 struct BlockDesc {

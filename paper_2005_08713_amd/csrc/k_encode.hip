@@ -18,6 +18,8 @@
 //                 lengths, a prefix sum to bit offsets, MSB-first packing into
 //                 an LDS window, written once to the final position in HBM.
 // Per tile: block offsets (scan), tile offsets (scan), tile header.
+#include <algorithm>
+
 #include "isx_common.h"
 
 namespace isx {
@@ -113,16 +115,22 @@ __global__ void __launch_bounds__(256) k_prep_blocks(PlanHdr H, const uint8_t *_
 }
 
 // ---------------------------------------------------------------- symbols
-constexpr int kSymNT = 1024;
-constexpr int kCellsPT = 3;  // 3 x 1024 cells = one 128x128 H-block (3 types)
+constexpr int kCellsPT = 3;  // 3 cells per thread: 1024 threads cover a 128x128 H-block (3 types)
 
+// Blocks are split in two classes by size: more than 768 4x4 cells (1024
+// threads) and at most 768 cells (256 threads); the plan lists the blocks of
+// each class, large ones first.
+template <int kSymNT>
 __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t *__restrict__ plan,
-                                                        uint8_t *__restrict__ ws)
+                                                        uint8_t *__restrict__ ws, uint32_t list0,
+                                                        uint32_t nlist)
 {
     __shared__ uint32_t hist[256];
     __shared__ int32_t wsh[kSymNT / 64];
     __shared__ uint32_t s_zir, s_dig[kNumWz], s_F[16], s_nruns, s_zero;
-    for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
+    const uint32_t *list = (const uint32_t *)(plan + H.list_off) + list0;
+    for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
+    const uint32_t blk = list[li];
     __syncthreads();
     const BlockDesc B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkAcc A = ((const BlkAcc *)(ws + H.ws_acc))[blk];
@@ -183,7 +191,7 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
         }
     }
 
-    if (tid < 256) hist[tid] = 0;
+    for (uint32_t i = tid; i < 256; i += kSymNT) hist[i] = 0;
     if (tid < kNumWz) s_dig[tid] = 0;
     if (tid < 16) s_F[tid] = 0;
     if (tid == 0) { s_zir = 0; s_nruns = 0; s_zero = 0; }
@@ -248,11 +256,11 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
         }
         __syncthreads();
         uint32_t slot = B.slot + (uint32_t)b;
-        if (tid < 256) {
-            uint32_t hv = hist[tid];
-            if (tid == 0) hv = s_zero;
-            seghist[(uint64_t)slot * 256 + tid] = (uint16_t)hv;
-            hist[tid] = 0;
+        for (uint32_t i = tid; i < 256; i += kSymNT) {
+            uint32_t hv = hist[i];
+            if (i == 0) hv = s_zero;
+            seghist[(uint64_t)slot * 256 + i] = (uint16_t)hv;
+            hist[i] = 0;
         }
         if (tid < kNumWz) { segstat[slot].dig[tid] = s_dig[tid]; }
         if (tid == 0) {
@@ -704,9 +712,13 @@ __global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__re
     __shared__ int32_t shi[4];
     const uint8_t *ws = ws_c;
     const uint32_t tid = threadIdx.x;
-    const uint64_t nitems = (uint64_t)H.total_blocks * 33;
-    for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const uint32_t blk = (uint32_t)(item / 33), y = (uint32_t)(item % 33);
+    // non-persistent: grid (blocks, 33) with y = 0 the header and y = 1.. the
+    // segments; persistent: a 1-D grid looping over segment-major items
+    const bool pers = gridDim.y == 1;
+    const uint64_t nitems = pers ? (uint64_t)H.total_blocks * 33 : 1;
+    for (uint64_t item = pers ? blockIdx.x : 0; item < nitems; item += pers ? gridDim.x : 1) {
+    const uint32_t blk = pers ? (uint32_t)(item % H.total_blocks) : blockIdx.x;
+    const uint32_t y = pers ? (uint32_t)(item / H.total_blocks) : blockIdx.y;
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
     const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[B.tile];
@@ -860,8 +872,14 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             hipError_t e = launch_forward_level(H, d_plan, d_pixels, d_ws, st - ENC_FWD0, stream);
             if (e != hipSuccess) return e;
         } else if (st == ENC_SYM) {
-            if (H.total_blocks)
-                hipLaunchKernelGGL(k_enc_symbols, dim3(H.blk_grid), dim3(kSymNT), 0, stream, H, d_plan, d_ws);
+            if (H.n_big) {
+                uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(H.n_big, H.num_cus * H.blocks_per_cu) : H.n_big;
+                hipLaunchKernelGGL(k_enc_symbols<1024>, dim3(g), dim3(1024), 0, stream, H, d_plan, d_ws, 0u, H.n_big);
+            }
+            if (H.n_small) {
+                uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(H.n_small, H.num_cus * H.blocks_per_cu * 4) : H.n_small;
+                hipLaunchKernelGGL(k_enc_symbols<256>, dim3(g), dim3(256), 0, stream, H, d_plan, d_ws, H.n_big, H.n_small);
+            }
         } else if (st == ENC_CODE) {
             if (H.total_blocks) hipLaunchKernelGGL(k_enc_code, dim3(H.blk_grid), dim3(256), 0, stream, H, d_ws);
         } else if (st == ENC_BOFF) {
@@ -873,7 +891,7 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             hipLaunchKernelGGL(k_enc_tile_finish, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws, d_out);
         } else if (st == ENC_PACK) {
             if (H.total_blocks)
-                hipLaunchKernelGGL(k_enc_pack, dim3(H.blocks_per_cu ? H.blk_grid : H.total_blocks * 33), dim3(256), 0,
+                hipLaunchKernelGGL(k_enc_pack, H.blocks_per_cu ? dim3(H.blk_grid) : dim3(H.total_blocks, 33), dim3(256), 0,
                                    stream, H, d_ws, d_out);
         }
     }
