@@ -92,12 +92,13 @@ void tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb)
     }
     T.nblocks_stream = start;
     T.nblocks = prefix_needed;
-    // per-channel arena layout (int32 elements)
+    // per-channel arena layout (int32 elements); a decode to level z only
+    // needs the bands of levels z+1 .. L
     uint64_t off = 0;
     T.ll_pitch = round4(T.ll_w);
     T.ll_off = off;
     off = al(off + (uint64_t)T.ll_pitch * T.ll_h, 64);
-    for (uint32_t l = 1; l <= d.levels; l++) {
+    for (uint32_t l = (uint32_t)target_level + 1; l <= d.levels; l++) {
         LevelGeo &G = T.lv[l];
         uint32_t bw[3] = {(G.w + 1) / 2, G.w / 2, G.w / 2};
         uint32_t bh[3] = {G.h / 2, (G.h + 1) / 2, G.h / 2};
@@ -109,16 +110,14 @@ void tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb)
     }
     T.chan_elems = al(off, 64);
     tb.arena_elems = T.chan_elems * d.channels;
-    // LL ping-pong: odd levels (LL_1 largest), even levels (LL_2 largest)
-    if (d.levels >= 2) {
-        T.tmp_pitch[0] = round4(T.lv[2].w);
-        T.tmp_chan[0] = al((uint64_t)T.tmp_pitch[0] * T.lv[2].h, 64);
-        tb.tmp_elems[0] = T.tmp_chan[0] * d.channels;
-    }
-    if (d.levels >= 3) {
-        T.tmp_pitch[1] = round4(T.lv[3].w);
-        T.tmp_chan[1] = al((uint64_t)T.tmp_pitch[1] * T.lv[3].h, 64);
-        tb.tmp_elems[1] = T.tmp_chan[1] * d.channels;
+    // LL ping-pong for the intermediate LL_k, k in [z+1, L-1]: odd k in
+    // buffer 0, even k in buffer 1, each sized for its largest (smallest k)
+    for (uint32_t k = (uint32_t)target_level + 1; k + 1 <= d.levels; k++) {
+        int which = (k & 1) ? 0 : 1;
+        if (tb.tmp_elems[which]) continue;
+        T.tmp_pitch[which] = round4(T.lv[k + 1].w);
+        T.tmp_chan[which] = al((uint64_t)T.tmp_pitch[which] * T.lv[k + 1].h, 64);
+        tb.tmp_elems[which] = T.tmp_chan[which] * d.channels;
     }
     // symbols
     uint64_t sb = 0;

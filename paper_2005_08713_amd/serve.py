@@ -1,0 +1,301 @@
+"""Tile-decode serving with continuous batching over an HBM-resident slide.
+
+A slide is cut into square tiles, each encoded on its own (Sec. 4: separate
+blocks per scale let any tile be decoded at any resolution level).  The
+encoded tiles stay in one device arena.  A request (z, X, Y) asks for the
+512x512 view at zoom z: the 2^z x 2^z source tiles (X 2^z + i, Y 2^z + j),
+each decoded to level z (only its coarser blocks) straight into its place in
+the request's output buffer.
+
+The server loop admits arrived requests into a free batch slot as long as the
+slot's workspace and output memory allow, launches the whole batch as one
+isx_decode_run on the slot's stream, and keeps going while earlier batches
+run; completed batches release their slot.  Latency = completion - arrival.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import isx
+
+
+@dataclass
+class Request:
+    rid: int
+    z: int
+    X: int
+    Y: int
+    arrival: float = 0.0
+    done: float = -1.0
+    slot: int = -1
+    out_off: int = 0
+
+
+class Slide:
+    """Encoded tiles of a slide, resident in HBM, with a host index."""
+
+    def __init__(self, tiles_x, tiles_y, tile=512, levels=6, seed=501, batch=256, device="cuda",
+                 log=None):
+        import torch
+        from .synth import SlideGen
+        self.tx, self.ty, self.tile, self.levels = tiles_x, tiles_y, tile, levels
+        self.n = tiles_x * tiles_y
+        gen = SlideGen(tiles_x, tiles_y, tile, seed, device)
+        self.gen = gen
+        desc = [isx.tile_desc(tile, tile, 3, 1, 8, levels, pixel_offset=i * tile * tile * 3)
+                for i in range(batch)]
+        enc = isx.Encoder(desc, device)
+        parts, self.offsets, self.sizes = [], np.zeros(self.n, np.int64), np.zeros(self.n, np.int64)
+        total = 0
+        t0 = time.perf_counter()
+        for b0 in range(0, self.n, batch):
+            ids = list(range(b0, min(self.n, b0 + batch)))
+            px = gen.tiles(ids, b0 // batch)
+            if len(ids) < batch:
+                pad = torch.zeros((batch - len(ids),) + px.shape[1:], dtype=px.dtype, device=device)
+                px = torch.cat([px, pad])
+            enc.run(px.reshape(-1))
+            torch.cuda.synchronize()
+            st = enc.status.cpu().numpy()
+            if (st[:len(ids)] != 0).any():
+                raise RuntimeError("slide encode failed")
+            off = enc.offsets.cpu().numpy()
+            sz = enc.sizes.cpu().numpy()
+            end = int(off[len(ids) - 1] + sz[len(ids) - 1])
+            parts.append(enc.out[:end].clone())
+            for k, i in enumerate(ids):
+                self.offsets[i] = total + off[k]
+                self.sizes[i] = sz[k]
+            total += (end + 255) // 256 * 256
+            if parts[-1].numel() % 256:
+                parts.append(torch.zeros(256 - parts[-1].numel() % 256, dtype=torch.uint8, device=device))
+            if log and (b0 // batch) % 16 == 0:
+                log(f"[slide] encoded {min(self.n, b0 + batch)}/{self.n} tiles, {total / 1e9:.2f} GB")
+        self.arena = torch.cat(parts)
+        self.encode_s = time.perf_counter() - t0
+        self.raw_bytes = self.n * tile * tile * 3
+        self.desc = isx.tile_desc(tile, tile, 3, 1, 8, levels)
+
+    def sources(self, z, X, Y):
+        """Source tiles of request (z, X, Y): list of (tile id, i, j)."""
+        s = 1 << z
+        out = []
+        for j in range(s):
+            for i in range(s):
+                tx, ty = X * s + i, Y * s + j
+                if tx < self.tx and ty < self.ty:
+                    out.append((ty * self.tx + tx, i, j))
+        return out
+
+    def grid(self, z):
+        s = 1 << z
+        return -(-self.tx // s), -(-self.ty // s)
+
+
+def viewer_trace(slide: Slide, n_viewers=32, steps=200, zmax=6, vw=4, vh=3, seed=502):
+    """Requests of viewers doing random walks: pan w.p. 0.8, zoom +-1 w.p. 0.2;
+    each step requests the newly visible tiles of the viewport."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    state = []
+    for _ in range(n_viewers):
+        z = int(rng.integers(0, zmax + 1))
+        gx, gy = slide.grid(z)
+        state.append([z, int(rng.integers(0, max(1, gx - vw + 1))), int(rng.integers(0, max(1, gy - vh + 1)))])
+    seen = [set() for _ in range(n_viewers)]
+    reqs = []
+    for _ in range(steps):
+        for v in range(n_viewers):
+            z, x, y = state[v]
+            if rng.uniform() < 0.8:
+                dx, dy = [(1, 0), (-1, 0), (0, 1), (0, -1)][int(rng.integers(0, 4))]
+                x, y = x + dx, y + dy
+            else:
+                nz = min(zmax, max(0, z + (1 if rng.uniform() < 0.5 else -1)))
+                if nz > z:
+                    x, y = x // 2, y // 2
+                elif nz < z:
+                    x, y = x * 2, y * 2
+                z = nz
+            gx, gy = slide.grid(z)
+            x = min(max(0, x), max(0, gx - vw))
+            y = min(max(0, y), max(0, gy - vh))
+            state[v] = [z, x, y]
+            vis = {(z, x + i, y + j) for i in range(vw) for j in range(vh) if x + i < gx and y + j < gy}
+            for t in sorted(vis - seen[v]):
+                reqs.append(t)
+            seen[v] = vis
+    return reqs
+
+
+def poisson_arrivals(n, lam, seed=502):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / lam, size=n))
+
+
+class _Slot:
+    def __init__(self, ws_bytes, out_bytes, max_jobs, plan_bytes, device):
+        import torch
+        self.stream = torch.cuda.Stream()
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+        self.out = torch.zeros(out_bytes, dtype=torch.uint8, device=device)
+        self.status = torch.zeros(max_jobs, dtype=torch.int32, device=device)
+        self.h_plan = torch.empty(plan_bytes, dtype=torch.uint8).pin_memory()
+        self.d_plan = torch.empty(plan_bytes, dtype=torch.uint8, device=device)
+        self.event = None
+        self.reqs = []
+        self.busy = False
+
+
+class Server:
+    """Continuous-batching decode server over a Slide.
+
+    Memory: `slots` batch slots, each with `ws_bytes` of decode workspace and
+    room for `max_reqs` 512x512x3 outputs; a batch is formed from arrived
+    requests in order while its jobs' workspace (library figure) fits."""
+
+    def __init__(self, slide: Slide, slots=3, ws_bytes=256 << 20, max_reqs=64, device="cuda",
+                 tune=None):
+        self.slide = slide
+        self.t = slide.tile
+        self.req_bytes = self.t * self.t * 3
+        self.max_reqs = max_reqs
+        self.max_jobs = 16384  # decode jobs (source tiles) per batch
+        self.tune = tune if tune is not None else isx.tuning()
+        # plan bytes upper bound for max_jobs jobs
+        probe = self._jobs([Request(0, 0, 0, 0)], dummy=self.max_jobs)
+        pb = int(isx.lib().isx_decode_plan_bytes(probe, len(probe)))
+        self.plan_cap = pb + (1 << 16)
+        self.ws_cap = ws_bytes
+        self.slots = [_Slot(ws_bytes, max_reqs * self.req_bytes, self.max_jobs, self.plan_cap, device)
+                      for _ in range(slots)]
+        self.ws_est = {}
+
+    def _jobs(self, reqs, dummy=0):
+        jobs = []
+        if dummy:
+            for k in range(dummy):
+                j = isx.DecodeJob()
+                j.tile = self.slide.desc
+                j.in_offset, j.in_bytes = 0, 1
+                j.out_offset, j.out_row_stride_bytes, j.target_level = 0, self.t * 3, 0
+                jobs.append(j)
+            return (isx.DecodeJob * len(jobs))(*jobs)
+        for r in reqs:
+            sub = self.t >> r.z
+            for tid, i, j in self.slide.sources(r.z, r.X, r.Y):
+                jb = isx.DecodeJob()
+                jb.tile = self.slide.desc
+                jb.in_offset = int(self.slide.offsets[tid])
+                jb.in_bytes = int(self.slide.sizes[tid])
+                jb.out_offset = r.out_off + (j * sub * self.t + i * sub) * 3
+                jb.out_row_stride_bytes = self.t * 3
+                jb.target_level = r.z
+                jobs.append(jb)
+        return (isx.DecodeJob * len(jobs))(*jobs)
+
+    def req_ws(self, z):
+        """Workspace of one request at zoom z (cached library figure)."""
+        if z not in self.ws_est:
+            r = Request(0, z, 0, 0)
+            jobs = self._jobs([r])
+            self.ws_est[z] = int(isx.lib().isx_decode_workspace_bytes(jobs, len(jobs)))
+        return self.ws_est[z]
+
+    def launch(self, slot: _Slot, reqs):
+        import torch
+        L = isx.lib()
+        for k, r in enumerate(reqs):
+            r.out_off = k * self.req_bytes
+        jobs = self._jobs(reqs)
+        n = len(jobs)
+        need = int(L.isx_decode_workspace_bytes(jobs, n))
+        if need > self.ws_cap:
+            raise RuntimeError("batch exceeds the slot workspace")
+        pb = int(L.isx_decode_plan_bytes(jobs, n))
+        hp = (ctypes.c_uint8 * pb).from_address(slot.h_plan.data_ptr())
+        rc = L.isx_decode_plan_build_tuned(jobs, n, ctypes.byref(self.tune), hp, pb)
+        if rc:
+            raise isx.IsxError(rc, "serve plan")
+        with torch.cuda.stream(slot.stream):
+            for r in reqs:  # views that run off the slide: clear the part no tile covers
+                if len(self.slide.sources(r.z, r.X, r.Y)) < (1 << (2 * r.z)):
+                    slot.out[r.out_off:r.out_off + self.req_bytes].zero_()
+            slot.d_plan[:pb].copy_(slot.h_plan[:pb], non_blocking=True)
+            rc = L.isx_decode_run(hp, isx._ptr(slot.d_plan), isx._ptr(self.slide.arena), isx._ptr(slot.out),
+                                  isx._ptr(slot.status), isx._ptr(slot.ws), slot.ws.numel(),
+                                  ctypes.c_void_p(slot.stream.cuda_stream))
+            if rc:
+                raise isx.IsxError(rc, "serve decode")
+            slot.event = torch.cuda.Event()
+            slot.event.record(slot.stream)
+        slot.reqs = reqs
+        slot.busy = True
+        slot.njobs = n
+
+    def run(self, reqs, log=None, check=None):
+        """Serve `reqs` (with .arrival in seconds from start); returns stats."""
+        import torch
+        pending = deque(sorted(reqs, key=lambda r: r.arrival))
+        ready = deque()
+        t0 = time.perf_counter()
+        done = 0
+        batches = 0
+        px = 0
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            # completions
+            for s in self.slots:
+                if s.busy and s.event.query():
+                    tdone = time.perf_counter() - t0
+                    st = s.status[:s.njobs].cpu()
+                    if int(st.abs().sum()) != 0:
+                        raise RuntimeError("decode error in a served batch")
+                    for r in s.reqs:
+                        r.done = tdone
+                        px += sum((self.t >> r.z) ** 2 for _ in self.slide.sources(r.z, r.X, r.Y))
+                    if check:
+                        check(s, s.reqs)
+                    done += len(s.reqs)
+                    s.busy = False
+            while pending and pending[0].arrival <= now:
+                ready.append(pending.popleft())
+            free = [s for s in self.slots if not s.busy]
+            if ready and free:
+                batch, ws, nj = [], 0, 0
+                while ready and len(batch) < self.max_reqs:
+                    need = self.req_ws(ready[0].z)
+                    jobs = 1 << (2 * ready[0].z)
+                    if batch and (ws + need > self.ws_cap * 0.9 or nj + jobs > self.max_jobs):
+                        break
+                    ws += need
+                    nj += jobs
+                    batch.append(ready.popleft())
+                self.launch(free[0], batch)
+                batches += 1
+            elif not ready and pending:
+                wait = pending[0].arrival - (time.perf_counter() - t0)
+                if wait > 2e-4 and not any(s.busy for s in self.slots):
+                    time.sleep(wait - 1e-4)
+        wall = time.perf_counter() - t0
+        lat = np.array([r.done - r.arrival for r in reqs]) * 1e3
+        return {"requests": len(reqs), "batches": batches, "wall_s": wall,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "decoded_mpx_s": px / 1e6 / wall,
+                "offered_rps": len(reqs) / max(reqs[-1].arrival, 1e-9), "served_rps": len(reqs) / wall}
+
+    def decode_alone(self, r: Request):
+        """Decode one request by itself (slot 0), returns its output bytes (host)."""
+        import torch
+        s = self.slots[0]
+        while s.busy:
+            if s.event.query():
+                s.busy = False
+        self.launch(s, [r])
+        s.event.synchronize()
+        s.busy = False
+        return s.out[:self.req_bytes].cpu().numpy().copy()

@@ -157,3 +157,79 @@ def tile_batch(n_tiles: int, seed: int, content_seed_base: int,
         pixels = [_he_tile(j) for j in jobs]
     return [{"pixels": px, "levels": lv, "qstep": q}
             for px, (w, h, lv, q) in zip(pixels, specs)]
+
+
+# --------------------------------------------------------------------------
+# Whole-slide generator on the GPU (torch), for the served-slide workload.
+class SlideGen:
+    """H&E-like slide of tiles_x x tiles_y square tiles, generated tile batch
+    by tile batch on the GPU.
+
+    Recipe (same structure as ``he_like``): 8 Gaussian blobs per 4096^2 area
+    (sigma ~U(100, 600) px, amplitude ~U(0.5, 1)) form the tissue field,
+    thresholded at its 60% quantile (40% tissue); a second blob set mixes
+    pink and purple stain colours; background ~U{230..245}; N(0, 2^2) noise.
+    The two fields are evaluated on a 32-px grid (blobs only within 4 sigma)
+    and bilinearly upsampled per tile.  Blob parameters come from numpy
+    PCG64(seed); the per-pixel background and noise of tile batch b come from
+    a torch generator seeded with seed * 1000 + b.
+    """
+
+    def __init__(self, tiles_x: int, tiles_y: int, tile: int = 512, seed: int = 501, device="cuda"):
+        import torch
+        self.tx, self.ty, self.tile, self.seed, self.device = tiles_x, tiles_y, tile, seed, device
+        W, H = tiles_x * tile, tiles_y * tile
+        self.step = 32
+        gw, gh = W // self.step + 2, H // self.step + 2
+        rng = np.random.Generator(np.random.PCG64(seed))
+        nb = max(1, int(round(8 * W * H / 4096.0 ** 2)))
+        fields = []
+        for _ in range(2):
+            f = torch.zeros((gh, gw), dtype=torch.float32, device=device)
+            cx = rng.uniform(0, W, nb)
+            cy = rng.uniform(0, H, nb)
+            sg = rng.uniform(100, 600, nb)
+            am = rng.uniform(0.5, 1.0, nb)
+            for x, y, s, a in zip(cx, cy, sg, am):
+                x0 = max(0, int((x - 4 * s) / self.step)); x1 = min(gw, int((x + 4 * s) / self.step) + 1)
+                y0 = max(0, int((y - 4 * s) / self.step)); y1 = min(gh, int((y + 4 * s) / self.step) + 1)
+                if x1 <= x0 or y1 <= y0:
+                    continue
+                xs = torch.arange(x0, x1, device=device, dtype=torch.float32) * self.step
+                ys = torch.arange(y0, y1, device=device, dtype=torch.float32) * self.step
+                gx = torch.exp(-(xs - x) ** 2 / (2 * s * s))
+                gy = torch.exp(-(ys - y) ** 2 / (2 * s * s))
+                f[y0:y1, x0:x1] += float(a) * torch.outer(gy, gx)
+            fields.append(f)
+        self.tissue, self.stain = fields
+        flat = self.tissue.flatten()
+        if flat.numel() > 4_000_000:
+            idx = torch.linspace(0, flat.numel() - 1, 4_000_000, device=device).long()
+            flat = flat[idx]
+        self.thr = float(torch.quantile(flat, 0.60))
+        lo, hi = float(self.stain.min()), float(self.stain.max())
+        self.stain = (self.stain - lo) / max(hi - lo, 1e-12)
+
+    def tiles(self, ids, batch_index: int):
+        """uint8 tensor (len(ids), tile, tile, 3) for tile ids (ty * tiles_x + tx)."""
+        import torch
+        import torch.nn.functional as F
+        T, st = self.tile, self.step
+        k = T // st
+        g = torch.Generator(device=self.device)
+        g.manual_seed(self.seed * 1000 + batch_index)
+        out = torch.empty((len(ids), T, T, 3), dtype=torch.uint8, device=self.device)
+        pink = torch.tensor([232.0, 150.0, 190.0], device=self.device)
+        purple = torch.tensor([130.0, 70.0, 160.0], device=self.device)
+        for n, tid in enumerate(ids):
+            tx, ty = tid % self.tx, tid // self.tx
+            fa = self.tissue[ty * k:ty * k + k + 1, tx * k:tx * k + k + 1][None, None]
+            fb = self.stain[ty * k:ty * k + k + 1, tx * k:tx * k + k + 1][None, None]
+            fa = F.interpolate(fa, size=(T + 1, T + 1), mode="bilinear", align_corners=True)[0, 0, :T, :T]
+            fb = F.interpolate(fb, size=(T + 1, T + 1), mode="bilinear", align_corners=True)[0, 0, :T, :T]
+            img = torch.randint(230, 246, (T, T, 3), generator=g, device=self.device).float()
+            col = torch.round((1 - fb)[..., None] * pink + fb[..., None] * purple)
+            img = torch.where((fa > self.thr)[..., None], col, img)
+            img = img + 2.0 * torch.randn((T, T, 3), generator=g, device=self.device)
+            out[n] = torch.clamp(torch.round(img), 0, 255).to(torch.uint8)
+        return out

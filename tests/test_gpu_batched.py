@@ -119,3 +119,44 @@ def test_autotuner_picks_a_valid_setting(tmp_path, monkeypatch):
     assert os.path.exists(tmp_path / "tune.json")
     again = autotune.tune(descs, d_pix, reps=1)
     assert again == res
+
+
+def test_serving_results_identical_alone_and_in_the_mix():
+    """Requests decoded inside mixed continuous batches equal the same request
+    decoded alone, and equal the oracle's stitched level-z decodes."""
+    import torch
+    from paper_2005_08713_amd import serve
+    slide = serve.Slide(6, 5, tile=512, levels=6, seed=7, batch=16)
+    srv = serve.Server(slide, slots=3, ws_bytes=192 << 20, max_reqs=16)
+    trace = serve.viewer_trace(slide, n_viewers=8, steps=6, zmax=3, seed=9)
+    reqs = [serve.Request(i, z, X, Y) for i, (z, X, Y) in enumerate(trace[:60])]
+    times = serve.poisson_arrivals(len(reqs), 4000.0, seed=3)
+    for r, t in zip(reqs, times):
+        r.arrival = float(t)
+    got = {}
+
+    def check(slot, rs):
+        host = slot.out.cpu().numpy()
+        for r in rs:
+            got[r.rid] = host[r.out_off:r.out_off + srv.req_bytes].copy()
+
+    stats = srv.run(reqs, check=check)
+    print("serve stats", stats, flush=True)
+    assert stats["batches"] >= 2 and len(got) == len(reqs)
+    # each result the same alone
+    for r in reqs[::7]:
+        alone = srv.decode_alone(serve.Request(r.rid, r.z, r.X, r.Y))
+        assert np.array_equal(alone, got[r.rid]), r
+    # and equal to the oracle on the stitched sources (a few requests)
+    enc = slide.arena.cpu().numpy()
+    for r in reqs[:4]:
+        exp = np.zeros((512, 512, 3), np.uint8)
+        sub = 512 >> r.z
+        for tid, i, j in slide.sources(r.z, r.X, r.Y):
+            blob = enc[slide.offsets[tid]:slide.offsets[tid] + slide.sizes[tid]].tobytes()
+            exp[j * sub:(j + 1) * sub, i * sub:(i + 1) * sub] = oracle.decode_tile(blob, r.z)
+        assert np.array_equal(got[r.rid].reshape(512, 512, 3), exp), r
+    # the slide's own pixels round-trip at zoom 0
+    px = slide.gen.tiles([0], 0)[0].cpu().numpy()
+    blob = enc[slide.offsets[0]:slide.offsets[0] + slide.sizes[0]].tobytes()
+    assert np.array_equal(oracle.decode_tile(blob, 0), px)
