@@ -96,6 +96,18 @@ class Slide:
         s = 1 << z
         return -(-self.tx // s), -(-self.ty // s)
 
+    def source_arrays(self, z, X, Y):
+        """Vectorised sources(): (tile ids, i, j) arrays."""
+        s = 1 << z
+        jj, ii = np.divmod(np.arange(s * s), s)
+        tx, ty = X * s + ii, Y * s + jj
+        ok = (tx < self.tx) & (ty < self.ty)
+        return (ty * self.tx + tx)[ok], ii[ok], jj[ok]
+
+    def source_count(self, z, X, Y):
+        s = 1 << z
+        return max(0, min(s, self.tx - X * s)) * max(0, min(s, self.ty - Y * s))
+
 
 def viewer_trace(slide: Slide, n_viewers=32, steps=200, zmax=6, vw=4, vh=3, seed=502):
     """Requests of viewers doing random walks: pan w.p. 0.8, zoom +-1 w.p. 0.2;
@@ -137,6 +149,21 @@ def poisson_arrivals(n, lam, seed=502):
     return np.cumsum(rng.exponential(1.0 / lam, size=n))
 
 
+JOB_DTYPE = np.dtype([("pixel_offset", "<u8"), ("width", "<u4"), ("height", "<u4"),
+                      ("row_stride", "<u4"), ("channels", "u1"), ("bps", "u1"), ("bits", "u1"),
+                      ("levels", "u1"), ("ct", "u1"), ("r0", "u1", (3,)), ("qstep", "<u2"),
+                      ("r1", "<u2"), ("in_offset", "<u8"), ("in_bytes", "<u8"),
+                      ("out_offset", "<u8"), ("out_stride", "<u4"), ("target", "u1"),
+                      ("drop", "u1"), ("res", "<u2")])
+assert JOB_DTYPE.itemsize == 64
+
+
+def _fill_tile(a, d):
+    a["width"], a["height"], a["row_stride"] = d.width, d.height, d.row_stride_bytes
+    a["channels"], a["bps"], a["bits"], a["levels"] = d.channels, d.bytes_per_sample, d.bits, d.levels
+    a["ct"], a["qstep"] = d.colour_transform, d.qstep
+
+
 class _Slot:
     def __init__(self, ws_bytes, out_bytes, max_jobs, plan_bytes, device):
         import torch
@@ -168,7 +195,7 @@ class Server:
         self.tune = tune if tune is not None else isx.tuning()
         # plan bytes upper bound for max_jobs jobs
         probe = self._jobs([Request(0, 0, 0, 0)], dummy=self.max_jobs)
-        pb = int(isx.lib().isx_decode_plan_bytes(probe, len(probe)))
+        pb = int(isx.lib().isx_decode_plan_bytes(probe.ctypes.data, len(probe)))
         self.plan_cap = pb + (1 << 16)
         self.ws_cap = ws_bytes
         self.slots = [_Slot(ws_bytes, max_reqs * self.req_bytes, self.max_jobs, self.plan_cap, device)
@@ -176,34 +203,34 @@ class Server:
         self.ws_est = {}
 
     def _jobs(self, reqs, dummy=0):
-        jobs = []
+        """Decode jobs (a numpy array laid out as isx_decode_job) for requests."""
+        d = self.slide.desc
         if dummy:
-            for k in range(dummy):
-                j = isx.DecodeJob()
-                j.tile = self.slide.desc
-                j.in_offset, j.in_bytes = 0, 1
-                j.out_offset, j.out_row_stride_bytes, j.target_level = 0, self.t * 3, 0
-                jobs.append(j)
-            return (isx.DecodeJob * len(jobs))(*jobs)
+            a = np.zeros(dummy, dtype=JOB_DTYPE)
+            _fill_tile(a, d)
+            a["in_bytes"] = 1
+            a["out_stride"] = self.t * 3
+            return a
+        parts = []
         for r in reqs:
+            ids, ii, jj = self.slide.source_arrays(r.z, r.X, r.Y)
+            a = np.zeros(len(ids), dtype=JOB_DTYPE)
+            _fill_tile(a, d)
             sub = self.t >> r.z
-            for tid, i, j in self.slide.sources(r.z, r.X, r.Y):
-                jb = isx.DecodeJob()
-                jb.tile = self.slide.desc
-                jb.in_offset = int(self.slide.offsets[tid])
-                jb.in_bytes = int(self.slide.sizes[tid])
-                jb.out_offset = r.out_off + (j * sub * self.t + i * sub) * 3
-                jb.out_row_stride_bytes = self.t * 3
-                jb.target_level = r.z
-                jobs.append(jb)
-        return (isx.DecodeJob * len(jobs))(*jobs)
+            a["in_offset"] = self.slide.offsets[ids]
+            a["in_bytes"] = self.slide.sizes[ids]
+            a["out_offset"] = r.out_off + (jj * sub * self.t + ii * sub) * 3
+            a["out_stride"] = self.t * 3
+            a["target"] = r.z
+            parts.append(a)
+        return np.concatenate(parts) if parts else np.zeros(0, dtype=JOB_DTYPE)
 
     def req_ws(self, z):
         """Workspace of one request at zoom z (cached library figure)."""
         if z not in self.ws_est:
             r = Request(0, z, 0, 0)
             jobs = self._jobs([r])
-            self.ws_est[z] = int(isx.lib().isx_decode_workspace_bytes(jobs, len(jobs)))
+            self.ws_est[z] = int(isx.lib().isx_decode_workspace_bytes(jobs.ctypes.data, len(jobs)))
         return self.ws_est[z]
 
     def launch(self, slot: _Slot, reqs):
@@ -213,17 +240,20 @@ class Server:
             r.out_off = k * self.req_bytes
         jobs = self._jobs(reqs)
         n = len(jobs)
-        need = int(L.isx_decode_workspace_bytes(jobs, n))
+        jp = jobs.ctypes.data
+        need = int(L.isx_decode_workspace_bytes(jp, n))
         if need > self.ws_cap:
             raise RuntimeError("batch exceeds the slot workspace")
-        pb = int(L.isx_decode_plan_bytes(jobs, n))
+        pb = int(L.isx_decode_plan_bytes(jp, n))
+        if pb > self.plan_cap:
+            raise RuntimeError("batch plan exceeds the slot's plan buffer")
         hp = (ctypes.c_uint8 * pb).from_address(slot.h_plan.data_ptr())
-        rc = L.isx_decode_plan_build_tuned(jobs, n, ctypes.byref(self.tune), hp, pb)
+        rc = L.isx_decode_plan_build_tuned(jp, n, ctypes.byref(self.tune), hp, pb)
         if rc:
             raise isx.IsxError(rc, "serve plan")
         with torch.cuda.stream(slot.stream):
             for r in reqs:  # views that run off the slide: clear the part no tile covers
-                if len(self.slide.sources(r.z, r.X, r.Y)) < (1 << (2 * r.z)):
+                if self.slide.source_count(r.z, r.X, r.Y) < (1 << (2 * r.z)):
                     slot.out[r.out_off:r.out_off + self.req_bytes].zero_()
             slot.d_plan[:pb].copy_(slot.h_plan[:pb], non_blocking=True)
             rc = L.isx_decode_run(hp, isx._ptr(slot.d_plan), isx._ptr(self.slide.arena), isx._ptr(slot.out),
@@ -257,7 +287,7 @@ class Server:
                         raise RuntimeError("decode error in a served batch")
                     for r in s.reqs:
                         r.done = tdone
-                        px += sum((self.t >> r.z) ** 2 for _ in self.slide.sources(r.z, r.X, r.Y))
+                        px += (self.t >> r.z) ** 2 * self.slide.source_count(r.z, r.X, r.Y)
                     if check:
                         check(s, s.reqs)
                     done += len(s.reqs)
