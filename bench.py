@@ -37,8 +37,9 @@ def parse():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--levels", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle check and CPU baseline")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with measured HBM bytes per launch of the dominant kernel")
+    ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="JSON record of measured HBM bytes per launch of the dominant kernel "
+                         "(used only if the kernel's source is unchanged since it was measured)")
     ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single",
                     help="single: one 4096x4096 image (default); batch: 4096 uneven tiles; "
                          "serve: tile-decode requests against an HBM-resident slide")
@@ -199,9 +200,12 @@ def main():
         ach = alg / (avg_ms * 1e-3) / 1e9
         traffic = None
         if args.traffic and os.path.exists(args.traffic):
+            import hashlib
             with open(args.traffic) as f:
                 tr = json.load(f)
-            if tr.get("kernel") == dname:
+            src = os.path.join(ROOT, tr.get("source", ""))
+            fresh = os.path.isfile(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == tr.get("source_sha256")
+            if tr.get("kernel") == dname and fresh:
                 traffic = tr.get("bytes_per_launch")
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": dname,
