@@ -124,7 +124,7 @@ void tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb)
     for (uint32_t i = 0; i < T.nblocks; i++) {
         BlockDesc B;
         block_geometry(T, i, B);
-        sb += ((uint64_t)B.p * B.wb * B.hb / 8 * T.dmax + 15) & ~15ull;
+        sb += block_sym_bytes(B, T.dmax);
     }
     tb.sym_bytes = sb;
 }
@@ -216,7 +216,6 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         H.ws_segstat = o; o = al(o + total_slots * sizeof(SegStat));
     }
     H.ws_tileout = o; o = al(o + (uint64_t)n * sizeof(TileOut));
-    if (mode == MODE_DECODE) { H.ws_lut = o; o = al(o + total_blocks * kLutBytes); }
     for (int32_t i = 0; i < n; i++) {
         TileGeo &T = tb[i].g;
         uint64_t base = o / 4;  // int32 elements
@@ -516,8 +515,7 @@ const char *isx_stage_name(int32_t mode, int32_t stage)
         if (stage == ENC_PACK) return "enc_pack";
     } else if (mode == 1) {
         if (stage == DEC_PREP) return "dec_prep";
-        if (stage == DEC_HDR) return "dec_header";
-        if (stage == DEC_SEG) return "dec_segments";
+        if (stage == DEC_SEG) return "dec_entropy";
         if (stage == DEC_REASM) return "dec_reassemble";
         if (stage >= DEC_INV15 && stage <= DEC_FINAL) return inv[DEC_FINAL - stage];
     }

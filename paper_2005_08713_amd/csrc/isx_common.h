@@ -69,7 +69,7 @@ struct PlanHdr {
     uint64_t ws_bytes;
     // workspace regions (byte offsets from ws base)
     uint64_t ws_blockdesc, ws_acc, ws_seghist, ws_segstat, ws_blkstat, ws_blkplan, ws_tileout,
-        ws_lut, ws_misc;
+        ws_misc;
     // plan regions (byte offsets from plan base)
     uint64_t tiles_off, work_off;
     uint32_t lvl_first[kMaxLevels + 2];  // per level: first WorkItem index
@@ -138,17 +138,7 @@ struct BlkPlan {
     uint64_t seg_bitpos[32];  // decode: absolute bit position of each segment
 };
 
-constexpr int kLutK = 12;          // decode prefix table: 2^12 entries of uint16
-struct DecLeaves {                 // per block, after the prefix table
-    uint32_t acode[256];           // left-aligned codes, increasing (pre-order)
-    uint8_t len[256];
-    uint8_t sym[256];
-    uint32_t m;
-    uint32_t single;
-    uint32_t pad[2];
-};
-constexpr uint64_t kLutBytes = ((uint64_t)(1u << kLutK) * 2 + sizeof(DecLeaves) + 255) & ~255ull;
-
+constexpr int kLutK = 12;          // decode prefix table (LDS): 2^12 entries of uint16
 struct TileOut {
     uint64_t size;
     uint64_t offset;
@@ -160,6 +150,13 @@ struct TileOut {
 __host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline uint32_t round4(uint32_t a) { return (a + 3u) & ~3u; }
 __host__ __device__ inline uint32_t bitlen32(uint32_t v) { return v ? 32u - (uint32_t)__builtin_clz(v) : 0u; }
+// Bytes between the bitplanes of a block's symbol area (p*n symbols per
+// plane, padded to 16 bytes so each plane is written with 16-byte stores).
+__host__ __device__ inline uint32_t plane_stride(uint32_t pn) { return (pn + 15u) & ~15u; }
+__host__ __device__ inline uint64_t block_sym_bytes(const BlockDesc &B, uint32_t dmax)
+{
+    return (uint64_t)plane_stride((uint32_t)B.p * B.wb * B.hb / 8) * dmax;
+}
 
 // Geometry of tile-local block `local` (Sec. 4 blocks; group order LL, then
 // H-blocks of level L .. 1; channel-major, then raster; the empty corner cell
@@ -234,8 +231,7 @@ enum EncStage {
 };
 enum DecStage {
     DEC_PREP = 0,
-    DEC_HDR,
-    DEC_SEG,
+    DEC_SEG,   // block headers + code tables + segments (one kernel)
     DEC_REASM,
     DEC_INV15,                     // inverse of level 15 .. level 2 (intermediate outputs)
     DEC_FINAL = DEC_INV15 + kMaxLevels,  // inverse of level z+1 fused with the output stage

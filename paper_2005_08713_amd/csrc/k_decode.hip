@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
         uint64_t sz = 0, ssz = 0;
         if (local < T.nblocks) {
             block_geometry(T, local, B);
-            ssz = ((uint64_t)B.p * B.wb * B.hb / 8 * T.dmax + 15) & ~15ull;
+            ssz = block_sym_bytes(B, T.dmax);
             if (st == D_OK) {
                 uint64_t o = 24 + 4ull * local;
                 sz = (uint64_t)base[o] | ((uint64_t)base[o + 1] << 8) | ((uint64_t)base[o + 2] << 16) |
@@ -150,155 +150,17 @@ struct LdsBits {
     }
 };
 
-__global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__restrict__ enc,
-                                                   uint8_t *__restrict__ ws,
-                                                   int32_t *__restrict__ status)
-{
-    __shared__ uint32_t hw[132];
-    __shared__ uint32_t s_info[8];
-    __shared__ uint32_t s_acode[256];
-    __shared__ uint8_t s_len[256], s_sym[256];
-    const uint32_t lane = threadIdx.x;
-    for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
-    __syncthreads();
-    const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
-    BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
-    uint16_t *lut = (uint16_t *)(ws + H.ws_lut + (uint64_t)blk * kLutBytes);
-    DecLeaves *LV = (DecLeaves *)((uint8_t *)lut + (1u << kLutK) * 2);
-    if (status[B.tile] != D_OK || B.byte_len == 0) {
-        if (lane == 0) { P.nseg = 0; P.err = 1; P.d = 1; }
-        continue;
-    }
-    const uint8_t *src = enc + B.byte_off;
-    const uint32_t blen = B.byte_len;
-    // stage the first 512 bytes (the largest header is ~400 bytes)
-    for (uint32_t i = lane; i < 128; i += 64) {
-        uint32_t x = 0;
-        for (int k = 0; k < 4; k++) x = (x << 8) | rd_byte(src, blen, 4 * i + k);
-        hw[i] = x;
-    }
-    if (lane < 4) hw[128 + lane] = 0;
-    __syncthreads();
-    const uint32_t p = B.p, n = (uint32_t)B.wb * B.hb / 8;
-    if (lane == 0) {
-        const uint64_t lim = (uint64_t)(blen < 512 ? blen : 512) * 8;
-        LdsBits r;
-        r.w = hw; r.nwords = 130;
-        r.seek(0);
-        int32_t err = 0;
-        uint32_t d = r.get(5);
-        uint32_t masks[3] = {0, 0, 0};
-        if (d >= 1 && d <= B.dmax)
-            for (uint32_t t = 0; t < p; t++) masks[t] = r.get(d);
-        else err = D_CORRUPT;
-        uint32_t nseg = 0;
-        if (!err) {
-            for (int b = (int)d - 1; b >= 0; b--) {
-                uint32_t pm = 0;
-                for (uint32_t t = 0; t < p; t++) pm |= (((masks[t] >> b) & 1u) ^ 1u) << t;
-                if (pm) {
-                    P.seg_plane[nseg] = (uint8_t)b;
-                    P.seg_M[nseg] = n * __popc(pm);
-                    nseg++;
-                }
-            }
-        }
-        uint32_t czr = 0, wz = 0, m = 0, single = 0;
-        if (!err && nseg) {
-            czr = r.get(8);
-            wz = r.get(4);
-            uint32_t beta = bitlen32(p * n - 1), wzhi = beta > 2 ? beta : 2;
-            if (wz < 2 || wz > wzhi) err = D_CORRUPT;
-            // pre-order tree: a node is 0 (internal) or 1 + 8-bit symbol (leaf).
-            // Walk with the left-aligned code A and depth of the current node;
-            // after a leaf the next node is at A + 2^(32-depth), depth 32 - ctz.
-            uint64_t A = 0;
-            uint32_t depth = 0, nodes = 0;
-            uint32_t seen[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            while (!err) {
-                if (++nodes > 511 || r.pos + 1 > lim) { err = D_CORRUPT; break; }
-                uint32_t peek = r.get(1);
-                if (!peek) {
-                    if (depth >= 32) { err = D_CORRUPT; break; }
-                    depth++;
-                    continue;
-                }
-                if (r.pos + 8 > lim) { err = D_CORRUPT; break; }
-                uint32_t sym = r.get(8);
-                if ((seen[sym >> 5] >> (sym & 31)) & 1u) { err = D_CORRUPT; break; }
-                seen[sym >> 5] |= 1u << (sym & 31);
-                s_acode[m] = (uint32_t)A;
-                s_len[m] = (uint8_t)depth;
-                s_sym[m] = (uint8_t)sym;
-                m++;
-                if (depth == 0) break;  // a lone leaf is the whole tree
-                A += 1ull << (32 - depth);
-                if (A >= (1ull << 32)) break;  // the rightmost leaf closes the tree
-                depth = 32 - (uint32_t)__builtin_ctzll(A);
-            }
-            single = (m == 1);
-            const uint32_t tb = bitlen32(p * n) - 1 + 5;
-            uint64_t acc = 0;
-            for (uint32_t s = 0; s < nseg && !err; s++) {
-                if (r.pos + tb > lim) { err = D_TRUNC; break; }
-                P.seg_bits[s] = r.get(tb);
-                acc += P.seg_bits[s];
-            }
-            if (!err) {
-                uint64_t start = (uint64_t)B.byte_off * 8 + r.pos;
-                if (r.pos + acc > (uint64_t)blen * 8) err = D_TRUNC;
-                for (uint32_t s = 0; s < nseg; s++) {
-                    P.seg_bitpos[s] = start;
-                    start += P.seg_bits[s];
-                }
-            }
-        } else if (!err && r.pos > (uint64_t)blen * 8) {
-            err = D_TRUNC;
-        }
-        P.d = d; P.nseg = err ? 0 : nseg; P.czr = czr; P.wz = wz; P.m = m; P.p = p; P.n = n;
-        for (uint32_t t = 0; t < 3; t++) P.masks[t] = masks[t];
-        P.err = err ? 1 : 0;
-        s_info[0] = err ? 0 : nseg;
-        s_info[1] = m;
-        s_info[2] = single;
-        if (err) atomicMin(&status[B.tile], err);
-    }
-    __syncthreads();
-    const uint32_t nseg = s_info[0], m = s_info[1];
-    if (!nseg) continue;
-    for (uint32_t j = lane; j < m; j += 64) {
-        LV->acode[j] = s_acode[j];
-        LV->len[j] = s_len[j];
-        LV->sym[j] = s_sym[j];
-    }
-    if (lane == 0) { LV->m = m; LV->single = s_info[2]; }
-    // prefix table: entry e belongs to the last leaf whose left-aligned code
-    // is <= e << (32 - K); sym | len << 8, or kLutLong for codes longer than K
-    const uint32_t per = (1u << kLutK) / 64;
-    uint32_t e0 = lane * per;
-    uint32_t lo = 0, hi = m;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (s_acode[mid] <= (e0 << (32 - kLutK))) lo = mid; else hi = mid;
-    }
-    uint32_t j = lo;
-    for (uint32_t e = e0; e < e0 + per; e++) {
-        uint32_t key = e << (32 - kLutK);
-        while (j + 1 < m && s_acode[j + 1] <= key) j++;
-        uint32_t L = s_len[j];
-        lut[e] = (L <= (uint32_t)kLutK) ? (uint16_t)(s_sym[j] | (L << 8)) : kLutLong;
-    }
-    }
-}
-
 // ------------------------------------------------------------------ segments
-// Window over the stream (MSB-first), loads bounded to [lo, hi) bytes.
-struct BitWin {
+// Window over the stream (MSB-first): `buf` holds nb >= 33 valid bits of the
+// stream from the current position, `pre` the next 32-bit word; loads are
+// bounded to [lo, hi) bytes.
+struct BitRd {
     const uint8_t *base;
     uint64_t lo, hi;
-    uint64_t wpos;  // bit position of win's MSB (multiple of 32)
-    uint64_t win;
-    uint32_t nxt;
+    uint64_t buf;
+    uint32_t nb;
+    uint64_t nextw;
+    uint32_t pre;
     __device__ inline uint32_t load(uint64_t wi) const
     {
         uint64_t b = wi * 4;
@@ -309,19 +171,24 @@ struct BitWin {
     }
     __device__ inline void seek(uint64_t pos)
     {
-        wpos = pos & ~31ull;
-        uint64_t wi = wpos >> 5;
-        win = ((uint64_t)load(wi) << 32) | load(wi + 1);
-        nxt = load(wi + 2);
+        uint64_t w = pos >> 5;
+        uint32_t o = (uint32_t)(pos & 31);
+        buf = (((uint64_t)load(w) << 32) | load(w + 1)) << o;
+        nb = 64 - o;
+        nextw = w + 2;
+        pre = load(nextw);
     }
-    __device__ inline uint32_t peek(uint64_t pos)
+    __device__ inline uint32_t peek() const { return (uint32_t)(buf >> 32); }
+    __device__ inline void skip(uint32_t k)  // k <= 32
     {
-        while (pos - wpos >= 32) {
-            win = (win << 32) | nxt;
-            wpos += 32;
-            nxt = load((wpos >> 5) + 2);
+        buf <<= k;
+        nb -= k;
+        if (nb < 32) {
+            buf |= (uint64_t)pre << (32 - nb);
+            nb += 32;
+            nextw++;
+            pre = load(nextw);
         }
-        return (uint32_t)((win << (pos - wpos)) >> 32);
     }
 };
 
@@ -360,14 +227,14 @@ struct SegCtx {
     uint32_t m, czr, wz, single;
 };
 
-// One token at bit `pos`: returns the symbol, advances pos; *cnt = counter
-// (valid when the symbol is C_zr).
-__device__ inline uint32_t next_token(const SegCtx &C, BitWin &R, uint64_t &pos, uint32_t *cnt)
+// One token at the reader's position: returns the symbol, advances pos;
+// *cnt = counter (valid when the symbol is C_zr).
+__device__ inline uint32_t next_token(const SegCtx &C, BitRd &R, uint64_t &pos, uint32_t *cnt)
 {
     uint32_t v, L;
     if (C.single) { v = C.lsym[0]; L = 0; }
     else {
-        uint32_t pk = R.peek(pos);
+        uint32_t pk = R.peek();
         uint16_t e = C.lut[pk >> (32 - kLutK)];
         if (!(e & kLutLong)) { v = e & 0xffu; L = (e >> 8) & 0x3fu; }
         else {
@@ -376,76 +243,207 @@ __device__ inline uint32_t next_token(const SegCtx &C, BitWin &R, uint64_t &pos,
             v = C.lsym[lo]; L = C.llen[lo];
         }
     }
+    R.skip(L);
     pos += L;
     *cnt = 0;
     if (v == C.czr) {
-        *cnt = R.peek(pos) >> (32 - C.wz);
+        *cnt = R.peek() >> (32 - C.wz);
+        R.skip(C.wz);
         pos += C.wz;
     }
     return v;
 }
 
 constexpr int kSyncBits = 128;  // token starts remembered per chunk (re-sync window)
+constexpr int kDecWaves = 8;
+constexpr uint32_t kMaxSeg = 3 * 128 * 128 / 8;  // symbols in the largest segment
 
-// Segments of one block: one wave per segment, the segment's bits split into
-// 64 chunks.  Phase 1: every lane decodes its chunk from the chunk start
-// (speculatively, for lanes > 0) and remembers its token starts in the first
-// kSyncBits bits.  Phase 2: a lane whose start differs from its left
-// neighbour's exit re-decodes from that exit until it reaches a remembered
-// token start (then its old exit stands) or its chunk end; repeated until no
-// lane changes (Huffman codes resynchronise within a few tokens).  Phase 3:
-// per-chunk run maps, a wave scan gives each lane its output position and
-// pending run.  Phase 4: decode again and write the non-zero symbols (the
-// plane was zeroed first, so runs write nothing).
-__global__ void __launch_bounds__(256) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
-                                                      uint8_t *__restrict__ ws,
-                                                      int32_t *__restrict__ status)
+struct DecShared {
+    uint32_t hw[132];          // first 512 bytes of the block (header), big-endian words
+    uint16_t lut[1 << kLutK];
+    uint32_t acode[256];
+    uint8_t llen[256], lsym[256];
+    uint32_t vis[kDecWaves][64][kSyncBits / 32];
+    uint32_t nseg, czr, wz, m, err;
+    uint8_t seg_plane[32];
+    uint32_t seg_M[32], seg_bits[32];
+    uint64_t seg_bitpos[32];
+};
+
+// Block header (Fig. 3 layout as read): d, masks, C_zr, wz, pre-order code
+// tree, seek table.  Lane 0 only.  Fills S and the block plan's d/masks/
+// segments (used by the reassembly).
+__device__ void parse_header(const BlockDesc &B, BlkPlan &P, DecShared &S)
 {
-    __shared__ uint16_t lut[1 << kLutK];
-    __shared__ uint32_t acode[256];
-    __shared__ uint8_t llen[256], lsym[256];
-    __shared__ uint32_t vis[4][64][kSyncBits / 32];
+    const uint32_t p = B.p, n = (uint32_t)B.wb * B.hb / 8;
+    const uint32_t blen = B.byte_len;
+    const uint64_t lim = (uint64_t)(blen < 512 ? blen : 512) * 8;
+    LdsBits r;
+    r.w = S.hw; r.nwords = 130;
+    r.seek(0);
+    int32_t err = 0;
+    uint32_t d = r.get(5);
+    uint32_t masks[3] = {0, 0, 0};
+    if (d >= 1 && d <= B.dmax)
+        for (uint32_t t = 0; t < p; t++) masks[t] = r.get(d);
+    else err = D_CORRUPT;
+    uint32_t nseg = 0;
+    if (!err) {
+        for (int b = (int)d - 1; b >= 0; b--) {
+            uint32_t pm = 0;
+            for (uint32_t t = 0; t < p; t++) pm |= (((masks[t] >> b) & 1u) ^ 1u) << t;
+            if (pm) {
+                S.seg_plane[nseg] = (uint8_t)b;
+                S.seg_M[nseg] = n * __popc(pm);
+                nseg++;
+            }
+        }
+    }
+    uint32_t czr = 0, wz = 0, m = 0;
+    if (!err && nseg) {
+        czr = r.get(8);
+        wz = r.get(4);
+        uint32_t beta = bitlen32(p * n - 1), wzhi = beta > 2 ? beta : 2;
+        if (wz < 2 || wz > wzhi) err = D_CORRUPT;
+        // pre-order tree: 0 = internal, 1 + 8-bit symbol = leaf.  Walk with
+        // the left-aligned code A and depth of the current node; after a leaf
+        // the next node is at A + 2^(32-depth), depth 32 - ctz.
+        uint64_t A = 0;
+        uint32_t depth = 0, nodes = 0;
+        uint32_t seen[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        while (!err) {
+            if (++nodes > 511 || r.pos + 1 > lim) { err = D_CORRUPT; break; }
+            if (!r.get(1)) {
+                if (depth >= 32) { err = D_CORRUPT; break; }
+                depth++;
+                continue;
+            }
+            if (r.pos + 8 > lim) { err = D_CORRUPT; break; }
+            uint32_t sym = r.get(8);
+            if ((seen[sym >> 5] >> (sym & 31)) & 1u) { err = D_CORRUPT; break; }
+            seen[sym >> 5] |= 1u << (sym & 31);
+            S.acode[m] = (uint32_t)A;
+            S.llen[m] = (uint8_t)depth;
+            S.lsym[m] = (uint8_t)sym;
+            m++;
+            if (depth == 0) break;  // a lone leaf is the whole tree
+            A += 1ull << (32 - depth);
+            if (A >= (1ull << 32)) break;  // the rightmost leaf closes the tree
+            depth = 32 - (uint32_t)__builtin_ctzll(A);
+        }
+        const uint32_t tb = bitlen32(p * n) - 1 + 5;
+        uint64_t acc = 0;
+        for (uint32_t s = 0; s < nseg && !err; s++) {
+            if (r.pos + tb > lim) { err = D_TRUNC; break; }
+            S.seg_bits[s] = r.get(tb);
+            acc += S.seg_bits[s];
+        }
+        if (!err) {
+            uint64_t start = (uint64_t)B.byte_off * 8 + r.pos;
+            if (r.pos + acc > (uint64_t)blen * 8) err = D_TRUNC;
+            for (uint32_t s = 0; s < nseg; s++) {
+                S.seg_bitpos[s] = start;
+                start += S.seg_bits[s];
+            }
+        }
+    } else if (!err && r.pos > (uint64_t)blen * 8) {
+        err = D_TRUNC;
+    }
+    S.nseg = err ? 0 : nseg; S.czr = czr; S.wz = wz; S.m = m; S.err = (uint32_t)err;
+    P.d = d; P.nseg = err ? 0 : nseg; P.p = p; P.n = n; P.err = err ? 1 : 0;
+    for (uint32_t t = 0; t < 3; t++) P.masks[t] = masks[t];
+    for (uint32_t s = 0; s < nseg && !err; s++) { P.seg_plane[s] = S.seg_plane[s]; P.seg_M[s] = S.seg_M[s]; }
+}
+
+// Entropy decode of a block: header, prefix table (4096 entries in LDS:
+// entry e belongs to the last leaf whose left-aligned code is <= e << 20),
+// then one wave per segment, the segment's bits split into 64 chunks.
+// Phase 1: every lane decodes its chunk from the chunk start (speculatively,
+// for lanes > 0) and remembers its token starts in the first kSyncBits bits.
+// Phase 2: a lane whose start differs from its left neighbour's exit
+// re-decodes from that exit until it reaches a remembered token start (then
+// its old exit stands) or its chunk end; repeated until no lane changes
+// (Huffman codes resynchronise within a few tokens).  Phase 3: per-chunk run
+// maps, a wave scan gives each lane its output position and pending run.
+// Phase 4: decode again and write the non-zero symbols (the plane was zeroed
+// first, so runs write nothing).
+__global__ void __launch_bounds__(64 * kDecWaves) k_dec_blocks(PlanHdr H, const uint8_t *__restrict__ enc,
+                                                               uint8_t *__restrict__ ws,
+                                                               int32_t *__restrict__ status)
+{
+    __shared__ DecShared S;
+    // per-wave staging of one segment's symbol plane (M <= 3 * 2048 bytes)
+    __shared__ uint4 stg[kDecWaves][kMaxSeg / 16];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
-    const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
-    const uint32_t nseg = P.nseg;
-    if (!nseg || status[B.tile] != D_OK) continue;
+    BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
+    const uint8_t *src = enc + B.byte_off;
+    const uint32_t blen = B.byte_len;
+    __syncthreads();  // the previous block is done with S
+    for (uint32_t i = tid; i < 128; i += blockDim.x) {
+        uint32_t x = 0;
+        for (int k = 0; k < 4; k++) x = (x << 8) | rd_byte(src, blen, 4 * i + k);
+        S.hw[i] = x;
+    }
+    if (tid < 4) S.hw[128 + tid] = 0;
     __syncthreads();
-    const uint16_t *glut = (const uint16_t *)(ws + H.ws_lut + (uint64_t)blk * kLutBytes);
-    const DecLeaves *LV = (const DecLeaves *)((const uint8_t *)glut + (1u << kLutK) * 2);
-    const uint32_t m = LV->m;
-    for (uint32_t i = tid; i < (1u << kLutK) / 2; i += blockDim.x)
-        ((uint32_t *)lut)[i] = ((const uint32_t *)glut)[i];
-    for (uint32_t j = tid; j < m; j += blockDim.x) { acode[j] = LV->acode[j]; llen[j] = LV->len[j]; lsym[j] = LV->sym[j]; }
-    const uint32_t pn = P.p * P.n;
-    // zero the kept planes (runs and literal zeros are then not written)
-    for (uint32_t s = 0; s < nseg; s++) {
-        uint8_t *dst = ws + B.sym_off + (uint64_t)P.seg_plane[s] * pn;
-        uint32_t M = P.seg_M[s];
-        if ((((uintptr_t)dst) & 3u) == 0) {
-            for (uint32_t i = tid; i < M / 4; i += blockDim.x) ((uint32_t *)dst)[i] = 0;
-            for (uint32_t i = (M / 4) * 4 + tid; i < M; i += blockDim.x) dst[i] = 0;
+    if (tid == 0) {
+        // the tile status is read once, so the whole workgroup takes the
+        // same branch below
+        if (status[B.tile] != D_OK || blen == 0) {
+            P.nseg = 0; P.err = 1; P.d = 1;
+            S.nseg = 0;
         } else {
-            for (uint32_t i = tid; i < M; i += blockDim.x) dst[i] = 0;
+            parse_header(B, P, S);
+            if (S.err) atomicMin(&status[B.tile], (int32_t)S.err);
+        }
+    }
+    __syncthreads();
+    const uint32_t nseg = S.nseg, m = S.m;
+    if (!nseg) continue;
+    {
+        const uint32_t per = (1u << kLutK) / (64 * kDecWaves);
+        const uint32_t e0 = tid * per;
+        uint32_t lo = 0, hi = m;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (S.acode[mid] <= (e0 << (32 - kLutK))) lo = mid; else hi = mid;
+        }
+        uint32_t j = lo;
+        for (uint32_t e = e0; e < e0 + per; e++) {
+            uint32_t key = e << (32 - kLutK);
+            while (j + 1 < m && S.acode[j + 1] <= key) j++;
+            uint32_t L = S.llen[j];
+            S.lut[e] = (L <= (uint32_t)kLutK) ? (uint16_t)(S.lsym[j] | (L << 8)) : kLutLong;
         }
     }
     __syncthreads();
     SegCtx C;
-    C.lut = lut; C.acode = acode; C.llen = llen; C.lsym = lsym; C.m = m;
-    C.czr = P.czr; C.wz = P.wz; C.single = (m == 1);
-    const uint32_t Bb = (1u << P.wz) - 1u;
-    BitWin R;
+    C.lut = S.lut; C.acode = S.acode; C.llen = S.llen; C.lsym = S.lsym; C.m = m;
+    C.czr = S.czr; C.wz = S.wz; C.single = (m == 1);
+    const uint32_t Bb = (1u << S.wz) - 1u;
+    const uint32_t pstride = plane_stride((uint32_t)B.p * B.wb * B.hb / 8);
+    BitRd R;
     R.base = enc; R.lo = B.byte_off; R.hi = B.byte_off + B.byte_len;
     int32_t err = 0;
-    for (uint32_t s = wave; s < nseg; s += 4) {
-        const uint32_t M = P.seg_M[s];
-        uint8_t *out = ws + B.sym_off + (uint64_t)P.seg_plane[s] * pn;
-        const uint64_t S0 = P.seg_bitpos[s], N = P.seg_bits[s], SE = S0 + N;
-        if (C.single && lsym[0] != C.czr) {
+    for (uint32_t s = wave; s < nseg; s += kDecWaves) {
+        const uint32_t M = S.seg_M[s];
+        if (M > kMaxSeg) { err = D_CORRUPT; continue; }  // not reachable for 128-grid blocks
+        uint4 *gout = (uint4 *)(ws + B.sym_off + (uint64_t)S.seg_plane[s] * pstride);
+        uint8_t *out = (uint8_t *)stg[wave];
+        const uint32_t M16 = (M + 15) / 16;
+        for (uint32_t i = lane; i < M16; i += 64) stg[wave][i] = make_uint4(0, 0, 0, 0);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t S0 = S.seg_bitpos[s], N = S.seg_bits[s], SE = S0 + N;
+        if (C.single && S.lsym[0] != C.czr) {
             // zero-length codewords: the segment is M copies of the leaf
             if (N != 0) err = D_CORRUPT;
-            else if (lsym[0]) for (uint32_t i = lane; i < M; i += 64) out[i] = lsym[0];
+            else if (S.lsym[0]) for (uint32_t i = lane; i < M; i += 64) out[i] = S.lsym[0];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t i = lane; i < M16; i += 64) gout[i] = stg[wave][i];
             continue;
         }
         uint64_t chunk = (N + 63) / 64;
@@ -455,7 +453,8 @@ __global__ void __launch_bounds__(256) k_dec_segments(PlanHdr H, const uint8_t *
         const bool active = cs < SE;
         const uint64_t ce = active ? (cs + chunk < SE ? cs + chunk : SE) : cs;
         // phase 1
-        uint32_t *mv = vis[wave][lane];
+        uint32_t *mv = S.vis[wave][lane];
+#pragma unroll
         for (int k = 0; k < kSyncBits / 32; k++) mv[k] = 0;
         uint64_t start = cs, exit1 = cs;
         if (active) {
@@ -482,10 +481,8 @@ __global__ void __launch_bounds__(256) k_dec_segments(PlanHdr H, const uint8_t *
                 bool synced = false;
                 if (pos < ce) R.seek(pos);
                 while (pos < ce) {
-                    if (pos >= cs) {
-                        uint64_t rel = pos - cs;
-                        if (rel < kSyncBits && ((mv[rel >> 5] >> (rel & 31)) & 1u)) { synced = true; break; }
-                    }
+                    uint64_t rel = pos - cs;
+                    if (rel < kSyncBits && ((mv[rel >> 5] >> (rel & 31)) & 1u)) { synced = true; break; }
                     uint32_t c;
                     next_token(C, R, pos, &c);
                 }
@@ -551,6 +548,11 @@ __global__ void __launch_bounds__(256) k_dec_segments(PlanHdr H, const uint8_t *
             }
         }
         if (N == 0 && lane == 0 && M != 0) err = D_CORRUPT;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = lane; i < M16; i += 64) gout[i] = stg[wave][i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     if (err) atomicMin(&status[B.tile], err);
     }
@@ -583,7 +585,7 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
             for (uint32_t u = 0; u < p; u++) pm |= (((P.masks[u] >> b) & 1u) ^ 1u) << u;
             if (!((pm >> t) & 1u)) continue;
             uint32_t rank = __popc(pm & ((1u << t) - 1u));
-            uint32_t v = *(const uint16_t *)(ws + B.sym_off + (uint64_t)b * p * n + rank * n + 2 * ci);
+            uint32_t v = *(const uint16_t *)(ws + B.sym_off + (uint64_t)b * plane_stride(p * n) + rank * n + 2 * ci);
             if (b == d - 1) sgn = v;
             else {
 #pragma unroll
@@ -623,12 +625,10 @@ hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
     for (int st = first; st <= last; st++) {
         if (st == DEC_PREP) {
             hipLaunchKernelGGL(k_dec_prep, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_encoded, d_ws, d_status);
-        } else if (st == DEC_HDR) {
-            if (H.total_blocks)
-                hipLaunchKernelGGL(k_dec_header, dim3(H.blk_grid), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
         } else if (st == DEC_SEG) {
             if (H.total_blocks)
-                hipLaunchKernelGGL(k_dec_segments, dim3(H.blk_grid), dim3(256), 0, stream, H, d_encoded, d_ws, d_status);
+                hipLaunchKernelGGL(k_dec_blocks, dim3(H.blk_grid), dim3(64 * kDecWaves), 0, stream, H, d_encoded, d_ws,
+                                   d_status);
         } else if (st == DEC_REASM) {
             if (H.total_blocks)
                 hipLaunchKernelGGL(k_dec_reasm, dim3(H.blk_grid), dim3(1024), 0, stream, H, d_plan, d_ws, d_status);

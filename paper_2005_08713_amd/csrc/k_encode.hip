@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(256) k_prep_blocks(PlanHdr H, const uint8_t *_
         uint64_t sz = 0;
         if (local < T.nblocks) {
             block_geometry(T, local, B);
-            sz = ((uint64_t)B.p * B.wb * B.hb / 8 * T.dmax + 15) & ~15ull;
+            sz = block_sym_bytes(B, T.dmax);
         }
         uint64_t tot;
         uint64_t ex = block_excl_sum_u64<256>(sz, sh, &tot);
@@ -127,7 +127,8 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
 {
     __shared__ uint32_t hist[256];
     __shared__ int32_t wsh[kSymNT / 64];
-    __shared__ uint32_t s_zir, s_dig[kNumWz], s_F[16], s_nruns, s_zero;
+    __shared__ uint32_t s_zir, s_dig[kNumWz], s_F[16], s_nruns, s_zero, s_pruns;
+    __shared__ __align__(16) uint16_t stg[kSymNT * kCellsPT];  // one plane's symbols (2 per cell)
     const uint32_t *list = (const uint32_t *)(plan + H.list_off) + list0;
     for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
     const uint32_t blk = list[li];
@@ -155,6 +156,7 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
     uint32_t sgn[kCellsPT];
     uint32_t ctype[kCellsPT], cci[kCellsPT];
     const uint32_t ncell = p * cpt;
+#pragma unroll
     for (int k = 0; k < kCellsPT; k++) {
         uint32_t cell = tid * kCellsPT + k;
         sgn[k] = 0;
@@ -168,12 +170,17 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
         cci[k] = ci;
         uint32_t band = ci / wq, cg = ci % wq;
         uint32_t r0 = 4 * band, c0 = 4 * cg;
-        const uint32_t tw = B.tw[t], th = B.th[t];
+        // per-type fields read through the global copy (a runtime index into a
+        // register copy would put the whole descriptor in scratch)
+        const BlockDesc &Bg = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+        const uint32_t tw = Bg.tw[t], th = Bg.th[t];
+        const uint64_t toff = Bg.off[t];
+        const uint32_t tpitch = Bg.pitch[t];
 #pragma unroll
         for (int rr = 0; rr < 4; rr++) {
             uint32_t row = r0 + rr;
             if (row >= th || c0 >= tw) continue;
-            const int32_t *src = wsi + B.off[t] + (uint64_t)row * B.pitch[t] + c0;
+            const int32_t *src = wsi + toff + (uint64_t)row * tpitch + c0;
             int32_t v[4];
             if (c0 + 3 < tw) {
                 int4 q = *(const int4 *)src;
@@ -194,7 +201,7 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
     for (uint32_t i = tid; i < 256; i += kSymNT) hist[i] = 0;
     if (tid < kNumWz) s_dig[tid] = 0;
     if (tid < 16) s_F[tid] = 0;
-    if (tid == 0) { s_zir = 0; s_nruns = 0; s_zero = 0; }
+    if (tid == 0) { s_zir = 0; s_nruns = 0; s_zero = 0; s_pruns = 0; }
     __syncthreads();
 
     uint32_t nseg = 0;
@@ -202,11 +209,12 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
         uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
         if (!pm) continue;
         uint32_t M = n * __popc(pm);
-        uint8_t *segp = ws + B.sym_off + (uint64_t)b * p * n;
+        uint8_t *segp = ws + B.sym_off + (uint64_t)b * plane_stride(p * n);
         // symbols of own cells
         uint32_t sy[kCellsPT], pos[kCellsPT];
         int32_t lastnz = -1;
         uint32_t zeros = 0;
+#pragma unroll
         for (int k = 0; k < kCellsPT; k++) {
             sy[k] = 0;
             pos[k] = 0xffffffffu;
@@ -222,7 +230,7 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
             uint32_t ps = rank * n + 2 * cci[k];
             pos[k] = ps;
             sy[k] = v;
-            *(uint16_t *)(segp + ps) = (uint16_t)v;
+            stg[ps >> 1] = (uint16_t)v;
             uint32_t top = v & 0xffu, bot = v >> 8;
             if (top) { atomicAdd(&hist[top], 1u); lastnz = (int32_t)ps; } else zeros++;
             if (bot) { atomicAdd(&hist[bot], 1u); lastnz = (int32_t)ps + 1; } else zeros++;
@@ -231,10 +239,14 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
         for (int o = 32; o >= 1; o >>= 1) zeros += __shfl_xor(zeros, o, 64);
         if ((tid & 63) == 0 && zeros) atomicAdd(&s_zero, zeros);
         int32_t prev = block_excl_max_i32<kSymNT>(lastnz, wsh);
-        // runs terminated inside this thread (by a non-zero symbol or the segment end)
+        // runs terminated inside this thread (by a non-zero symbol or the
+        // segment end); per-thread sums, then one atomic per wave
         int32_t cur = prev;
+        uint32_t rz = 0, rn = 0;
+#pragma unroll
         for (int k = 0; k < kCellsPT; k++) {
             if (pos[k] == 0xffffffffu) continue;
+#pragma unroll
             for (int h = 0; h < 2; h++) {
                 uint32_t s = h ? (sy[k] >> 8) : (sy[k] & 0xffu);
                 int32_t ps = (int32_t)pos[k] + h;
@@ -243,18 +255,29 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
                     int32_t L = s ? (ps - cur - 1) : (ps - cur);
                     if (L >= 2) {
                         atomicAdd(&s_F[bitlen32((uint32_t)L)], 1u);
-                        atomicAdd(&s_zir, (uint32_t)L);
-                        atomicAdd(&s_nruns, 1u);
-                        for (int i = 0; i < kNumWz; i++) {
-                            uint32_t Bb = (1u << (i + 2)) - 1u;
-                            atomicAdd(&s_dig[i], bij_digits((uint32_t)L, Bb));
-                        }
+                        rz += (uint32_t)L;
+                        rn++;
+                        // digits beyond the first, for the widths whose base 2^w-1 < L
+                        for (int i = 0; i < kNumWz && ((1u << (i + 2)) - 1u) < (uint32_t)L; i++)
+                            atomicAdd(&s_dig[i], bij_digits((uint32_t)L, (1u << (i + 2)) - 1u) - 1u);
                     }
                     if (s) cur = ps;
                 }
             }
         }
+        if (__any(rn)) {
+            for (int o = 32; o >= 1; o >>= 1) {
+                rz += __shfl_xor(rz, o, 64);
+                rn += __shfl_xor(rn, o, 64);
+            }
+            if ((tid & 63) == 0 && rn) {
+                atomicAdd(&s_zir, rz);
+                atomicAdd(&s_pruns, rn);
+            }
+        }
         __syncthreads();
+        // the plane's symbols, contiguous, as 16-byte stores
+        for (uint32_t i = tid; i < (M + 15) / 16; i += kSymNT) ((uint4 *)segp)[i] = ((const uint4 *)stg)[i];
         uint32_t slot = B.slot + (uint32_t)b;
         for (uint32_t i = tid; i < 256; i += kSymNT) {
             uint32_t hv = hist[i];
@@ -262,15 +285,16 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
             seghist[(uint64_t)slot * 256 + i] = (uint16_t)hv;
             hist[i] = 0;
         }
-        if (tid < kNumWz) { segstat[slot].dig[tid] = s_dig[tid]; }
+        if (tid < kNumWz) { segstat[slot].dig[tid] = s_dig[tid] + s_pruns; }
         if (tid == 0) {
             segstat[slot].zir = s_zir;
+            s_nruns += s_pruns;
             P.seg_plane[nseg] = (uint8_t)b;
             P.seg_M[nseg] = M;
         }
         __syncthreads();
         if (tid < kNumWz) s_dig[tid] = 0;
-        if (tid == 0) { s_zir = 0; s_zero = 0; }
+        if (tid == 0) { s_zir = 0; s_zero = 0; s_pruns = 0; }
         nseg++;
         __syncthreads();
     }
@@ -702,30 +726,30 @@ __device__ inline void flush_bits(const uint32_t *st, uint64_t abs_bit, uint32_t
     }
 }
 
-__global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__restrict__ ws_c,
-                                                  uint8_t *__restrict__ out)
+struct PackShared {
+    uint32_t st[kStageWords];
+    uint32_t s_code[256];
+    uint8_t s_len[256];
+    uint64_t sh[4];
+    int32_t shi[4];
+};
+
+// Pack one item: y = 0 the block header, y = 1.. segment y-1.
+__device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__restrict__ ws,
+                                          uint8_t *__restrict__ out, PackShared &S, uint32_t blk,
+                                          uint32_t y)
 {
-    __shared__ uint32_t st[kStageWords];
-    __shared__ uint32_t s_code[256];
-    __shared__ uint8_t s_len[256];
-    __shared__ uint64_t sh[4];
-    __shared__ int32_t shi[4];
-    const uint8_t *ws = ws_c;
+    uint32_t *st = S.st, *s_code = S.s_code;
+    uint8_t *s_len = S.s_len;
+    uint64_t *sh = S.sh;
+    int32_t *shi = S.shi;
     const uint32_t tid = threadIdx.x;
-    // non-persistent: grid (blocks, 33) with y = 0 the header and y = 1.. the
-    // segments; persistent: a 1-D grid looping over segment-major items
-    const bool pers = gridDim.y == 1;
-    const uint64_t nitems = pers ? (uint64_t)H.total_blocks * 33 : 1;
-    for (uint64_t item = pers ? blockIdx.x : 0; item < nitems; item += pers ? gridDim.x : 1) {
-    const uint32_t blk = pers ? (uint32_t)(item % H.total_blocks) : blockIdx.x;
-    const uint32_t y = pers ? (uint32_t)(item / H.total_blocks) : blockIdx.y;
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
     const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[B.tile];
-    if (O.status != ISX_STATUS_OK) continue;
+    if (O.status != ISX_STATUS_OK) return;
     const uint32_t nseg = P.nseg;
-    if (y > nseg) continue;
-    __syncthreads();
+    if (y > nseg) return;
     uint32_t *outw = (uint32_t *)out;
     const uint64_t bit0 = (O.offset + P.byte_off) * 8;
     if (y == 0) {
@@ -765,7 +789,7 @@ __global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__re
         }
         __syncthreads();
         flush_bits(st, bit0, nbits, outw);
-        continue;
+        return;
     }
     // segment y-1: tokens of the plane's symbols
     const uint32_t s = y - 1;
@@ -780,7 +804,7 @@ __global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__re
     s_len[tid] = P.len[tid];
     __syncthreads();
     const uint32_t M = P.seg_M[s];
-    const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * P.p * P.n;
+    const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride(P.p * P.n);
     const uint32_t czr = P.czr, wz = P.wz, Bb = (1u << wz) - 1u;
     const uint32_t lz = s_len[czr];
     const uint32_t chunk = (M + 255) / 256;
@@ -844,8 +868,31 @@ __global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__re
     }
     __syncthreads();
     flush_bits(st, abit, nbits, outw);
+}
+
+__global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__restrict__ ws,
+                                                  uint8_t *__restrict__ out)
+{
+    __shared__ PackShared S;
+    pack_item(H, ws, out, S, blockIdx.x, blockIdx.y);
+}
+
+// Persistent variant: segment-major items over a fixed grid.
+__global__ void __launch_bounds__(256) k_enc_pack_pers(PlanHdr H, const uint8_t *__restrict__ ws,
+                                                       uint8_t *__restrict__ out)
+{
+    __shared__ PackShared S;
+    const uint64_t nitems = (uint64_t)H.total_blocks * 33;
+    for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const uint32_t blk = (uint32_t)(item % H.total_blocks), y = (uint32_t)(item / H.total_blocks);
+        const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
+        if (y > P.nseg) continue;
+        __syncthreads();
+        pack_item(H, ws, out, S, blk, y);
     }
 }
+
+
 
 // ---------------------------------------------------------------- launch
 hipError_t launch_forward_level(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
@@ -891,8 +938,12 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             hipLaunchKernelGGL(k_enc_tile_finish, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws, d_out);
         } else if (st == ENC_PACK) {
             if (H.total_blocks)
-                hipLaunchKernelGGL(k_enc_pack, H.blocks_per_cu ? dim3(H.blk_grid) : dim3(H.total_blocks, 33), dim3(256), 0,
-                                   stream, H, d_ws, d_out);
+            {
+                if (H.blocks_per_cu)
+                    hipLaunchKernelGGL(k_enc_pack_pers, dim3(H.blk_grid), dim3(256), 0, stream, H, d_ws, d_out);
+                else
+                    hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, 33), dim3(256), 0, stream, H, d_ws, d_out);
+            }
         }
     }
     return hipGetLastError();

@@ -396,7 +396,15 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
     if (fused) fill_maps<TQ>(rmap, cmap, qx0, qy0, ow, oh);
     const int tx = (threadIdx.x % TPR) * 4, ty = threadIdx.x / TPR;
     int32_t v[3][NR][4];
-    for (int k = 0; k < nc; k++) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        if (k >= nc) {
+#pragma unroll
+            for (int rr = 0; rr < NR; rr++)
+#pragma unroll
+                for (int xx = 0; xx < 4; xx++) v[k][rr][xx] = 0;
+            continue;
+        }
         __syncthreads();
         if (fused) {
             stage_inverse<TQ>(T, z + 1, c0 + k, rmap, cmap, wsi, win);
@@ -417,6 +425,49 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
     }
     const int32_t top = (1 << T.bits) - 1;
     const uint32_t C = T.channels, bps = T.bps;
+    // RGB u8 rows whose start is 4-byte aligned: stage each output row in LDS
+    // (the window is free now) and store whole dwords, contiguous per row
+    const uint64_t rowbase0 = T.pix_offset + (uint64_t)(2 * qx0) * 3;
+    const bool staged = bps == 1 && C == 3 && ((rowbase0 | T.pix_stride) & 3u) == 0 &&
+                        (((uintptr_t)pix) & 3u) == 0;
+    if (staged) {
+        __syncthreads();
+        uint8_t *ob = (uint8_t *)win;  // T2 rows x (T2 * 3) bytes
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            int ly = ty + RSTEP * rr;
+#pragma unroll
+            for (int xx = 0; xx < 4; xx++) {
+                int32_t o0, o1, o2;
+                if (T.ct == 1) {
+                    int32_t Y = v[0][rr][xx], cb = v[1][rr][xx], cr = v[2][rr][xx];
+                    int32_t g = Y - ((cb + cr) >> 2);
+                    o0 = cr + g; o1 = g; o2 = cb + g;
+                } else {
+                    o0 = v[0][rr][xx]; o1 = v[1][rr][xx]; o2 = v[2][rr][xx];
+                }
+                o0 = o0 < 0 ? 0 : (o0 > top ? top : o0);
+                o1 = o1 < 0 ? 0 : (o1 > top ? top : o1);
+                o2 = o2 < 0 ? 0 : (o2 > top ? top : o2);
+                uint8_t *q = ob + ly * (T2 * 3) + (tx + xx) * 3;
+                q[0] = (uint8_t)o0; q[1] = (uint8_t)o1; q[2] = (uint8_t)o2;
+            }
+        }
+        __syncthreads();
+        const int nx = min(T2, ow - 2 * qx0);  // valid pixels in the row
+        const int nbytes = nx * 3;
+        const int ndw = nbytes / 4;
+        for (int i = threadIdx.x; i < T2 * (T2 * 3 / 4); i += blockDim.x) {
+            int ly = i / (T2 * 3 / 4), k = i % (T2 * 3 / 4);
+            int y = 2 * qy0 + ly;
+            if (y >= oh) continue;
+            uint8_t *row = pix + rowbase0 + (uint64_t)y * T.pix_stride;
+            const uint8_t *src = ob + ly * (T2 * 3);
+            if (k < ndw) ((uint32_t *)row)[k] = ((const uint32_t *)src)[k];
+            else if (k == ndw) for (int b = 4 * ndw; b < nbytes; b++) row[b] = src[b];
+        }
+        return;
+    }
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) {
         int y = 2 * qy0 + ty + RSTEP * rr;
@@ -430,8 +481,10 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
                 int32_t g = Y - ((cb + cr) >> 2);
                 o[0][xx] = cr + g; o[1][xx] = g; o[2][xx] = cb + g;
             } else {
+#pragma unroll
                 for (int k = 0; k < 3; k++) o[k][xx] = v[k][rr][xx];
             }
+#pragma unroll
             for (int k = 0; k < 3; k++) o[k][xx] = o[k][xx] < 0 ? 0 : (o[k][xx] > top ? top : o[k][xx]);
         }
         uint8_t *row = pix + T.pix_offset + (uint64_t)y * T.pix_stride;
@@ -444,7 +497,9 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
             for (int xx = 0; xx < 4; xx++) {
                 int x = x0 + xx;
                 if (x >= ow) break;
-                for (int k = 0; k < nc; k++) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    if (k >= nc) break;
                     uint32_t e = ((uint32_t)x * C + c0 + k) * bps;
                     row[e] = (uint8_t)(o[k][xx] & 0xff);
                     if (bps == 2) row[e + 1] = (uint8_t)(o[k][xx] >> 8);
