@@ -188,7 +188,7 @@ def main():
     symbols = {q: stream_symbol_count(streams[q]) for q, enc, dec in pairs}
     sym_avg = float(np.mean(list(symbols.values())))
     alg = {
-        ("dec", "dec_entropy"): s_avg + sym_avg,
+        ("dec", "dec_segments"): s_avg + sym_avg,
         ("enc", "enc_symbols"): raw * 4 + sym_avg,
         ("enc", "enc_pack"): sym_avg + s_avg,
         ("enc", "forward_l1"): raw + raw * 4,

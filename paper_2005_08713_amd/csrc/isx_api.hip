@@ -198,6 +198,7 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         if (T.levels > H.max_levels) H.max_levels = T.levels;
         if (T.nblocks > H.max_nblocks) H.max_nblocks = T.nblocks;
     }
+    if (mode == MODE_DECODE && total_blocks >= (1ull << 27)) return ISX_E_UNSUPPORTED;  // segment item = block << 5 | segment
     H.total_blocks = (uint32_t)total_blocks;
     H.total_slots = (uint32_t)total_slots;
     H.blk_grid = H.total_blocks;
@@ -214,6 +215,10 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     if (mode == MODE_ENCODE) {
         H.ws_seghist = o; o = al(o + total_slots * 256 * sizeof(uint16_t));
         H.ws_segstat = o; o = al(o + total_slots * sizeof(SegStat));
+    }
+    if (mode == MODE_DECODE) {
+        H.ws_lut = o; o = al(o + total_blocks * kLutStride);
+        H.ws_items = o; o = al(o + 64 + 2 * total_blocks * 32 * sizeof(uint32_t));
     }
     H.ws_tileout = o; o = al(o + (uint64_t)n * sizeof(TileOut));
     for (int32_t i = 0; i < n; i++) {
@@ -515,7 +520,8 @@ const char *isx_stage_name(int32_t mode, int32_t stage)
         if (stage == ENC_PACK) return "enc_pack";
     } else if (mode == 1) {
         if (stage == DEC_PREP) return "dec_prep";
-        if (stage == DEC_SEG) return "dec_entropy";
+        if (stage == DEC_HDR) return "dec_header";
+        if (stage == DEC_SEG) return "dec_segments";
         if (stage == DEC_REASM) return "dec_reassemble";
         if (stage >= DEC_INV15 && stage <= DEC_FINAL) return inv[DEC_FINAL - stage];
     }

@@ -69,7 +69,7 @@ struct PlanHdr {
     uint64_t ws_bytes;
     // workspace regions (byte offsets from ws base)
     uint64_t ws_blockdesc, ws_acc, ws_seghist, ws_segstat, ws_blkstat, ws_blkplan, ws_tileout,
-        ws_misc;
+        ws_lut, ws_items;
     // plan regions (byte offsets from plan base)
     uint64_t tiles_off, work_off;
     uint32_t lvl_first[kMaxLevels + 2];  // per level: first WorkItem index
@@ -138,7 +138,15 @@ struct BlkPlan {
     uint64_t seg_bitpos[32];  // decode: absolute bit position of each segment
 };
 
-constexpr int kLutK = 12;          // decode prefix table (LDS): 2^12 entries of uint16
+// decode code tables, per block: prefix table of 2^kLutK uint16 entries, then
+// the left-aligned codes (uint32[256]), lengths and symbols (uint8[256] each)
+constexpr int kLutK = 11;
+constexpr uint32_t kLutBytes16 = (1u << kLutK) * 2;
+constexpr uint32_t kLutStride = kLutBytes16 + 1024 + 256 + 256;
+constexpr uint32_t kMaxSeg = 3 * 128 * 128 / 8;  // symbols in the largest segment
+constexpr uint32_t kSegWords = 2048;             // segment bits staged in LDS (larger: read from HBM)
+constexpr uint32_t kBigSegBits = 16384;          // queue class of a segment
+constexpr uint32_t kSegWavesPerCu = 8;
 struct TileOut {
     uint64_t size;
     uint64_t offset;
@@ -231,7 +239,8 @@ enum EncStage {
 };
 enum DecStage {
     DEC_PREP = 0,
-    DEC_SEG,   // block headers + code tables + segments (one kernel)
+    DEC_HDR,
+    DEC_SEG,
     DEC_REASM,
     DEC_INV15,                     // inverse of level 15 .. level 2 (intermediate outputs)
     DEC_FINAL = DEC_INV15 + kMaxLevels,  // inverse of level z+1 fused with the output stage

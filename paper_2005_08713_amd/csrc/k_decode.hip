@@ -5,12 +5,14 @@
 //  k_dec_prep      per job: tile header and block-size table checks, block
 //                  descriptors and byte offsets (scan) of the blocks needed
 //                  for the target level.
-//  k_dec_header    per block: d, masks, C_zr, wz, recursive code tree (Fig. 3:
-//                  0 = internal node, 1 + 8 bits = leaf), seek table; builds a
-//                  4096-entry prefix table plus the sorted left-aligned codes
-//                  (any valid tree is accepted, not only canonical ones).
-//  k_dec_segments  per segment: tokens -> symbols (runs of zeros from the
-//                  bijective-base counters, a literal C_zr from a zero counter).
+//  k_dec_header    per block (one wave, scalar parse): d, masks, C_zr, wz,
+//                  recursive code tree (Fig. 3: 0 = internal node, 1 + 8 bits
+//                  = leaf), seek table; builds the prefix table plus the
+//                  sorted left-aligned codes (any valid tree is accepted, not
+//                  only canonical ones) and queues one item per segment.
+//  k_dec_segments  per segment (persistent waves over the queue): tokens ->
+//                  symbols (runs of zeros from the bijective-base counters, a
+//                  literal C_zr from a zero counter).
 //  k_dec_reasm     per block: symbols -> signed-magnitude bits -> integers ->
 //                  dequantised coefficients in the band arrays.
 // Every read of the stream is bounded by the job's input region; an error
@@ -63,6 +65,7 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
     BlockDesc *descs = (BlockDesc *)(ws + H.ws_blockdesc);
     const uint8_t *base = enc + T.enc_offset;
     const uint64_t avail = T.enc_bytes;
+    if (job == 0 && threadIdx.x < 16) ((uint32_t *)(ws + H.ws_items))[threadIdx.x] = 0;  // segment queue
     if (threadIdx.x == 0) {
         int32_t st = D_OK;
         if (avail < 24) st = D_TRUNC;
@@ -125,78 +128,325 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
 }
 
 // ------------------------------------------------------------------ header
-// Bits of the block header staged in LDS, read through a 64-bit window.
-struct LdsBits {
-    const uint32_t *w;  // big-endian words
-    uint32_t nwords;
-    uint64_t pos;       // next bit
-    uint64_t win;       // bits [wpos, wpos + 64)
-    uint64_t wpos;
-    __device__ inline uint32_t word(uint64_t i) const { return i < nwords ? w[i] : 0u; }
-    __device__ inline void seek(uint64_t p)
-    {
-        pos = p;
-        wpos = p & ~31ull;
-        win = ((uint64_t)word(wpos >> 5) << 32) | word((wpos >> 5) + 1);
-    }
-    __device__ inline uint32_t get(uint32_t n)  // n <= 32
-    {
-        if (!n) return 0;
-        while (pos - wpos > 32) { wpos += 32; win = (win << 32) | word((wpos >> 5) + 1); }
-        uint32_t off = (uint32_t)(pos - wpos);
-        uint64_t v = (win << off) >> (64 - n);
-        pos += n;
-        return (uint32_t)v;
-    }
-};
-
-// ------------------------------------------------------------------ segments
-// Window over the stream (MSB-first): `buf` holds nb >= 33 valid bits of the
-// stream from the current position, `pre` the next 32-bit word; loads are
-// bounded to [lo, hi) bytes.
-struct BitRd {
-    const uint8_t *base;
-    uint64_t lo, hi;
+// Wave-uniform reader of the staged header words (big-endian, in LDS): every
+// value goes through readfirstlane, so the whole parse runs on the scalar
+// unit.  `buf` holds `avail` >= 32 valid bits, left-aligned.
+struct UBits {
+    const uint32_t *w;
+    uint32_t nw;
     uint64_t buf;
-    uint32_t nb;
-    uint64_t nextw;
-    uint32_t pre;
-    __device__ inline uint32_t load(uint64_t wi) const
+    uint32_t avail, nx, pos;
+    __device__ inline uint32_t fetch(uint32_t i) const
     {
-        uint64_t b = wi * 4;
-        if (b >= lo && b + 4 <= hi) return __builtin_bswap32(*(const uint32_t *)(base + b));
-        uint32_t x = 0;
-        for (int k = 0; k < 4; k++) x = (x << 8) | ((b + k >= lo && b + k < hi) ? base[b + k] : 0u);
-        return x;
+        return __builtin_amdgcn_readfirstlane(i < nw ? w[i] : 0u);
     }
-    __device__ inline void seek(uint64_t pos)
+    __device__ inline void init(const uint32_t *words, uint32_t n)
     {
-        uint64_t w = pos >> 5;
-        uint32_t o = (uint32_t)(pos & 31);
-        buf = (((uint64_t)load(w) << 32) | load(w + 1)) << o;
-        nb = 64 - o;
-        nextw = w + 2;
-        pre = load(nextw);
+        w = words; nw = n;
+        buf = ((uint64_t)fetch(0) << 32) | fetch(1);
+        avail = 64; nx = 2; pos = 0;
     }
     __device__ inline uint32_t peek() const { return (uint32_t)(buf >> 32); }
     __device__ inline void skip(uint32_t k)  // k <= 32
     {
         buf <<= k;
-        nb -= k;
-        if (nb < 32) {
-            buf |= (uint64_t)pre << (32 - nb);
-            nb += 32;
-            nextw++;
-            pre = load(nextw);
+        avail -= k;
+        pos += k;
+        if (avail <= 32) {
+            buf |= (uint64_t)fetch(nx++) << (32 - avail);
+            avail += 32;
         }
+    }
+    __device__ inline uint32_t get(uint32_t k)  // k <= 32
+    {
+        uint32_t v = k ? peek() >> (32 - k) : 0u;
+        skip(k);
+        return v;
     }
 };
 
+// Per block, one wave: header (layout of Fig. 3 as read: d, masks, C_zr, wz,
+// pre-order code tree with 0 = internal node and 1 + 8 bits = leaf, seek
+// table), then the prefix table and sorted left-aligned codes of the tree
+// (any valid tree is accepted, not only canonical ones), then one work item
+// per kept segment, appended to the large- or small-segment list.
+__global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__restrict__ enc,
+                                                   uint8_t *__restrict__ ws,
+                                                   int32_t *__restrict__ status)
+{
+    __shared__ uint32_t hw[132];
+    __shared__ uint32_t s_acode[256];
+    __shared__ uint8_t s_len[256], s_sym[256];
+    __shared__ uint32_t s_bits[32], s_M[32];
+    __shared__ uint64_t s_pos[32];
+    __shared__ uint8_t s_plane[32];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t blk = blockIdx.x;
+    const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+    BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
+    const uint32_t blen = B.byte_len;
+    const int32_t tst = __builtin_amdgcn_readfirstlane(status[B.tile]);
+    if (tst != D_OK || blen == 0) {
+        if (lane == 0) { P.nseg = 0; P.err = 1; P.d = 1; }
+        return;
+    }
+    const uint8_t *src = enc + B.byte_off;
+    // the first 512 bytes hold any header (<= ~400 bytes)
+    for (uint32_t i = lane; i < 128; i += 64) {
+        uint32_t x = 0;
+        for (int k = 0; k < 4; k++) x = (x << 8) | rd_byte(src, blen, 4 * i + k);
+        hw[i] = x;
+    }
+    if (lane < 4) hw[128 + lane] = 0;
+    __syncthreads();
+    const uint32_t p = B.p, n = (uint32_t)B.wb * B.hb / 8;
+    const uint32_t lim = (blen < 512 ? blen : 512) * 8;
+    UBits r;
+    r.init(hw, 130);
+    int32_t err = 0;
+    const uint32_t d = r.get(5);
+    uint32_t masks[3] = {0, 0, 0};
+    if (d >= 1 && d <= B.dmax) {
+        for (uint32_t t = 0; t < p; t++) masks[t] = r.get(d);
+    } else {
+        err = D_CORRUPT;
+    }
+    uint32_t nseg = 0;
+    if (!err) {
+        for (int b = (int)d - 1; b >= 0; b--) {
+            uint32_t pm = 0;
+            for (uint32_t t = 0; t < p; t++) pm |= (((masks[t] >> b) & 1u) ^ 1u) << t;
+            if (pm) {
+                s_plane[nseg] = (uint8_t)b;
+                s_M[nseg] = n * __popc(pm);
+                nseg++;
+            }
+        }
+    }
+    uint32_t czr = 0, wz = 0, m = 0;
+    if (!err && nseg) {
+        czr = r.get(8);
+        wz = r.get(4);
+        const uint32_t beta = bitlen32(p * n - 1), wzhi = beta > 2 ? beta : 2;
+        if (wz < 2 || wz > wzhi) err = D_CORRUPT;
+        // walk with the left-aligned code A and depth of the current node; a
+        // run of 0 bits is a chain of internal nodes; after a leaf the next
+        // node is at A + 2^(32-depth), depth 32 - ctz.
+        uint64_t A = 0;
+        uint32_t depth = 0, nodes = 0;
+        uint64_t seen0 = 0, seen1 = 0, seen2 = 0, seen3 = 0;
+        while (!err) {
+            const uint32_t pk = r.peek();
+            const uint32_t z = pk ? (uint32_t)__builtin_clz(pk) : 32u;
+            if (z) {
+                if (nodes + z > 511 || r.pos + z > lim || depth + z > 32) { err = D_CORRUPT; break; }
+                nodes += z;
+                depth += z;
+                r.skip(z);
+                continue;
+            }
+            if (nodes + 1 > 511 || r.pos + 9 > lim) { err = D_CORRUPT; break; }
+            nodes++;
+            const uint32_t sym = r.get(9) & 0xffu;
+            const uint32_t q = sym >> 6;
+            const uint64_t bit = 1ull << (sym & 63);
+            const uint64_t cur = q == 0 ? seen0 : q == 1 ? seen1 : q == 2 ? seen2 : seen3;
+            if (cur & bit) { err = D_CORRUPT; break; }
+            seen0 |= q == 0 ? bit : 0ull;
+            seen1 |= q == 1 ? bit : 0ull;
+            seen2 |= q == 2 ? bit : 0ull;
+            seen3 |= q == 3 ? bit : 0ull;
+            s_acode[m] = (uint32_t)A;
+            s_len[m] = (uint8_t)depth;
+            s_sym[m] = (uint8_t)sym;
+            m++;
+            if (depth == 0) break;  // a lone leaf is the whole tree
+            A += 1ull << (32 - depth);
+            if (A >= (1ull << 32)) break;  // the rightmost leaf closes the tree
+            depth = 32 - (uint32_t)__builtin_ctzll(A);
+        }
+        const uint32_t tb = bitlen32(p * n) - 1 + 5;
+        uint64_t acc = 0;
+        for (uint32_t s = 0; s < nseg && !err; s++) {
+            if (r.pos + tb > lim) { err = D_TRUNC; break; }
+            const uint32_t v = r.get(tb);
+            s_bits[s] = v;
+            acc += v;
+        }
+        if (!err) {
+            uint64_t start = B.byte_off * 8 + r.pos;
+            if (r.pos + acc > (uint64_t)blen * 8) err = D_TRUNC;
+            for (uint32_t s = 0; s < nseg; s++) {
+                s_pos[s] = start;
+                start += s_bits[s];
+            }
+        }
+    } else if (!err && r.pos > blen * 8) {
+        err = D_TRUNC;
+    }
+    if (err) nseg = 0;
+    __syncthreads();
+    if (lane == 0) {
+        P.d = d; P.nseg = nseg; P.czr = czr; P.wz = wz; P.m = m; P.p = p; P.n = n;
+        P.err = err ? 1 : 0;
+        for (uint32_t t = 0; t < 3; t++) P.masks[t] = masks[t];
+        if (err) atomicMin(&status[B.tile], err);
+    }
+    if (!nseg) return;
+    if (lane < nseg) {
+        P.seg_plane[lane] = s_plane[lane];
+        P.seg_M[lane] = s_M[lane];
+        P.seg_bits[lane] = s_bits[lane];
+        P.seg_bitpos[lane] = s_pos[lane];
+    }
+    // prefix table: entry e belongs to the last leaf whose left-aligned code
+    // is <= e << (32 - K): sym | len << 8, or kLutLong for codes longer than K
+    uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
+    {
+        constexpr uint32_t per = (1u << kLutK) / 64;
+        const uint32_t e0 = lane * per;
+        uint32_t lo = 0, hi = m;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_acode[mid] <= (e0 << (32 - kLutK))) lo = mid; else hi = mid;
+        }
+        uint32_t j = lo;
+        uint32_t packed[per / 2];
+#pragma unroll
+        for (uint32_t k = 0; k < per; k++) {
+            const uint32_t key = (e0 + k) << (32 - kLutK);
+            while (j + 1 < m && s_acode[j + 1] <= key) j++;
+            const uint32_t L = s_len[j];
+            const uint32_t e = (L <= (uint32_t)kLutK) ? (s_sym[j] | (L << 8)) : kLutLong;
+            if (k & 1) packed[k / 2] |= e << 16; else packed[k / 2] = e;
+        }
+        uint4 *dst = (uint4 *)(tab + (uint64_t)e0 * 2);
+#pragma unroll
+        for (uint32_t k = 0; k < per / 8; k++)
+            dst[k] = make_uint4(packed[4 * k], packed[4 * k + 1], packed[4 * k + 2], packed[4 * k + 3]);
+    }
+    uint32_t *acode = (uint32_t *)(tab + kLutBytes16);
+    uint8_t *llen = tab + kLutBytes16 + 1024, *lsym = llen + 256;
+    for (uint32_t j = lane; j < 256; j += 64) {
+        acode[j] = j < m ? s_acode[j] : 0xffffffffu;
+        llen[j] = j < m ? s_len[j] : 0;
+        lsym[j] = j < m ? s_sym[j] : 0;
+    }
+    // work items: large segments first in the decode order
+    uint32_t *ctr = (uint32_t *)(ws + H.ws_items);
+    const bool big = lane < nseg && s_bits[lane] >= kBigSegBits;
+    const uint64_t bm = __ballot(big);
+    const uint32_t nbig = __popcll(bm), nsmall = nseg - nbig;
+    uint32_t bb = 0, sb = 0;
+    if (lane == 0) {
+        if (nbig) bb = atomicAdd(&ctr[0], nbig);
+        if (nsmall) sb = atomicAdd(&ctr[1], nsmall);
+    }
+    bb = __shfl(bb, 0, 64);
+    sb = __shfl(sb, 0, 64);
+    if (lane < nseg) {
+        const uint64_t below = (1ull << lane) - 1ull;
+        const uint32_t item = (blk << 5) | lane;
+        uint32_t *list = (uint32_t *)(ws + H.ws_items + 64);
+        if (big) list[bb + __popcll(bm & below)] = item;
+        else list[H.total_blocks * 32ull + sb + (lane - __popcll(bm & below))] = item;
+    }
+}
+
+// ------------------------------------------------------------------ segments
+// Bit sources of one segment.  Positions are relative to the segment start;
+// win(r) = the 32 stream bits from r on (MSB first).
+struct SrcLds {
+    const uint32_t *w;  // staged words, from the word holding the first bit
+    uint32_t off;       // bit offset of the segment start in w[0]
+    uint32_t nw;        // staged words (w[nw], w[nw + 1] are zero)
+    __device__ inline uint32_t win(uint32_t r) const
+    {
+        const uint32_t b = r + off, i = b >> 5;
+        const uint64_t x = ((uint64_t)w[i] << 32) | w[i + 1];
+        return (uint32_t)(x >> (32 - (b & 31)));
+    }
+    __device__ inline uint32_t win_safe(uint32_t r) const
+    {
+        const uint32_t b = r + off;
+        uint32_t i = b >> 5;
+        i = i < nw ? i : nw;
+        const uint64_t x = ((uint64_t)w[i] << 32) | w[i + 1];
+        return (uint32_t)(x >> (32 - (b & 31)));
+    }
+};
+
+// big-endian word `wi` of the stream, bytes outside [lo, hi) read as 0
+__device__ inline uint32_t stream_word(const uint8_t *enc, uint64_t lo, uint64_t hi, uint64_t wi)
+{
+    const uint64_t b = wi * 4;
+    if (b >= lo && b + 4 <= hi) return __builtin_bswap32(*(const uint32_t *)(enc + b));
+    uint32_t x = 0;
+    for (int k = 0; k < 4; k++) x = (x << 8) | ((b + k >= lo && b + k < hi) ? enc[b + k] : 0u);
+    return x;
+}
+
+struct SrcGlb {
+    const uint8_t *enc;
+    uint64_t lo, hi, w0;  // readable bytes; word of the first bit
+    uint32_t off;
+    __device__ inline uint32_t win(uint32_t r) const
+    {
+        const uint32_t b = r + off;
+        const uint64_t i = w0 + (b >> 5);
+        const uint64_t x = ((uint64_t)stream_word(enc, lo, hi, i) << 32) | stream_word(enc, lo, hi, i + 1);
+        return (uint32_t)(x >> (32 - (b & 31)));
+    }
+    __device__ inline uint32_t win_safe(uint32_t r) const { return win(r); }
+};
+
+struct DecTab {
+    const uint16_t *lut;
+    const uint32_t *acode;
+    const uint8_t *llen, *lsym;
+    uint32_t m, czr, wz;
+};
+
+// One token at r: returns the symbol; c = counter of a C_zr symbol (else 0),
+// adv = bits taken.
+template <class Src>
+__device__ inline uint32_t dec_token(const Src &S, const DecTab &T, uint32_t r, uint32_t &c, uint32_t &adv)
+{
+    const uint32_t w = S.win(r);
+    const uint32_t e = T.lut[w >> (32 - kLutK)];
+    uint32_t v, L, cw;
+    if (!(e & kLutLong)) {
+        v = e & 0xffu;
+        L = (e >> 8) & 0x3fu;
+        cw = w << L;
+    } else {
+        uint32_t lo = 0, hi = T.m;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (T.acode[mid] <= w) lo = mid; else hi = mid;
+        }
+        v = T.lsym[lo];
+        L = T.llen[lo];
+        cw = S.win_safe(r + L);
+    }
+    const bool z = (v == T.czr);
+    c = z ? (cw >> (32 - T.wz)) : 0u;
+    adv = L + (z ? T.wz : 0u);
+    return v;
+}
+
 // Run-length bookkeeping of a token range as an affine map on (pos, R):
 // pos = output position, R = value of the pending run of C_zr digits.
+// Values saturate at kSat (only corrupt streams get there).
 constexpr uint32_t kSat = 1u << 30;
-__device__ inline uint32_t smul(uint32_t a, uint32_t b) { uint64_t r = (uint64_t)a * b; return r > kSat ? kSat : (uint32_t)r; }
 __device__ inline uint32_t sadd(uint32_t a, uint32_t b) { uint32_t r = a + b; return r > kSat ? kSat : r; }
+__device__ inline uint32_t smul(uint32_t a, uint32_t b) { uint64_t r = (uint64_t)a * b; return r > kSat ? kSat : (uint32_t)r; }
+// R * (2^wz - 1) + c, saturated
+__device__ inline uint32_t run_push(uint32_t R, uint32_t c, uint32_t wz)
+{
+    const uint64_t x = ((uint64_t)R << wz) - R + c;
+    return x > kSat ? kSat : (uint32_t)x;
+}
 struct RunXf {
     uint32_t lit;  // the range holds a literal symbol
     uint32_t P0;   // B^(digits before the first literal)
@@ -204,6 +454,7 @@ struct RunXf {
     uint32_t mid;  // output symbols from the first literal up to the trailing digits
     uint32_t V1;   // value of the trailing digits (pending run)
 };
+__device__ inline RunXf xf_id() { RunXf f = {0, 1, 0, 0, 0}; return f; }
 __device__ inline RunXf xf_combine(const RunXf &a, const RunXf &b)
 {
     RunXf r;
@@ -219,342 +470,222 @@ __device__ inline RunXf xf_combine(const RunXf &a, const RunXf &b)
     }
     return r;
 }
-
-struct SegCtx {
-    const uint16_t *lut;
-    const uint32_t *acode;
-    const uint8_t *llen, *lsym;
-    uint32_t m, czr, wz, single;
-};
-
-// One token at the reader's position: returns the symbol, advances pos;
-// *cnt = counter (valid when the symbol is C_zr).
-__device__ inline uint32_t next_token(const SegCtx &C, BitRd &R, uint64_t &pos, uint32_t *cnt)
+// append one token (a C_zr digit when dig, else an output symbol)
+__device__ inline void xf_push(RunXf &f, bool dig, uint32_t c, uint32_t wz)
 {
-    uint32_t v, L;
-    if (C.single) { v = C.lsym[0]; L = 0; }
-    else {
-        uint32_t pk = R.peek();
-        uint16_t e = C.lut[pk >> (32 - kLutK)];
-        if (!(e & kLutLong)) { v = e & 0xffu; L = (e >> 8) & 0x3fu; }
-        else {
-            uint32_t lo = 0, hi = C.m;
-            while (hi - lo > 1) { uint32_t mid = (lo + hi) >> 1; if (C.acode[mid] <= pk) lo = mid; else hi = mid; }
-            v = C.lsym[lo]; L = C.llen[lo];
-        }
-    }
-    R.skip(L);
-    pos += L;
-    *cnt = 0;
-    if (v == C.czr) {
-        *cnt = R.peek() >> (32 - C.wz);
-        R.skip(C.wz);
-        pos += C.wz;
-    }
-    return v;
+    const uint32_t R = f.lit ? f.V1 : f.V0;
+    const uint32_t Rn = run_push(R, c, wz);
+    const uint32_t P0n = run_push(f.P0, 0, wz);
+    const uint32_t midl = f.lit ? sadd(f.mid, sadd(f.V1, 1u)) : 1u;
+    const bool first = dig && !f.lit;
+    f.V0 = first ? Rn : f.V0;
+    f.P0 = first ? P0n : f.P0;
+    f.V1 = dig ? (f.lit ? Rn : f.V1) : 0u;
+    f.mid = dig ? f.mid : midl;
+    f.lit = dig ? f.lit : 1u;
 }
 
-constexpr int kSyncBits = 128;  // token starts remembered per chunk (re-sync window)
-constexpr int kDecWaves = 8;
-constexpr uint32_t kMaxSeg = 3 * 128 * 128 / 8;  // symbols in the largest segment
+constexpr uint32_t kSyncWin = 128;  // phase-1 bits before the resynchronisation point
 
-struct DecShared {
-    uint32_t hw[132];          // first 512 bytes of the block (header), big-endian words
+// Decode of one segment by one wave: the segment's N bits are split into 64
+// chunks.  Phase 1: every lane decodes its chunk from the chunk start
+// (speculatively, for lanes > 0), keeping the run map of the tokens before
+// and from the first token start sw at or after kSyncWin bits, and its exit
+// (first token start at or after the chunk end).  Phase 2: a lane whose
+// start differs from its left neighbour's exit decodes again from that exit;
+// on reaching sw the rest of phase 1 stands (Huffman codes resynchronise),
+// else it decodes the whole chunk; repeated until no lane changes.  A wave
+// scan of the run maps gives each lane its output position and pending run;
+// phase 3 decodes again and writes the non-zero symbols (the plane was
+// zeroed, so runs write nothing).
+template <class Src>
+__device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uint32_t M, uint8_t *out)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wz = T.wz, czr = T.czr;
+    uint32_t chunk = (N + 63) / 64;
+    chunk = (chunk + 31) & ~31u;
+    if (chunk < 32) chunk = 32;
+    const uint32_t cs = lane * chunk;
+    const bool active = cs < N;
+    const uint32_t ce = active ? (cs + chunk < N ? cs + chunk : N) : cs;
+    // phase 1
+    RunXf fpre = xf_id(), G = xf_id();
+    uint32_t r = cs;
+    {
+        const uint32_t l1 = (cs + kSyncWin < ce) ? cs + kSyncWin : ce;
+        while (r < l1) {
+            uint32_t c, adv;
+            const uint32_t v = dec_token(S, T, r, c, adv);
+            r += adv;
+            xf_push(fpre, v == czr && c, c, wz);
+        }
+    }
+    const uint32_t sw = r;
+    while (r < ce) {
+        uint32_t c, adv;
+        const uint32_t v = dec_token(S, T, r, c, adv);
+        r += adv;
+        xf_push(G, v == czr && c, c, wz);
+    }
+    const uint32_t exit1 = r;
+    RunXf f = xf_combine(fpre, G);
+    uint32_t start = cs, exitc = exit1;
+    // phase 2
+    for (int it = 0; it < 64; it++) {
+        const uint32_t left = __shfl_up(exitc, 1, 64);
+        const uint32_t want = (lane == 0) ? 0u : left;
+        const bool chg = active && want != start;
+        if (!__any(chg)) break;
+        if (chg) {
+            start = want;
+            RunXf Pm = xf_id();
+            uint32_t q = want;
+            while (q < sw && q < ce) {
+                uint32_t c, adv;
+                const uint32_t v = dec_token(S, T, q, c, adv);
+                q += adv;
+                xf_push(Pm, v == czr && c, c, wz);
+            }
+            if (q == sw) {
+                f = xf_combine(Pm, G);
+                exitc = exit1;
+            } else {
+                while (q < ce) {
+                    uint32_t c, adv;
+                    const uint32_t v = dec_token(S, T, q, c, adv);
+                    q += adv;
+                    xf_push(Pm, v == czr && c, c, wz);
+                }
+                f = Pm;
+                exitc = q;
+            }
+        }
+    }
+    if (!active) f = xf_id();
+    // exclusive scan of the run maps
+    RunXf x = f;
+    for (int o = 1; o < 64; o <<= 1) {
+        RunXf y;
+        y.lit = __shfl_up(x.lit, o, 64); y.P0 = __shfl_up(x.P0, o, 64); y.V0 = __shfl_up(x.V0, o, 64);
+        y.mid = __shfl_up(x.mid, o, 64); y.V1 = __shfl_up(x.V1, o, 64);
+        if ((int)lane >= o) x = xf_combine(y, x);
+    }
+    RunXf ex;
+    ex.lit = __shfl_up(x.lit, 1, 64); ex.P0 = __shfl_up(x.P0, 1, 64); ex.V0 = __shfl_up(x.V0, 1, 64);
+    ex.mid = __shfl_up(x.mid, 1, 64); ex.V1 = __shfl_up(x.V1, 1, 64);
+    if (lane == 0) ex = xf_id();
+    uint32_t op, run;
+    if (ex.lit) { op = sadd(ex.V0, ex.mid); run = ex.V1; }
+    else { op = 0; run = ex.V0; }
+    // phase 3: write
+    int32_t err = 0;
+    const bool last = active && (lane == 63 || cs + chunk >= N);
+    if (active) {
+        uint32_t q = start;
+        bool bad = false;
+        while (q < ce) {
+            uint32_t c, adv;
+            const uint32_t v = dec_token(S, T, q, c, adv);
+            q += adv;
+            const bool dig = (v == czr) && c;
+            const uint32_t opr = sadd(op, run);
+            bad |= !dig && (run == 1 || opr >= M);
+            if (!dig && v && opr < M) out[opr] = (uint8_t)v;
+            op = dig ? op : opr + 1;
+            run = dig ? run_push(run, c, wz) : 0u;
+        }
+        if (last) {
+            if (run) {
+                bad |= run < 2;
+                op = sadd(op, run);
+            }
+            bad |= (q != N || op != M);
+        }
+        if (bad) err = D_CORRUPT;
+    }
+    if (N == 0 && lane == 0 && M != 0) err = D_CORRUPT;
+    return err;
+}
+
+struct SegShared {
     uint16_t lut[1 << kLutK];
     uint32_t acode[256];
     uint8_t llen[256], lsym[256];
-    uint32_t vis[kDecWaves][64][kSyncBits / 32];
-    uint32_t nseg, czr, wz, m, err;
-    uint8_t seg_plane[32];
-    uint32_t seg_M[32], seg_bits[32];
-    uint64_t seg_bitpos[32];
+    uint32_t bits[kSegWords + 2];
+    uint4 stg[kMaxSeg / 16];
 };
 
-// Block header (Fig. 3 layout as read): d, masks, C_zr, wz, pre-order code
-// tree, seek table.  Lane 0 only.  Fills S and the block plan's d/masks/
-// segments (used by the reassembly).
-__device__ void parse_header(const BlockDesc &B, BlkPlan &P, DecShared &S)
+// Persistent waves taking (block, segment) items from the two lists (large
+// segments first); per item: code tables and the segment's bits to LDS, the
+// symbol plane built in LDS and copied out.
+__global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
+                                                     uint8_t *__restrict__ ws,
+                                                     int32_t *__restrict__ status)
 {
-    const uint32_t p = B.p, n = (uint32_t)B.wb * B.hb / 8;
-    const uint32_t blen = B.byte_len;
-    const uint64_t lim = (uint64_t)(blen < 512 ? blen : 512) * 8;
-    LdsBits r;
-    r.w = S.hw; r.nwords = 130;
-    r.seek(0);
-    int32_t err = 0;
-    uint32_t d = r.get(5);
-    uint32_t masks[3] = {0, 0, 0};
-    if (d >= 1 && d <= B.dmax)
-        for (uint32_t t = 0; t < p; t++) masks[t] = r.get(d);
-    else err = D_CORRUPT;
-    uint32_t nseg = 0;
-    if (!err) {
-        for (int b = (int)d - 1; b >= 0; b--) {
-            uint32_t pm = 0;
-            for (uint32_t t = 0; t < p; t++) pm |= (((masks[t] >> b) & 1u) ^ 1u) << t;
-            if (pm) {
-                S.seg_plane[nseg] = (uint8_t)b;
-                S.seg_M[nseg] = n * __popc(pm);
-                nseg++;
-            }
+    __shared__ SegShared S;
+    const uint32_t lane = threadIdx.x;
+    uint32_t *ctr = (uint32_t *)(ws + H.ws_items);
+    const uint32_t nbig = __builtin_amdgcn_readfirstlane(ctr[0]);
+    const uint32_t ntot = nbig + __builtin_amdgcn_readfirstlane(ctr[1]);
+    const uint32_t *list = (const uint32_t *)(ws + H.ws_items + 64);
+    for (;;) {
+        uint32_t idx = 0;
+        if (lane == 0) idx = atomicAdd(&ctr[2], 1u);
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        if (idx >= ntot) break;
+        const uint32_t item =
+            __builtin_amdgcn_readfirstlane(idx < nbig ? list[idx] : list[H.total_blocks * 32ull + (idx - nbig)]);
+        const uint32_t blk = item >> 5, s = item & 31;
+        const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+        const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
+        if (__builtin_amdgcn_readfirstlane(status[B.tile]) != D_OK) continue;
+        const uint32_t M = P.seg_M[s];
+        const uint64_t S0 = P.seg_bitpos[s];
+        const uint32_t N = P.seg_bits[s];
+        uint4 *gout = (uint4 *)(ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride((uint32_t)B.p * B.wb * B.hb / 8));
+        if (M > kMaxSeg) {  // not reachable for 128-grid blocks
+            if (lane == 0) atomicMin(&status[B.tile], D_CORRUPT);
+            continue;
         }
-    }
-    uint32_t czr = 0, wz = 0, m = 0;
-    if (!err && nseg) {
-        czr = r.get(8);
-        wz = r.get(4);
-        uint32_t beta = bitlen32(p * n - 1), wzhi = beta > 2 ? beta : 2;
-        if (wz < 2 || wz > wzhi) err = D_CORRUPT;
-        // pre-order tree: 0 = internal, 1 + 8-bit symbol = leaf.  Walk with
-        // the left-aligned code A and depth of the current node; after a leaf
-        // the next node is at A + 2^(32-depth), depth 32 - ctz.
-        uint64_t A = 0;
-        uint32_t depth = 0, nodes = 0;
-        uint32_t seen[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        while (!err) {
-            if (++nodes > 511 || r.pos + 1 > lim) { err = D_CORRUPT; break; }
-            if (!r.get(1)) {
-                if (depth >= 32) { err = D_CORRUPT; break; }
-                depth++;
-                continue;
-            }
-            if (r.pos + 8 > lim) { err = D_CORRUPT; break; }
-            uint32_t sym = r.get(8);
-            if ((seen[sym >> 5] >> (sym & 31)) & 1u) { err = D_CORRUPT; break; }
-            seen[sym >> 5] |= 1u << (sym & 31);
-            S.acode[m] = (uint32_t)A;
-            S.llen[m] = (uint8_t)depth;
-            S.lsym[m] = (uint8_t)sym;
-            m++;
-            if (depth == 0) break;  // a lone leaf is the whole tree
-            A += 1ull << (32 - depth);
-            if (A >= (1ull << 32)) break;  // the rightmost leaf closes the tree
-            depth = 32 - (uint32_t)__builtin_ctzll(A);
+        const uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
+        __syncthreads();  // the previous item is done with S
+        {
+            const uint4 *src = (const uint4 *)tab;
+            uint4 *dst = (uint4 *)S.lut;
+            for (uint32_t i = lane; i < kLutStride / 16; i += 64) dst[i] = src[i];
         }
-        const uint32_t tb = bitlen32(p * n) - 1 + 5;
-        uint64_t acc = 0;
-        for (uint32_t s = 0; s < nseg && !err; s++) {
-            if (r.pos + tb > lim) { err = D_TRUNC; break; }
-            S.seg_bits[s] = r.get(tb);
-            acc += S.seg_bits[s];
-        }
-        if (!err) {
-            uint64_t start = (uint64_t)B.byte_off * 8 + r.pos;
-            if (r.pos + acc > (uint64_t)blen * 8) err = D_TRUNC;
-            for (uint32_t s = 0; s < nseg; s++) {
-                S.seg_bitpos[s] = start;
-                start += S.seg_bits[s];
-            }
-        }
-    } else if (!err && r.pos > (uint64_t)blen * 8) {
-        err = D_TRUNC;
-    }
-    S.nseg = err ? 0 : nseg; S.czr = czr; S.wz = wz; S.m = m; S.err = (uint32_t)err;
-    P.d = d; P.nseg = err ? 0 : nseg; P.p = p; P.n = n; P.err = err ? 1 : 0;
-    for (uint32_t t = 0; t < 3; t++) P.masks[t] = masks[t];
-    for (uint32_t s = 0; s < nseg && !err; s++) { P.seg_plane[s] = S.seg_plane[s]; P.seg_M[s] = S.seg_M[s]; }
-}
-
-// Entropy decode of a block: header, prefix table (4096 entries in LDS:
-// entry e belongs to the last leaf whose left-aligned code is <= e << 20),
-// then one wave per segment, the segment's bits split into 64 chunks.
-// Phase 1: every lane decodes its chunk from the chunk start (speculatively,
-// for lanes > 0) and remembers its token starts in the first kSyncBits bits.
-// Phase 2: a lane whose start differs from its left neighbour's exit
-// re-decodes from that exit until it reaches a remembered token start (then
-// its old exit stands) or its chunk end; repeated until no lane changes
-// (Huffman codes resynchronise within a few tokens).  Phase 3: per-chunk run
-// maps, a wave scan gives each lane its output position and pending run.
-// Phase 4: decode again and write the non-zero symbols (the plane was zeroed
-// first, so runs write nothing).
-__global__ void __launch_bounds__(64 * kDecWaves) k_dec_blocks(PlanHdr H, const uint8_t *__restrict__ enc,
-                                                               uint8_t *__restrict__ ws,
-                                                               int32_t *__restrict__ status)
-{
-    __shared__ DecShared S;
-    // per-wave staging of one segment's symbol plane (M <= 3 * 2048 bytes)
-    __shared__ uint4 stg[kDecWaves][kMaxSeg / 16];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
-    const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
-    BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
-    const uint8_t *src = enc + B.byte_off;
-    const uint32_t blen = B.byte_len;
-    __syncthreads();  // the previous block is done with S
-    for (uint32_t i = tid; i < 128; i += blockDim.x) {
-        uint32_t x = 0;
-        for (int k = 0; k < 4; k++) x = (x << 8) | rd_byte(src, blen, 4 * i + k);
-        S.hw[i] = x;
-    }
-    if (tid < 4) S.hw[128 + tid] = 0;
-    __syncthreads();
-    if (tid == 0) {
-        // the tile status is read once, so the whole workgroup takes the
-        // same branch below
-        if (status[B.tile] != D_OK || blen == 0) {
-            P.nseg = 0; P.err = 1; P.d = 1;
-            S.nseg = 0;
-        } else {
-            parse_header(B, P, S);
-            if (S.err) atomicMin(&status[B.tile], (int32_t)S.err);
-        }
-    }
-    __syncthreads();
-    const uint32_t nseg = S.nseg, m = S.m;
-    if (!nseg) continue;
-    {
-        const uint32_t per = (1u << kLutK) / (64 * kDecWaves);
-        const uint32_t e0 = tid * per;
-        uint32_t lo = 0, hi = m;
-        while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (S.acode[mid] <= (e0 << (32 - kLutK))) lo = mid; else hi = mid;
-        }
-        uint32_t j = lo;
-        for (uint32_t e = e0; e < e0 + per; e++) {
-            uint32_t key = e << (32 - kLutK);
-            while (j + 1 < m && S.acode[j + 1] <= key) j++;
-            uint32_t L = S.llen[j];
-            S.lut[e] = (L <= (uint32_t)kLutK) ? (uint16_t)(S.lsym[j] | (L << 8)) : kLutLong;
-        }
-    }
-    __syncthreads();
-    SegCtx C;
-    C.lut = S.lut; C.acode = S.acode; C.llen = S.llen; C.lsym = S.lsym; C.m = m;
-    C.czr = S.czr; C.wz = S.wz; C.single = (m == 1);
-    const uint32_t Bb = (1u << S.wz) - 1u;
-    const uint32_t pstride = plane_stride((uint32_t)B.p * B.wb * B.hb / 8);
-    BitRd R;
-    R.base = enc; R.lo = B.byte_off; R.hi = B.byte_off + B.byte_len;
-    int32_t err = 0;
-    for (uint32_t s = wave; s < nseg; s += kDecWaves) {
-        const uint32_t M = S.seg_M[s];
-        if (M > kMaxSeg) { err = D_CORRUPT; continue; }  // not reachable for 128-grid blocks
-        uint4 *gout = (uint4 *)(ws + B.sym_off + (uint64_t)S.seg_plane[s] * pstride);
-        uint8_t *out = (uint8_t *)stg[wave];
+        const uint64_t lo = B.byte_off, hi = B.byte_off + B.byte_len;
+        const uint64_t w0 = S0 >> 5;
+        const uint32_t off = (uint32_t)(S0 & 31);
+        const uint32_t nw = N ? (uint32_t)(((S0 + N - 1) >> 5) + 2 - w0) : 0u;
+        const bool staged = nw <= kSegWords;
+        if (staged)
+            for (uint32_t i = lane; i < nw + 2; i += 64) S.bits[i] = i < nw ? stream_word(enc, lo, hi, w0 + i) : 0u;
         const uint32_t M16 = (M + 15) / 16;
-        for (uint32_t i = lane; i < M16; i += 64) stg[wave][i] = make_uint4(0, 0, 0, 0);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const uint64_t S0 = S.seg_bitpos[s], N = S.seg_bits[s], SE = S0 + N;
-        if (C.single && S.lsym[0] != C.czr) {
+        for (uint32_t i = lane; i < M16; i += 64) S.stg[i] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        DecTab T;
+        T.lut = S.lut; T.acode = S.acode; T.llen = S.llen; T.lsym = S.lsym;
+        T.m = P.m; T.czr = P.czr; T.wz = P.wz;
+        uint8_t *out = (uint8_t *)S.stg;
+        int32_t err = 0;
+        if (T.m == 1 && S.lsym[0] != T.czr) {
             // zero-length codewords: the segment is M copies of the leaf
             if (N != 0) err = D_CORRUPT;
             else if (S.lsym[0]) for (uint32_t i = lane; i < M; i += 64) out[i] = S.lsym[0];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            for (uint32_t i = lane; i < M16; i += 64) gout[i] = stg[wave][i];
-            continue;
+        } else if (staged) {
+            SrcLds src;
+            src.w = S.bits; src.off = off; src.nw = nw;
+            err = decode_segment(src, T, N, M, out);
+        } else {
+            SrcGlb src;
+            src.enc = enc; src.lo = lo; src.hi = hi; src.w0 = w0; src.off = off;
+            err = decode_segment(src, T, N, M, out);
         }
-        uint64_t chunk = (N + 63) / 64;
-        chunk = (chunk + 31) & ~31ull;
-        if (chunk < 32) chunk = 32;
-        const uint64_t cs = S0 + lane * chunk;
-        const bool active = cs < SE;
-        const uint64_t ce = active ? (cs + chunk < SE ? cs + chunk : SE) : cs;
-        // phase 1
-        uint32_t *mv = S.vis[wave][lane];
-#pragma unroll
-        for (int k = 0; k < kSyncBits / 32; k++) mv[k] = 0;
-        uint64_t start = cs, exit1 = cs;
-        if (active) {
-            uint64_t pos = cs;
-            R.seek(pos);
-            while (pos < ce) {
-                uint64_t rel = pos - cs;
-                if (rel < kSyncBits) mv[rel >> 5] |= 1u << (rel & 31);
-                uint32_t c;
-                next_token(C, R, pos, &c);
-            }
-            exit1 = pos;
-        }
-        uint64_t exitc = exit1;
-        // phase 2
-        for (int it = 0; it < 64; it++) {
-            uint64_t left = __shfl_up(exitc, 1, 64);
-            uint64_t want = (lane == 0) ? S0 : left;
-            bool chg = active && want != start;
-            if (!__any(chg)) break;
-            if (chg) {
-                start = want;
-                uint64_t pos = want;
-                bool synced = false;
-                if (pos < ce) R.seek(pos);
-                while (pos < ce) {
-                    uint64_t rel = pos - cs;
-                    if (rel < kSyncBits && ((mv[rel >> 5] >> (rel & 31)) & 1u)) { synced = true; break; }
-                    uint32_t c;
-                    next_token(C, R, pos, &c);
-                }
-                exitc = synced ? exit1 : pos;
-            }
-        }
-        // phase 3: run maps and their scan
-        RunXf f = {0, 1, 0, 0, 0};
-        if (active && start < ce) {
-            uint64_t pos = start;
-            R.seek(pos);
-            while (pos < ce) {
-                uint32_t c;
-                uint32_t v = next_token(C, R, pos, &c);
-                if (v == C.czr && c) {
-                    if (!f.lit) { f.V0 = sadd(smul(f.V0, Bb), c); f.P0 = smul(f.P0, Bb); }
-                    else f.V1 = sadd(smul(f.V1, Bb), c);
-                } else {
-                    if (!f.lit) { f.lit = 1; f.mid = 1; }
-                    else { f.mid = sadd(f.mid, sadd(f.V1, 1)); f.V1 = 0; }
-                }
-            }
-        }
-        RunXf x = f;
-        for (int o = 1; o < 64; o <<= 1) {
-            RunXf y;
-            y.lit = __shfl_up(x.lit, o, 64); y.P0 = __shfl_up(x.P0, o, 64); y.V0 = __shfl_up(x.V0, o, 64);
-            y.mid = __shfl_up(x.mid, o, 64); y.V1 = __shfl_up(x.V1, o, 64);
-            if ((int)lane >= o) x = xf_combine(y, x);
-        }
-        RunXf ex;
-        ex.lit = __shfl_up(x.lit, 1, 64); ex.P0 = __shfl_up(x.P0, 1, 64); ex.V0 = __shfl_up(x.V0, 1, 64);
-        ex.mid = __shfl_up(x.mid, 1, 64); ex.V1 = __shfl_up(x.V1, 1, 64);
-        if (lane == 0) { ex.lit = 0; ex.P0 = 1; ex.V0 = 0; ex.mid = 0; ex.V1 = 0; }
-        uint32_t opos, orun;
-        if (ex.lit) { opos = sadd(ex.V0, ex.mid); orun = ex.V1; }
-        else { opos = 0; orun = ex.V0; }
-        // phase 4: write
-        const bool last = active && (lane == 63 || cs + chunk >= SE);
-        if (active) {
-            uint64_t pos = start;
-            uint32_t op = opos, run = orun;
-            if (pos < ce) R.seek(pos);
-            while (pos < ce) {
-                uint32_t c;
-                uint32_t v = next_token(C, R, pos, &c);
-                if (v == C.czr && c) { run = sadd(smul(run, Bb), c); continue; }
-                if (run) {
-                    if (run < 2) { err = D_CORRUPT; break; }
-                    op = sadd(op, run);
-                    run = 0;
-                }
-                if (op >= M) { err = D_CORRUPT; break; }
-                if (v) out[op] = (uint8_t)v;
-                op++;
-            }
-            if (last && !err) {
-                if (run) {
-                    if (run < 2) err = D_CORRUPT;
-                    op = sadd(op, run);
-                }
-                if (pos != SE || op != M) err = D_CORRUPT;
-            }
-        }
-        if (N == 0 && lane == 0 && M != 0) err = D_CORRUPT;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        for (uint32_t i = lane; i < M16; i += 64) gout[i] = stg[wave][i];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
-    if (err) atomicMin(&status[B.tile], err);
+        __syncthreads();
+        for (uint32_t i = lane; i < M16; i += 64) gout[i] = S.stg[i];
+        if (err) atomicMin(&status[B.tile], err);
     }
 }
 
@@ -625,10 +756,13 @@ hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
     for (int st = first; st <= last; st++) {
         if (st == DEC_PREP) {
             hipLaunchKernelGGL(k_dec_prep, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_encoded, d_ws, d_status);
+        } else if (st == DEC_HDR) {
+            if (H.total_blocks)
+                hipLaunchKernelGGL(k_dec_header, dim3(H.total_blocks), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
         } else if (st == DEC_SEG) {
             if (H.total_blocks)
-                hipLaunchKernelGGL(k_dec_blocks, dim3(H.blk_grid), dim3(64 * kDecWaves), 0, stream, H, d_encoded, d_ws,
-                                   d_status);
+                hipLaunchKernelGGL(k_dec_segments, dim3(H.num_cus * kSegWavesPerCu), dim3(64), 0, stream, H, d_encoded,
+                                   d_ws, d_status);
         } else if (st == DEC_REASM) {
             if (H.total_blocks)
                 hipLaunchKernelGGL(k_dec_reasm, dim3(H.blk_grid), dim3(1024), 0, stream, H, d_plan, d_ws, d_status);

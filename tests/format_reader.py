@@ -145,6 +145,25 @@ def decode_block(data: bytes, p: int, wb: int, hb: int, info: dict | None = None
     return np.where(sign == 1, -mag, mag)
 
 
+def block_payload_bits(data: bytes, p: int, wb: int, hb: int):
+    """(first bit of the seek table, first payload bit, end of the payload)
+    of one block, or None when the block keeps no bit plane."""
+    n = wb * hb // 8
+    bits = Bits(data)
+    d = bits.get(5)
+    masks = [bits.get(d) for _ in range(p)]
+    planes = [b for b in range(d) if any(((masks[t] >> b) & 1) == 0 for t in range(p))]
+    if not planes:
+        return None
+    bits.get(8)
+    bits.get(4)
+    parse_tree(bits)
+    seek = bits.pos
+    t = (p * n).bit_length() - 1 + 5
+    total = sum(bits.get(t) for _ in planes)
+    return seek, bits.pos, bits.pos + total
+
+
 def parse_tile(blob: bytes):
     """Returns (header dict, list of (geometry, block bytes))."""
     assert blob[:4] == b"ISX1" and blob[4] == 1

@@ -118,3 +118,43 @@ def test_batch_of_uneven_tiles_matches_per_tile_oracle():
     dec = isx.decode_streams(got, levels=zs)
     for i, t in enumerate(tiles):
         assert np.array_equal(dec[i], oracle.decode_tile(got[i], zs[i])), i
+
+
+def test_corrupt_segments_detected_like_oracle():
+    """Bit flips in seek tables and segment payloads: the GPU decoder reports
+    an error exactly when the oracle does, and decodes the same pixels when
+    neither does (most flips of a single code bit still give a valid token
+    sequence for a while; the run, length and end checks catch them)."""
+    from tests import format_reader as fr
+    rng = np.random.default_rng(77)
+    cases = [(96, 80, 3, 3, 1, 901), (64, 64, 1, 2, 1, 902), (140, 130, 3, 4, 4, 903)]
+    blobs, base = [], []
+    for w, h, c, lv, q, seed in cases:
+        img = synth.he_like(w, h, seed, sigma=(60.0, 300.0)) if c == 3 else \
+            synth.random_image(w, h, 1, 8, seed=seed, kind="ramp")
+        blob = oracle.encode_tile(img, lv, qstep=q)
+        hdr, blocks = fr.parse_tile(blob)
+        off = 24 + 4 * hdr["nblocks"]
+        ranges = []
+        for g, data in blocks:
+            r = fr.block_payload_bits(data, g[4], g[5], g[6])
+            if r is not None and r[2] > r[0]:
+                ranges.append((off * 8 + r[0], off * 8 + r[2]))
+            off += len(data)
+        for k in range(24):
+            lo, hi = ranges[int(rng.integers(len(ranges)))]
+            bit = int(rng.integers(lo, hi))
+            b = bytearray(blob)
+            b[bit >> 3] ^= 0x80 >> (bit & 7)
+            blobs.append(bytes(b))
+            base.append(blob)
+    got, st = isx.decode_streams(blobs, return_status=True)
+    n_err = 0
+    for i, blob in enumerate(blobs):
+        ost = oracle.decode_status(blob)
+        assert (st[i] != 0) == (ost != 0), (i, st[i], ost)
+        if ost == 0:
+            assert np.array_equal(got[i], oracle.decode_tile(blob, 0)), i
+        else:
+            n_err += 1
+    assert n_err > len(blobs) // 4
