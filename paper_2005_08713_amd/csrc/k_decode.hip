@@ -129,22 +129,24 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
 
 // ------------------------------------------------------------------ header
 // Wave-uniform reader of the staged header words (big-endian, in LDS): every
-// value goes through readfirstlane, so the whole parse runs on the scalar
-// unit.  `buf` holds `avail` >= 32 valid bits, left-aligned.
+// value goes through readfirstlane, so the parse runs on the scalar unit.
+// `buf` holds `avail` >= 32 valid bits, left-aligned; the next word is loaded
+// one refill ahead.
+__device__ inline uint32_t rfl(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
 struct UBits {
     const uint32_t *w;
     uint32_t nw;
     uint64_t buf;
     uint32_t avail, nx, pos;
-    __device__ inline uint32_t fetch(uint32_t i) const
-    {
-        return __builtin_amdgcn_readfirstlane(i < nw ? w[i] : 0u);
-    }
+    uint32_t pre;  // next word (vector register until used)
+    __device__ inline uint32_t load(uint32_t i) const { return i < nw ? w[i] : 0u; }
     __device__ inline void init(const uint32_t *words, uint32_t n)
     {
         w = words; nw = n;
-        buf = ((uint64_t)fetch(0) << 32) | fetch(1);
-        avail = 64; nx = 2; pos = 0;
+        buf = ((uint64_t)rfl(load(0)) << 32) | rfl(load(1));
+        pre = load(2);
+        avail = 64; nx = 3; pos = 0;
     }
     __device__ inline uint32_t peek() const { return (uint32_t)(buf >> 32); }
     __device__ inline void skip(uint32_t k)  // k <= 32
@@ -153,8 +155,9 @@ struct UBits {
         avail -= k;
         pos += k;
         if (avail <= 32) {
-            buf |= (uint64_t)fetch(nx++) << (32 - avail);
+            buf |= (uint64_t)rfl(pre) << (32 - avail);
             avail += 32;
+            pre = load(nx++);
         }
     }
     __device__ inline uint32_t get(uint32_t k)  // k <= 32
@@ -180,6 +183,7 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
     __shared__ uint32_t s_bits[32], s_M[32];
     __shared__ uint64_t s_pos[32];
     __shared__ uint8_t s_plane[32];
+    __shared__ uint32_t s_seen[8];
     const uint32_t lane = threadIdx.x;
     const uint32_t blk = blockIdx.x;
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
@@ -229,33 +233,30 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         wz = r.get(4);
         const uint32_t beta = bitlen32(p * n - 1), wzhi = beta > 2 ? beta : 2;
         if (wz < 2 || wz > wzhi) err = D_CORRUPT;
-        // walk with the left-aligned code A and depth of the current node; a
-        // run of 0 bits is a chain of internal nodes; after a leaf the next
-        // node is at A + 2^(32-depth), depth 32 - ctz.
+        // walk with the left-aligned code A and depth of the current node: a
+        // run of z 0-bits is a chain of internal nodes, then a leaf; after a
+        // leaf the next node is at A + 2^(32-depth), depth 32 - ctz.  Every
+        // violation (internal node at depth 32, more than 511 nodes, bits
+        // past the header, a 257th leaf, a repeated symbol) is the same
+        // error, so the checks are grouped.
         uint64_t A = 0;
         uint32_t depth = 0, nodes = 0;
-        uint64_t seen0 = 0, seen1 = 0, seen2 = 0, seen3 = 0;
+        if (lane < 8) s_seen[lane] = 0;
         while (!err) {
             const uint32_t pk = r.peek();
-            const uint32_t z = pk ? (uint32_t)__builtin_clz(pk) : 32u;
-            if (z) {
-                if (nodes + z > 511 || r.pos + z > lim || depth + z > 32) { err = D_CORRUPT; break; }
-                nodes += z;
-                depth += z;
-                r.skip(z);
+            if (pk == 0) {  // 32 internal nodes
+                depth += 32; nodes += 32;
+                r.skip(32);
+                if (depth > 32 || nodes > 511 || r.pos > lim) err = D_CORRUPT;
                 continue;
             }
-            if (nodes + 1 > 511 || r.pos + 9 > lim) { err = D_CORRUPT; break; }
-            nodes++;
-            const uint32_t sym = r.get(9) & 0xffu;
-            const uint32_t q = sym >> 6;
-            const uint64_t bit = 1ull << (sym & 63);
-            const uint64_t cur = q == 0 ? seen0 : q == 1 ? seen1 : q == 2 ? seen2 : seen3;
-            if (cur & bit) { err = D_CORRUPT; break; }
-            seen0 |= q == 0 ? bit : 0ull;
-            seen1 |= q == 1 ? bit : 0ull;
-            seen2 |= q == 2 ? bit : 0ull;
-            seen3 |= q == 3 ? bit : 0ull;
+            const uint32_t z = (uint32_t)__builtin_clz(pk);
+            depth += z;
+            nodes += z + 1;
+            r.skip(z);
+            const uint32_t sym = r.peek() >> 23 & 0xffu;
+            r.skip(9);
+            if (depth > 32 || nodes > 511 || r.pos > lim) { err = D_CORRUPT; break; }
             s_acode[m] = (uint32_t)A;
             s_len[m] = (uint8_t)depth;
             s_sym[m] = (uint8_t)sym;
@@ -263,7 +264,17 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
             if (depth == 0) break;  // a lone leaf is the whole tree
             A += 1ull << (32 - depth);
             if (A >= (1ull << 32)) break;  // the rightmost leaf closes the tree
+            if (m == 256) { err = D_CORRUPT; break; }  // more leaves: a symbol repeats
             depth = 32 - (uint32_t)__builtin_ctzll(A);
+        }
+        __syncthreads();
+        if (!err) {  // repeated symbols
+            bool dup = false;
+            for (uint32_t j = lane; j < m; j += 64) {
+                const uint32_t v = s_sym[j];
+                dup |= (atomicOr(&s_seen[v >> 5], 1u << (v & 31)) >> (v & 31)) & 1u;
+            }
+            if (__any(dup)) err = D_CORRUPT;
         }
         const uint32_t tb = bitlen32(p * n) - 1 + 5;
         uint64_t acc = 0;
