@@ -210,6 +210,35 @@ def main():
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": dname,
                 "avg_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(alg)}
+    # quality-progressive decode of the lossless stream: r magnitude planes
+    # left out of every block (decode only, full resolution)
+    prog = {}
+    q1_enc = pairs[0][1]
+    for r in (0, 2, 4, 6):
+        job = isx.DecodeJob()
+        job.tile = isx.tile_desc(W, H, C, 1, 8, L, qstep=1)
+        job.in_offset, job.in_bytes = 0, q1_enc.capacity
+        job.out_offset, job.out_row_stride_bytes, job.target_level = 0, W * C, 0
+        job.drop_bitplanes = r
+        dec_r = isx.Decoder([job], W * H * C)
+        dec_r.run(q1_enc.out)
+        torch.cuda.synchronize()
+        if int(dec_r.status.abs().sum().item()) != 0:
+            raise SystemExit(f"progressive decode r={r} failed")
+        if r == 2 and not args.no_cpu:
+            import oracle
+            ref = oracle.decode_tile(streams[1], 0, drop=2)
+            if not np.array_equal(dec_r.out[:W * H * C].cpu().numpy().reshape(H, W, C), ref):
+                raise SystemExit("progressive decode differs from the oracle")
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(5):
+            dec_r.run(q1_enc.out)
+        b.record(stream)
+        torch.cuda.synchronize()
+        prog[str(r)] = round(px / 1e6 / (a.elapsed_time(b) / 5 * 1e-3), 1)
+        del dec_r
+    log(f"[bench] progressive decode MP/s by dropped planes: {prog}")
     value = len(modes) * px / 1e6 / (ms * 1e-3)
     e2e_bytes = sum(2 * (raw + b) for b in stream_bytes.values())
     out = {
@@ -232,6 +261,7 @@ def main():
                    "end_to_end_hbm_frac": round(e2e_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "progressive_decode_mps": prog,
     }
     print(json.dumps(out), flush=True)
 

@@ -72,7 +72,14 @@ typedef struct {
  * coefficients").  `tile` repeats the encoded tile's parameters (the host
  * plans the workspace from them; the device checks them against the stream
  * header and reports ISX_E_CORRUPT on mismatch); tile.pixel_offset and
- * tile.row_stride_bytes are ignored. */
+ * tile.row_stride_bytes are ignored.
+ * drop_bitplanes = r > 0 asks for a lower-quality decode (Sec. 5: the seek
+ * table of a block lets the decoder discard its least significant planes):
+ * the magnitude planes b < r of every block are skipped (not decoded, not
+ * checked; the sign plane is kept), and a coefficient whose kept magnitude
+ * bits are not all zero is rebuilt at the midpoint of its unknown range,
+ * |q| = kept + 2^(r-1); otherwise it is 0.  The output is clamped to the
+ * sample range.  r = 0 is the exact decode; r > 31 is ISX_E_INVALID_ARG. */
 typedef struct {
     isx_tile_desc tile;
     uint64_t in_offset;            /* byte offset of the encoded tile in d_encoded    */
@@ -80,7 +87,7 @@ typedef struct {
     uint64_t out_offset;           /* byte offset of the output image in d_pixels_out  */
     uint32_t out_row_stride_bytes; /* >= out_width*channels*bytes_per_sample           */
     uint8_t target_level;          /* 0 .. tile.levels                                 */
-    uint8_t drop_bitplanes;        /* must be 0 (quality-progressive decode not built) */
+    uint8_t drop_bitplanes;        /* 0 .. 31: quality-progressive decode, see below    */
     uint16_t reserved;
 } isx_decode_job;                  /* 64 bytes */
 

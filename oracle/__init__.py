@@ -54,6 +54,8 @@ def lib():
         L.oracle_encode_tile.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, i32, i32, P, u64]
         L.oracle_decode_tile.restype = i32
         L.oracle_decode_tile.argtypes = [P, u64, i32, P, i32]
+        L.oracle_decode_tile_q.restype = i32
+        L.oracle_decode_tile_q.argtypes = [P, u64, i32, i32, P, i32]
         L.oracle_read_header.restype = i32
         L.oracle_read_header.argtypes = [P, u64, P]
         L.oracle_forward_dump.restype = i64
@@ -77,6 +79,8 @@ def lib():
         L.oracle_encode_block.argtypes = [P, i32, i32, i32, P, u64, P]
         L.oracle_decode_block.restype = i32
         L.oracle_decode_block.argtypes = [P, u64, i32, i32, i32, P]
+        L.oracle_decode_block_q.restype = i32
+        L.oracle_decode_block_q.argtypes = [P, u64, i32, i32, i32, i32, P]
         L.oracle_count_blocks.restype = i32
         L.oracle_count_blocks.argtypes = [i32, i32, i32, i32]
         L.oracle_block_geometry.restype = i32
@@ -145,23 +149,25 @@ def read_header(blob: bytes) -> dict:
     return dict(zip(keys, map(int, o)))
 
 
-def decode_tile(blob: bytes, level: int = 0) -> np.ndarray:
+def decode_tile(blob: bytes, level: int = 0, drop: int = 0) -> np.ndarray:
+    """Decode at resolution level `level`; `drop` = number of least significant
+    magnitude planes left out of every block (quality-progressive decode)."""
     hd = read_header(blob)
     w, h, c, bps = hd["width"], hd["height"], hd["channels"], hd["bytes_per_sample"]
     ow, oh = -(-w // (1 << level)), -(-h // (1 << level))
     dt = np.uint8 if bps == 1 else np.uint16
     out = np.zeros((oh, ow, c), dtype=dt)
     b = np.frombuffer(blob, dtype=np.uint8)
-    rc = lib().oracle_decode_tile(_ptr(b), len(b), level, _ptr(out), ow * c * bps)
+    rc = lib().oracle_decode_tile_q(_ptr(b), len(b), level, drop, _ptr(out), ow * c * bps)
     if rc:
         raise OracleError(rc)
     return out
 
 
-def decode_status(blob: bytes, level: int = 0) -> int:
+def decode_status(blob: bytes, level: int = 0, drop: int = 0) -> int:
     """Decode and return only the status code (for robustness tests)."""
     try:
-        decode_tile(blob, level)
+        decode_tile(blob, level, drop)
     except OracleError as e:
         return e.code
     return OK
@@ -275,10 +281,10 @@ def encode_block(types: np.ndarray):
     return out[:n].tobytes(), info
 
 
-def decode_block(blob: bytes, p: int, wb: int, hb: int) -> np.ndarray:
+def decode_block(blob: bytes, p: int, wb: int, hb: int, drop: int = 0) -> np.ndarray:
     b = np.frombuffer(blob, dtype=np.uint8)
     out = np.zeros((p, hb, wb), dtype=np.int32)
-    rc = lib().oracle_decode_block(_ptr(b), len(b), p, wb, hb, _ptr(out))
+    rc = lib().oracle_decode_block_q(_ptr(b), len(b), p, wb, hb, drop, _ptr(out))
     if rc:
         raise OracleError(rc)
     return out

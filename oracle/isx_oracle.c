@@ -934,8 +934,15 @@ static int tree_read(BitReader *r, TNode *nodes, int *nn, int depth, int *nleave
     return OR_OK;
 }
 
+/* Quality-progressive decode (Sec. 5: the seek table lets a decoder drop
+ * any number of the least significant planes of a block).  Reading: `drop`
+ * = r removes the magnitude planes b < r of every block (the sign plane is
+ * always kept); their segments are skipped through the seek table and not
+ * checked.  A coefficient whose kept magnitude bits are not all zero is
+ * reconstructed at the midpoint of its unknown range, |q| = kept + 2^(r-1);
+ * otherwise it is 0.  r = 0 is the exact decode. */
 static int decode_block(const uint8_t *buf, uint64_t nbytes, int p, int wb, int hb,
-                        int32_t *q /* p x 128 x 128 out */)
+                        int32_t *q /* p x 128 x 128 out */, int drop)
 {
     int n = wb * hb / 8;
     BitReader r = {buf, nbytes * 8, 0, 0};
@@ -985,6 +992,10 @@ static int decode_block(const uint8_t *buf, uint64_t nbytes, int p, int wb, int 
         int bi = seg_plane[s];
         int M = 0;
         for (int t = 0; t < p; t++) if (present[t][bi]) M += n;
+        if (bi < drop && bi != d - 1) { /* dropped magnitude plane */
+            pos_bits += seglen_bits[s];
+            continue;
+        }
         BitReader sr = {buf, pos_bits + seglen_bits[s], pos_bits, 0};
         int k = 0;
         uint64_t run = 0;
@@ -1049,6 +1060,7 @@ static int decode_block(const uint8_t *buf, uint64_t nbytes, int p, int wb, int 
     for (size_t i = 0; i < (size_t)p * 128 * 128; i++) {
         uint32_t u = (uint32_t)q[i];
         int32_t mag = (int32_t)(u & 0x7fffffffu);
+        if (drop > 0 && mag != 0) mag += (int32_t)1 << (drop - 1);
         q[i] = (u & 0x80000000u) ? -mag : mag;
     }
     return OR_OK;
@@ -1280,10 +1292,11 @@ int32_t oracle_read_header(const uint8_t *in, uint64_t len, int32_t out[9])
  * the high-pass blocks of the finer levels) interleaved, same sample type
  * as the source.  Reading: samples are clamped to [0, 2^bits - 1] after
  * the inverse colour transform (a no-op for a lossless full-size decode). */
-int32_t oracle_decode_tile(const uint8_t *in, uint64_t len, int32_t z,
-                           uint8_t *out, int32_t out_row_stride)
+int32_t oracle_decode_tile_q(const uint8_t *in, uint64_t len, int32_t z, int32_t drop,
+                             uint8_t *out, int32_t out_row_stride)
 {
     int32_t hd[9];
+    if (drop < 0 || drop > 31) return OR_E_INVALID;
     int rc = oracle_read_header(in, len, hd);
     if (rc) return rc;
     int w = hd[0], h = hd[1], ch = hd[2], bps = hd[3], bits = hd[4], lv = hd[5], ct = hd[6], qs = hd[7], nb = hd[8];
@@ -1316,7 +1329,7 @@ int32_t oracle_decode_tile(const uint8_t *in, uint64_t len, int32_t z,
         if (geo[i].level != 0 && geo[i].level <= z) break; /* finer levels not needed */
         if (pos + sz > len) { rc = OR_E_TRUNCATED; break; }
         const BlockGeo *g = &geo[i];
-        rc = decode_block(in + pos, sz, g->p, g->wb, g->hb, q);
+        rc = decode_block(in + pos, sz, g->p, g->wb, g->hb, q, drop);
         if (rc) break;
         TypeView tv[3];
         block_views(&pyr[g->chan], g, tv);
@@ -1357,6 +1370,13 @@ int32_t oracle_decode_tile(const uint8_t *in, uint64_t len, int32_t z,
     }
     for (int c = 0; c < ch; c++) { free(planes[c]); pyramid_free(&pyr[c]); }
     return rc;
+}
+
+/* Exact decode at level z (drop = 0). */
+int32_t oracle_decode_tile(const uint8_t *in, uint64_t len, int32_t z,
+                           uint8_t *out, int32_t out_row_stride)
+{
+    return oracle_decode_tile_q(in, len, z, 0, out, out_row_stride);
 }
 
 /* ================================================================== */
@@ -1426,14 +1446,15 @@ int64_t oracle_encode_block(const int32_t *types, int32_t p, int32_t wb, int32_t
 }
 
 /* Decode a single block into p dense Wb x Hb arrays. */
-int32_t oracle_decode_block(const uint8_t *in, uint64_t len, int32_t p, int32_t wb, int32_t hb,
-                            int32_t *types)
+int32_t oracle_decode_block_q(const uint8_t *in, uint64_t len, int32_t p, int32_t wb, int32_t hb,
+                              int32_t drop, int32_t *types)
 {
     if (p != 1 && p != 3) return OR_E_INVALID;
+    if (drop < 0 || drop > 31) return OR_E_INVALID;
     if (wb < 4 || hb < 4 || wb > 128 || hb > 128 || wb % 4 || hb % 4) return OR_E_INVALID;
     int32_t *q = (int32_t *)malloc(sizeof(int32_t) * 3 * 128 * 128);
     if (!q) return OR_E_NOMEM;
-    int rc = decode_block(in, len, p, wb, hb, q);
+    int rc = decode_block(in, len, p, wb, hb, q, drop);
     if (!rc)
         for (int t = 0; t < p; t++)
             for (int r = 0; r < hb; r++)
@@ -1441,6 +1462,12 @@ int32_t oracle_decode_block(const uint8_t *in, uint64_t len, int32_t p, int32_t 
                     types[(size_t)t * wb * hb + r * wb + c] = q[(size_t)t * 128 * 128 + r * 128 + c];
     free(q);
     return rc;
+}
+
+int32_t oracle_decode_block(const uint8_t *in, uint64_t len, int32_t p, int32_t wb, int32_t hb,
+                            int32_t *types)
+{
+    return oracle_decode_block_q(in, len, p, wb, hb, 0, types);
 }
 
 int32_t oracle_blockinfo_size(void) { return (int32_t)sizeof(BlockInfo); }

@@ -171,7 +171,7 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         if (mode == MODE_DECODE) {
             const isx_decode_job &j = jobs[i];
             if (j.target_level > d.levels) return ISX_E_INVALID_ARG;
-            if (j.drop_bitplanes != 0) return ISX_E_UNSUPPORTED;
+            if (j.drop_bitplanes > 31) return ISX_E_INVALID_ARG;
             z = j.target_level;
         } else if (d.row_stride_bytes < (uint64_t)d.width * d.channels * d.bytes_per_sample) {
             return ISX_E_INVALID_ARG;
@@ -189,6 +189,9 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
             T.pix_stride = j.out_row_stride_bytes;
             T.enc_offset = j.in_offset;
             T.enc_bytes = j.in_bytes;
+            T.drop = j.drop_bitplanes;
+        } else {
+            T.drop = 0;
         }
         T.block_base = (uint32_t)total_blocks;
         T.slot_base = (uint32_t)total_slots;

@@ -49,7 +49,7 @@ struct TileGeo {
     uint32_t nblocks;      // blocks handled in this call (decode: prefix to target level)
     uint32_t nblocks_stream;  // blocks of the complete stream
     uint32_t slot_base;    // first global plane slot
-    uint32_t pad;
+    uint32_t drop;         // decode: magnitude planes left out (quality-progressive)
     uint64_t sym_base;     // byte offset of this tile's symbol area (ws)
     LevelGeo lv[kMaxLevels + 1];  // index 1..levels
 };
@@ -86,7 +86,7 @@ struct PlanHdr {
 struct BlockDesc {
     uint32_t tile;
     uint32_t local;        // index within the tile's stream
-    uint8_t level, chan, p, pad0;
+    uint8_t level, chan, p, drop;  // drop: decode, magnitude planes left out
     uint16_t bx, by;
     uint16_t wb, hb;       // padded block size (multiples of 4, <= 128)
     uint8_t tw[3], th[3];  // extent of each type inside the cell (<= 128)

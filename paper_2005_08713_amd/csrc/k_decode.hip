@@ -94,6 +94,7 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
         uint64_t sz = 0, ssz = 0;
         if (local < T.nblocks) {
             block_geometry(T, local, B);
+            B.drop = (uint8_t)T.drop;
             ssz = block_sym_bytes(B, T.dmax);
             if (st == D_OK) {
                 uint64_t o = 24 + 4ull * local;
@@ -296,14 +297,18 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         err = D_TRUNC;
     }
     if (err) nseg = 0;
+    // quality-progressive decode: the segments of magnitude planes b < drop
+    // (the trailing ones) are neither queued nor read back
+    uint32_t nkeep = nseg;
+    while (nkeep > 0 && s_plane[nkeep - 1] < B.drop && s_plane[nkeep - 1] != d - 1) nkeep--;
     __syncthreads();
     if (lane == 0) {
-        P.d = d; P.nseg = nseg; P.czr = czr; P.wz = wz; P.m = m; P.p = p; P.n = n;
+        P.d = d; P.nseg = nkeep; P.czr = czr; P.wz = wz; P.m = m; P.p = p; P.n = n;
         P.err = err ? 1 : 0;
         for (uint32_t t = 0; t < 3; t++) P.masks[t] = masks[t];
         if (err) atomicMin(&status[B.tile], err);
     }
-    if (!nseg) return;
+    if (!nkeep) return;
     if (lane < nseg) {
         P.seg_plane[lane] = s_plane[lane];
         P.seg_M[lane] = s_M[lane];
@@ -345,9 +350,9 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
     }
     // work items: large segments first in the decode order
     uint32_t *ctr = (uint32_t *)(ws + H.ws_items);
-    const bool big = lane < nseg && s_bits[lane] >= kBigSegBits;
+    const bool big = lane < nkeep && s_bits[lane] >= kBigSegBits;
     const uint64_t bm = __ballot(big);
-    const uint32_t nbig = __popcll(bm), nsmall = nseg - nbig;
+    const uint32_t nbig = __popcll(bm), nsmall = nkeep - nbig;
     uint32_t bb = 0, sb = 0;
     if (lane == 0) {
         if (nbig) bb = atomicAdd(&ctr[0], nbig);
@@ -355,7 +360,7 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
     }
     bb = __shfl(bb, 0, 64);
     sb = __shfl(sb, 0, 64);
-    if (lane < nseg) {
+    if (lane < nkeep) {
         const uint64_t below = (1ull << lane) - 1ull;
         const uint32_t item = (blk << 5) | lane;
         uint32_t *list = (uint32_t *)(ws + H.ws_items + 64);
@@ -733,6 +738,11 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
 #pragma unroll
                 for (int i = 0; i < 16; i++) mag[i] |= ((v >> i) & 1u) << b;
             }
+        }
+        if (B.drop) {  // midpoint of the dropped magnitude bits
+            const uint32_t half = 1u << (B.drop - 1);
+#pragma unroll
+            for (int i = 0; i < 16; i++) mag[i] += mag[i] ? half : 0u;
         }
         uint32_t band = ci / wq, cg = ci % wq;
         uint32_t r0 = 4 * band, c0 = 4 * cg;

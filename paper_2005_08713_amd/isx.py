@@ -344,8 +344,10 @@ def _parse_header(blob: bytes):
     return tile_desc(w, h, ch, bps, bits, lv, ct=ct, qstep=q)
 
 
-def decode_streams(blobs, levels=None, device="cuda", return_status=False):
-    """Decode a batch of tile streams on the GPU (one call); returns numpy images."""
+def decode_streams(blobs, levels=None, device="cuda", return_status=False, drop=None):
+    """Decode a batch of tile streams on the GPU (one call); returns numpy images.
+    `levels` / `drop`: one value, or one per stream (resolution level z and
+    magnitude planes left out)."""
     torch = _torch()
     jobs, outs, in_off, out_off = [], [], 0, 0
     parts = []
@@ -359,6 +361,8 @@ def decode_streams(blobs, levels=None, device="cuda", return_status=False):
         j.out_offset = out_off
         j.out_row_stride_bytes = ow * d.channels * d.bytes_per_sample
         j.target_level = z
+        if drop is not None:
+            j.drop_bitplanes = drop[i] if isinstance(drop, (list, tuple)) else drop
         jobs.append(j)
         outs.append((out_off, oh, ow, d.channels, d.bytes_per_sample))
         parts.append(np.frombuffer(blob, np.uint8))

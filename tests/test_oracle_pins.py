@@ -430,6 +430,61 @@ def test_c1_workload_roundtrip():
         assert len(blob) < img.nbytes
 
 
+# ---------------------------------------------------------------- quality-progressive decode
+def _drop_planes(q, r):
+    """Definition of the reduced-quality coefficient: magnitude bits below r
+    unknown; a non-zero kept part is placed at the middle of its range."""
+    if r == 0:
+        return q
+    mag = np.abs(q) >> r << r
+    mag = np.where(mag != 0, mag + (1 << (r - 1)), 0)
+    return np.sign(q) * mag
+
+
+@pytest.mark.parametrize("kind", ["he8_lossless", "he8_step4", "gray12", "sparse"])
+def test_progressive_block_decode_matches_truncated_reader(kind):
+    """Blocks decoded with r planes left out equal the independent reader's
+    exact coefficients with the low r magnitude bits replaced per the
+    definition (Sec. 5: the seek table lets a decoder drop LSB planes)."""
+    if kind == "he8_lossless":
+        img, lv, q = synth.he_like(150, 140, 31), 3, 1
+    elif kind == "he8_step4":
+        img, lv, q = synth.he_like(150, 140, 32), 3, 4
+    elif kind == "gray12":
+        img, lv, q = synth.random_image(130, 70, 1, 12, seed=33, kind="ramp"), 2, 1
+    else:
+        img, lv, q = synth.random_image(140, 100, 3, 8, seed=34, kind="sparse"), 3, 1
+    bits = 12 if kind == "gray12" else 8
+    blob = oracle.encode_tile(img, lv, bits=bits, qstep=q)
+    hdr, blocks = fr.parse_tile(blob)
+    n_changed = 0
+    for g, data in blocks:
+        p, wb, hb = g[4], g[5], g[6]
+        exact = fr.decode_block(data, p, wb, hb)
+        for r in (1, 2, 3, 5, 9, 31):
+            got = oracle.decode_block(data, p, wb, hb, drop=r).astype(np.int64)
+            exp = _drop_planes(exact, r)
+            assert np.array_equal(got, exp), (g[:4], r)
+            n_changed += int((got != exact).sum())
+    assert n_changed > 0
+
+
+def test_progressive_tile_decode_limits_and_monotone_error():
+    img = synth.he_like(200, 160, 35)
+    blob = oracle.encode_tile(img, 4)
+    assert np.array_equal(oracle.decode_tile(blob, 0, drop=0), img)
+    # every magnitude plane dropped: all coefficients 0, and the inverse
+    # colour transform of (0, 0, 0) is black
+    for z in (0, 2):
+        assert not oracle.decode_tile(blob, z, drop=31).any()
+    errs = []
+    for r in (0, 1, 2, 3, 4, 6):
+        d = oracle.decode_tile(blob, 0, drop=r).astype(np.int64)
+        errs.append(np.abs(d - img.astype(np.int64)).mean())
+    assert errs[0] == 0 and all(a <= b + 1e-9 for a, b in zip(errs, errs[1:])), errs
+    assert oracle.decode_status(blob, 0, drop=32) == -1
+
+
 # ---------------------------------------------------------------- robustness
 def test_corrupt_and_truncated_streams_are_rejected_without_crash():
     img = synth.he_like(64, 48, 9)
