@@ -720,19 +720,25 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
     const uint32_t d = P.d, nseg = P.nseg;
     const uint32_t step = (B.level == 0) ? 1u : T.qstep;
     int32_t *wsi = (int32_t *)ws;
+    const uint8_t *sym = ws + B.sym_off;
+    const uint32_t pstr = plane_stride(p * n);
     for (uint32_t cell = tid; cell < p * cpt; cell += blockDim.x) {
-        uint32_t t = cell / cpt, ci = cell % cpt;
+        const uint32_t t = cell / cpt, ci = cell % cpt;
         uint32_t mag[16];
 #pragma unroll
         for (int i = 0; i < 16; i++) mag[i] = 0;
         uint32_t sgn = 0;
+        // predicated loads, several planes in flight
+#pragma unroll 4
         for (uint32_t s = 0; s < nseg; s++) {
-            uint32_t b = P.seg_plane[s];
+            const uint32_t b = P.seg_plane[s];
             uint32_t pm = 0;
             for (uint32_t u = 0; u < p; u++) pm |= (((P.masks[u] >> b) & 1u) ^ 1u) << u;
-            if (!((pm >> t) & 1u)) continue;
-            uint32_t rank = __popc(pm & ((1u << t) - 1u));
-            uint32_t v = *(const uint16_t *)(ws + B.sym_off + (uint64_t)b * plane_stride(p * n) + rank * n + 2 * ci);
+            uint32_t v = 0;
+            if ((pm >> t) & 1u) {
+                const uint32_t rank = __popc(pm & ((1u << t) - 1u));
+                v = *(const uint16_t *)(sym + (uint64_t)b * pstr + rank * n + 2 * ci);
+            }
             if (b == d - 1) sgn = v;
             else {
 #pragma unroll
@@ -744,20 +750,27 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
 #pragma unroll
             for (int i = 0; i < 16; i++) mag[i] += mag[i] ? half : 0u;
         }
-        uint32_t band = ci / wq, cg = ci % wq;
-        uint32_t r0 = 4 * band, c0 = 4 * cg;
+        const uint32_t band = ci / wq, cg = ci % wq;
+        const uint32_t r0 = 4 * band, c0 = 4 * cg;
         const uint32_t tw = B.tw[t], th = B.th[t];
+        const uint64_t toff = B.off[t];
+        const uint32_t tpitch = B.pitch[t];
+#pragma unroll
         for (int rr = 0; rr < 4; rr++) {
-            uint32_t row = r0 + rr;
-            if (row >= th) break;
-            int32_t *dst = wsi + B.off[t] + (uint64_t)row * B.pitch[t] + c0;
+            const uint32_t row = r0 + rr;
+            if (row >= th || c0 >= tw) continue;
+            int32_t o[4];
+#pragma unroll
             for (int cc = 0; cc < 4; cc++) {
-                if (c0 + cc >= tw) break;
-                int i = rr * 4 + cc;
+                const int i = rr * 4 + cc;
                 int32_t q = (int32_t)mag[i];
                 if (step > 1 && q) q = q * (int32_t)step + (int32_t)(step / 2);
-                dst[cc] = ((sgn >> i) & 1u) ? -q : q;
+                o[cc] = ((sgn >> i) & 1u) ? -q : q;
             }
+            int32_t *dst = wsi + toff + (uint64_t)row * tpitch + c0;
+            if (c0 + 3 < tw) *(int4 *)dst = make_int4(o[0], o[1], o[2], o[3]);
+            else
+                for (int cc = 0; cc < 4 && c0 + cc < tw; cc++) dst[cc] = o[cc];
         }
     }
     }

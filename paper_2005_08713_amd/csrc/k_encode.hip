@@ -315,13 +315,78 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
 // ---------------------------------------------------------------- Huffman
 // Code lengths of the per-block Huffman code (Sec. 3 / Sec. 4): leaves with
 // f > 0 sorted by (f, symbol); two-queue merge taking the leaf on equal
-// weight; length = depth.  256 threads; the merge itself is sequential.
+// weight; length = depth.
+//
+// The merge runs in rounds over the whole workgroup.  With s the sum of the
+// two smallest candidates (the next internal weight), every candidate of
+// weight <= s precedes every internal node created from now on (leaves win
+// ties, older internal nodes precede newer ones), so the sequential merge
+// pairs these candidates two by two in their merged order before it looks
+// at a new node: one round makes all floor(T/2) of those merges at once
+// (T = candidates <= s).  This gives the same tree as the one-at-a-time
+// merge; blocks take about ten rounds.
 struct HuffScratch {
     uint32_t w[512];
     uint16_t par[512];
     uint16_t srt[256];
+    uint16_t ord[512];
     uint32_t m;
 };
+
+__device__ void huff_merge_rounds(HuffScratch &S, uint32_t m)
+{
+    const uint32_t v = threadIdx.x;
+    constexpr uint32_t INF = 0xffffffffu;
+    uint32_t qa = 0, qb = 0, ne = 0;  // leaf head, internal head, internal count
+    while (ne + 1 < m) {
+        // the two smallest candidates (leaf first on ties)
+        const uint32_t x0 = qa < m ? S.w[qa] : INF, x1 = qa + 1 < m ? S.w[qa + 1] : INF;
+        const uint32_t y0 = qb < ne ? S.w[m + qb] : INF, y1 = qb + 1 < ne ? S.w[m + qb + 1] : INF;
+        uint32_t sum;
+        if (x0 <= y0) sum = x0 + (x1 <= y0 ? x1 : y0);
+        else sum = y0 + (x0 <= y1 ? x0 : y1);
+        // candidates <= sum in each queue (both sorted)
+        const uint32_t cl = __syncthreads_count(qa + v < m && S.w[qa + v] <= sum);
+        const uint32_t ci = __syncthreads_count(qb + v < ne && S.w[m + qb + v] <= sum);
+        const uint32_t T = cl + ci, P = T / 2;
+        // merged order: a leaf goes before internal nodes of equal weight
+        if (v < cl) {
+            const uint32_t x = S.w[qa + v];
+            uint32_t lo = 0, hi = ci;  // internal nodes < x
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (S.w[m + qb + mid] < x) lo = mid + 1; else hi = mid;
+            }
+            S.ord[v + lo] = (uint16_t)(qa + v);
+        }
+        if (v < ci) {
+            const uint32_t y = S.w[m + qb + v];
+            uint32_t lo = 0, hi = cl;  // leaves <= y
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (S.w[qa + mid] <= y) lo = mid + 1; else hi = mid;
+            }
+            S.ord[v + lo] = (uint16_t)(m + qb + v);
+        }
+        __syncthreads();
+        if (v < P) {
+            const uint32_t a = S.ord[2 * v], b = S.ord[2 * v + 1];
+            const uint32_t id = m + ne + v;
+            S.w[id] = S.w[a] + S.w[b];
+            S.par[a] = (uint16_t)id;
+            S.par[b] = (uint16_t)id;
+        }
+        // leaves among the consumed 2P candidates
+        const uint32_t lastleaf = (T & 1u) ? (S.ord[T - 1] < m ? 1u : 0u) : 0u;
+        const uint32_t nl = cl - lastleaf;
+        __syncthreads();
+        qa += nl;
+        qb += 2 * P - nl;
+        ne += P;
+    }
+    if (v == 0) S.par[m + ne - 1] = 0xffff;
+    __syncthreads();
+}
 
 __device__ void huff_lengths(const uint32_t *f, uint8_t *len, HuffScratch &S)
 {
@@ -340,27 +405,7 @@ __device__ void huff_lengths(const uint32_t *f, uint8_t *len, HuffScratch &S)
         S.w[r] = fv;
     }
     __syncthreads();
-    if (v == 0) {
-        uint32_t qa = 0, qb = m, qe = m;
-        uint32_t wa = S.w[0];
-        for (uint32_t step = 0; step + 1 < m; step++) {
-            uint32_t pick[2], pw[2];
-            for (int t = 0; t < 2; t++) {
-                bool leaf;
-                if (qa >= m) leaf = false;
-                else if (qb >= qe) leaf = true;
-                else leaf = wa <= S.w[qb];
-                if (leaf) { pick[t] = qa; pw[t] = wa; qa++; wa = (qa < m) ? S.w[qa] : 0; }
-                else { pick[t] = qb; pw[t] = S.w[qb]; qb++; }
-            }
-            S.w[qe] = pw[0] + pw[1];
-            S.par[pick[0]] = (uint16_t)qe;
-            S.par[pick[1]] = (uint16_t)qe;
-            qe++;
-        }
-        S.par[qe - 1] = 0xffff;
-    }
-    __syncthreads();
+    huff_merge_rounds(S, m);
     if (v < m) {
         uint32_t dpt = 0, x = v;
         while (S.par[x] != 0xffff) { x = S.par[x]; dpt++; }
@@ -476,22 +521,27 @@ struct CodeShared {
     uint32_t cnt[40], first[40], below[40];
     uint32_t scal[16];
     uint64_t red[4];
+    uint32_t plane[32];             // kept planes, segment order
+    uint32_t zir[32];               // per segment: zeros inside runs
+    uint32_t dig[32][kNumWz];       // per segment: run digits per counter width
     HuffScratch hs;
 };
 
-__device__ void seg_lengths(CodeShared &C, const SegStat *segstat, uint32_t slot0, const BlkPlan &Pr,
-                            uint32_t nseg, uint32_t czr, uint32_t wz)
+// Bits of every segment under the current code: symbol counts times code
+// lengths, C_zr counted once per run digit plus once per literal C_zr.
+__device__ void seg_lengths(CodeShared &C, uint32_t nseg, uint32_t czr, uint32_t wz)
 {
     const uint32_t v = threadIdx.x;
     if (v < 32) C.segbits[v] = 0;
     __syncthreads();
-    uint32_t cost = C.len[v] + (v == czr ? wz : 0u);
+    const uint32_t cost = C.len[v] + (v == czr ? wz : 0u);
     for (uint32_t s = 0; s < nseg; s++) {
         uint32_t cnt = C.sh_hist[s][v];
-        if (v == 0) cnt -= segstat[slot0 + Pr.seg_plane[s]].zir;
+        if (v == 0) cnt -= C.zir[s];
         uint32_t add = cnt * cost;
-        if (v == 0) add += segstat[slot0 + Pr.seg_plane[s]].dig[wz - 2] * (C.len[czr] + wz);
-        if (add) atomicAdd(&C.segbits[s], add);
+        if (v == 0) add += C.dig[s][wz - 2] * (C.len[czr] + wz);
+        for (int o = 32; o >= 1; o >>= 1) add += __shfl_xor(add, o, 64);
+        if ((v & 63) == 0 && add) atomicAdd(&C.segbits[s], add);
     }
     __syncthreads();
 }
@@ -518,18 +568,27 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
         }
         continue;
     }
+    // segment statistics to LDS (independent loads, all threads)
+    const uint32_t slot = B.slot;
+    if (v < nseg) C.plane[v] = P.seg_plane[v];
+    __syncthreads();
+    for (uint32_t i = v; i < nseg * (kNumWz + 1); i += blockDim.x) {
+        const uint32_t sg = i / (kNumWz + 1), k = i % (kNumWz + 1);
+        const SegStat &st = segstat[slot + C.plane[sg]];
+        if (k == kNumWz) C.zir[sg] = st.zir;
+        else C.dig[sg][k] = st.dig[k];
+    }
     // per-segment histograms into LDS, block histogram
     uint32_t h = 0;
-    for (uint32_t s = 0; s < nseg; s++) {
-        uint16_t x = seghist[(uint64_t)(B.slot + P.seg_plane[s]) * 256 + v];
-        C.sh_hist[s][v] = x;
+#pragma unroll 4
+    for (uint32_t sg = 0; sg < nseg; sg++) {
+        const uint16_t x = seghist[(uint64_t)(slot + C.plane[sg]) * 256 + v];
+        C.sh_hist[sg][v] = x;
         h += x;
     }
-    if (v == 0) {
-        uint32_t Z = 0;
-        for (uint32_t s = 0; s < nseg; s++) Z += segstat[B.slot + P.seg_plane[s]].zir;
-        C.scal[0] = Z;
-    }
+    __syncthreads();
+    uint32_t Z = 0;
+    for (uint32_t sg = 0; sg < nseg; sg++) Z += C.zir[sg];
     // C_zr: least frequent symbol, smallest value on ties (Sec. 4)
     uint64_t key = ((uint64_t)h << 8) | v;
     for (int o = 32; o >= 1; o >>= 1) { uint64_t y = __shfl_xor(key, o, 64); key = y < key ? y : key; }
@@ -538,42 +597,47 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
     uint64_t kmin = C.red[0];
     for (int i = 1; i < 4; i++) kmin = C.red[i] < kmin ? C.red[i] : kmin;
     const uint32_t czr = (uint32_t)(kmin & 0xff);
-    uint32_t lit = h - (v == 0 ? C.scal[0] : 0u);
+    uint32_t lit = h - (v == 0 ? Z : 0u);
     C.lit[v] = lit;
     C.f[v] = lit + (v == czr ? S.nruns : 0u);
     __syncthreads();
     // provisional code (each run one C_zr token) -> l
     huff_lengths(C.f, C.len, C.hs);
     const uint32_t l = C.len[czr];
-    // counter width: Eq. 3 as read, minimised over [2, max(2, beta)]
+    // counter width: Eq. 3 as read, minimised over [2, max(2, beta)]; lane
+    // w - 2 prices width w, smallest width on ties
     const uint32_t beta = bitlen32(p * n - 1);
     const uint32_t wzhi = beta > 2 ? beta : 2;
-    if (v == 0) {
-        uint64_t best = ~0ull;
-        uint32_t bw = 2;
-        for (uint32_t w = 2; w <= wzhi; w++) {
+    if (v < 64) {
+        const uint32_t w = v + 2;
+        uint64_t key2 = ~0ull;
+        if (w <= wzhi) {
             uint64_t cost = 0;
             for (uint32_t i = 1; i < 16; i++) cost += (uint64_t)S.F[i] * ((i + w - 1) / w) * (w + l);
-            if (cost < best) { best = cost; bw = w; }
+            key2 = (cost << 6) | v;  // cost < 2^56: counts < 2^24, factors < 2^6 each
         }
-        uint32_t D = 0;
-        for (uint32_t s = 0; s < nseg; s++) D += segstat[B.slot + P.seg_plane[s]].dig[bw - 2];
-        C.scal[1] = bw;
-        C.scal[2] = D;
+        for (int o = 32; o >= 1; o >>= 1) { uint64_t y = __shfl_xor(key2, o, 64); key2 = y < key2 ? y : key2; }
+        if (v == 0) {
+            const uint32_t bw = (uint32_t)(key2 & 63u) + 2;
+            uint32_t D = 0;
+            for (uint32_t sg = 0; sg < nseg; sg++) D += C.dig[sg][bw - 2];
+            C.scal[1] = bw;
+            C.scal[2] = D;
+        }
     }
     __syncthreads();
     const uint32_t wz = C.scal[1];
     C.f[v] = C.lit[v] + (v == czr ? C.scal[2] : 0u);
     __syncthreads();
     huff_lengths(C.f, C.len, C.hs);
-    seg_lengths(C, segstat, B.slot, P, nseg, czr, wz);
+    seg_lengths(C, nseg, czr, wz);
     // seek-table overflow -> length-limited fallback
     uint32_t limited = 0;
     {
         uint32_t ov = (v < nseg) && (C.segbits[v] >= (1u << tb));
         if (__syncthreads_or(ov)) {
             package_merge_lengths(C.f, 14, C.len, C.hs, Q);
-            seg_lengths(C, segstat, B.slot, P, nseg, czr, wz);
+            seg_lengths(C, nseg, czr, wz);
             limited = 1;
         }
     }
@@ -587,7 +651,7 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
     if (v < nseg) P.seg_bits[v] = C.segbits[v];
     if (v == 0) {
         uint32_t over = 0, sum = 0;
-        for (uint32_t s = 0; s < nseg; s++) { sum += C.segbits[s]; over |= C.segbits[s] >= (1u << tb); }
+        for (uint32_t sg = 0; sg < nseg; sg++) { sum += C.segbits[sg]; over |= C.segbits[sg] >= (1u << tb); }
         P.czr = czr; P.wz = wz; P.m = m; P.tbits = tb; P.limited = limited;
         P.hdr_bits = 5 + p * d + 8 + 4 + (10 * m - 1) + nseg * tb;
         P.bytes = (P.hdr_bits + sum + 7) / 8;

@@ -89,35 +89,66 @@ __global__ void __launch_bounds__(256) k_fwd_level(PlanHdr H, const uint8_t *__r
     if (threadIdx.x < WN) rmap[threadIdx.x] = reflect_idx(2 * qy0 - 2 + (int)threadIdx.x, h);
     else if (threadIdx.x < 2 * WN) cmap[threadIdx.x - WN] = reflect_idx(2 * qx0 - 2 + (int)threadIdx.x - WN, w);
     __syncthreads();
-    // stage window rows [2qy0-2, 2qy0+2TQ+1], same columns (reflected)
+    // stage window rows [2qy0-2, 2qy0+2TQ+1], same columns (reflected); all
+    // of a thread's loads are issued before its LDS stores
+    constexpr int NI = (WN * WN + 255) / 256;
+    int32_t vals[NI];
     if (level == 1) {
         const uint32_t C = T.channels, bps = T.bps;
-        for (int i = threadIdx.x; i < WN * WN; i += blockDim.x) {
-            int lr = i / WN, lc = i % WN;
-            const uint8_t *px = pix + T.pix_offset + (uint64_t)rmap[lr] * T.pix_stride + (uint32_t)cmap[lc] * C * bps;
-            int32_t v;
-            if (bps == 1) {
-                if (T.ct) {
-                    int32_t R = px[0], Gc = px[1], Bc = px[2];
-                    v = c == 0 ? ((R + 2 * Gc + Bc) >> 2) : (c == 1 ? Bc - Gc : R - Gc);
-                } else v = px[c];
-            } else {
-                const uint16_t *p16 = (const uint16_t *)px;
-                if (T.ct) {
-                    int32_t R = p16[0], Gc = p16[1], Bc = p16[2];
-                    v = c == 0 ? ((R + 2 * Gc + Bc) >> 2) : (c == 1 ? Bc - Gc : R - Gc);
-                } else v = p16[c];
+        if (bps == 1 && T.ct) {
+            // one branch-free loop per channel, so the loads of all samples
+            // are scheduled together
+            auto rgb = [&](auto f) {
+#pragma unroll
+                for (int k = 0; k < NI; k++) {
+                    const int i = (int)threadIdx.x + 256 * k;
+                    if (i >= WN * WN) break;
+                    const int lr = i / WN, lc = i % WN;
+                    const uint8_t *px =
+                        pix + T.pix_offset + (uint64_t)rmap[lr] * T.pix_stride + (uint32_t)cmap[lc] * C;
+                    vals[k] = f((int32_t)px[0], (int32_t)px[1], (int32_t)px[2]);
+                }
+            };
+            if (c == 0) rgb([](int32_t R, int32_t Gc, int32_t Bc) { return (R + 2 * Gc + Bc) >> 2; });
+            else if (c == 1) rgb([](int32_t, int32_t Gc, int32_t Bc) { return Bc - Gc; });
+            else rgb([](int32_t R, int32_t Gc, int32_t) { return R - Gc; });
+        } else {
+#pragma unroll
+            for (int k = 0; k < NI; k++) {
+                const int i = (int)threadIdx.x + 256 * k;
+                if (i >= WN * WN) break;
+                const int lr = i / WN, lc = i % WN;
+                const uint8_t *px = pix + T.pix_offset + (uint64_t)rmap[lr] * T.pix_stride + (uint32_t)cmap[lc] * C * bps;
+                int32_t v;
+                if (bps == 1) {
+                    v = px[c];
+                } else {
+                    const uint16_t *p16 = (const uint16_t *)px;
+                    if (T.ct) {
+                        int32_t R = p16[0], Gc = p16[1], Bc = p16[2];
+                        v = c == 0 ? ((R + 2 * Gc + Bc) >> 2) : (c == 1 ? Bc - Gc : R - Gc);
+                    } else v = p16[c];
+                }
+                vals[k] = v;
             }
-            win[lr * WP + lc] = v;
         }
     } else {
         int k = level - 1, which = (k & 1) ? 0 : 1;
         const int32_t *src = wsi + T.tmp_off[which] + (uint64_t)c * T.tmp_chan[which];
         const uint32_t spitch = T.tmp_pitch[which];
-        for (int i = threadIdx.x; i < WN * WN; i += blockDim.x) {
-            int lr = i / WN, lc = i % WN;
-            win[lr * WP + lc] = src[(uint64_t)rmap[lr] * spitch + cmap[lc]];
+#pragma unroll
+        for (int k2 = 0; k2 < NI; k2++) {
+            const int i = (int)threadIdx.x + 256 * k2;
+            if (i >= WN * WN) break;
+            const int lr = i / WN, lc = i % WN;
+            vals[k2] = src[(uint64_t)rmap[lr] * spitch + cmap[lc]];
         }
+    }
+#pragma unroll
+    for (int k = 0; k < NI; k++) {
+        const int i = (int)threadIdx.x + 256 * k;
+        if (i >= WN * WN) break;
+        win[(i / WN) * WP + (i % WN)] = vals[k];
     }
     __syncthreads();
     // rows: predict at odd columns 1..2TQ+1, update at even columns 2..2TQ (all rows)

@@ -63,6 +63,14 @@ def test_huffman_lengths_match_oracle():
         a, b = b, a + b
     for lim in (14, 12, 10):
         assert np.array_equal(isx.debug_huffman(f, lim), oracle.huffman_lengths(f, limit=lim))
+    # unlimited on the same weights (one merge per round), and tie-heavy cases
+    # where leaves and internal nodes of equal weight meet
+    assert np.array_equal(isx.debug_huffman(f, 0), oracle.huffman_lengths(f))
+    for g in (np.ones(256, dtype=np.uint64),
+              np.array([1 << (k % 12) for k in range(256)], dtype=np.uint64),
+              np.array([(k % 3) + 1 for k in range(256)], dtype=np.uint64),
+              np.array([1, 1, 2, 2, 4, 4, 8, 8] + [0] * 248, dtype=np.uint64)):
+        assert np.array_equal(isx.debug_huffman(g, 0), oracle.huffman_lengths(g))
     for trial in range(20):
         f = rng.integers(0, 5000, size=256).astype(np.uint64)
         f[rng.random(256) < 0.3] = 0
