@@ -330,8 +330,23 @@ struct HuffScratch {
     uint16_t par[512];
     uint16_t srt[256];
     uint16_t ord[512];
+    __attribute__((aligned(16))) uint32_t key[256];
+    uint32_t cnt[8];
     uint32_t m;
 };
+
+// Number of keys in k[0..256) below x (k is in LDS, read 4 at a time).
+__device__ inline uint32_t count_below(const uint32_t *k, uint32_t x)
+{
+    const uint4 *k4 = (const uint4 *)k;
+    uint32_t r = 0;
+#pragma unroll 16
+    for (uint32_t u = 0; u < 64; u++) {
+        const uint4 q = k4[u];
+        r += (q.x < x) + (q.y < x) + (q.z < x) + (q.w < x);
+    }
+    return r;
+}
 
 __device__ void huff_merge_rounds(HuffScratch &S, uint32_t m)
 {
@@ -345,9 +360,19 @@ __device__ void huff_merge_rounds(HuffScratch &S, uint32_t m)
         uint32_t sum;
         if (x0 <= y0) sum = x0 + (x1 <= y0 ? x1 : y0);
         else sum = y0 + (x0 <= y1 ? x0 : y1);
-        // candidates <= sum in each queue (both sorted)
-        const uint32_t cl = __syncthreads_count(qa + v < m && S.w[qa + v] <= sum);
-        const uint32_t ci = __syncthreads_count(qb + v < ne && S.w[m + qb + v] <= sum);
+        // candidates <= sum in each queue (both sorted): per-wave ballots,
+        // one barrier for both counts (4 waves)
+        const uint64_t bl = __ballot(qa + v < m && S.w[qa + v] <= sum);
+        const uint64_t bi = __ballot(qb + v < ne && S.w[m + qb + v] <= sum);
+        uint32_t *cs = S.cnt;
+        if ((v & 63) == 0) {
+            cs[v >> 6] = (uint32_t)__popcll(bl);
+            cs[4 + (v >> 6)] = (uint32_t)__popcll(bi);
+        }
+        __syncthreads();
+        uint32_t cl = 0, ci = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) { cl += cs[k]; ci += cs[4 + k]; }
         const uint32_t T = cl + ci, P = T / 2;
         // merged order: a leaf goes before internal nodes of equal weight
         if (v < cl) {
@@ -395,12 +420,12 @@ __device__ void huff_lengths(const uint32_t *f, uint8_t *len, HuffScratch &S)
     uint32_t m = __syncthreads_count(fv > 0);
     len[v] = 0;
     if (m <= 1) { __syncthreads(); return; }
+    // rank by (f, symbol): key f << 8 | symbol (f < 2^24), absent = max
+    const uint32_t kv = fv > 0 ? (fv << 8) | v : 0xffffffffu;
+    S.key[v] = kv;
+    __syncthreads();
     if (fv > 0) {
-        uint32_t r = 0;
-        for (uint32_t u = 0; u < 256; u++) {
-            uint32_t fu = f[u];
-            r += (fu > 0) && (fu < fv || (fu == fv && u < v));
-        }
+        const uint32_t r = count_below(S.key, kv);
         S.srt[r] = (uint16_t)v;
         S.w[r] = fv;
     }
@@ -477,14 +502,19 @@ __device__ void package_merge_lengths(const uint32_t *f, int limit, uint8_t *len
     __syncthreads();
 }
 
-// Canonical codes (sort by (length, symbol), count up) and the leaf order.
+// Canonical codes (sort by (length, symbol), count up) and the leaf order:
+// the position of a symbol in (length, symbol) order is its count of smaller
+// keys, its index within its length that position minus the symbols of
+// shorter codes.
 __device__ void canonical(const uint8_t *len, uint32_t *code, uint8_t *order, uint32_t *s_cnt,
-                          uint32_t *s_first, uint32_t *s_below)
+                          uint32_t *s_first, uint32_t *s_below, uint32_t *s_key)
 {
     const uint32_t v = threadIdx.x;
     if (v < 40) s_cnt[v] = 0;
     __syncthreads();
-    uint32_t lv = len[v];
+    const uint32_t lv = len[v];
+    const uint32_t kv = lv ? (lv << 8) | v : 0xffffffffu;
+    s_key[v] = kv;
     if (lv) atomicAdd(&s_cnt[lv], 1u);
     __syncthreads();
     if (v == 0) {
@@ -500,10 +530,9 @@ __device__ void canonical(const uint8_t *len, uint32_t *code, uint8_t *order, ui
     }
     __syncthreads();
     if (lv) {
-        uint32_t idx = 0;
-        for (uint32_t u = 0; u < v; u++) idx += len[u] == lv;
-        code[v] = s_first[lv] + idx;
-        order[s_below[lv] + idx] = (uint8_t)v;
+        const uint32_t pos = count_below(s_key, kv);
+        code[v] = s_first[lv] + (pos - s_below[lv]);
+        order[pos] = (uint8_t)v;
     } else {
         code[v] = 0;
     }
@@ -641,7 +670,7 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
             limited = 1;
         }
     }
-    canonical(C.len, C.code, C.order, C.cnt, C.first, C.below);
+    canonical(C.len, C.code, C.order, C.cnt, C.first, C.below, C.hs.key);
     uint32_t m = __syncthreads_count(C.f[v] > 0);
     if (m == 1 && C.f[v] > 0) C.order[0] = (uint8_t)v;  // single leaf: code length 0
     __syncthreads();
