@@ -667,17 +667,62 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
         const uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
         __syncthreads();  // the previous item is done with S
         {
+            // code tables (352 x 16 bytes): all loads of a lane first
+            static_assert(kLutStride / 16 > 320 && kLutStride / 16 <= 384, "table copy layout");
             const uint4 *src = (const uint4 *)tab;
             uint4 *dst = (uint4 *)S.lut;
-            for (uint32_t i = lane; i < kLutStride / 16; i += 64) dst[i] = src[i];
+            const uint4 a0 = src[lane], a1 = src[lane + 64], a2 = src[lane + 128], a3 = src[lane + 192],
+                        a4 = src[lane + 256];
+            const bool l5 = lane + 320 < kLutStride / 16;
+            const uint4 a5 = l5 ? src[lane + 320] : make_uint4(0, 0, 0, 0);
+            dst[lane] = a0; dst[lane + 64] = a1; dst[lane + 128] = a2; dst[lane + 192] = a3; dst[lane + 256] = a4;
+            if (l5) dst[lane + 320] = a5;
         }
         const uint64_t lo = B.byte_off, hi = B.byte_off + B.byte_len;
         const uint64_t w0 = S0 >> 5;
         const uint32_t off = (uint32_t)(S0 & 31);
         const uint32_t nw = N ? (uint32_t)(((S0 + N - 1) >> 5) + 2 - w0) : 0u;
         const bool staged = nw <= kSegWords;
-        if (staged)
-            for (uint32_t i = lane; i < nw + 2; i += 64) S.bits[i] = i < nw ? stream_word(enc, lo, hi, w0 + i) : 0u;
+        if (staged) {
+            // words w0 .. w0+nw-1 from 16-byte loads (4 per lane in flight);
+            // a chunk not wholly inside the block falls back to bytes
+            const bool al16 = (((uintptr_t)enc) & 15u) == 0;
+            const uint64_t c0 = (w0 * 4) & ~15ull, c1 = (w0 + nw) * 4;
+            const uint32_t nch = (uint32_t)((c1 - c0 + 15) / 16);
+            for (uint32_t base = 0; base < nch; base += 256) {
+                uint4 q[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t ci = base + lane + 64 * k;
+                    const uint64_t cb = c0 + 16ull * ci;
+                    if (ci < nch && al16 && cb >= lo && cb + 16 <= hi) q[k] = *(const uint4 *)(enc + cb);
+                    else if (ci < nch) {
+                        q[k].x = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4));
+                        q[k].y = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4 + 1));
+                        q[k].z = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4 + 2));
+                        q[k].w = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4 + 3));
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t ci = base + lane + 64 * k;
+                    if (ci >= nch) continue;
+                    const int64_t r0 = (int64_t)((c0 / 4) + 4ull * ci) - (int64_t)w0;  // staged index of q[k].x
+                    if (r0 >= 0 && r0 + 3 < (int64_t)nw) {
+                        S.bits[r0] = __builtin_bswap32(q[k].x);
+                        S.bits[r0 + 1] = __builtin_bswap32(q[k].y);
+                        S.bits[r0 + 2] = __builtin_bswap32(q[k].z);
+                        S.bits[r0 + 3] = __builtin_bswap32(q[k].w);
+                    } else {
+                        if (r0 >= 0 && r0 < (int64_t)nw) S.bits[r0] = __builtin_bswap32(q[k].x);
+                        if (r0 + 1 >= 0 && r0 + 1 < (int64_t)nw) S.bits[r0 + 1] = __builtin_bswap32(q[k].y);
+                        if (r0 + 2 >= 0 && r0 + 2 < (int64_t)nw) S.bits[r0 + 2] = __builtin_bswap32(q[k].z);
+                        if (r0 + 3 >= 0 && r0 + 3 < (int64_t)nw) S.bits[r0 + 3] = __builtin_bswap32(q[k].w);
+                    }
+                }
+            }
+            if (lane < 2) S.bits[nw + lane] = 0u;
+        }
         const uint32_t M16 = (M + 15) / 16;
         for (uint32_t i = lane; i < M16; i += 64) S.stg[i] = make_uint4(0, 0, 0, 0);
         __syncthreads();
