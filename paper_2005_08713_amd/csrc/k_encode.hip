@@ -794,6 +794,7 @@ __global__ void __launch_bounds__(256) k_enc_tile_finish(PlanHdr H, const uint8_
 
 // ---------------------------------------------------------------- pack
 constexpr int kStageWords = 4160;  // > (2^17 + 64) / 32
+constexpr uint32_t kPackPT = 24;   // symbols per thread: 256 x 24 >= 6144
 
 __device__ inline void put_bits(uint32_t *st, uint32_t pos, uint32_t val, uint32_t nb)
 {
@@ -900,32 +901,56 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
     const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride(P.p * P.n);
     const uint32_t czr = P.czr, wz = P.wz, Bb = (1u << wz) - 1u;
     const uint32_t lz = s_len[czr];
-    const uint32_t chunk = (M + 255) / 256;
+    const uint32_t chunk = (M + 255) / 256;  // <= kPackPT for M <= 6144
     const uint32_t lo = tid * chunk;
     uint32_t hi = lo + chunk;
     if (hi > M) hi = M;
-    uint8_t loc[32];
+    uint32_t lw[kPackPT / 4];  // the thread's symbols, 4 per register
     int32_t lastnz = -1;
-    for (uint32_t i = 0; i < 32; i++) {
-        uint32_t ps = lo + i;
-        loc[i] = (ps < hi) ? syms[ps] : 0;
-        if (ps < hi && loc[i]) lastnz = (int32_t)ps;
+#pragma unroll
+    for (uint32_t k = 0; k < kPackPT / 4; k++) lw[k] = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kPackPT; i++) {
+        const uint32_t ps = lo + i;
+        const uint32_t b = (ps < hi) ? syms[ps] : 0u;
+        lw[i / 4] |= b << (8 * (i % 4));
+        if (b) lastnz = (int32_t)ps;
     }
+#define LOC(i) ((lw[(i) / 4] >> (8 * ((i) % 4))) & 0xffu)
     int32_t prev = block_excl_max_i32<256>(lastnz, shi);
-    // pass 1: bit count
+    // token bits, branch-free: a symbol that ends a zero run (non-zero, or
+    // the segment's last) emits the run (one zero literal for length 1, else
+    // nd(L) digit tokens) and then itself when non-zero
+    const uint32_t tokz = lz + wz;
+    const uint32_t lit0 = s_len[0] + (czr == 0 ? wz : 0u);
+    // nd(L) = 1 + #{k >= 1 : B + B^2 + ... + B^k < L}; 8 digits cover L <= 6144
+    uint32_t thr[7];
+    {
+        uint64_t pw = Bb, t = Bb;
+#pragma unroll
+        for (int k = 0; k < 7; k++) {
+            thr[k] = t > 0xffffffffull ? 0xffffffffu : (uint32_t)t;
+            pw *= Bb;
+            t += pw;
+        }
+    }
     uint32_t bits = 0;
     {
         int32_t cur = prev;
-        for (uint32_t i = 0; i < 32 && lo + i < hi; i++) {
-            uint32_t v = loc[i];
-            int32_t ps = (int32_t)(lo + i);
-            bool endseg = (uint32_t)ps == M - 1;
-            if (v || endseg) {
-                int32_t L = v ? (ps - cur - 1) : (ps - cur);
-                if (L == 1) bits += s_len[0] + (czr == 0 ? wz : 0u);
-                else if (L >= 2) bits += bij_digits((uint32_t)L, Bb) * (lz + wz);
-                if (v) { bits += s_len[v] + (v == czr ? wz : 0u); cur = ps; }
-            }
+#pragma unroll
+        for (uint32_t i = 0; i < kPackPT; i++) {
+            const uint32_t v = LOC(i);
+            const int32_t ps = (int32_t)(lo + i);
+            const bool valid = (uint32_t)ps < hi;
+            const bool term = valid && (v != 0 || (uint32_t)ps == M - 1);
+            const int32_t L = v ? (ps - cur - 1) : (ps - cur);
+            uint32_t nd = 1;
+#pragma unroll
+            for (int k = 0; k < 7; k++) nd += thr[k] < (uint32_t)L;
+            const uint32_t runb = (L == 1) ? lit0 : (L >= 2 ? nd * tokz : 0u);
+            const uint32_t litb = v ? s_len[v] + (v == czr ? wz : 0u) : 0u;
+            bits += term ? runb + litb : 0u;
+            cur = (valid && v) ? ps : cur;
         }
     }
     uint64_t off = block_excl_sum_u64<256>(bits, sh, nullptr);
@@ -933,32 +958,36 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
     {
         uint32_t bp = o + (uint32_t)off;
         int32_t cur = prev;
-        for (uint32_t i = 0; i < 32 && lo + i < hi; i++) {
-            uint32_t v = loc[i];
-            int32_t ps = (int32_t)(lo + i);
-            bool endseg = (uint32_t)ps == M - 1;
-            if (v || endseg) {
-                int32_t L = v ? (ps - cur - 1) : (ps - cur);
-                if (L == 1) {
-                    put_bits(st, bp, s_code[0], s_len[0]); bp += s_len[0];
-                    if (czr == 0) bp += wz;  // literal C_zr: counter 0
-                } else if (L >= 2) {
-                    // bijective base-(2^wz - 1) digits, most significant first
-                    uint32_t dg[16], nd = 0, x = (uint32_t)L;
-                    while (x > 0) { uint32_t q = (x - 1) / Bb; dg[nd++] = x - q * Bb; x = q; }
-                    for (int k = (int)nd - 1; k >= 0; k--) {
-                        put_bits(st, bp, s_code[czr], lz); bp += lz;
-                        put_bits(st, bp, dg[k], wz); bp += wz;
-                    }
+#pragma unroll
+        for (uint32_t i = 0; i < kPackPT; i++) {
+            const uint32_t v = LOC(i);
+            const int32_t ps = (int32_t)(lo + i);
+            const bool valid = (uint32_t)ps < hi;
+            const bool term = valid && (v != 0 || (uint32_t)ps == M - 1);
+            const int32_t L = v ? (ps - cur - 1) : (ps - cur);
+            cur = (valid && v) ? ps : cur;
+            if (!term) continue;
+            if (L == 1) {
+                put_bits(st, bp, s_code[0], s_len[0]);  // literal zero (counter 0 when it is C_zr)
+                bp += lit0;
+            } else if (L >= 2) {
+                // bijective base-(2^wz - 1) digits, most significant first
+                uint32_t dg[8], nd = 0, x = (uint32_t)L;
+                while (x > 0 && nd < 8) { uint32_t q = (x - 1) / Bb; dg[nd++] = x - q * Bb; x = q; }
+                for (int k = (int)nd - 1; k >= 0; k--) {
+                    put_bits(st, bp, s_code[czr], lz);
+                    put_bits(st, bp + lz, dg[k], wz);
+                    bp += tokz;
                 }
-                if (v) {
-                    put_bits(st, bp, s_code[v], s_len[v]); bp += s_len[v];
-                    if (v == czr) bp += wz;
-                    cur = ps;
-                }
+            }
+            if (v) {
+                const uint32_t lv = s_len[v];
+                put_bits(st, bp, s_code[v], lv);
+                bp += lv + (v == czr ? wz : 0u);
             }
         }
     }
+#undef LOC
     __syncthreads();
     flush_bits(st, abit, nbits, outw);
 }
