@@ -794,7 +794,8 @@ __global__ void __launch_bounds__(256) k_enc_tile_finish(PlanHdr H, const uint8_
 
 // ---------------------------------------------------------------- pack
 constexpr int kStageWords = 4160;  // > (2^17 + 64) / 32
-constexpr uint32_t kPackPT = 24;   // symbols per thread: 256 x 24 >= 6144
+constexpr uint32_t kPackNT = 512;  // packer workgroup
+constexpr uint32_t kPackPT = 12;   // symbols per thread: 512 x 12 >= 6144
 
 __device__ inline void put_bits(uint32_t *st, uint32_t pos, uint32_t val, uint32_t nb)
 {
@@ -824,8 +825,8 @@ struct PackShared {
     uint32_t st[kStageWords];
     uint32_t s_code[256];
     uint8_t s_len[256];
-    uint64_t sh[4];
-    int32_t shi[4];
+    uint64_t sh[kPackNT / 64];
+    int32_t shi[kPackNT / 64];
 };
 
 // Pack one item: y = 0 the block header, y = 1.. segment y-1.
@@ -876,7 +877,7 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
                     zj = lj - lp + (uint32_t)__builtin_ctz(~cp);  // trailing ones of the previous code
                 }
             }
-            uint64_t ex = block_excl_sum_u64<256>(tid < m ? (uint64_t)(zj + 9) : 0ull, sh, nullptr);
+            uint64_t ex = block_excl_sum_u64<kPackNT>(tid < m ? (uint64_t)(zj + 9) : 0ull, sh, nullptr);
             if (tid < m) put_bits(st, tree0 + (uint32_t)ex + zj, 0x100u | sym, 9);
             const uint32_t seek0 = tree0 + 10 * m - 1;
             if (tid < nseg) put_bits(st, seek0 + tid * P.tbits, P.seg_bits[tid], P.tbits);
@@ -894,14 +895,16 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
     const uint32_t o = (uint32_t)(abit & 31u);
     const uint32_t nw = (o + nbits + 31) >> 5;
     for (uint32_t i = tid; i < nw + 1; i += blockDim.x) st[i] = 0;
-    s_code[tid] = P.code[tid];
-    s_len[tid] = P.len[tid];
+    if (tid < 256) {
+        s_code[tid] = P.code[tid];
+        s_len[tid] = P.len[tid];
+    }
     __syncthreads();
     const uint32_t M = P.seg_M[s];
     const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride(P.p * P.n);
     const uint32_t czr = P.czr, wz = P.wz, Bb = (1u << wz) - 1u;
     const uint32_t lz = s_len[czr];
-    const uint32_t chunk = (M + 255) / 256;  // <= kPackPT for M <= 6144
+    const uint32_t chunk = (M + kPackNT - 1) / kPackNT;  // <= kPackPT for M <= 6144
     const uint32_t lo = tid * chunk;
     uint32_t hi = lo + chunk;
     if (hi > M) hi = M;
@@ -917,7 +920,7 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
         if (b) lastnz = (int32_t)ps;
     }
 #define LOC(i) ((lw[(i) / 4] >> (8 * ((i) % 4))) & 0xffu)
-    int32_t prev = block_excl_max_i32<256>(lastnz, shi);
+    int32_t prev = block_excl_max_i32<kPackNT>(lastnz, shi);
     // token bits, branch-free: a symbol that ends a zero run (non-zero, or
     // the segment's last) emits the run (one zero literal for length 1, else
     // nd(L) digit tokens) and then itself when non-zero
@@ -953,7 +956,7 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
             cur = (valid && v) ? ps : cur;
         }
     }
-    uint64_t off = block_excl_sum_u64<256>(bits, sh, nullptr);
+    uint64_t off = block_excl_sum_u64<kPackNT>(bits, sh, nullptr);
     // pass 2: write
     {
         uint32_t bp = o + (uint32_t)off;
@@ -992,7 +995,7 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
     flush_bits(st, abit, nbits, outw);
 }
 
-__global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__restrict__ ws,
+__global__ void __launch_bounds__(kPackNT) k_enc_pack(PlanHdr H, const uint8_t *__restrict__ ws,
                                                   uint8_t *__restrict__ out)
 {
     __shared__ PackShared S;
@@ -1000,7 +1003,7 @@ __global__ void __launch_bounds__(256) k_enc_pack(PlanHdr H, const uint8_t *__re
 }
 
 // Persistent variant: segment-major items over a fixed grid.
-__global__ void __launch_bounds__(256) k_enc_pack_pers(PlanHdr H, const uint8_t *__restrict__ ws,
+__global__ void __launch_bounds__(kPackNT) k_enc_pack_pers(PlanHdr H, const uint8_t *__restrict__ ws,
                                                        uint8_t *__restrict__ out)
 {
     __shared__ PackShared S;
@@ -1062,9 +1065,9 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             if (H.total_blocks)
             {
                 if (H.blocks_per_cu)
-                    hipLaunchKernelGGL(k_enc_pack_pers, dim3(H.blk_grid), dim3(256), 0, stream, H, d_ws, d_out);
+                    hipLaunchKernelGGL(k_enc_pack_pers, dim3(H.blk_grid), dim3(kPackNT), 0, stream, H, d_ws, d_out);
                 else
-                    hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, 33), dim3(256), 0, stream, H, d_ws, d_out);
+                    hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, 33), dim3(kPackNT), 0, stream, H, d_ws, d_out);
             }
         }
     }
