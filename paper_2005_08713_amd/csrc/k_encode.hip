@@ -121,14 +121,13 @@ constexpr int kCellsPT = 3;  // 3 cells per thread: 1024 threads cover a 128x128
 // threads) and at most 768 cells (256 threads); the plan lists the blocks of
 // each class, large ones first.
 template <int kSymNT>
-__global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t *__restrict__ plan,
+__global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint8_t *__restrict__ plan,
                                                         uint8_t *__restrict__ ws, uint32_t list0,
                                                         uint32_t nlist)
 {
     __shared__ uint32_t hist[256];
     __shared__ int32_t wsh[kSymNT / 64];
     __shared__ uint32_t s_zir, s_dig[kNumWz], s_F[16], s_nruns, s_zero, s_pruns;
-    __shared__ __align__(16) uint16_t stg[kSymNT * kCellsPT];  // one plane's symbols (2 per cell)
     const uint32_t *list = (const uint32_t *)(plan + H.list_off) + list0;
     for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
     const uint32_t blk = list[li];
@@ -151,52 +150,69 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
     for (int t = 0; t < 3; t++)
         pres[t] = (t < (int)p) ? ((A.or_mag[t] & ((1u << (d - 1)) - 1u)) | (((A.neg >> t) & 1u) << (d - 1))) : 0u;
 
-    // load own cells (16 magnitudes + sign bits each)
-    uint32_t mag[kCellsPT][16];
-    uint32_t sgn[kCellsPT];
-    uint32_t ctype[kCellsPT], cci[kCellsPT];
+    // phase A: every cell (4x4 coefficients) once -- its signed-magnitude
+    // bits go straight to the block's symbol planes (the 16-bit pair of 4x2
+    // area symbols of each kept plane, Eq. 1-2); consecutive threads take
+    // consecutive cells so the 2-byte stores coalesce
     const uint32_t ncell = p * cpt;
-#pragma unroll
+    const uint32_t pstr = plane_stride(p * n);
+    uint8_t *symb = ws + B.sym_off;
+    const BlockDesc &Bg = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+#pragma unroll 1
     for (int k = 0; k < kCellsPT; k++) {
-        uint32_t cell = tid * kCellsPT + k;
-        sgn[k] = 0;
-        ctype[k] = 3;
-        cci[k] = 0;
-#pragma unroll
-        for (int i = 0; i < 16; i++) mag[k][i] = 0;
-        if (cell >= ncell) continue;
-        uint32_t t = cell / cpt, ci = cell % cpt;
-        ctype[k] = t;
-        cci[k] = ci;
-        uint32_t band = ci / wq, cg = ci % wq;
-        uint32_t r0 = 4 * band, c0 = 4 * cg;
-        // per-type fields read through the global copy (a runtime index into a
-        // register copy would put the whole descriptor in scratch)
-        const BlockDesc &Bg = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+        const uint32_t cell = (uint32_t)k * kSymNT + tid;
+        if (cell >= ncell) break;
+        const uint32_t t = cell / cpt, ci = cell % cpt;
+        const uint32_t band = ci / wq, cg = ci % wq;
+        const uint32_t r0 = 4 * band, c0 = 4 * cg;
+        // per-type fields read through the global copy (a runtime index into
+        // a register copy would put the whole descriptor in scratch)
         const uint32_t tw = Bg.tw[t], th = Bg.th[t];
         const uint64_t toff = Bg.off[t];
         const uint32_t tpitch = Bg.pitch[t];
+        uint32_t mag[16], sgn = 0;
 #pragma unroll
         for (int rr = 0; rr < 4; rr++) {
-            uint32_t row = r0 + rr;
-            if (row >= th || c0 >= tw) continue;
-            const int32_t *src = wsi + toff + (uint64_t)row * tpitch + c0;
-            int32_t v[4];
-            if (c0 + 3 < tw) {
-                int4 q = *(const int4 *)src;
-                v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-            } else {
+            const uint32_t row = r0 + rr;
+            int32_t v[4] = {0, 0, 0, 0};
+            if (row < th && c0 < tw) {
+                const int32_t *src = wsi + toff + (uint64_t)row * tpitch + c0;
+                if (c0 + 3 < tw) {
+                    const int4 q = *(const int4 *)src;
+                    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+                } else {
 #pragma unroll
-                for (int cc = 0; cc < 4; cc++) v[cc] = (c0 + cc < tw) ? src[cc] : 0;
+                    for (int cc = 0; cc < 4; cc++) v[cc] = (c0 + cc < tw) ? src[cc] : 0;
+                }
             }
 #pragma unroll
             for (int cc = 0; cc < 4; cc++) {
-                int32_t x = v[cc];
-                mag[k][rr * 4 + cc] = (uint32_t)(x < 0 ? -x : x);
-                sgn[k] |= (x < 0 ? 1u : 0u) << (rr * 4 + cc);
+                mag[rr * 4 + cc] = (uint32_t)(v[cc] < 0 ? -v[cc] : v[cc]);
+                sgn |= (v[cc] < 0 ? 1u : 0u) << (rr * 4 + cc);
             }
         }
+        for (int b = (int)d - 1; b >= 0; b--) {
+            const uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
+            if (!((pm >> t) & 1u)) continue;
+            uint32_t v = 0;
+            if ((uint32_t)b == d - 1) v = sgn;
+            else {
+#pragma unroll
+                for (int i = 0; i < 16; i++) v |= ((mag[i] >> b) & 1u) << i;
+            }
+            const uint32_t rank = __popc(pm & ((1u << t) - 1u));
+            *(uint16_t *)(symb + (uint64_t)b * pstr + rank * n + 2 * ci) = (uint16_t)v;
+        }
     }
+    // phase B reads the planes back with a thread-contiguous cell layout
+    uint32_t ctype[kCellsPT], cci[kCellsPT];
+#pragma unroll
+    for (int k = 0; k < kCellsPT; k++) {
+        const uint32_t cell = tid * kCellsPT + k;
+        ctype[k] = cell < ncell ? cell / cpt : 3u;
+        cci[k] = cell < ncell ? cell % cpt : 0u;
+    }
+    __threadfence_block();
 
     for (uint32_t i = tid; i < 256; i += kSymNT) hist[i] = 0;
     if (tid < kNumWz) s_dig[tid] = 0;
@@ -210,7 +226,7 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
         if (!pm) continue;
         uint32_t M = n * __popc(pm);
         uint8_t *segp = ws + B.sym_off + (uint64_t)b * plane_stride(p * n);
-        // symbols of own cells
+        // symbols of own cells (written in phase A)
         uint32_t sy[kCellsPT], pos[kCellsPT];
         int32_t lastnz = -1;
         uint32_t zeros = 0;
@@ -218,20 +234,17 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
         for (int k = 0; k < kCellsPT; k++) {
             sy[k] = 0;
             pos[k] = 0xffffffffu;
-            uint32_t t = ctype[k];
+            const uint32_t t = ctype[k];
             if (t > 2 || !((pm >> t) & 1u)) continue;
-            uint32_t v = 0;
-            if ((uint32_t)b == d - 1) v = sgn[k];
-            else {
+            const uint32_t rank = __popc(pm & ((1u << t) - 1u));
+            pos[k] = rank * n + 2 * cci[k];
+            sy[k] = *(const uint16_t *)(segp + pos[k]);
+        }
 #pragma unroll
-                for (int i = 0; i < 16; i++) v |= ((mag[k][i] >> b) & 1u) << i;
-            }
-            uint32_t rank = __popc(pm & ((1u << t) - 1u));
-            uint32_t ps = rank * n + 2 * cci[k];
-            pos[k] = ps;
-            sy[k] = v;
-            stg[ps >> 1] = (uint16_t)v;
-            uint32_t top = v & 0xffu, bot = v >> 8;
+        for (int k = 0; k < kCellsPT; k++) {
+            if (pos[k] == 0xffffffffu) continue;
+            const uint32_t v = sy[k], ps = pos[k];
+            const uint32_t top = v & 0xffu, bot = v >> 8;
             if (top) { atomicAdd(&hist[top], 1u); lastnz = (int32_t)ps; } else zeros++;
             if (bot) { atomicAdd(&hist[bot], 1u); lastnz = (int32_t)ps + 1; } else zeros++;
         }
@@ -276,8 +289,6 @@ __global__ void __launch_bounds__(kSymNT) k_enc_symbols(PlanHdr H, const uint8_t
             }
         }
         __syncthreads();
-        // the plane's symbols, contiguous, as 16-byte stores
-        for (uint32_t i = tid; i < (M + 15) / 16; i += kSymNT) ((uint4 *)segp)[i] = ((const uint4 *)stg)[i];
         uint32_t slot = B.slot + (uint32_t)b;
         for (uint32_t i = tid; i < 256; i += kSymNT) {
             uint32_t hv = hist[i];
