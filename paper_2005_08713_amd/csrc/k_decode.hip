@@ -453,15 +453,20 @@ __device__ inline uint32_t dec_token(const Src &S, const DecTab &T, uint32_t r, 
 
 // Run-length bookkeeping of a token range as an affine map on (pos, R):
 // pos = output position, R = value of the pending run of C_zr digits.
-// Values saturate at kSat (only corrupt streams get there).
-constexpr uint32_t kSat = 1u << 30;
-__device__ inline uint32_t sadd(uint32_t a, uint32_t b) { uint32_t r = a + b; return r > kSat ? kSat : r; }
-__device__ inline uint32_t smul(uint32_t a, uint32_t b) { uint64_t r = (uint64_t)a * b; return r > kSat ? kSat : (uint32_t)r; }
-// R * (2^wz - 1) + c, saturated
+// Values saturate at kSat = 2^18: a segment holds at most 6144 symbols, so a
+// saturated value always ends as a corrupt-stream error, and every per-token
+// product (R < 2^18 times 2^wz - 1 < 2^13) stays in 32 bits.
+constexpr uint32_t kSat = 1u << 18;
+__device__ inline uint32_t sadd(uint32_t a, uint32_t b) { return min(a + b, kSat); }  // a, b <= kSat
+__device__ inline uint32_t smul(uint32_t a, uint32_t b)
+{
+    const uint64_t r = (uint64_t)a * b;
+    return r > kSat ? kSat : (uint32_t)r;
+}
+// R * (2^wz - 1) + c, saturated (R <= kSat, wz <= 13, c < 2^wz)
 __device__ inline uint32_t run_push(uint32_t R, uint32_t c, uint32_t wz)
 {
-    const uint64_t x = ((uint64_t)R << wz) - R + c;
-    return x > kSat ? kSat : (uint32_t)x;
+    return min((R << wz) - R + c, kSat);
 }
 struct RunXf {
     uint32_t lit;  // the range holds a literal symbol
@@ -486,17 +491,18 @@ __device__ inline RunXf xf_combine(const RunXf &a, const RunXf &b)
     }
     return r;
 }
-// append one token (a C_zr digit when dig, else an output symbol)
+// append one token (a C_zr digit when dig, else an output symbol); no branches
 __device__ inline void xf_push(RunXf &f, bool dig, uint32_t c, uint32_t wz)
 {
-    const uint32_t R = f.lit ? f.V1 : f.V0;
+    const bool lit = f.lit != 0;
+    const uint32_t R = lit ? f.V1 : f.V0;
     const uint32_t Rn = run_push(R, c, wz);
     const uint32_t P0n = run_push(f.P0, 0, wz);
-    const uint32_t midl = f.lit ? sadd(f.mid, sadd(f.V1, 1u)) : 1u;
-    const bool first = dig && !f.lit;
+    const uint32_t midl = lit ? min(f.mid + f.V1 + 1u, kSat) : 1u;
+    const bool first = dig && !lit;
     f.V0 = first ? Rn : f.V0;
     f.P0 = first ? P0n : f.P0;
-    f.V1 = dig ? (f.lit ? Rn : f.V1) : 0u;
+    f.V1 = dig ? (lit ? Rn : f.V1) : 0u;
     f.mid = dig ? f.mid : midl;
     f.lit = dig ? f.lit : 1u;
 }
