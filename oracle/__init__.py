@@ -69,6 +69,11 @@ def lib():
         L.oracle_rct_inverse.restype = None
         L.oracle_rct_inverse.argtypes = [i32, i32, i32, P]
         L.oracle_rct_selftest_u8.restype = i64
+        L.oracle_ycocg_selftest_u8.restype = i64
+        L.oracle_ycocg_forward.restype = None
+        L.oracle_ycocg_forward.argtypes = [i32, i32, i32, P]
+        L.oracle_ycocg_inverse.restype = None
+        L.oracle_ycocg_inverse.argtypes = [i32, i32, i32, P]
         L.oracle_area_coord.restype = None
         L.oracle_area_coord.argtypes = [i32, i32, i32, i32, P]
         L.oracle_huffman_lengths.restype = i32
@@ -99,8 +104,8 @@ def _as_hwc(pixels: np.ndarray) -> np.ndarray:
     a = np.ascontiguousarray(pixels)
     if a.ndim == 2:
         a = a[:, :, None]
-    if a.dtype not in (np.uint8, np.uint16):
-        raise TypeError("pixels must be uint8 or uint16")
+    if a.dtype not in (np.uint8, np.uint16, np.uint32):
+        raise TypeError("pixels must be uint8, uint16 or uint32")
     return a
 
 
@@ -155,7 +160,7 @@ def decode_tile(blob: bytes, level: int = 0, drop: int = 0) -> np.ndarray:
     hd = read_header(blob)
     w, h, c, bps = hd["width"], hd["height"], hd["channels"], hd["bytes_per_sample"]
     ow, oh = -(-w // (1 << level)), -(-h // (1 << level))
-    dt = np.uint8 if bps == 1 else np.uint16
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[bps]
     out = np.zeros((oh, ow, c), dtype=dt)
     b = np.frombuffer(blob, dtype=np.uint8)
     rc = lib().oracle_decode_tile_q(_ptr(b), len(b), level, drop, _ptr(out), ow * c * bps)
@@ -243,6 +248,22 @@ def rct_inverse(y, cb, cr):
 
 def rct_selftest_u8() -> int:
     return int(lib().oracle_rct_selftest_u8())
+
+
+def ycocg_forward(r, g, b):
+    o = np.zeros(3, dtype=np.int32)
+    lib().oracle_ycocg_forward(int(r), int(g), int(b), _ptr(o))
+    return tuple(int(v) for v in o)
+
+
+def ycocg_inverse(y, co, cg):
+    o = np.zeros(3, dtype=np.int32)
+    lib().oracle_ycocg_inverse(int(y), int(co), int(cg), _ptr(o))
+    return tuple(int(v) for v in o)
+
+
+def ycocg_selftest_u8() -> int:
+    return int(lib().oracle_ycocg_selftest_u8())
 
 
 def area_coord(k, wb, hb, d):

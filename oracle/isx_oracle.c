@@ -41,7 +41,7 @@
 
 #define OR_BLOCK 128      /* Sec. 4: wavelet data partitioned in 128*128 blocks */
 #define OR_MAX_LEVELS 15
-#define OR_MAX_CHANNELS 8
+#define OR_MAX_CHANNELS 64
 #define OR_LIMITED_LEN 14 /* length limit of the fallback code (seek-table overflow) */
 
 /* floor(a / b) for b > 0, written out (C division truncates toward zero). */
@@ -83,6 +83,51 @@ void oracle_rct_inverse(int32_t y, int32_t cb, int32_t cr, int32_t out[3])
     out[0] = cr + g; /* R */
     out[1] = g;      /* G */
     out[2] = cb + g; /* B */
+}
+
+/* ================================================================== */
+/* Alternative reversible colour transform (the generality row of the   */
+/* build: the paper asks for arbitrary channels and bit depths; Sec. 3  */
+/* leaves the colour transform open).  Reading: YCoCg-R, the lifting    */
+/* form of YCoCg, exactly reversible in integers:                        */
+/*   Co = R - B, t = B + floor(Co/2), Cg = G - t, Y = t + floor(Cg/2)    */
+/* inverse: t = Y - floor(Cg/2), G = Cg + t, B = t - floor(Co/2),        */
+/* R = B + Co.  Stream channel order Y, Co, Cg.  Pinned by: exhaustive   */
+/* inverse(forward) over all RGB8 triples, hand-worked values, and its   */
+/* relation to the real YCoCg matrix (Y within 1 of R/4 + G/2 + B/4).    */
+/* ================================================================== */
+void oracle_ycocg_forward(int32_t r, int32_t g, int32_t b, int32_t out[3])
+{
+    int32_t co = r - b;
+    int32_t t = b + (int32_t)floor_div(co, 2);
+    int32_t cg = g - t;
+    out[0] = t + (int32_t)floor_div(cg, 2);
+    out[1] = co;
+    out[2] = cg;
+}
+
+void oracle_ycocg_inverse(int32_t y, int32_t co, int32_t cg, int32_t out[3])
+{
+    int32_t t = y - (int32_t)floor_div(cg, 2);
+    int32_t g = cg + t;
+    int32_t b = t - (int32_t)floor_div(co, 2);
+    out[0] = b + co; /* R */
+    out[1] = g;      /* G */
+    out[2] = b;      /* B */
+}
+
+int64_t oracle_ycocg_selftest_u8(void)
+{
+    int64_t bad = 0;
+    for (int r = 0; r < 256; r++)
+        for (int g = 0; g < 256; g++)
+            for (int b = 0; b < 256; b++) {
+                int32_t f[3], v[3];
+                oracle_ycocg_forward(r, g, b, f);
+                oracle_ycocg_inverse(f[0], f[1], f[2], v);
+                if (v[0] != r || v[1] != g || v[2] != b) bad++;
+            }
+    return bad;
 }
 
 /* Exhaustive inverse(forward) check over all 2^24 RGB8 triples; returns the
@@ -1161,11 +1206,13 @@ static int validate_params(int w, int h, int channels, int bps, int bits, int le
 {
     if (w < 1 || h < 1 || w > 65535 || h > 65535) return OR_E_INVALID;
     if (channels < 1 || channels > OR_MAX_CHANNELS) return OR_E_INVALID;
-    if (bps != 1 && bps != 2) return OR_E_INVALID;
-    if (bits < 1 || bits > 8 * bps) return OR_E_INVALID;
+    /* Reading: samples of 1, 2 or 4 bytes; 4-byte samples carry at most 24
+     * significant bits, so that every coefficient stays within 32 bits */
+    if (bps != 1 && bps != 2 && bps != 4) return OR_E_INVALID;
+    if (bits < 1 || bits > (bps == 4 ? 24 : 8 * bps)) return OR_E_INVALID;
     if (levels < 0 || levels > OR_MAX_LEVELS) return OR_E_INVALID;
-    if (ct != 0 && ct != 1) return OR_E_INVALID;
-    if (ct == 1 && channels != 3) return OR_E_INVALID;
+    if (ct < 0 || ct > 2) return OR_E_INVALID;
+    if (ct != 0 && channels != 3) return OR_E_INVALID;
     if (qstep < 1 || qstep > 65535) return OR_E_INVALID;
     return OR_OK;
 }
@@ -1182,12 +1229,15 @@ static int tile_forward(const uint8_t *pix, int w, int h, int stride, int channe
             int32_t s[OR_MAX_CHANNELS] = {0};
             for (int c = 0; c < channels; c++) {
                 const uint8_t *e = pix + (size_t)y * stride + ((size_t)x * channels + c) * bps;
-                s[c] = bps == 1 ? e[0] : (int32_t)(e[0] | (e[1] << 8));
-                if (s[c] >= (1 << bits)) { free(planes); return OR_E_INVALID; }
+                uint32_t u = e[0];
+                for (int k = 1; k < bps; k++) u |= (uint32_t)e[k] << (8 * k);
+                if (u >= (1u << bits)) { free(planes); return OR_E_INVALID; }
+                s[c] = (int32_t)u;
             }
-            if (ct == 1) {
+            if (ct == 1 || ct == 2) {
                 int32_t f[3];
-                oracle_rct_forward(s[0], s[1], s[2], f);
+                if (ct == 1) oracle_rct_forward(s[0], s[1], s[2], f);
+                else oracle_ycocg_forward(s[0], s[1], s[2], f);
                 s[0] = f[0]; s[1] = f[1]; s[2] = f[2];
             }
             for (int c = 0; c < channels; c++) planes[((size_t)c * h + y) * w + x] = s[c];
@@ -1355,16 +1405,16 @@ int32_t oracle_decode_tile_q(const uint8_t *in, uint64_t len, int32_t z, int32_t
             for (int x = 0; x < ow; x++) {
                 int32_t s[OR_MAX_CHANNELS];
                 for (int c = 0; c < ch; c++) s[c] = planes[c][(size_t)y * ow + x];
-                if (ct == 1) {
+                if (ct == 1 || ct == 2) {
                     int32_t v[3];
-                    oracle_rct_inverse(s[0], s[1], s[2], v);
+                    if (ct == 1) oracle_rct_inverse(s[0], s[1], s[2], v);
+                    else oracle_ycocg_inverse(s[0], s[1], s[2], v);
                     s[0] = v[0]; s[1] = v[1]; s[2] = v[2];
                 }
                 for (int c = 0; c < ch; c++) {
                     int32_t v = s[c] < 0 ? 0 : (s[c] > top ? top : s[c]);
                     uint8_t *e = out + (size_t)y * out_row_stride + ((size_t)x * ch + c) * bps;
-                    e[0] = (uint8_t)(v & 0xff);
-                    if (bps == 2) e[1] = (uint8_t)(v >> 8);
+                    for (int k = 0; k < bps; k++) e[k] = (uint8_t)((uint32_t)v >> (8 * k));
                 }
             }
     }

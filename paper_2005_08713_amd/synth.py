@@ -91,11 +91,11 @@ def random_image(width: int, height: int, channels: int, bits: int,
     kind: 'uniform' (iid uniform over [0, 2^bits)), 'const', 'max'
     (all samples 2^bits-1), 'checker' (alternating 0 / max), 'ramp',
     'sparse' (mostly zero with a few random samples).
-    Returns uint8 for bits <= 8 else uint16, shape (h, w, c).
+    Returns uint8 for bits <= 8, uint16 for bits <= 16, else uint32; shape (h, w, c).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     top = (1 << bits) - 1
-    dt = np.uint8 if bits <= 8 else np.uint16
+    dt = np.uint8 if bits <= 8 else (np.uint16 if bits <= 16 else np.uint32)
     shape = (height, width, channels)
     if kind == "uniform":
         a = rng.integers(0, top + 1, size=shape)

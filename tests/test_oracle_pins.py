@@ -44,6 +44,26 @@ def test_rct_random_16bit_roundtrip():
         assert oracle.rct_inverse(*oracle.rct_forward(r, g, b)) == (r, g, b)
 
 
+def test_ycocg_exhaustive_rgb8_roundtrip_and_real_transform():
+    """YCoCg-R (the alternative reversible colour transform): exact round trip
+    over all RGB8 triples; against the real YCoCg matrix, Co is exactly R - B,
+    Y lies in (R + 2G + B)/4 - 3/4 .. (R + 2G + B)/4 and Cg in
+    G - (R + B)/2 .. G - (R + B)/2 + 1/2 (the two floors of the lifting
+    steps); a gray pixel maps to (v, 0, 0)."""
+    assert oracle.ycocg_selftest_u8() == 0
+    rng = np.random.default_rng(6)
+    for r, g, b in rng.integers(0, 1 << 24, size=(3000, 3)):
+        y, co, cg = oracle.ycocg_forward(r, g, b)
+        assert co == r - b
+        exact_y = (int(r) + 2 * int(g) + int(b)) / 4
+        assert exact_y - 0.75 <= y <= exact_y
+        exact_cg = int(g) - (int(r) + int(b)) / 2
+        assert exact_cg <= cg <= exact_cg + 0.5
+        assert oracle.ycocg_inverse(y, co, cg) == (r, g, b)
+    for v in (0, 1, 255, 65535, (1 << 24) - 1):
+        assert oracle.ycocg_forward(v, v, v) == (v, 0, 0)
+
+
 # ---------------------------------------------------------------- 5/3 lifting
 LEGALL_LO = np.array([-1, 2, 6, 2, -1]) / 8.0
 LEGALL_HI = np.array([-1, 2, -1]) / 2.0
@@ -389,6 +409,64 @@ def test_lossless_roundtrip_and_level_decode(case):
             planes = np.stack([cr + g, g, cb + g], axis=-1)
         exp = np.clip(planes, 0, top).astype(img.dtype)
         assert np.array_equal(oracle.decode_tile(blob, z), exp)
+
+
+def _inv_colour(planes, ct):
+    """Inverse colour transform written from each transform's definition."""
+    if ct == 1:
+        y, cb, cr = planes[..., 0], planes[..., 1], planes[..., 2]
+        g = y - np.floor_divide(cb + cr, 4)
+        return np.stack([cr + g, g, cb + g], axis=-1)
+    if ct == 2:
+        y, co, cg = planes[..., 0], planes[..., 1], planes[..., 2]
+        t = y - np.floor_divide(cg, 2)
+        g = cg + t
+        b = t - np.floor_divide(co, 2)
+        return np.stack([b + co, g, b], axis=-1)
+    return planes
+
+
+GENERAL = [
+    # (w, h, c, bits, levels, qstep, ct, kind): alternative colour transform,
+    # 9-bit RGB (27-bit pixels), 4-byte samples up to 24 bits, many channels
+    (150, 97, 3, 8, 4, 1, 2, "uniform"), (64, 40, 3, 9, 3, 1, 2, "ramp"), (120, 88, 3, 9, 3, 1, 1, "uniform"),
+    (77, 50, 3, 12, 3, 3, 2, "uniform"), (60, 45, 1, 24, 3, 1, 0, "uniform"), (70, 33, 3, 20, 4, 1, 1, "ramp"),
+    (40, 40, 3, 24, 2, 5, 2, "uniform"), (50, 30, 16, 8, 3, 1, 0, "uniform"), (20, 12, 64, 10, 2, 1, 0, "ramp"),
+]
+
+
+@pytest.mark.parametrize("case", GENERAL, ids=lambda c: "x".join(map(str, c)))
+def test_generality_roundtrip_levels_and_reader(case):
+    w, h, c, bits, lv, q, ct, kind = case
+    img = synth.random_image(w, h, c, bits, seed=w * 5 + h, kind=kind)
+    blob = oracle.encode_tile(img, lv, bits=bits, ct=ct, qstep=q)
+    hdr, coefs = fr.tile_coefficients(blob)
+    assert (hdr["ct"], hdr["channels"], hdr["bits"], hdr["bytes_per_sample"]) == (ct, c, bits, img.itemsize)
+    fd = oracle.forward_dump(img, lv, bits=bits, ct=ct, qstep=q)
+    for ch in range(c):
+        assert np.array_equal(coefs[ch]["LL"], fd[ch]["LL"])
+    top = (1 << bits) - 1
+    if q == 1:
+        assert np.array_equal(oracle.decode_tile(blob, 0), img)
+    for z in range(1, lv + 1):
+        if q > 1 and z < lv:
+            continue  # lossy: only the coarsest LL is exact
+        llz = oracle.forward_dump(img, z, bits=bits, ct=ct)
+        planes = np.stack([d["LL"] for d in llz], axis=-1).astype(np.int64)
+        exp = np.clip(_inv_colour(planes, ct), 0, top).astype(img.dtype)
+        assert np.array_equal(oracle.decode_tile(blob, z), exp)
+
+
+def test_generality_limits_rejected():
+    ok = synth.random_image(8, 8, 3, 8, seed=1)
+    with pytest.raises(oracle.OracleError):
+        oracle.encode_tile(ok[:, :, :2], 1, ct=2)  # colour transforms need 3 channels
+    with pytest.raises(oracle.OracleError):
+        oracle.encode_tile(ok, 1, ct=3)
+    with pytest.raises(oracle.OracleError):
+        oracle.encode_tile(synth.random_image(8, 8, 1, 24, seed=2), 1, bits=25)
+    with pytest.raises(oracle.OracleError):
+        oracle.encode_tile(np.zeros((4, 4, 65), np.uint8), 1, ct=0)
 
 
 def test_constant_image_blocks_are_header_only():
