@@ -44,12 +44,16 @@ extern "C" {
 #define ISX_E_PENDING 1          /* (device status) initial value before completion     */
 
 #define ISX_CT_NONE 0
-#define ISX_CT_RCT 1  /* reversible colour transform (Y, Cb, Cr), channels == 3 */
+#define ISX_CT_RCT 1    /* reversible colour transform (Y, Cb, Cr), channels == 3       */
+#define ISX_CT_YCOCG 2  /* YCoCg-R, the lifting form of YCoCg (Y, Co, Cg), channels == 3 */
 
 /* One tile (image) to encode, or the parameters of an encoded tile.
- * Limits: 1 <= width, height <= 65535; 1 <= channels <= 8; bytes_per_sample
- * 1 (uint8) or 2 (uint16, little endian); 1 <= bits <= 8*bytes_per_sample and
- * every sample < 2^bits; 0 <= levels <= 15; qstep >= 1 (1 = lossless).
+ * Limits: 1 <= width, height <= 65535; 1 <= channels <= 64; bytes_per_sample
+ * 1 (uint8), 2 (uint16) or 4 (uint32), little endian; 1 <= bits <=
+ * 8*bytes_per_sample, at most 24 for 4-byte samples (coefficients then fit
+ * 32 bits), and every sample < 2^bits; 0 <= levels <= 15; qstep >= 1
+ * (1 = lossless).  16- and 32-bit samples need pixel_offset and
+ * row_stride_bytes to be multiples of the sample size.
  * Pixels are interleaved: sample (x, y, c) is at byte
  *   pixel_offset + y*row_stride_bytes + (x*channels + c)*bytes_per_sample. */
 typedef struct {
@@ -60,7 +64,7 @@ typedef struct {
     uint8_t bytes_per_sample;
     uint8_t bits;
     uint8_t levels;
-    uint8_t colour_transform;  /* ISX_CT_NONE or ISX_CT_RCT                         */
+    uint8_t colour_transform;  /* ISX_CT_NONE, ISX_CT_RCT or ISX_CT_YCOCG           */
     uint8_t reserved0[3];
     uint16_t qstep;            /* dead-zone quantiser step on HL/LH/HH (Sec. 3)     */
     uint16_t reserved1;
@@ -68,11 +72,13 @@ typedef struct {
 
 /* One decode job: reconstruct an encoded tile at resolution level
  * target_level (0 = full size; z gives the ceil(W/2^z) x ceil(H/2^z) image
- * built from the coarser blocks only, Sec. 4 "discarding the high-pass
- * coefficients").  `tile` repeats the encoded tile's parameters (the host
- * plans the workspace from them; the device checks them against the stream
- * header and reports ISX_E_CORRUPT on mismatch); tile.pixel_offset and
- * tile.row_stride_bytes are ignored.
+ * built from the coarser blocks only: the decompression part of Sec. 5
+ * leaves out the high-pass blocks of the finer levels).  `tile` repeats the
+ * encoded tile's parameters (the host plans the workspace from them; the
+ * device checks them against the stream header and reports ISX_E_CORRUPT on
+ * mismatch); tile.pixel_offset and tile.row_stride_bytes are ignored; for
+ * 16- and 32-bit samples out_offset and out_row_stride_bytes must be
+ * multiples of the sample size.
  * drop_bitplanes = r > 0 asks for a lower-quality decode (Sec. 5: the seek
  * table of a block lets the decoder discard its least significant planes):
  * the magnitude planes b < r of every block are skipped (not decoded, not

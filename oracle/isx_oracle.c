@@ -10,10 +10,10 @@
  * available); every reading taken here is marked "Reading:" at the place it
  * is used.  What is computed, stage by stage (Sec. 3 Fig. 1, Sec. 4):
  *
- *   pixels -> reversible colour transform (Sec. 3 "optional colorspace
- *   transformation"; Sec. 4 "standard")
+ *   pixels -> reversible colour transform (Sec. 3: optional; Sec. 4:
+ *   named as a standard stage and not specified)
  *   -> recursive 2-D 5/3 Le Gall integer lifting (Sec. 4)
- *   -> quantisation of the high-pass bands (Sec. 3, "as in JPEG2000")
+ *   -> quantisation of the high-pass bands (Sec. 3, JPEG2000-style)
  *   -> 128x128 coefficient blocks (Sec. 4; Fig. 3 caption)
  *   -> signed-magnitude bitplanes, 4x2 areas in snake order (Sec. 4 Eq. 1)
  *   -> one byte symbol per area (Sec. 4 Eq. 2)
@@ -62,8 +62,8 @@ static int bit_length(uint64_t v)
 static int roundup4(int v) { return (v + 3) / 4 * 4; }
 
 /* ================================================================== */
-/* Colour transform.  Reading: the paper only calls it "standard" and    */
-/* optional (Sec. 3, Sec. 4); the reversible component transform of the */
+/* Colour transform.  Reading: the paper only says the stage is optional */
+/* and standard (Sec. 3, Sec. 4); the reversible component transform of  */
 /* JPEG2000 lineage the paper compares to is used:                       */
 /*   Y = floor((R + 2G + B) / 4),  Cb = B - G,  Cr = R - G               */
 /* and its exact inverse G = Y - floor((Cb + Cr)/4), R = Cr + G,         */
@@ -147,8 +147,8 @@ int64_t oracle_rct_selftest_u8(void)
 }
 
 /* ================================================================== */
-/* 1-D 5/3 Le Gall integer lifting (Sec. 4 "MATLAB's 5/3 Le Gall integer */
-/* lifting").  Reading (MATLAB's exact code is not available): the       */
+/* 1-D 5/3 Le Gall integer lifting (Sec. 4 names the MATLAB 5/3 integer */
+/* lifting).  Reading (MATLAB's exact code is not available): the       */
 /* reversible 5/3 of JPEG2000 with whole-sample symmetric extension:     */
 /*   d[n] = x[2n+1] - floor((x[2n] + x[2n+2]) / 2)                       */
 /*   s[n] = x[2n]   + floor((d[n-1] + d[n] + 2) / 4)                     */
@@ -198,7 +198,7 @@ void oracle_lift53_inverse_1d(const int32_t *low, const int32_t *high, int32_t n
 }
 
 /* ================================================================== */
-/* One 2-D level (Sec. 4; Sec. 3 "recursive wavelet transformation").   */
+/* One 2-D level (Sec. 4; Sec. 3: the wavelet transform is recursive).  */
 /* Reading: rows first, then columns (the order is not in the paper).   */
 /* Subbands of a w x h input: LL ceil(w/2) x ceil(h/2); HL (horizontal  */
 /* high, vertical low) floor(w/2) x ceil(h/2); LH ceil(w/2) x floor(h/2);*/
@@ -352,8 +352,8 @@ static int32_t *pyramid_inverse(const Pyramid *p, int z, int *ow, int *oh)
 }
 
 /* ================================================================== */
-/* Quantisation (Sec. 3: "the same image quantization methods as in     */
-/* JPEG2000").  Reading: dead-zone scalar quantiser with step D on the  */
+/* Quantisation (Sec. 3: lossy images use the quantisation of JPEG2000). */
+/* Reading: dead-zone scalar quantiser with step D on the               */
 /* HL, LH and HH bands of every level (LL always D = 1):                 */
 /*   q = sign(c) floor(|c| / D);  c' = 0 if q = 0 else                   */
 /*   sign(q) (|q| D + floor(D/2)).  D = 1 is the identity.               */
@@ -415,8 +415,8 @@ static uint64_t br_get(BitReader *r, int nbits)
 }
 
 /* ================================================================== */
-/* Huffman code lengths (Sec. 3: "a Huffman code is used"; Sec. 4: "the  */
-/* Huffman code is created as normal").  Reading (tie-breaks are not in  */
+/* Huffman code lengths (Sec. 3 and Sec. 4: an ordinary Huffman code per */
+/* block).  Reading (tie-breaks are not in                                */
 /* the paper): leaves with f > 0 sorted by (f, symbol); the classical    */
 /* two-queue merge, taking the leaf queue's front on equal weight; code  */
 /* length = leaf depth.  One leaf -> length 0.                           */
@@ -591,7 +591,7 @@ static void tree_write(BitWriter *w, const TNode *nodes, int v)
 }
 
 /* ================================================================== */
-/* Area order T(k) (Sec. 4 Eq. 1, Fig. 2(c) "snake order").  Eq. 1 is   */
+/* Area order T(k) (Sec. 4 Eq. 1, Fig. 2(c): a snake order).  Eq. 1 is  */
 /* garbled as printed (its plane index leaves [0,d-1] after one plane    */
 /* and its row index collides).  Reading that keeps its readable parts:  */
 /* with n = Wb*Hb/8 areas per plane and k' = k mod n,                    */
@@ -624,7 +624,8 @@ static int smr_bit(int32_t v, int b, int d)
 
 /* Symbol of the 4x2 area with top-left (i, j) in plane b (Sec. 4 Eq. 2:  */
 /* S = sum over m in {i,i+1}, n in {j..j+3} of B(m,n,b) 2^((n-j)+4(m-i))).*/
-/* Reading: the caption of Fig. 2 says "clockwise" but Eq. 2 is raster;   */
+/* Reading: the caption of Fig. 2 describes a clockwise bit order but     */
+/* Eq. 2 is raster;                                                       */
 /* Eq. 2 is followed.  Samples outside the type's extent are zero pad.    */
 typedef struct {
     const int32_t *v; /* top-left of the region inside its band */
@@ -835,7 +836,7 @@ static int encode_block(const TypeView *types, int p, int wb, int hb,
     uint64_t B = ((uint64_t)1 << wz) - 1;
 
     /* Final code: C_zr frequency = literal C_zr + every run digit (Sec. 4:
-     * "frequency ... taking into account the number of zero-runs"). */
+     * the symbol frequencies count the zero runs). */
     uint64_t f[256];
     for (int v = 0; v < 256; v++) f[v] = lit[v];
     for (int s = 0; s < nseg; s++) {

@@ -20,11 +20,12 @@ int validate_desc(const isx_tile_desc &d)
 {
     if (d.width < 1 || d.height < 1 || d.width > 65535 || d.height > 65535) return ISX_E_INVALID_ARG;
     if (d.channels < 1 || d.channels > kMaxChannels) return ISX_E_INVALID_ARG;
-    if (d.bytes_per_sample != 1 && d.bytes_per_sample != 2) return ISX_E_INVALID_ARG;
-    if (d.bits < 1 || d.bits > 8 * d.bytes_per_sample) return ISX_E_INVALID_ARG;
+    if (d.bytes_per_sample != 1 && d.bytes_per_sample != 2 && d.bytes_per_sample != 4) return ISX_E_INVALID_ARG;
+    // 4-byte samples carry at most 24 bits: every coefficient then fits 32 bits
+    if (d.bits < 1 || d.bits > (d.bytes_per_sample == 4 ? 24 : 8 * d.bytes_per_sample)) return ISX_E_INVALID_ARG;
     if (d.levels > kMaxLevels) return ISX_E_INVALID_ARG;
-    if (d.colour_transform > 1) return ISX_E_INVALID_ARG;
-    if (d.colour_transform == ISX_CT_RCT && d.channels != 3) return ISX_E_INVALID_ARG;
+    if (d.colour_transform > ISX_CT_YCOCG) return ISX_E_INVALID_ARG;
+    if (d.colour_transform != ISX_CT_NONE && d.channels != 3) return ISX_E_INVALID_ARG;
     if (d.qstep < 1) return ISX_E_INVALID_ARG;
     return ISX_OK;
 }
@@ -175,8 +176,8 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
             z = j.target_level;
         } else if (d.row_stride_bytes < (uint64_t)d.width * d.channels * d.bytes_per_sample) {
             return ISX_E_INVALID_ARG;
-        } else if (d.bytes_per_sample == 2 && ((d.pixel_offset | d.row_stride_bytes) & 1u)) {
-            return ISX_E_INVALID_ARG;  // 16-bit samples are read as aligned uint16
+        } else if (d.bytes_per_sample > 1 && ((d.pixel_offset | d.row_stride_bytes) & (d.bytes_per_sample - 1u))) {
+            return ISX_E_INVALID_ARG;  // 16/32-bit samples are read as aligned words
         }
         tile_geometry(d, z, tb[i]);
         TileGeo &T = tb[i].g;
@@ -185,6 +186,7 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
             uint32_t ow = T.width, oh = T.height;
             for (int k = 0; k < z; k++) { ow = (ow + 1) / 2; oh = (oh + 1) / 2; }
             if (j.out_row_stride_bytes < (uint64_t)ow * T.channels * T.bps) return ISX_E_INVALID_ARG;
+            if (T.bps > 1 && ((j.out_offset | j.out_row_stride_bytes) & (T.bps - 1u))) return ISX_E_INVALID_ARG;
             T.pix_offset = j.out_offset;
             T.pix_stride = j.out_row_stride_bytes;
             T.enc_offset = j.in_offset;

@@ -12,7 +12,7 @@ namespace isx {
 
 constexpr int kBlock = 128;        // Sec. 4: wavelet data partitioned in 128x128 blocks
 constexpr int kMaxLevels = 15;
-constexpr int kMaxChannels = 8;
+constexpr int kMaxChannels = 64;
 constexpr int kMaxPlanes = 31;     // d is a 5-bit field; magnitudes < 2^30
 constexpr int kNumWz = 14;         // counter widths 2..15 tracked per segment
 constexpr uint32_t kPlanMagic = 0x4e4c5058u;  // "XPLN"

@@ -1,6 +1,5 @@
-// k_decode.hip -- decoder of the codec for gfx950: the encode pipeline in
-// reverse (Sec. 4: "traversing the pipeline in reverse"; lower resolutions by
-// decoding only the coarser blocks).
+// k_decode.hip -- decoder of the codec for gfx950: the encode pipeline run
+// backwards (Sec. 5; lower resolutions by decoding only the coarser blocks).
 //
 //  k_dec_prep      per job: tile header and block-size table checks, block
 //                  descriptors and byte offsets (scan) of the blocks needed

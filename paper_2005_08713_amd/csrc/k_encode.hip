@@ -8,7 +8,7 @@
 //                 (Eq. 1 order: 4-row bands, 4-column groups, upper area then
 //                 lower area; Eq. 2 bit weights), a 256-bin histogram per
 //                 segment, and the maximal zero runs of each segment via a
-//                 workgroup prefix-max scan of "last non-zero position".
+//                 workgroup prefix-max scan of the last non-zero position.
 //  k_enc_code     C_zr = least frequent symbol (smallest on ties), a
 //                 provisional Huffman code to get l, the counter width wz
 //                 minimising Eq. 3, the final Huffman code (two-queue merge,

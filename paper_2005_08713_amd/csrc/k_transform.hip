@@ -39,23 +39,50 @@ __device__ inline const WorkItem &find_item(const WorkItem *items, uint32_t firs
     return items[first + lo];
 }
 
-__device__ inline int32_t load_sample(const uint8_t *pix, const TileGeo &T, int x, int y, int c)
+// One sample: 1, 2 or 4 bytes, little endian (16/32-bit samples are aligned;
+// 4-byte samples hold at most 24 bits).
+__device__ inline int32_t sample_at(const uint8_t *px, uint32_t bps, uint32_t c)
 {
-    const uint8_t *row = pix + T.pix_offset + (uint64_t)y * T.pix_stride;
-    uint32_t e = ((uint32_t)x * T.channels + c) * T.bps;
-    if (T.bps == 1) return row[e];
-    return (int32_t)row[e] | ((int32_t)row[e + 1] << 8);
+    if (bps == 1) return px[c];
+    if (bps == 2) return ((const uint16_t *)px)[c];
+    return (int32_t)((const uint32_t *)px)[c];
 }
 
-// Sample of channel c after the colour transform (Y = floor((R+2G+B)/4),
-// Cb = B - G, Cr = R - G when ct = RCT).
+// Colour-transformed channel c of one pixel: RCT (Y = floor((R+2G+B)/4),
+// Cb = B - G, Cr = R - G) or YCoCg-R (Co = R - B, t = B + floor(Co/2),
+// Cg = G - t, Y = t + floor(Cg/2)); arithmetic shifts are floors.
+__device__ inline int32_t colour_fwd(int32_t R, int32_t G, int32_t B, uint32_t ct, int c)
+{
+    if (ct == 1) return c == 0 ? ((R + 2 * G + B) >> 2) : (c == 1 ? B - G : R - G);
+    const int32_t co = R - B, t = B + (co >> 1), cg = G - t;
+    return c == 0 ? t + (cg >> 1) : (c == 1 ? co : cg);
+}
+
+// Inverse colour transform in place (a, b, c) = (Y, Cb, Cr) or (Y, Co, Cg) ->
+// (R, G, B); ct = 0 leaves the channels.
+__device__ inline void colour_inv(uint32_t ct, int32_t &a, int32_t &b, int32_t &c)
+{
+    if (ct == 1) {
+        const int32_t g = a - ((b + c) >> 2);
+        const int32_t R = c + g, B = b + g;
+        a = R; b = g; c = B;
+    } else if (ct == 2) {
+        const int32_t t = a - (c >> 1), g = c + t, B = t - (b >> 1);
+        a = B + b; b = g; c = B;
+    }
+}
+
+__device__ inline int32_t load_sample(const uint8_t *pix, const TileGeo &T, int x, int y, int c)
+{
+    const uint8_t *px = pix + T.pix_offset + (uint64_t)y * T.pix_stride + (uint64_t)x * T.channels * T.bps;
+    return sample_at(px, T.bps, (uint32_t)c);
+}
+
 __device__ inline int32_t load_colour(const uint8_t *pix, const TileGeo &T, int x, int y, int c)
 {
     if (T.ct == 0) return load_sample(pix, T, x, y, c);
-    int32_t r = load_sample(pix, T, x, y, 0), g = load_sample(pix, T, x, y, 1), b = load_sample(pix, T, x, y, 2);
-    if (c == 0) return (r + 2 * g + b) >> 2;
-    if (c == 1) return b - g;
-    return r - g;
+    return colour_fwd(load_sample(pix, T, x, y, 0), load_sample(pix, T, x, y, 1), load_sample(pix, T, x, y, 2),
+                      T.ct, c);
 }
 
 __device__ inline uint32_t wave_or(uint32_t v)
@@ -95,7 +122,7 @@ __global__ void __launch_bounds__(256) k_fwd_level(PlanHdr H, const uint8_t *__r
     int32_t vals[NI];
     if (level == 1) {
         const uint32_t C = T.channels, bps = T.bps;
-        if (bps == 1 && T.ct) {
+        if (bps == 1 && T.ct == 1) {
             // one branch-free loop per channel, so the loads of all samples
             // are scheduled together
             auto rgb = [&](auto f) {
@@ -119,17 +146,8 @@ __global__ void __launch_bounds__(256) k_fwd_level(PlanHdr H, const uint8_t *__r
                 if (i >= WN * WN) break;
                 const int lr = i / WN, lc = i % WN;
                 const uint8_t *px = pix + T.pix_offset + (uint64_t)rmap[lr] * T.pix_stride + (uint32_t)cmap[lc] * C * bps;
-                int32_t v;
-                if (bps == 1) {
-                    v = px[c];
-                } else {
-                    const uint16_t *p16 = (const uint16_t *)px;
-                    if (T.ct) {
-                        int32_t R = p16[0], Gc = p16[1], Bc = p16[2];
-                        v = c == 0 ? ((R + 2 * Gc + Bc) >> 2) : (c == 1 ? Bc - Gc : R - Gc);
-                    } else v = p16[c];
-                }
-                vals[k] = v;
+                vals[k] = T.ct ? colour_fwd(sample_at(px, bps, 0), sample_at(px, bps, 1), sample_at(px, bps, 2), T.ct, c)
+                               : sample_at(px, bps, (uint32_t)c);
             }
         }
     } else {
@@ -469,14 +487,8 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
             int ly = ty + RSTEP * rr;
 #pragma unroll
             for (int xx = 0; xx < 4; xx++) {
-                int32_t o0, o1, o2;
-                if (T.ct == 1) {
-                    int32_t Y = v[0][rr][xx], cb = v[1][rr][xx], cr = v[2][rr][xx];
-                    int32_t g = Y - ((cb + cr) >> 2);
-                    o0 = cr + g; o1 = g; o2 = cb + g;
-                } else {
-                    o0 = v[0][rr][xx]; o1 = v[1][rr][xx]; o2 = v[2][rr][xx];
-                }
+                int32_t o0 = v[0][rr][xx], o1 = v[1][rr][xx], o2 = v[2][rr][xx];
+                colour_inv(T.ct, o0, o1, o2);
                 o0 = o0 < 0 ? 0 : (o0 > top ? top : o0);
                 o1 = o1 < 0 ? 0 : (o1 > top ? top : o1);
                 o2 = o2 < 0 ? 0 : (o2 > top ? top : o2);
@@ -507,14 +519,9 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
         int32_t o[3][4];
 #pragma unroll
         for (int xx = 0; xx < 4; xx++) {
-            if (T.ct == 1) {
-                int32_t Y = v[0][rr][xx], cb = v[1][rr][xx], cr = v[2][rr][xx];
-                int32_t g = Y - ((cb + cr) >> 2);
-                o[0][xx] = cr + g; o[1][xx] = g; o[2][xx] = cb + g;
-            } else {
 #pragma unroll
-                for (int k = 0; k < 3; k++) o[k][xx] = v[k][rr][xx];
-            }
+            for (int k = 0; k < 3; k++) o[k][xx] = v[k][rr][xx];
+            colour_inv(T.ct, o[0][xx], o[1][xx], o[2][xx]);
 #pragma unroll
             for (int k = 0; k < 3; k++) o[k][xx] = o[k][xx] < 0 ? 0 : (o[k][xx] > top ? top : o[k][xx]);
         }
@@ -532,8 +539,9 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
                 for (int k = 0; k < 3; k++) {
                     if (k >= nc) break;
                     uint32_t e = ((uint32_t)x * C + c0 + k) * bps;
-                    row[e] = (uint8_t)(o[k][xx] & 0xff);
-                    if (bps == 2) row[e + 1] = (uint8_t)(o[k][xx] >> 8);
+                    if (bps == 1) row[e] = (uint8_t)o[k][xx];
+                    else if (bps == 2) *(uint16_t *)(row + e) = (uint16_t)o[k][xx];
+                    else *(uint32_t *)(row + e) = (uint32_t)o[k][xx];
                 }
             }
         }

@@ -296,7 +296,8 @@ def _as_device_pixels(img: np.ndarray, device="cuda"):
 
 
 def encode_image(img: np.ndarray, levels: int, bits=None, ct=None, qstep=1, device="cuda") -> bytes:
-    """Encode one image (numpy, HxW[xC], uint8/uint16) on the GPU; returns the tile stream."""
+    """Encode one image (numpy, HxW[xC], uint8/uint16/uint32) on the GPU; returns the
+    tile stream.  uint32 samples need an explicit ``bits`` (at most 24)."""
     torch = _torch()
     d_pix, a = _as_device_pixels(img, device)
     h, w, c = a.shape
@@ -382,7 +383,7 @@ def decode_streams(blobs, levels=None, device="cuda", return_status=False, drop=
     res = []
     for (o, oh, ow, c, bps), s in zip(outs, st):
         n = oh * ow * c * bps
-        a = host[o:o + n].view(np.uint8 if bps == 1 else np.uint16).reshape(oh, ow, c)
+        a = host[o:o + n].view({1: np.uint8, 2: np.uint16, 4: np.uint32}[bps]).reshape(oh, ow, c)
         res.append(a.copy())
     if return_status:
         return res, [int(x) for x in st]

@@ -42,15 +42,30 @@ def test_block_counts_match_oracle_geometry():
 
 def test_host_validation_rejects_bad_descriptors():
     L = isx.lib()
-    bad = [isx.tile_desc(0, 5, 1, 1, 8, 1), isx.tile_desc(5, 5, 9, 1, 8, 1),
+    bad = [isx.tile_desc(0, 5, 1, 1, 8, 1), isx.tile_desc(5, 5, 65, 1, 8, 1),
            isx.tile_desc(5, 5, 1, 1, 9, 1), isx.tile_desc(5, 5, 1, 3, 8, 1),
            isx.tile_desc(5, 5, 1, 1, 8, 16), isx.tile_desc(5, 5, 2, 1, 8, 1, ct=1),
-           isx.tile_desc(5, 5, 1, 1, 8, 1, qstep=0)]
+           isx.tile_desc(5, 5, 1, 1, 8, 1, qstep=0), isx.tile_desc(5, 5, 2, 1, 8, 1, ct=2),
+           isx.tile_desc(5, 5, 3, 1, 8, 1, ct=3), isx.tile_desc(5, 5, 1, 4, 25, 1),
+           isx.tile_desc(5, 5, 1, 2, 17, 1), isx.tile_desc(5, 5, 1, 4, 0, 1)]
     for d in bad:
         assert L.isx_encode_workspace_bytes(ctypes.byref(d), 1) == 0
         assert L.isx_max_encoded_bytes(ctypes.byref(d), 1) == 0
     d = isx.tile_desc(64, 64, 3, 1, 8, 3)
     assert L.isx_encode_workspace_bytes(ctypes.byref(d), 1) > 64 * 64 * 3 * 4
+    # the widest accepted descriptors plan; misaligned 16/32-bit samples do not
+    for ok in (isx.tile_desc(5, 5, 64, 1, 8, 2), isx.tile_desc(5, 5, 1, 4, 24, 2),
+               isx.tile_desc(5, 5, 3, 2, 16, 2, ct=2)):
+        assert L.isx_encode_plan_bytes(ctypes.byref(ok), 1) > 0
+    for mis in (isx.tile_desc(5, 5, 1, 4, 24, 2, pixel_offset=2), isx.tile_desc(5, 5, 1, 2, 9, 1, row_stride=11)):
+        assert L.isx_encode_plan_bytes(ctypes.byref(mis), 1) == 0
+    j = isx.DecodeJob()
+    j.tile, j.in_bytes, j.out_row_stride_bytes = isx.tile_desc(8, 8, 1, 2, 16, 1), 4096, 16
+    arr = (isx.DecodeJob * 1)(j)
+    assert L.isx_decode_plan_bytes(arr, 1) > 0
+    for off, stride in ((1, 16), (0, 17)):
+        arr[0].out_offset, arr[0].out_row_stride_bytes = off, stride
+        assert L.isx_decode_plan_bytes(arr, 1) == 0
     # a call with a null device pointer fails on the host before any launch
     rc = L.isx_encode_tiles(ctypes.byref(d), 1, None, None, 0, None, None, None, None, 0, None)
     assert rc == isx.E_INVALID_ARG

@@ -189,3 +189,43 @@ def test_progressive_decode_matches_oracle():
     got = isx.decode_streams(blobs, levels=levels, drop=drops)
     for i, (g, e) in enumerate(zip(got, exp)):
         assert np.array_equal(g, e), (i, levels[i], drops[i])
+
+
+GENERAL = [
+    # (w, h, c, bits, levels, qstep, ct, kind): YCoCg-R, 9-bit RGB, 4-byte
+    # samples with up to 24 bits, 16 and 64 channels
+    (150, 97, 3, 8, 4, 1, 2, "uniform"), (64, 40, 3, 9, 3, 1, 2, "ramp"), (120, 88, 3, 9, 3, 1, 1, "uniform"),
+    (77, 50, 3, 12, 3, 3, 2, "uniform"), (60, 45, 1, 24, 3, 1, 0, "uniform"), (70, 33, 3, 20, 4, 1, 1, "ramp"),
+    (40, 40, 3, 24, 2, 5, 2, "uniform"), (50, 30, 16, 8, 3, 1, 0, "uniform"), (20, 12, 64, 10, 2, 1, 0, "ramp"),
+    (300, 140, 3, 8, 5, 1, 2, "sparse"), (33, 31, 5, 16, 2, 2, 0, "uniform"), (1, 1, 3, 24, 0, 1, 2, "max"),
+]
+
+
+@pytest.mark.parametrize("case", GENERAL, ids=lambda c: "x".join(map(str, c)))
+def test_generality_matches_oracle(case):
+    """Forward coefficients, stream bytes, every resolution level and a
+    reduced-quality decode equal the oracle's for the alternative colour
+    transform, deep samples and many channels."""
+    w, h, c, bits, lv, q, ct, kind = case
+    img = synth.random_image(w, h, c, bits, seed=w * 5 + h, kind=kind)
+    print("general", case, flush=True)
+    got = isx.debug_forward(img, lv, bits=bits, ct=ct, qstep=q)
+    ref = oracle.forward_dump(img, lv, bits=bits, ct=ct, qstep=q)
+    for ch in range(c):
+        assert np.array_equal(got[ch]["LL"], ref[ch]["LL"]), (ch, "LL")
+        for l in range(1, lv + 1):
+            for nm in ("HL", "LH", "HH"):
+                assert np.array_equal(got[ch][nm][l], ref[ch][nm][l]), (ch, nm, l)
+    blob = isx.encode_image(img, lv, bits=bits, ct=ct, qstep=q)
+    assert blob == oracle.encode_tile(img, lv, bits=bits, ct=ct, qstep=q)
+    levels = list(range(lv + 1))
+    dec = isx.decode_streams([blob] * len(levels), levels=levels)
+    for z, g in zip(levels, dec):
+        assert g.dtype == img.dtype
+        assert np.array_equal(g, oracle.decode_tile(blob, z)), z
+    if q == 1:
+        assert np.array_equal(dec[0], img.reshape(dec[0].shape))
+    r = min(3, bits)
+    prog = isx.decode_streams([blob], drop=r)[0]
+    assert np.array_equal(prog, oracle.decode_tile(blob, 0, drop=r))
+
