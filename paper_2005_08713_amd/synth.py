@@ -5,9 +5,10 @@ on radiology images (CR/DX/MG, 12-16 bit single channel) whose datasets are
 not available here (Sec. 5).  These generators produce stand-ins with the
 same shapes, value ranges and spatial structure:
 
-* ``he_like``  -- H&E-stained tissue on a bright background, RGB uint8.
+* ``he_like``  -- H&E-stained tissue on a bright background, RGB uint8
+  (or 9-bit RGB in uint16, as the paper's pathology scans).
 * ``rad_like`` -- a smooth radial gradient with blob structures and Poisson
-  counting noise, single channel uint16 with 12 significant bits.
+  counting noise, single channel uint16 with 12 (or more) significant bits.
 * ``tile_batch`` -- a batch of RGB tiles of uneven size (square 512/256/128
   tiles plus ragged edge tiles), with per-tile wavelet levels and
   lossless/quantised mode, as produced when a slide is cut into tiles.
@@ -40,13 +41,18 @@ def _blob_field(rng, w, h, nblobs, sig_lo, sig_hi, amp_lo, amp_hi):
 
 
 def he_like(width: int, height: int, seed: int, sigma=(20.0, 60.0),
-            tissue: float = 0.40) -> np.ndarray:
-    """H&E-like RGB uint8 image, shape (height, width, 3).
+            tissue: float = 0.40, bits: int = 8) -> np.ndarray:
+    """H&E-like RGB image, shape (height, width, 3): uint8, or uint16 for
+    bits > 8 (the 9-bit-per-channel scans).
 
     Background ~U{230..245} per pixel and channel; tissue where an 8-blob
     field exceeds its (1-tissue) quantile, coloured by a second 8-blob field
-    mixing pink and purple stain colours; additive N(0, 2^2) noise.
+    mixing pink and purple stain colours; additive N(0, 2^2) noise.  For
+    bits > 8 the background and stain colours are scaled by 2^(bits-8) and
+    the noise by the same factor before rounding.
     """
+    if bits != 8:
+        return _he_like_deep(width, height, seed, sigma, tissue, bits)
     rng = np.random.Generator(np.random.PCG64(seed))
     img = rng.integers(230, 246, size=(height, width, 3)).astype(np.float64)
     f = _blob_field(rng, width, height, 8, sigma[0], sigma[1], 0.5, 1.0)
@@ -61,13 +67,30 @@ def he_like(width: int, height: int, seed: int, sigma=(20.0, 60.0),
     return np.clip(np.rint(img), 0, 255).astype(np.uint8)
 
 
-def rad_like(width: int, height: int, seed: int) -> np.ndarray:
+def _he_like_deep(width, height, seed, sigma, tissue, bits):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = float(1 << (bits - 8))
+    img = rng.uniform(230.0, 246.0, size=(height, width, 3)) * k
+    f = _blob_field(rng, width, height, 8, sigma[0], sigma[1], 0.5, 1.0)
+    mask = f > np.quantile(f, 1.0 - tissue)
+    hfield = _blob_field(rng, width, height, 8, sigma[0], sigma[1], 0.5, 1.0)
+    lo, hi = hfield.min(), hfield.max()
+    hmix = (hfield - lo) / (hi - lo) if hi > lo else np.zeros_like(hfield)
+    colour = ((1.0 - hmix)[..., None] * PINK + hmix[..., None] * PURPLE) * k
+    img[mask] = colour[mask]
+    img += rng.normal(0.0, 2.0 * k, size=img.shape)
+    return np.clip(np.rint(img), 0, (1 << bits) - 1).astype(np.uint16 if bits <= 16 else np.uint32)
+
+
+def rad_like(width: int, height: int, seed: int, bits: int = 12) -> np.ndarray:
     """Radiology-like uint16 image (12 significant bits), shape (height, width).
 
     lambda = 2000 + 300 (1 - 2 r / r_max) plus 20 Gaussian blobs with
     amplitude ~U(-600, 1200) and sigma ~U(50, 800) px (scaled down for
     images smaller than 8192 px), clipped to [1, 4000]; Poisson counts
-    clipped to [0, 4095].
+    clipped to [0, 4095].  For another ``bits`` the intensity field is
+    scaled by 2^(bits-12) before the Poisson draw and the counts are clipped
+    to [0, 2^bits - 1].
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     ys, xs = np.mgrid[0:height, 0:width].astype(np.float64)
@@ -80,8 +103,10 @@ def rad_like(width: int, height: int, seed: int) -> np.ndarray:
     lam += _blob_field(rng, width, height, 20, 50.0 * scale + 1.0,
                        800.0 * scale + 2.0, -600.0, 1200.0)
     lam = np.clip(lam, 1.0, 4000.0)
+    if bits != 12:
+        lam *= 2.0 ** (bits - 12)
     counts = rng.poisson(lam)
-    return np.clip(counts, 0, 4095).astype(np.uint16)
+    return np.clip(counts, 0, (1 << bits) - 1).astype(np.uint16)
 
 
 def random_image(width: int, height: int, channels: int, bits: int,
