@@ -184,6 +184,56 @@ int32_t isx_encode_plan_build_tuned(const isx_tile_desc *h_descs, int32_t n_tile
 int32_t isx_decode_plan_build_tuned(const isx_decode_job *h_jobs, int32_t n_jobs,
                                     const isx_tuning *tuning, void *h_plan, uint64_t plan_bytes);
 
+/* ---- region decode (whole-slide pyramids) ----------------------------------
+ * A whole slide encoded as ONE tile is one non-redundant wavelet pyramid
+ * (Sec. 3: the blocks of every scale are stored separately, Sec. 5: a viewer
+ * decodes only the blocks of the scale and area it shows).  A region job
+ * reconstructs the rectangle [x0, x0+width) x [y0, y0+height) of the level-z
+ * image (z = job.target_level) from the blocks it depends on: at each level
+ * l = z+1 .. L the inverse lifting of a sample reaches two band samples to
+ * either side, so the blocks read are those covering the region's halo at
+ * every level, plus the LL blocks under the coarsest halo.  The result is
+ * identical, sample for sample, to cropping the full level-z decode.
+ *
+ * isx_stream_block_offsets reads a stream's header and size table (host
+ * memory: the first 24 + 4 * block_count bytes of the stream) and writes
+ * the byte offset of every block from the stream start, plus the stream
+ * length, into h_offsets[0 .. block_count] (block_count + 1 entries).
+ * Returns ISX_OK, ISX_E_INVALID_ARG (null pointers, n_offsets too small),
+ * ISX_E_TRUNCATED (head_bytes shorter than the table) or ISX_E_CORRUPT
+ * (not a stream of this codec). */
+int32_t isx_stream_block_offsets(const void *h_head, uint64_t head_bytes, uint64_t *h_offsets,
+                                 uint64_t n_offsets);
+
+/* One region job.  job: the stream (tile parameters, in_offset, in_bytes),
+ * the output (out_offset; out_row_stride_bytes >= width * channels *
+ * bytes_per_sample), the level (target_level) and drop_bitplanes, exactly
+ * as for a whole-tile decode job.  The region must lie inside the level
+ * image (1 <= width, height; x0 + width <= ceil(W / 2^z), likewise y).
+ * h_block_offsets: the stream's block offsets from isx_stream_block_offsets
+ * (host memory, read while the plan is built, not kept).  The device checks
+ * every block's size against the stream's own table and reports
+ * ISX_E_TRUNCATED if they disagree. */
+typedef struct {
+    isx_decode_job job;
+    uint32_t x0, y0;
+    uint32_t width, height;
+    const uint64_t *h_block_offsets;
+} isx_region_job;                  /* 88 bytes */
+
+/* Sizes and plan of a batch of region jobs (0 on invalid input).  The plan
+ * is a decode plan: isx_decode_run / isx_decode_run_stages run it. */
+uint64_t isx_region_workspace_bytes(const isx_region_job *h_jobs, int32_t n_jobs);
+uint64_t isx_region_plan_bytes(const isx_region_job *h_jobs, int32_t n_jobs);
+int32_t isx_region_plan_build(const isx_region_job *h_jobs, int32_t n_jobs, const isx_tuning *tuning,
+                              void *h_plan, uint64_t plan_bytes);
+
+/* Decode a batch of region jobs in one call (plan built and copied into the
+ * workspace, then run), as isx_decode_tiles does for whole tiles. */
+int32_t isx_decode_regions(const void *d_encoded, const isx_region_job *h_jobs, int32_t n_jobs,
+                           void *d_pixels_out, int32_t *d_status, void *d_workspace,
+                           uint64_t workspace_bytes, void *stream);
+
 /* ---- stage-wise runs (profiling) -------------------------------------------
  * The encode and decode runs are fixed sequences of kernel stages; these
  * entry points enqueue stages [first, first + count) of the full sequence

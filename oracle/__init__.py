@@ -169,6 +169,16 @@ def decode_tile(blob: bytes, level: int = 0, drop: int = 0) -> np.ndarray:
     return out
 
 
+def decode_region(blob: bytes, level: int, x0: int, y0: int, w: int, h: int, drop: int = 0) -> np.ndarray:
+    """Region [x0, x0+w) x [y0, y0+h) of the level-`level` image.  By
+    definition this is the crop of the whole decode at that level (Sec. 5:
+    a viewer shows part of one scale); no other arithmetic."""
+    full = decode_tile(blob, level, drop)
+    if not (0 <= x0 and 0 <= y0 and w >= 1 and h >= 1 and x0 + w <= full.shape[1] and y0 + h <= full.shape[0]):
+        raise OracleError(E_INVALID)
+    return full[y0:y0 + h, x0:x0 + w].copy()
+
+
 def decode_status(blob: bytes, level: int = 0, drop: int = 0) -> int:
     """Decode and return only the status code (for robustness tests)."""
     try:

@@ -57,10 +57,21 @@ uint32_t dmax_bound(uint32_t bits, uint32_t levels)
 struct TileBuild {
     TileGeo g;
     uint64_t arena_elems = 0, tmp_elems[2] = {0, 0}, sym_bytes = 0;
+    std::vector<SelBlock> sel;  // region decode: the blocks it reads, in stream order
+    // decode: range [kx0, kx1) x [ky0, ky1) of LL_k needed, k = z .. levels
+    uint32_t kx0[kMaxLevels + 1] = {}, kx1[kMaxLevels + 1] = {}, ky0[kMaxLevels + 1] = {},
+             ky1[kMaxLevels + 1] = {};
 };
 
-// Geometry of one tile; offsets are relative (filled in later).
-void tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb)
+struct RegionIn {           // region decode: [x0, x1) x [y0, y1) of the level-z image
+    uint32_t x0, y0, x1, y1;
+    const uint64_t *offs;   // byte offset of every block, then the stream length
+};
+
+// Geometry of one tile; offsets are relative (filled in later).  For a
+// decode to level z it also fixes the arena windows: the whole bands, or for
+// a region the blocks under its halo at every level.
+int tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb, const RegionIn *reg = nullptr)
 {
     TileGeo &T = tb.g;
     memset(&T, 0, sizeof(T));
@@ -93,41 +104,109 @@ void tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb)
     }
     T.nblocks_stream = start;
     T.nblocks = prefix_needed;
+    // windows.  K_k is the range of LL_k the decode needs (k = z: the
+    // output).  Undoing level k at sample n reads band samples floor(n/2)-1
+    // .. floor(n/2)+1 (Sec. 3: the 5/3 lifting steps reach one neighbour
+    // each); K_k keeps one more on either side.  The window of level k is
+    // K_k widened to whole 128-blocks.
+    const uint32_t z = (uint32_t)target_level, L = d.levels;
+    auto ll_size = [&](uint32_t k, bool xdim) -> uint32_t {
+        if (k == 0) return xdim ? T.width : T.height;
+        if (k < L) return xdim ? T.lv[k + 1].w : T.lv[k + 1].h;
+        return xdim ? T.ll_w : T.ll_h;
+    };
+    uint32_t a0 = reg ? reg->x0 : 0, a1 = reg ? reg->x1 : ll_size(z, true);
+    uint32_t b0 = reg ? reg->y0 : 0, b1 = reg ? reg->y1 : ll_size(z, false);
+    T.rx0 = a0; T.rx1 = a1; T.ry0 = b0; T.ry1 = b1;
+    tb.kx0[z] = a0; tb.kx1[z] = a1; tb.ky0[z] = b0; tb.ky1[z] = b1;
+    auto cover = [](uint32_t lo, uint32_t hi, uint32_t n, uint32_t &o, uint32_t &len) {
+        o = lo / kBlock * kBlock;
+        uint32_t e = div_up(hi, kBlock) * kBlock;
+        len = (e < n ? e : n) - o;
+    };
+    for (uint32_t k = z + 1; k <= L; k++) {
+        const uint32_t nx = ll_size(k, true), ny = ll_size(k, false);
+        a0 = a0 / 2 >= 2 ? a0 / 2 - 2 : 0; a1 = a1 / 2 + 2 < nx ? a1 / 2 + 2 : nx;
+        b0 = b0 / 2 >= 2 ? b0 / 2 - 2 : 0; b1 = b1 / 2 + 2 < ny ? b1 / 2 + 2 : ny;
+        tb.kx0[k] = a0; tb.kx1[k] = a1; tb.ky0[k] = b0; tb.ky1[k] = b1;
+        LevelGeo &G = T.lv[k];
+        cover(a0, a1, nx, G.wx0, G.ww);
+        cover(b0, b1, ny, G.wy0, G.wh);
+    }
+    uint32_t ll_ww, ll_wh;
+    if (L > z) {
+        T.ll_wx0 = T.lv[L].wx0; T.ll_wy0 = T.lv[L].wy0; ll_ww = T.lv[L].ww; ll_wh = T.lv[L].wh;
+    } else {
+        cover(a0, a1, T.ll_w, T.ll_wx0, ll_ww);
+        cover(b0, b1, T.ll_h, T.ll_wy0, ll_wh);
+    }
     // per-channel arena layout (int32 elements); a decode to level z only
     // needs the bands of levels z+1 .. L
     uint64_t off = 0;
-    T.ll_pitch = round4(T.ll_w);
+    T.ll_pitch = round4(ll_ww);
     T.ll_off = off;
-    off = al(off + (uint64_t)T.ll_pitch * T.ll_h, 64);
-    for (uint32_t l = (uint32_t)target_level + 1; l <= d.levels; l++) {
+    off = al(off + (uint64_t)T.ll_pitch * ll_wh, 64);
+    for (uint32_t l = z + 1; l <= L; l++) {
         LevelGeo &G = T.lv[l];
         uint32_t bw[3] = {(G.w + 1) / 2, G.w / 2, G.w / 2};
         uint32_t bh[3] = {G.h / 2, (G.h + 1) / 2, G.h / 2};
         for (int t = 0; t < 3; t++) {
-            G.pitch[t] = round4(bw[t] ? bw[t] : 1);
+            if (reg) { G.pitch[t] = round4(G.ww); bh[t] = G.wh; }
+            else G.pitch[t] = round4(bw[t] ? bw[t] : 1);
             G.off[t] = off;
             off = al(off + (uint64_t)G.pitch[t] * bh[t], 64);
         }
     }
     T.chan_elems = al(off, 64);
     tb.arena_elems = T.chan_elems * d.channels;
-    // LL ping-pong for the intermediate LL_k, k in [z+1, L-1]: odd k in
-    // buffer 0, even k in buffer 1, each sized for its largest (smallest k)
-    for (uint32_t k = (uint32_t)target_level + 1; k + 1 <= d.levels; k++) {
+    // LL ping-pong for the intermediate LL_k, k in [z+1, L-1] (held in the
+    // window of level k): odd k in buffer 0, even k in buffer 1, each sized
+    // for the largest window of its parity
+    for (uint32_t k = z + 1; k + 1 <= L; k++) {
         int which = (k & 1) ? 0 : 1;
-        if (tb.tmp_elems[which]) continue;
-        T.tmp_pitch[which] = round4(T.lv[k + 1].w);
-        T.tmp_chan[which] = al((uint64_t)T.tmp_pitch[which] * T.lv[k + 1].h, 64);
-        tb.tmp_elems[which] = T.tmp_chan[which] * d.channels;
+        uint32_t p = round4(T.lv[k].ww);
+        if (p > T.tmp_pitch[which]) T.tmp_pitch[which] = p;
+    }
+    for (uint32_t k = z + 1; k + 1 <= L; k++) {
+        int which = (k & 1) ? 0 : 1;
+        uint64_t e = al((uint64_t)T.tmp_pitch[which] * T.lv[k].wh, 64);
+        if (e > T.tmp_chan[which]) T.tmp_chan[which] = e;
+    }
+    for (int which = 0; which < 2; which++) tb.tmp_elems[which] = T.tmp_chan[which] * d.channels;
+    // region decode: the blocks under the windows, in stream order
+    if (reg) {
+        std::vector<uint32_t> locals;
+        const uint32_t nll = T.ll_gx * T.ll_gy;
+        for (uint32_t c = 0; c < d.channels; c++)
+            for (uint32_t by = T.ll_wy0 / kBlock; by < div_up(T.ll_wy0 + ll_wh, kBlock); by++)
+                for (uint32_t bx = T.ll_wx0 / kBlock; bx < div_up(T.ll_wx0 + ll_ww, kBlock); bx++)
+                    locals.push_back(c * nll + by * T.ll_gx + bx);
+        for (uint32_t l = L; l > z; l--) {
+            const LevelGeo &G = T.lv[l];
+            for (uint32_t c = 0; c < d.channels; c++)
+                for (uint32_t by = G.wy0 / kBlock; by < div_up(G.wy0 + G.wh, kBlock); by++)
+                    for (uint32_t bx = G.wx0 / kBlock; bx < div_up(G.wx0 + G.ww, kBlock); bx++) {
+                        if (G.corner_empty && bx == G.gx - 1 && by == G.gy - 1) continue;
+                        locals.push_back(G.group_start + c * G.blocks_per_chan + by * G.gx + bx);
+                    }
+        }
+        tb.sel.clear();
+        for (uint32_t local : locals) {
+            const uint64_t o = reg->offs[local], e = reg->offs[local + 1];
+            if (e < o || e - o > 0xffffffffull) return ISX_E_INVALID_ARG;
+            tb.sel.push_back({local, (uint32_t)(e - o), o});
+        }
+        T.nblocks = (uint32_t)tb.sel.size();
     }
     // symbols
     uint64_t sb = 0;
     for (uint32_t i = 0; i < T.nblocks; i++) {
         BlockDesc B;
-        block_geometry(T, i, B);
+        block_geometry(T, reg ? tb.sel[i].local : i, B);
         sb += block_sym_bytes(B, T.dmax);
     }
     tb.sym_bytes = sb;
+    return ISX_OK;
 }
 
 struct Plan {
@@ -144,8 +223,10 @@ int device_cus()
 }
 
 int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs, int32_t n, Plan &P,
-               const isx_tuning *tune = nullptr)
+               const isx_tuning *tune = nullptr, const isx_region_job *regions = nullptr)
 {
+    if (mode == MODE_DECODE && !jobs && !regions) return ISX_E_INVALID_ARG;
+    auto job_at = [&](int32_t i) -> const isx_decode_job & { return regions ? regions[i].job : jobs[i]; };
     if (n < 1) return ISX_E_INVALID_ARG;
     std::vector<TileBuild> tb((size_t)n);
     PlanHdr &H = P.H;
@@ -165,12 +246,12 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     H.num_cus = (uint32_t)device_cus();
     uint64_t total_blocks = 0, total_slots = 0;
     for (int32_t i = 0; i < n; i++) {
-        const isx_tile_desc &d = mode == MODE_ENCODE ? descs[i] : jobs[i].tile;
+        const isx_tile_desc &d = mode == MODE_ENCODE ? descs[i] : job_at(i).tile;
         int rc = validate_desc(d);
         if (rc) return rc;
         int z = 0;
         if (mode == MODE_DECODE) {
-            const isx_decode_job &j = jobs[i];
+            const isx_decode_job &j = job_at(i);
             if (j.target_level > d.levels) return ISX_E_INVALID_ARG;
             if (j.drop_bitplanes > 31) return ISX_E_INVALID_ARG;
             z = j.target_level;
@@ -179,12 +260,23 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         } else if (d.bytes_per_sample > 1 && ((d.pixel_offset | d.row_stride_bytes) & (d.bytes_per_sample - 1u))) {
             return ISX_E_INVALID_ARG;  // 16/32-bit samples are read as aligned words
         }
-        tile_geometry(d, z, tb[i]);
+        RegionIn rg{}, *rgp = nullptr;
+        uint32_t ow = d.width, oh = d.height;
+        for (int k = 0; k < z; k++) { ow = (ow + 1) / 2; oh = (oh + 1) / 2; }
+        if (regions) {
+            const isx_region_job &R = regions[i];
+            if (!R.h_block_offsets || R.width < 1 || R.height < 1 || R.x0 >= ow || R.y0 >= oh ||
+                R.width > ow - R.x0 || R.height > oh - R.y0)
+                return ISX_E_INVALID_ARG;
+            rg = {R.x0, R.y0, R.x0 + R.width, R.y0 + R.height, R.h_block_offsets};
+            rgp = &rg;
+            ow = R.width;  // output row width
+        }
+        rc = tile_geometry(d, z, tb[i], rgp);
+        if (rc) return rc;
         TileGeo &T = tb[i].g;
         if (mode == MODE_DECODE) {
-            const isx_decode_job &j = jobs[i];
-            uint32_t ow = T.width, oh = T.height;
-            for (int k = 0; k < z; k++) { ow = (ow + 1) / 2; oh = (oh + 1) / 2; }
+            const isx_decode_job &j = job_at(i);
             if (j.out_row_stride_bytes < (uint64_t)ow * T.channels * T.bps) return ISX_E_INVALID_ARG;
             if (T.bps > 1 && ((j.out_offset | j.out_row_stride_bytes) & (T.bps - 1u))) return ISX_E_INVALID_ARG;
             T.pix_offset = j.out_offset;
@@ -260,6 +352,12 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
             it.wg_start = wg;
             uint32_t span = lvl == 0 ? 64u : 2u * H.tq;  // level-0 copies use 64x64 tiles
             it.ntx = div_up(w, span); it.nty = div_up(h, span);
+            if (inverse) {  // tiles over the range of LL_{lvl-1} the decode needs
+                const TileBuild &B = tb[i];
+                it.qx0 = B.kx0[lvl - 1] / 2; it.qy0 = B.ky0[lvl - 1] / 2;
+                it.ntx = div_up(B.kx1[lvl - 1] - 2 * it.qx0, span);
+                it.nty = div_up(B.ky1[lvl - 1] - 2 * it.qy0, span);
+            }
             it.nch = T.channels;
             wg += it.ntx * it.nty * it.nch;
             items.push_back(it);
@@ -275,14 +373,12 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         uint32_t wg = 0;
         for (int32_t i = 0; i < n; i++) {
             const TileGeo &T = tb[i].g;
-            uint32_t w, h;
-            if (T.target_level < T.levels) { w = T.lv[T.target_level + 1].w; h = T.lv[T.target_level + 1].h; }
-            else { w = T.ll_w; h = T.ll_h; }
             WorkItem it;
             memset(&it, 0, sizeof(it));
             it.tile = (uint32_t)i;
             it.wg_start = wg;
-            it.ntx = div_up(w, 2 * H.tq); it.nty = div_up(h, 2 * H.tq);
+            it.qx0 = T.rx0 / 2; it.qy0 = T.ry0 / 2;
+            it.ntx = div_up(T.rx1 - 2 * it.qx0, 2 * H.tq); it.nty = div_up(T.ry1 - 2 * it.qy0, 2 * H.tq);
             it.nch = T.ct ? 1 : div_up(T.channels, 3);
             wg += it.ntx * it.nty * it.nch;
             items.push_back(it);
@@ -296,7 +392,7 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         const TileGeo &T = tb[i].g;
         for (uint32_t b = 0; b < T.nblocks; b++) {
             BlockDesc B;
-            block_geometry(T, b, B);
+            block_geometry(T, tb[i].sel.empty() ? b : tb[i].sel[b].local, B);
             uint32_t cells = (uint32_t)B.p * B.wb * B.hb / 16;
             (cells > 768 ? big : small).push_back(T.block_base + b);
         }
@@ -307,6 +403,13 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     H.work_off = al(H.tiles_off + (uint64_t)n * sizeof(TileGeo), 64);
     H.list_off = al(H.work_off + items.size() * sizeof(WorkItem), 64);
     H.plan_bytes = H.list_off + (big.size() + small.size()) * sizeof(uint32_t);
+    // region decode: each job's selected blocks
+    for (int32_t i = 0; i < n; i++) {
+        if (tb[i].sel.empty()) continue;
+        H.plan_bytes = al(H.plan_bytes, 64);
+        tb[i].g.sel_off = H.plan_bytes;
+        H.plan_bytes += tb[i].sel.size() * sizeof(SelBlock);
+    }
     if (H.plan_bytes > kPlanRegion) {
         // large batches keep the plan after the workspace regions
         uint64_t extra = al(H.plan_bytes);
@@ -319,6 +422,9 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     if (!big.empty()) memcpy(P.bytes.data() + H.list_off, big.data(), big.size() * sizeof(uint32_t));
     if (!small.empty())
         memcpy(P.bytes.data() + H.list_off + big.size() * sizeof(uint32_t), small.data(), small.size() * sizeof(uint32_t));
+    for (int32_t i = 0; i < n; i++)
+        if (!tb[i].sel.empty())
+            memcpy(P.bytes.data() + tb[i].g.sel_off, tb[i].sel.data(), tb[i].sel.size() * sizeof(SelBlock));
     return ISX_OK;
 }
 
@@ -592,6 +698,69 @@ int32_t isx_decode_tiles(const void *d_encoded, const isx_decode_job *h_jobs, in
     if (!h_jobs) return ISX_E_INVALID_ARG;
     Plan P;
     int rc = build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P);
+    if (rc) return rc;
+    if (!d_encoded || !d_pixels_out || !d_status || !d_workspace) return ISX_E_INVALID_ARG;
+    if (workspace_bytes < P.H.ws_bytes) return ISX_E_WORKSPACE;
+    uint8_t *d_plan;
+    rc = upload_plan(P, (uint8_t *)d_workspace, (hipStream_t)stream, &d_plan);
+    if (rc) return rc;
+    return isx_decode_run(P.bytes.data(), d_plan, d_encoded, d_pixels_out, d_status, d_workspace,
+                          workspace_bytes, stream);
+}
+
+int32_t isx_stream_block_offsets(const void *h_head, uint64_t head_bytes, uint64_t *h_offsets, uint64_t n_offsets)
+{
+    if (!h_head || !h_offsets) return ISX_E_INVALID_ARG;
+    const uint8_t *h = (const uint8_t *)h_head;
+    if (head_bytes < 24) return ISX_E_TRUNCATED;
+    if (h[0] != 'I' || h[1] != 'S' || h[2] != 'X' || h[3] != '1' || h[4] != 1) return ISX_E_CORRUPT;
+    auto u32 = [&](uint64_t o) {
+        return (uint32_t)h[o] | ((uint32_t)h[o + 1] << 8) | ((uint32_t)h[o + 2] << 16) | ((uint32_t)h[o + 3] << 24);
+    };
+    const uint64_t nb = u32(20);
+    if (n_offsets < nb + 1) return ISX_E_INVALID_ARG;
+    if (head_bytes < 24 + 4 * nb) return ISX_E_TRUNCATED;
+    uint64_t off = 24 + 4 * nb;
+    for (uint64_t b = 0; b < nb; b++) {
+        h_offsets[b] = off;
+        off += u32(24 + 4 * b);
+    }
+    h_offsets[nb] = off;
+    return ISX_OK;
+}
+
+uint64_t isx_region_workspace_bytes(const isx_region_job *h_jobs, int32_t n_jobs)
+{
+    Plan P;
+    if (!h_jobs || build_plan(MODE_DECODE, nullptr, nullptr, n_jobs, P, nullptr, h_jobs)) return 0;
+    return P.H.ws_bytes;
+}
+
+uint64_t isx_region_plan_bytes(const isx_region_job *h_jobs, int32_t n_jobs)
+{
+    Plan P;
+    if (!h_jobs || build_plan(MODE_DECODE, nullptr, nullptr, n_jobs, P, nullptr, h_jobs)) return 0;
+    return P.H.plan_bytes;
+}
+
+int32_t isx_region_plan_build(const isx_region_job *h_jobs, int32_t n_jobs, const isx_tuning *tuning, void *h_plan,
+                              uint64_t plan_bytes)
+{
+    Plan P;
+    if (!h_jobs || !h_plan) return ISX_E_INVALID_ARG;
+    int rc = build_plan(MODE_DECODE, nullptr, nullptr, n_jobs, P, tuning, h_jobs);
+    if (rc) return rc;
+    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
+    memcpy(h_plan, P.bytes.data(), P.bytes.size());
+    return ISX_OK;
+}
+
+int32_t isx_decode_regions(const void *d_encoded, const isx_region_job *h_jobs, int32_t n_jobs, void *d_pixels_out,
+                           int32_t *d_status, void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!h_jobs) return ISX_E_INVALID_ARG;
+    Plan P;
+    int rc = build_plan(MODE_DECODE, nullptr, nullptr, n_jobs, P, nullptr, h_jobs);
     if (rc) return rc;
     if (!d_encoded || !d_pixels_out || !d_status || !d_workspace) return ISX_E_INVALID_ARG;
     if (workspace_bytes < P.H.ws_bytes) return ISX_E_WORKSPACE;

@@ -28,6 +28,10 @@ struct LevelGeo {          // level l (1..levels) of a tile
     uint32_t pitch[3];     // element pitch of the LH, HL, HH bands (type order)
     uint32_t pad;
     uint64_t off[3];       // int32-element offset of LH, HL, HH of channel 0 from ws base
+    // decode: the part of this level's bands held in the arena (band
+    // coordinates, block aligned), the same window for LL_l, LH, HL and HH;
+    // the whole band for a full decode, a region's halo cover otherwise
+    uint32_t wx0, wy0, ww, wh;
 };
 
 struct TileGeo {
@@ -51,6 +55,13 @@ struct TileGeo {
     uint32_t slot_base;    // first global plane slot
     uint32_t drop;         // decode: magnitude planes left out (quality-progressive)
     uint64_t sym_base;     // byte offset of this tile's symbol area (ws)
+    // decode: output region [rx0, rx1) x [ry0, ry1) of the level-z image
+    // (the whole image for a full decode), window origin of the LL_levels
+    // arena, and the plan offset of the selected-block list (0: the blocks
+    // are the stream prefix 0 .. nblocks-1)
+    uint32_t rx0, ry0, rx1, ry1;
+    uint32_t ll_wx0, ll_wy0;
+    uint64_t sel_off;
     LevelGeo lv[kMaxLevels + 1];  // index 1..levels
 };
 
@@ -59,7 +70,14 @@ struct WorkItem {          // transform work: one tile at one level
     uint32_t wg_start;     // first workgroup index of this item
     uint32_t ntx, nty;     // spatial tiles
     uint32_t nch;          // channel groups (workgroups per spatial tile)
-    uint32_t pad[3];
+    uint32_t qx0, qy0;     // decode: quad origin of the first spatial tile
+    uint32_t pad;
+};
+
+struct SelBlock {          // a block of a region decode: stream index, bytes
+    uint32_t local;        // index in the tile's block order
+    uint32_t len;          // its byte length (checked against the stream)
+    uint64_t off;          // its byte offset from the stream start
 };
 
 struct PlanHdr {
@@ -185,7 +203,8 @@ __host__ __device__ inline void block_geometry(const TileGeo &T, uint32_t local,
         if (cw == 128) B.tw[0] = 128;
         if (ch == 128) B.th[0] = 128;
         B.pitch[0] = T.ll_pitch; B.pitch[1] = B.pitch[2] = 0;
-        B.off[0] = T.ll_off + (uint64_t)c * T.chan_elems + (uint64_t)by * kBlock * T.ll_pitch + bx * kBlock;
+        B.off[0] = T.ll_off + (uint64_t)c * T.chan_elems + (uint64_t)(by * kBlock - T.ll_wy0) * T.ll_pitch +
+                   (bx * kBlock - T.ll_wx0);
         B.off[1] = B.off[2] = 0;
         return;
     }
@@ -211,7 +230,8 @@ __host__ __device__ inline void block_geometry(const TileGeo &T, uint32_t local,
         B.tw[t] = (uint8_t)(tw[t] >= 128 ? 128 : tw[t]);
         B.th[t] = (uint8_t)(th[t] >= 128 ? 128 : th[t]);
         B.pitch[t] = G.pitch[t];
-        B.off[t] = G.off[t] + (uint64_t)c * T.chan_elems + (uint64_t)by * kBlock * G.pitch[t] + bx * kBlock;
+        B.off[t] = G.off[t] + (uint64_t)c * T.chan_elems + (uint64_t)(by * kBlock - G.wy0) * G.pitch[t] +
+                   (bx * kBlock - G.wx0);
     }
 }
 

@@ -85,13 +85,19 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
     }
     __syncthreads();
     int32_t st = s_st;
-    uint64_t carry = 24 + 4ull * T.nblocks_stream, scarry = 0;
+    // region decode: the plan lists the blocks with their byte ranges (from
+    // the stream's size table, read by the host); each is checked here
+    // against the size table in the stream
+    const SelBlock *sel = T.sel_off ? (const SelBlock *)(plan + T.sel_off) : nullptr;
+    const uint64_t table_end = 24 + 4ull * T.nblocks_stream;
+    uint64_t carry = table_end, scarry = 0;
     uint32_t bad = 0;
     for (uint32_t b0 = 0; b0 < T.nblocks; b0 += 256) {
-        uint32_t local = b0 + threadIdx.x;
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t local = (sel && i < T.nblocks) ? sel[i].local : i;
         BlockDesc B;
         uint64_t sz = 0, ssz = 0;
-        if (local < T.nblocks) {
+        if (i < T.nblocks) {
             block_geometry(T, local, B);
             B.drop = (uint8_t)T.drop;
             ssz = block_sym_bytes(B, T.dmax);
@@ -102,15 +108,17 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
             }
         }
         uint64_t tot, stot;
-        uint64_t ex = dblock_excl_sum<256>(sz, sh, &tot);
+        uint64_t ex = sel ? 0 : dblock_excl_sum<256>(sz, sh, &tot);
         uint64_t sex = dblock_excl_sum<256>(ssz, sh, &stot);
-        if (local < T.nblocks) {
-            uint64_t off = carry + ex;
+        if (i < T.nblocks) {
+            uint64_t off = sel ? sel[i].off : carry + ex;
+            bool ok = sz > 0 && off >= table_end && off + sz <= avail;
+            if (sel && sz != sel[i].len) ok = false;
             B.tile = job;
             B.sym_off = T.sym_base + scarry + sex;
-            B.slot = T.slot_base + local * T.dmax;
+            B.slot = T.slot_base + i * T.dmax;
             B.dmax = T.dmax;
-            if (st == D_OK && off + sz <= avail && sz > 0) {
+            if (st == D_OK && ok) {
                 B.byte_off = T.enc_offset + off;
                 B.byte_len = (uint32_t)sz;
             } else {
@@ -118,9 +126,9 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
                 B.byte_len = 0;
                 if (st == D_OK) bad = 1;
             }
-            descs[T.block_base + local] = B;
+            descs[T.block_base + i] = B;
         }
-        carry += tot;
+        if (!sel) carry += tot;
         scarry += stot;
     }
     bad = __syncthreads_or(bad);

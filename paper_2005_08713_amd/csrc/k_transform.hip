@@ -368,12 +368,24 @@ __device__ inline void inverse_window(int32_t *win, bool do_cols, bool do_rows)
     }
 }
 
+// Interleaved coordinate g (reflected into the image) -> band index relative
+// to the level's arena window, clamped into it, with g's parity in bit 0.
+// Positions the window does not hold only feed outputs nobody reads.
+__device__ inline int32_t win_idx(int g, uint32_t o, uint32_t n)
+{
+    int r = (g >> 1) - (int)o;
+    r = r < 0 ? 0 : (r >= (int)n ? (int)n - 1 : r);
+    return (r << 1) | (g & 1);
+}
+
 template <int TQ>
-__device__ inline void fill_maps(int32_t *rmap, int32_t *cmap, int qx0, int qy0, int w, int h)
+__device__ inline void fill_maps(int32_t *rmap, int32_t *cmap, int qx0, int qy0, int w, int h, const LevelGeo &G)
 {
     constexpr int WN = 2 * TQ + 4;
-    if (threadIdx.x < WN) rmap[threadIdx.x] = reflect_idx(2 * qy0 - 2 + (int)threadIdx.x, h);
-    else if (threadIdx.x < 2 * WN) cmap[threadIdx.x - WN] = reflect_idx(2 * qx0 - 2 + (int)threadIdx.x - WN, w);
+    if (threadIdx.x < WN)
+        rmap[threadIdx.x] = win_idx(reflect_idx(2 * qy0 - 2 + (int)threadIdx.x, h), G.wy0, G.wh);
+    else if (threadIdx.x < 2 * WN)
+        cmap[threadIdx.x - WN] = win_idx(reflect_idx(2 * qx0 - 2 + (int)threadIdx.x - WN, w), G.wx0, G.ww);
 }
 
 // Inverse of level `level` into LL_{level-1} (an intermediate level).
@@ -391,20 +403,24 @@ __global__ void __launch_bounds__(256) k_inv_level(PlanHdr H, const uint8_t *__r
     uint32_t r = blockIdx.x - W.wg_start;
     int c = (int)(r % W.nch);
     uint32_t sp = r / W.nch;
-    int qx0 = (int)(sp % W.ntx) * TQ, qy0 = (int)(sp / W.ntx) * TQ;
+    int qx0 = (int)(W.qx0 + (sp % W.ntx) * TQ), qy0 = (int)(W.qy0 + (sp / W.ntx) * TQ);
     int32_t *wsi = (int32_t *)ws;
     const LevelGeo &G = T.lv[level];
-    fill_maps<TQ>(rmap, cmap, qx0, qy0, (int)G.w, (int)G.h);
+    fill_maps<TQ>(rmap, cmap, qx0, qy0, (int)G.w, (int)G.h, G);
     __syncthreads();
     stage_inverse<TQ>(T, level, c, rmap, cmap, wsi, win);
     __syncthreads();
     inverse_window<TQ>(win, G.h > 1, G.w > 1);
+    // LL_{level-1} is the low band of level-1: store the part inside that
+    // level's window
     int k = level - 1, which = (k & 1) ? 0 : 1;
+    const LevelGeo &D = T.lv[k];
     int32_t *dst = wsi + T.tmp_off[which] + (uint64_t)c * T.tmp_chan[which];
     uint32_t dp = T.tmp_pitch[which];
     for (int i = threadIdx.x; i < T2 * T2; i += blockDim.x) {
-        int x = 2 * qx0 + (i % T2), y = 2 * qy0 + (i / T2);
-        if (x < (int)G.w && y < (int)G.h) dst[(uint64_t)y * dp + x] = win[(2 + i / T2) * WP + 2 + (i % T2)];
+        int x = 2 * qx0 + (i % T2) - (int)D.wx0, y = 2 * qy0 + (i / T2) - (int)D.wy0;
+        if ((uint32_t)x < D.ww && (uint32_t)y < D.wh)
+            dst[(uint64_t)y * dp + x] = win[(2 + i / T2) * WP + 2 + (i % T2)];
     }
 }
 
@@ -433,7 +449,7 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
     uint32_t r = blockIdx.x - W.wg_start;
     int cg = (int)(r % W.nch);
     uint32_t sp = r / W.nch;
-    int qx0 = (int)(sp % W.ntx) * TQ, qy0 = (int)(sp / W.ntx) * TQ;
+    int qx0 = (int)(W.qx0 + (sp % W.ntx) * TQ), qy0 = (int)(W.qy0 + (sp / W.ntx) * TQ);
     int32_t *wsi = (int32_t *)ws;
     int z = T.target_level;
     int c0 = cg * 3, nc = (int)T.channels - c0;
@@ -442,7 +458,9 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
     const bool fused = z < T.levels;
     if (fused) { ow = (int)T.lv[z + 1].w; oh = (int)T.lv[z + 1].h; }
     else { ow = (int)T.ll_w; oh = (int)T.ll_h; }
-    if (fused) fill_maps<TQ>(rmap, cmap, qx0, qy0, ow, oh);
+    if (fused) fill_maps<TQ>(rmap, cmap, qx0, qy0, ow, oh, T.lv[z + 1]);
+    // output region of the level-z image (all of it for a full decode)
+    const int rx0 = (int)T.rx0, ry0 = (int)T.ry0, rx1 = (int)T.rx1, ry1 = (int)T.ry1;
     const int tx = (threadIdx.x % TPR) * 4, ty = threadIdx.x / TPR;
     int32_t v[3][NR][4];
 #pragma unroll
@@ -463,7 +481,9 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
             const int32_t *ll = wsi + T.ll_off + (uint64_t)(c0 + k) * T.chan_elems;
             for (int i = threadIdx.x; i < T2 * T2; i += blockDim.x) {
                 int x = 2 * qx0 + (i % T2), y = 2 * qy0 + (i / T2);
-                if (x < ow && y < oh) win[(2 + i / T2) * WP + 2 + (i % T2)] = ll[(uint64_t)y * T.ll_pitch + x];
+                if (x >= rx0 && x < rx1 && y >= ry0 && y < ry1)
+                    win[(2 + i / T2) * WP + 2 + (i % T2)] =
+                        ll[(uint64_t)(y - (int)T.ll_wy0) * T.ll_pitch + (x - (int)T.ll_wx0)];
             }
             __syncthreads();
         }
@@ -476,8 +496,9 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
     const uint32_t C = T.channels, bps = T.bps;
     // RGB u8 rows whose start is 4-byte aligned: stage each output row in LDS
     // (the window is free now) and store whole dwords, contiguous per row
-    const uint64_t rowbase0 = T.pix_offset + (uint64_t)(2 * qx0) * 3;
-    const bool staged = bps == 1 && C == 3 && ((rowbase0 | T.pix_stride) & 3u) == 0 &&
+    // (a region starting at an odd column takes the per-pixel path)
+    const uint64_t rowbase0 = T.pix_offset + (uint64_t)(2 * qx0 - rx0) * 3;
+    const bool staged = bps == 1 && C == 3 && 2 * qx0 >= rx0 && ((rowbase0 | T.pix_stride) & 3u) == 0 &&
                         (((uintptr_t)pix) & 3u) == 0;
     if (staged) {
         __syncthreads();
@@ -497,14 +518,14 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
             }
         }
         __syncthreads();
-        const int nx = min(T2, ow - 2 * qx0);  // valid pixels in the row
+        const int nx = min(T2, rx1 - 2 * qx0);  // valid pixels in the row
         const int nbytes = nx * 3;
         const int ndw = nbytes / 4;
         for (int i = threadIdx.x; i < T2 * (T2 * 3 / 4); i += blockDim.x) {
             int ly = i / (T2 * 3 / 4), k = i % (T2 * 3 / 4);
             int y = 2 * qy0 + ly;
-            if (y >= oh) continue;
-            uint8_t *row = pix + rowbase0 + (uint64_t)y * T.pix_stride;
+            if (y < ry0 || y >= ry1) continue;
+            uint8_t *row = pix + rowbase0 + (uint64_t)(y - ry0) * T.pix_stride;
             const uint8_t *src = ob + ly * (T2 * 3);
             if (k < ndw) ((uint32_t *)row)[k] = ((const uint32_t *)src)[k];
             else if (k == ndw) for (int b = 4 * ndw; b < nbytes; b++) row[b] = src[b];
@@ -514,7 +535,7 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) {
         int y = 2 * qy0 + ty + RSTEP * rr;
-        if (y >= oh) continue;
+        if (y < ry0 || y >= ry1) continue;
         int x0 = 2 * qx0 + tx;
         int32_t o[3][4];
 #pragma unroll
@@ -525,20 +546,22 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
 #pragma unroll
             for (int k = 0; k < 3; k++) o[k][xx] = o[k][xx] < 0 ? 0 : (o[k][xx] > top ? top : o[k][xx]);
         }
-        uint8_t *row = pix + T.pix_offset + (uint64_t)y * T.pix_stride;
-        if (bps == 1 && C == 3 && x0 + 3 < ow && ((((uintptr_t)(row + (uint32_t)x0 * 3)) & 3u) == 0)) {
-            uint32_t *d = (uint32_t *)(row + (uint32_t)x0 * 3);
+        uint8_t *row = pix + T.pix_offset + (uint64_t)(y - ry0) * T.pix_stride;  // region row
+        if (bps == 1 && C == 3 && x0 >= rx0 && x0 + 3 < rx1 &&
+            ((((uintptr_t)(row + (uint32_t)(x0 - rx0) * 3)) & 3u) == 0)) {
+            uint32_t *d = (uint32_t *)(row + (uint32_t)(x0 - rx0) * 3);
             d[0] = (uint32_t)o[0][0] | ((uint32_t)o[1][0] << 8) | ((uint32_t)o[2][0] << 16) | ((uint32_t)o[0][1] << 24);
             d[1] = (uint32_t)o[1][1] | ((uint32_t)o[2][1] << 8) | ((uint32_t)o[0][2] << 16) | ((uint32_t)o[1][2] << 24);
             d[2] = (uint32_t)o[2][2] | ((uint32_t)o[0][3] << 8) | ((uint32_t)o[1][3] << 16) | ((uint32_t)o[2][3] << 24);
         } else {
             for (int xx = 0; xx < 4; xx++) {
                 int x = x0 + xx;
-                if (x >= ow) break;
+                if (x < rx0) continue;
+                if (x >= rx1) break;
 #pragma unroll
                 for (int k = 0; k < 3; k++) {
                     if (k >= nc) break;
-                    uint32_t e = ((uint32_t)x * C + c0 + k) * bps;
+                    uint32_t e = ((uint32_t)(x - rx0) * C + c0 + k) * bps;
                     if (bps == 1) row[e] = (uint8_t)o[k][xx];
                     else if (bps == 2) *(uint16_t *)(row + e) = (uint16_t)o[k][xx];
                     else *(uint32_t *)(row + e) = (uint32_t)o[k][xx];

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libisx.so")
 
 OK, E_INVALID_ARG, E_CAPACITY, E_CORRUPT, E_TRUNCATED, E_UNSUPPORTED, E_WORKSPACE, E_HIP = (
     0, -1, -2, -3, -4, -5, -6, -7)
-CT_NONE, CT_RCT = 0, 1
+CT_NONE, CT_RCT, CT_YCOCG = 0, 1, 2
 
 
 class TileDesc(ctypes.Structure):
@@ -36,6 +36,12 @@ class DecodeJob(ctypes.Structure):
                 ("reserved", ctypes.c_uint16)]
 
 
+class RegionJob(ctypes.Structure):
+    _fields_ = [("job", DecodeJob), ("x0", ctypes.c_uint32), ("y0", ctypes.c_uint32),
+                ("width", ctypes.c_uint32), ("height", ctypes.c_uint32),
+                ("h_block_offsets", ctypes.c_void_p)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("transform_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 6)]
@@ -47,7 +53,7 @@ def tuning(transform_tile=0, blocks_per_cu=0) -> Tuning:
     return t
 
 
-assert ctypes.sizeof(TileDesc) == 32 and ctypes.sizeof(DecodeJob) == 64
+assert ctypes.sizeof(TileDesc) == 32 and ctypes.sizeof(DecodeJob) == 64 and ctypes.sizeof(RegionJob) == 88
 
 _lib = None
 
@@ -87,6 +93,11 @@ def lib():
             "isx_decode_run_stages": (i32, [P, P, P, P, P, P, u64, P, i32, i32]),
             "isx_encode_plan_build_tuned": (i32, [P, i32, P, P, u64]),
             "isx_decode_plan_build_tuned": (i32, [P, i32, P, P, u64]),
+            "isx_stream_block_offsets": (i32, [P, u64, P, u64]),
+            "isx_region_workspace_bytes": (u64, [P, i32]),
+            "isx_region_plan_bytes": (u64, [P, i32]),
+            "isx_region_plan_build": (i32, [P, i32, P, P, u64]),
+            "isx_decode_regions": (i32, [P, P, i32, P, P, P, u64, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -101,7 +112,9 @@ EXPORTS = ["isx_max_encoded_bytes", "isx_encode_workspace_bytes", "isx_decode_wo
            "isx_encode_plan_build", "isx_encode_run", "isx_decode_plan_bytes",
            "isx_decode_plan_build", "isx_decode_run", "isx_status_string", "isx_debug_forward",
            "isx_debug_huffman", "isx_stage_count", "isx_stage_name", "isx_encode_run_stages",
-           "isx_decode_run_stages", "isx_encode_plan_build_tuned", "isx_decode_plan_build_tuned"]
+           "isx_decode_run_stages", "isx_encode_plan_build_tuned", "isx_decode_plan_build_tuned",
+           "isx_stream_block_offsets", "isx_region_workspace_bytes", "isx_region_plan_bytes",
+           "isx_region_plan_build", "isx_decode_regions"]
 
 
 def status_string(code: int) -> str:
@@ -215,25 +228,37 @@ class Encoder:
 
 
 class Decoder:
-    """Decoder for a fixed list of jobs (plan uploaded once)."""
+    """Decoder for a fixed list of jobs (plan uploaded once): whole-tile
+    DecodeJobs, or RegionJobs (their block-offset arrays must stay alive
+    until the constructor returns)."""
 
     def __init__(self, jobs, out_bytes, device="cuda", tune=None, out=None):
         torch = _torch()
         L = lib()
         self.n = len(jobs)
-        self.jobs = (DecodeJob * self.n)()
+        regions = self.n > 0 and isinstance(jobs[0], RegionJob)
+        self.jobs = ((RegionJob if regions else DecodeJob) * self.n)()
         for i, j in enumerate(jobs):
             self.jobs[i] = j
-        pb = L.isx_decode_plan_bytes(self.jobs, self.n)
-        if pb == 0:
-            raise IsxError(E_INVALID_ARG, "decode plan")
-        self.h_plan = (ctypes.c_uint8 * pb)()
         self.tune = tune if tune is not None else tuning()
-        _check(L.isx_decode_plan_build_tuned(self.jobs, self.n, ctypes.byref(self.tune), self.h_plan,
-                                             pb), "decode plan")
+        if regions:
+            pb = L.isx_region_plan_bytes(self.jobs, self.n)
+            if pb == 0:
+                raise IsxError(E_INVALID_ARG, "region plan")
+            self.h_plan = (ctypes.c_uint8 * pb)()
+            _check(L.isx_region_plan_build(self.jobs, self.n, ctypes.byref(self.tune), self.h_plan, pb),
+                   "region plan")
+            self.ws_bytes = int(L.isx_region_workspace_bytes(self.jobs, self.n))
+        else:
+            pb = L.isx_decode_plan_bytes(self.jobs, self.n)
+            if pb == 0:
+                raise IsxError(E_INVALID_ARG, "decode plan")
+            self.h_plan = (ctypes.c_uint8 * pb)()
+            _check(L.isx_decode_plan_build_tuned(self.jobs, self.n, ctypes.byref(self.tune), self.h_plan,
+                                                 pb), "decode plan")
+            self.ws_bytes = int(L.isx_decode_workspace_bytes(self.jobs, self.n))
         self.graph = None
         self.d_plan = torch.frombuffer(bytearray(self.h_plan), dtype=torch.uint8).to(device)
-        self.ws_bytes = int(L.isx_decode_workspace_bytes(self.jobs, self.n))
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.out = out if out is not None else torch.zeros(max(1, out_bytes), dtype=torch.uint8,
                                                            device=device)
@@ -391,6 +416,71 @@ def decode_streams(blobs, levels=None, device="cuda", return_status=False, drop=
         if s != OK:
             raise IsxError(int(s), f"decode job {i}")
     return res
+
+
+def stream_block_offsets(head: bytes) -> np.ndarray:
+    """Byte offset of every block of a stream, then its length (uint64), from
+    the stream's first 24 + 4 * blocks bytes (the library's host parser)."""
+    import struct
+    if len(head) < 24:
+        raise IsxError(E_TRUNCATED, "stream head")
+    nb = struct.unpack_from("<I", head, 20)[0]
+    out = np.zeros(nb + 1, dtype=np.uint64)
+    buf = np.frombuffer(head, np.uint8)
+    _check(lib().isx_stream_block_offsets(buf.ctypes.data_as(ctypes.c_void_p), len(head),
+                                          out.ctypes.data_as(ctypes.c_void_p), nb + 1),
+           "isx_stream_block_offsets")
+    return out
+
+
+def region_job(desc: TileDesc, offsets: np.ndarray, level, x0, y0, w, h, in_offset=0, in_bytes=None,
+               out_offset=0, drop=0) -> RegionJob:
+    """Region [x0, x0+w) x [y0, y0+h) of the level-`level` image of one stream."""
+    r = RegionJob()
+    r.job.tile = desc
+    r.job.in_offset = in_offset
+    r.job.in_bytes = int(offsets[-1]) if in_bytes is None else in_bytes
+    r.job.out_offset = out_offset
+    r.job.out_row_stride_bytes = w * desc.channels * desc.bytes_per_sample
+    r.job.target_level, r.job.drop_bitplanes = level, drop
+    r.x0, r.y0, r.width, r.height = x0, y0, w, h
+    r.h_block_offsets = offsets.ctypes.data
+    return r
+
+
+def decode_regions(blob: bytes, regions, device="cuda", return_status=False):
+    """Decode regions (level, x0, y0, w, h[, drop]) of one stream in one call;
+    returns numpy images."""
+    torch = _torch()
+    d = _parse_header(blob)
+    offs = stream_block_offsets(blob[:24 + 4 * struct_u32(blob, 20)])
+    jobs, outs, off = [], [], 0
+    bps = d.bytes_per_sample
+    for reg in regions:
+        z, x0, y0, w, h = reg[:5]
+        drop = reg[5] if len(reg) > 5 else 0
+        jobs.append(region_job(d, offs, z, x0, y0, w, h, in_bytes=len(blob), out_offset=off, drop=drop))
+        outs.append((off, h, w))
+        off += h * w * d.channels * bps
+        off += (-off) % 16
+    d_enc = torch.from_numpy(np.frombuffer(blob, np.uint8).copy()).to(device)
+    dec = Decoder(jobs, off, device)
+    dec.run(d_enc)
+    torch.cuda.synchronize()
+    host = dec.out.cpu().numpy()
+    st = [int(x) for x in dec.status.cpu().numpy()]
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[bps]
+    res = [host[o:o + h * w * d.channels * bps].view(dt).reshape(h, w, d.channels).copy() for o, h, w in outs]
+    if return_status:
+        return res, st
+    for i, s in enumerate(st):
+        if s != OK:
+            raise IsxError(s, f"region job {i}")
+    return res
+
+
+def struct_u32(blob: bytes, off: int) -> int:
+    return int.from_bytes(blob[off:off + 4], "little")
 
 
 def debug_forward(img: np.ndarray, levels, bits=None, ct=None, qstep=1, device="cuda"):

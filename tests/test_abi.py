@@ -81,3 +81,45 @@ def test_max_encoded_bytes_covers_oracle_output():
         blob = oracle.encode_tile(img, lv, bits=bits)
         d = isx.tile_desc(w, h, c, img.itemsize, bits, lv)
         assert isx.lib().isx_max_encoded_bytes(ctypes.byref(d), 1) >= len(blob)
+
+
+def test_stream_block_offsets_and_region_validation():
+    """The host parser of a stream's size table, and the limits of region
+    jobs, checked on the CPU (plans only, no device call)."""
+    import numpy as np
+    import oracle
+    from paper_2005_08713_amd import synth
+    L = isx.lib()
+    img = synth.he_like(300, 200, 4)
+    blob = oracle.encode_tile(img, 3)
+    nb = int.from_bytes(blob[20:24], "little")
+    offs = isx.stream_block_offsets(blob[:24 + 4 * nb])
+    sizes = np.frombuffer(blob[24:24 + 4 * nb], np.uint32).astype(np.uint64)
+    assert offs[0] == 24 + 4 * nb and offs[-1] == len(blob)
+    assert np.array_equal(np.diff(offs), sizes)
+    with pytest.raises(isx.IsxError):
+        isx.stream_block_offsets(blob[:24 + 4 * nb - 1])
+    with pytest.raises(isx.IsxError):
+        isx.stream_block_offsets(b"JPEG" + blob[4:24 + 4 * nb])
+    d = isx._parse_header(blob)
+
+    def plan_bytes(z, x0, y0, w, h, stride=None):
+        r = isx.region_job(d, offs, z, x0, y0, w, h)
+        if stride is not None:
+            r.job.out_row_stride_bytes = stride
+        return L.isx_region_plan_bytes((isx.RegionJob * 1)(r), 1)
+
+    assert plan_bytes(0, 0, 0, 300, 200) > 0
+    assert plan_bytes(3, 37, 24, 1, 1) > 0
+    assert plan_bytes(1, 149, 99, 1, 1) > 0
+    for bad in [(0, 0, 0, 301, 200), (0, 300, 0, 1, 1), (1, 0, 0, 151, 1), (0, 5, 5, 0, 3), (4, 0, 0, 1, 1)]:
+        assert plan_bytes(*bad) == 0, bad
+    assert plan_bytes(0, 0, 0, 100, 100, stride=299) == 0
+    r = isx.region_job(d, offs, 0, 0, 0, 10, 10)
+    r.h_block_offsets = None
+    assert L.isx_region_plan_bytes((isx.RegionJob * 1)(r), 1) == 0
+    # a small region reads fewer blocks and a smaller workspace than the whole tile
+    small = isx.region_job(d, offs, 0, 10, 10, 20, 20)
+    whole = isx.region_job(d, offs, 0, 0, 0, 300, 200)
+    assert L.isx_region_workspace_bytes((isx.RegionJob * 1)(small), 1) < \
+        L.isx_region_workspace_bytes((isx.RegionJob * 1)(whole), 1)
