@@ -44,6 +44,8 @@ def parse():
                     help="single: one 4096x4096 image (default); batch: 4096 uneven tiles; "
                          "serve: tile-decode requests against an HBM-resident slide")
     ap.add_argument("--slide", type=str, default="64x48", help="serve: slide size in 512-px tiles")
+    ap.add_argument("--layout", choices=["tiles", "pyramid"], default="tiles",
+                    help="serve: the slide as independent 512-px tiles, or as one pyramid (region decode)")
     ap.add_argument("--rates", type=str, default="2000,5000,10000,20000", help="serve: requests/s")
     ap.add_argument("--requests", type=int, default=4000, help="serve: requests per rate")
     ap.add_argument("--tiles", type=int, default=4096, help="tiles of the batch workload")
@@ -399,16 +401,23 @@ def bench_serve(args):
     from paper_2005_08713_amd import serve
     torch.cuda.set_device(0)
     tx, ty = (int(v) for v in args.slide.split("x"))
-    log(f"[serve] building {tx}x{ty}-tile slide")
-    slide = serve.Slide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log)
-    enc_bytes = int(slide.sizes.sum())
-    log(f"[serve] slide encoded: {slide.raw_bytes / 1e9:.2f} GB raw -> {enc_bytes / 1e9:.2f} GB in HBM "
+    pyr = args.layout == "pyramid"
+    log(f"[serve] building {tx}x{ty}-tile slide ({args.layout})")
+    if pyr:
+        slide = serve.PyramidSlide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log)
+        enc_bytes = slide.size
+    else:
+        slide = serve.Slide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log)
+        enc_bytes = int(slide.sizes.sum())
+    log(f"[serve] slide encoded: {slide.raw_bytes / 1e9:.2f} GB raw -> {enc_bytes / 1e9:.3f} GB in HBM "
         f"({slide.encode_s:.1f} s incl. generation)")
     trace = serve.viewer_trace(slide, n_viewers=32, steps=400, zmax=6, seed=502)
     srv = serve.Server(slide, slots=3, ws_bytes=512 << 20, max_reqs=64)
     # correctness: a sample of requests alone vs in a mixed batch, and vs the oracle
     cpu = None
-    if not args.no_cpu:
+    if pyr:
+        cpu = _pyramid_checks(args, slide, srv, trace)
+    elif not args.no_cpu:
         import oracle
         enc = None
         sample = trace[:24]
@@ -453,17 +462,89 @@ def bench_serve(args):
         log(f"[serve] lambda={lam:.0f}/s: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms, "
             f"{st['decoded_mpx_s']:.0f} MP/s decoded, {st['batches']} batches")
     best = max(rows, key=lambda r: r["decoded_mpx_s"])
+    layout = (f"one {tx * 512}x{ty * 512} RGB pyramid (6 levels), region decode" if pyr else
+              f"{tx}x{ty} slide of 512x512 RGB tiles (6 levels)")
     out = {"metric": "p99 tile-decode ms (served slide, continuous batching)",
            "value": round(rows[-1]["p99_ms"], 3), "unit": "ms", "n_gpus": 1, "steps": len(rows),
            "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "int32", "data": "synthetic",
-           "config": {"workload": f"served {tx}x{ty} slide of 512x512 RGB tiles (6 levels), 32 viewers, "
-                                  f"zoom 0-6, Poisson arrivals", "slide_raw_bytes": slide.raw_bytes,
+           "config": {"workload": f"served {layout}, 32 viewers, zoom 0-6, 512x512 views, Poisson arrivals",
+                      "slide_raw_bytes": slide.raw_bytes,
                       "slide_encoded_bytes": enc_bytes,
                       "rates": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in rows],
                       "peak_decoded_mpx_s": round(best["decoded_mpx_s"], 1)},
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def _pyramid_checks(args, slide, srv, trace):
+    """Served views of the one-pyramid slide: equal to the same view decoded
+    alone; at zoom 0 equal to the slide's pixels; at zoom z >= 1 equal to
+    the crop of the GPU's whole-slide level-z decode (region decode equals
+    that crop at any size); and, for views at zoom >= 4, equal to the
+    oracle's crop of its own level-z decode (timed: the CPU baseline)."""
+    import torch
+    from paper_2005_08713_amd import isx, serve
+    sample = trace[:24] + [t for t in trace if t[0] >= 4][:4]
+    reqs = [serve.Request(i, z, X, Y) for i, (z, X, Y) in enumerate(sample)]
+    for r in reqs:
+        r.arrival = 0.0
+    got = {}
+
+    def check(slot, rs):
+        host = slot.out.cpu().numpy()
+        for r in rs:
+            got[r.rid] = host[r.out_off:r.out_off + srv.req_bytes].copy()
+    srv.run(reqs, check=check)
+    T = slide.tile
+
+    def expect(r, full):
+        x0, y0, w, h = slide.region(r.z, r.X, r.Y)
+        e = np.zeros((T, T, 3), np.uint8)
+        e[:h, :w] = full[y0:y0 + h, x0:x0 + w]
+        return e.reshape(-1)
+
+    fulls = {}
+    for r in reqs[:12]:
+        if r.z == 0:
+            full = slide.image
+            x0, y0, w, h = slide.region(0, r.X, r.Y)
+            e = np.zeros((T, T, 3), np.uint8)
+            e[:h, :w] = full[y0:y0 + h, x0:x0 + w].cpu().numpy()
+            exp = e.reshape(-1)
+        else:
+            if r.z not in fulls:
+                ow, oh = isx.out_size(slide.W, slide.H, r.z)
+                j = isx.DecodeJob()
+                j.tile, j.in_offset, j.in_bytes = slide.desc, 0, slide.size
+                j.out_offset, j.out_row_stride_bytes, j.target_level = 0, ow * 3, r.z
+                dec = isx.Decoder([j], ow * oh * 3)
+                dec.run(slide.arena)
+                torch.cuda.synchronize()
+                if int(dec.status[0]) != 0:
+                    raise SystemExit("whole-slide decode failed")
+                fulls[r.z] = dec.out.cpu().numpy().reshape(oh, ow, 3)
+                del dec
+            exp = expect(r, fulls[r.z])
+        if not np.array_equal(exp, got[r.rid]):
+            raise SystemExit(f"served pyramid view {r} differs from the whole-slide decode")
+        alone = srv.decode_alone(serve.Request(r.rid, r.z, r.X, r.Y))
+        if not np.array_equal(alone, got[r.rid]):
+            raise SystemExit(f"served pyramid view {r} differs alone vs in the mix")
+    log("[serve] pyramid views equal the whole-slide decode and their lone decodes")
+    if args.no_cpu:
+        return None
+    import oracle
+    blob = slide.arena.cpu().numpy().tobytes()
+    deep = [r for r in reqs if r.z >= 4][:4]
+    t0 = time.perf_counter()
+    for r in deep:
+        if not np.array_equal(expect(r, oracle.decode_tile(blob, r.z)), got[r.rid]):
+            raise SystemExit(f"served pyramid view {r} differs from the oracle")
+    t1 = time.perf_counter()
+    log("[serve] oracle parity ok on views at zoom >= 4")
+    return {"value": round(len(deep) / (t1 - t0), 3), "unit": "requests/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle: {len(deep)} views at zoom >= 4, each the crop of its whole level-z decode"}
 
 
 def stream_symbol_count(blob: bytes) -> int:

@@ -1,11 +1,16 @@
 """Tile-decode serving with continuous batching over an HBM-resident slide.
 
-A slide is cut into square tiles, each encoded on its own (Sec. 4: separate
-blocks per scale let any tile be decoded at any resolution level).  The
-encoded tiles stay in one device arena.  A request (z, X, Y) asks for the
-512x512 view at zoom z: the 2^z x 2^z source tiles (X 2^z + i, Y 2^z + j),
-each decoded to level z (only its coarser blocks) straight into its place in
-the request's output buffer.
+Two layouts of the same slide:
+
+* ``Slide``: cut into square tiles, each encoded on its own (Sec. 4: separate
+  blocks per scale let any tile be decoded at any resolution level).  A
+  request (z, X, Y) for the 512x512 view at zoom z decodes the 2^z x 2^z
+  source tiles (X 2^z + i, Y 2^z + j), each to level z (only its coarser
+  blocks), straight into its place in the request's output buffer.
+* ``PyramidSlide``: the whole slide as ONE stream, one non-redundant wavelet
+  pyramid.  The same request is one region job: the 512x512 window
+  [512 X, 512 X + 512) x [512 Y, 512 Y + 512) of the level-z image, decoded
+  from the blocks under its halo at levels z+1 .. L only.
 
 The server loop admits arrived requests into a free batch slot as long as the
 slot's workspace and output memory allow, launches the whole batch as one
@@ -109,7 +114,64 @@ class Slide:
         return max(0, min(s, self.tx - X * s)) * max(0, min(s, self.ty - Y * s))
 
 
-def viewer_trace(slide: Slide, n_viewers=32, steps=200, zmax=6, vw=4, vh=3, seed=502):
+class PyramidSlide:
+    """The slide of ``Slide`` (same generator, seed and tile batches, so the
+    same pixels) assembled in HBM and encoded as one tile: one pyramid, one
+    stream.  Host index: the byte offset of every block (from the stream's
+    size table)."""
+
+    def __init__(self, tiles_x, tiles_y, tile=512, levels=6, seed=501, batch=256, device="cuda", log=None):
+        import torch
+        from .synth import SlideGen
+        self.tx, self.ty, self.tile, self.levels = tiles_x, tiles_y, tile, levels
+        self.n = tiles_x * tiles_y
+        W, H = tiles_x * tile, tiles_y * tile
+        self.W, self.H = W, H
+        gen = SlideGen(tiles_x, tiles_y, tile, seed, device)
+        self.gen = gen
+        t0 = time.perf_counter()
+        img = torch.empty((H, W, 3), dtype=torch.uint8, device=device)
+        for b0 in range(0, self.n, batch):
+            ids = list(range(b0, min(self.n, b0 + batch)))
+            px = gen.tiles(ids, b0 // batch)
+            for k, t in enumerate(ids):
+                X, Y = t % tiles_x, t // tiles_x
+                img[Y * tile:(Y + 1) * tile, X * tile:(X + 1) * tile] = px[k]
+        torch.cuda.synchronize()
+        self.desc = isx.tile_desc(W, H, 3, 1, 8, levels)
+        enc = isx.Encoder([self.desc], device)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        enc.run(img.reshape(-1))
+        torch.cuda.synchronize()
+        self.encode_only_s = time.perf_counter() - t1
+        if int(enc.status[0]) != 0:
+            raise RuntimeError("pyramid encode failed")
+        size = int(enc.sizes[0])
+        self.arena = enc.out[int(enc.offsets[0]):int(enc.offsets[0]) + size].clone()
+        self.size = size
+        del enc
+        self.image = img
+        nb = int.from_bytes(self.arena[20:24].cpu().numpy().tobytes(), "little")
+        self.offsets = isx.stream_block_offsets(self.arena[:24 + 4 * nb].cpu().numpy().tobytes())
+        self.encode_s = time.perf_counter() - t0
+        self.raw_bytes = W * H * 3
+        if log:
+            log(f"[pyramid] {W}x{H} slide encoded as one stream: {size / 1e9:.3f} GB, {nb} blocks, "
+                f"encode {self.encode_only_s * 1e3:.1f} ms")
+
+    def grid(self, z):
+        s = 1 << z
+        return -(-self.tx // s), -(-self.ty // s)
+
+    def region(self, z, X, Y):
+        """(x0, y0, w, h) of view (z, X, Y) in the level-z image."""
+        ow, oh = isx.out_size(self.W, self.H, z)
+        x0, y0 = X * self.tile, Y * self.tile
+        return x0, y0, min(self.tile, ow - x0), min(self.tile, oh - y0)
+
+
+def viewer_trace(slide, n_viewers=32, steps=200, zmax=6, vw=4, vh=3, seed=502):
     """Requests of viewers doing random walks: pan w.p. 0.8, zoom +-1 w.p. 0.2;
     each step requests the newly visible tiles of the viewport."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -156,6 +218,9 @@ JOB_DTYPE = np.dtype([("pixel_offset", "<u8"), ("width", "<u4"), ("height", "<u4
                       ("out_offset", "<u8"), ("out_stride", "<u4"), ("target", "u1"),
                       ("drop", "u1"), ("res", "<u2")])
 assert JOB_DTYPE.itemsize == 64
+REGION_DTYPE = np.dtype([("job", JOB_DTYPE), ("x0", "<u4"), ("y0", "<u4"), ("w", "<u4"), ("h", "<u4"),
+                         ("offsets", "<u8")])
+assert REGION_DTYPE.itemsize == 88
 
 
 def _fill_tile(a, d):
@@ -185,17 +250,30 @@ class Server:
     room for `max_reqs` 512x512x3 outputs; a batch is formed from arrived
     requests in order while its jobs' workspace (library figure) fits."""
 
-    def __init__(self, slide: Slide, slots=3, ws_bytes=256 << 20, max_reqs=64, device="cuda",
+    def __init__(self, slide, slots=3, ws_bytes=256 << 20, max_reqs=64, device="cuda",
                  tune=None):
         self.slide = slide
+        self.pyr = isinstance(slide, PyramidSlide)
+        L = isx.lib()
+        if self.pyr:
+            self._plan_bytes, self._ws_bytes = L.isx_region_plan_bytes, L.isx_region_workspace_bytes
+            self._build = lambda jp, n, hp, pb: L.isx_region_plan_build(jp, n, ctypes.byref(self.tune), hp, pb)
+        else:
+            self._plan_bytes, self._ws_bytes = L.isx_decode_plan_bytes, L.isx_decode_workspace_bytes
+            self._build = lambda jp, n, hp, pb: L.isx_decode_plan_build_tuned(jp, n, ctypes.byref(self.tune),
+                                                                              hp, pb)
         self.t = slide.tile
         self.req_bytes = self.t * self.t * 3
         self.max_reqs = max_reqs
         self.max_jobs = 16384  # decode jobs (source tiles) per batch
         self.tune = tune if tune is not None else isx.tuning()
         # plan bytes upper bound for max_jobs jobs
-        probe = self._jobs([Request(0, 0, 0, 0)], dummy=self.max_jobs)
-        pb = int(isx.lib().isx_decode_plan_bytes(probe.ctypes.data, len(probe)))
+        if self.pyr:  # a region job lists at most ~ (4 + 2 * levels) x 4 blocks x channels per level
+            probe = self._jobs([Request(0, 0, 0, 0)] * max_reqs)
+            pb = int(self._plan_bytes(probe.ctypes.data, len(probe))) * 4
+        else:
+            probe = self._jobs([Request(0, 0, 0, 0)], dummy=self.max_jobs)
+            pb = int(self._plan_bytes(probe.ctypes.data, len(probe)))
         self.plan_cap = pb + (1 << 16)
         self.ws_cap = ws_bytes
         self.slots = [_Slot(ws_bytes, max_reqs * self.req_bytes, self.max_jobs, self.plan_cap, device)
@@ -203,8 +281,21 @@ class Server:
         self.ws_est = {}
 
     def _jobs(self, reqs, dummy=0):
-        """Decode jobs (a numpy array laid out as isx_decode_job) for requests."""
+        """Decode jobs (a numpy array laid out as isx_decode_job, or as
+        isx_region_job for a pyramid) for requests."""
         d = self.slide.desc
+        if self.pyr:
+            a = np.zeros(len(reqs), dtype=REGION_DTYPE)
+            _fill_tile(a["job"], d)
+            a["job"]["in_bytes"] = self.slide.size
+            a["job"]["out_stride"] = self.t * 3
+            a["offsets"] = self.slide.offsets.ctypes.data
+            if len(reqs):
+                g = np.array([self.slide.region(r.z, r.X, r.Y) for r in reqs], dtype=np.int64)
+                a["x0"], a["y0"], a["w"], a["h"] = g[:, 0], g[:, 1], g[:, 2], g[:, 3]
+                a["job"]["out_offset"] = [r.out_off for r in reqs]
+                a["job"]["target"] = [r.z for r in reqs]
+            return a
         if dummy:
             a = np.zeros(dummy, dtype=JOB_DTYPE)
             _fill_tile(a, d)
@@ -228,10 +319,28 @@ class Server:
     def req_ws(self, z):
         """Workspace of one request at zoom z (cached library figure)."""
         if z not in self.ws_est:
-            r = Request(0, z, 0, 0)
-            jobs = self._jobs([r])
-            self.ws_est[z] = int(isx.lib().isx_decode_workspace_bytes(jobs.ctypes.data, len(jobs)))
+            # the largest of a corner view (all sources present) and an
+            # interior view (the widest halo cover of a pyramid region)
+            gx, gy = self.slide.grid(z)
+            est = 0
+            for X, Y in ((0, 0), (gx // 2, gy // 2)):
+                jobs = self._jobs([Request(0, z, X, Y)])
+                est = max(est, int(self._ws_bytes(jobs.ctypes.data, len(jobs))))
+            self.ws_est[z] = est
         return self.ws_est[z]
+
+    def covered(self, r) -> bool:
+        """Does the view lie wholly inside the slide?"""
+        if self.pyr:
+            _, _, w, h = self.slide.region(r.z, r.X, r.Y)
+            return w == self.t and h == self.t
+        return self.slide.source_count(r.z, r.X, r.Y) == (1 << (2 * r.z))
+
+    def view_pixels(self, r) -> int:
+        if self.pyr:
+            _, _, w, h = self.slide.region(r.z, r.X, r.Y)
+            return w * h
+        return (self.t >> r.z) ** 2 * self.slide.source_count(r.z, r.X, r.Y)
 
     def launch(self, slot: _Slot, reqs):
         import torch
@@ -241,19 +350,19 @@ class Server:
         jobs = self._jobs(reqs)
         n = len(jobs)
         jp = jobs.ctypes.data
-        need = int(L.isx_decode_workspace_bytes(jp, n))
+        need = int(self._ws_bytes(jp, n))
         if need > self.ws_cap:
             raise RuntimeError("batch exceeds the slot workspace")
-        pb = int(L.isx_decode_plan_bytes(jp, n))
+        pb = int(self._plan_bytes(jp, n))
         if pb > self.plan_cap:
             raise RuntimeError("batch plan exceeds the slot's plan buffer")
         hp = (ctypes.c_uint8 * pb).from_address(slot.h_plan.data_ptr())
-        rc = L.isx_decode_plan_build_tuned(jp, n, ctypes.byref(self.tune), hp, pb)
+        rc = self._build(jp, n, hp, pb)
         if rc:
             raise isx.IsxError(rc, "serve plan")
         with torch.cuda.stream(slot.stream):
-            for r in reqs:  # views that run off the slide: clear the part no tile covers
-                if self.slide.source_count(r.z, r.X, r.Y) < (1 << (2 * r.z)):
+            for r in reqs:  # views that run off the slide: clear the part no source covers
+                if not self.covered(r):
                     slot.out[r.out_off:r.out_off + self.req_bytes].zero_()
             slot.d_plan[:pb].copy_(slot.h_plan[:pb], non_blocking=True)
             rc = L.isx_decode_run(hp, isx._ptr(slot.d_plan), isx._ptr(self.slide.arena), isx._ptr(slot.out),
@@ -287,7 +396,7 @@ class Server:
                         raise RuntimeError("decode error in a served batch")
                     for r in s.reqs:
                         r.done = tdone
-                        px += (self.t >> r.z) ** 2 * self.slide.source_count(r.z, r.X, r.Y)
+                        px += self.view_pixels(r)
                     if check:
                         check(s, s.reqs)
                     done += len(s.reqs)
@@ -299,7 +408,7 @@ class Server:
                 batch, ws, nj = [], 0, 0
                 while ready and len(batch) < self.max_reqs:
                     need = self.req_ws(ready[0].z)
-                    jobs = 1 << (2 * ready[0].z)
+                    jobs = 1 if self.pyr else 1 << (2 * ready[0].z)
                     if batch and (ws + need > self.ws_cap * 0.9 or nj + jobs > self.max_jobs):
                         break
                     ws += need

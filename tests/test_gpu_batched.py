@@ -160,3 +160,42 @@ def test_serving_results_identical_alone_and_in_the_mix():
     px = slide.gen.tiles([0], 0)[0].cpu().numpy()
     blob = enc[slide.offsets[0]:slide.offsets[0] + slide.sizes[0]].tobytes()
     assert np.array_equal(oracle.decode_tile(blob, 0), px)
+
+
+def test_pyramid_serving_regions_match_the_oracle():
+    """The same slide as one pyramid: served views equal the oracle's crops
+    of the level-z decode, equal the same view decoded alone, and at zoom 0
+    equal the slide's pixels."""
+    import torch
+    from paper_2005_08713_amd import serve
+    pyr = serve.PyramidSlide(5, 4, tile=256, levels=5, seed=7, batch=8)
+    srv = serve.Server(pyr, slots=3, ws_bytes=96 << 20, max_reqs=16)
+    trace = serve.viewer_trace(pyr, n_viewers=6, steps=6, zmax=4, seed=9)
+    reqs = [serve.Request(i, z, X, Y) for i, (z, X, Y) in enumerate(trace[:48])]
+    times = serve.poisson_arrivals(len(reqs), 4000.0, seed=3)
+    for r, t in zip(reqs, times):
+        r.arrival = float(t)
+    got = {}
+
+    def check(slot, rs):
+        host = slot.out.cpu().numpy()
+        for r in rs:
+            got[r.rid] = host[r.out_off:r.out_off + srv.req_bytes].copy()
+
+    stats = srv.run(reqs, check=check)
+    print("pyramid serve stats", stats, flush=True)
+    assert stats["batches"] >= 2 and len(got) == len(reqs)
+    blob = pyr.arena.cpu().numpy().tobytes()
+    full = {}
+    img = pyr.image.cpu().numpy()
+    for r in reqs[::3]:
+        x0, y0, w, h = pyr.region(r.z, r.X, r.Y)
+        if r.z not in full:
+            full[r.z] = oracle.decode_tile(blob, r.z)
+        exp = np.zeros((256, 256, 3), np.uint8)
+        exp[:h, :w] = full[r.z][y0:y0 + h, x0:x0 + w]
+        assert np.array_equal(got[r.rid].reshape(256, 256, 3), exp), r
+        if r.z == 0:
+            assert np.array_equal(exp[:h, :w], img[y0:y0 + h, x0:x0 + w])
+    for r in reqs[1::9]:
+        assert np.array_equal(srv.decode_alone(serve.Request(r.rid, r.z, r.X, r.Y)), got[r.rid]), r
