@@ -235,6 +235,17 @@ __host__ __device__ inline void block_geometry(const TileGeo &T, uint32_t local,
     }
 }
 
+// The 8 XCDs of the chip receive a launch's workgroups round-robin, and each
+// has its own L2.  Remapping the workgroup index this way gives every XCD one
+// contiguous range of the logical grid, so neighbouring tiles (which share
+// halo cache lines) and the channels of one tile run behind the same L2.
+constexpr uint32_t kXcds = 8;
+__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t n)
+{
+    const uint32_t per = n / kXcds, rem = n % kXcds, x = b % kXcds;
+    return x * per + (x < rem ? x : rem) + b / kXcds;
+}
+
 // Whole-sample symmetric extension of index i into [0, n).
 __host__ __device__ inline int reflect_idx(int i, int n)
 {

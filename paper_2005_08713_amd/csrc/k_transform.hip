@@ -104,9 +104,10 @@ __global__ void __launch_bounds__(256) k_fwd_level(PlanHdr H, const uint8_t *__r
     __shared__ int32_t rmap[WN], cmap[WN];
     const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
     const WorkItem *items = (const WorkItem *)(plan + H.work_off);
-    const WorkItem &W = find_item(items, H.lvl_first[level], H.lvl_count[level], blockIdx.x);
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem &W = find_item(items, H.lvl_first[level], H.lvl_count[level], bid);
     const TileGeo &T = tiles[W.tile];
-    uint32_t r = blockIdx.x - W.wg_start;
+    uint32_t r = bid - W.wg_start;
     int c = (int)(r % W.nch);
     uint32_t sp = r / W.nch;
     int qx0 = (int)(sp % W.ntx) * TQ, qy0 = (int)(sp / W.ntx) * TQ;
@@ -271,9 +272,10 @@ __global__ void __launch_bounds__(256) k_fwd_level0(PlanHdr H, const uint8_t *__
 {
     const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
     const WorkItem *items = (const WorkItem *)(plan + H.work_off);
-    const WorkItem &W = find_item(items, H.lvl_first[0], H.lvl_count[0], blockIdx.x);
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem &W = find_item(items, H.lvl_first[0], H.lvl_count[0], bid);
     const TileGeo &T = tiles[W.tile];
-    uint32_t r = blockIdx.x - W.wg_start;
+    uint32_t r = bid - W.wg_start;
     uint32_t nsp = W.ntx * W.nty;
     int c = (int)(r / nsp);
     uint32_t sp = r % nsp;
@@ -398,9 +400,10 @@ __global__ void __launch_bounds__(256) k_inv_level(PlanHdr H, const uint8_t *__r
     __shared__ int32_t rmap[WN], cmap[WN];
     const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
     const WorkItem *items = (const WorkItem *)(plan + H.work_off);
-    const WorkItem &W = find_item(items, H.lvl_first[level], H.lvl_count[level], blockIdx.x);
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem &W = find_item(items, H.lvl_first[level], H.lvl_count[level], bid);
     const TileGeo &T = tiles[W.tile];
-    uint32_t r = blockIdx.x - W.wg_start;
+    uint32_t r = bid - W.wg_start;
     int c = (int)(r % W.nch);
     uint32_t sp = r / W.nch;
     int qx0 = (int)(W.qx0 + (sp % W.ntx) * TQ), qy0 = (int)(W.qy0 + (sp / W.ntx) * TQ);
@@ -444,9 +447,10 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
     __shared__ int32_t rmap[WN], cmap[WN];
     const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
     const WorkItem *items = (const WorkItem *)(plan + H.work_off);
-    const WorkItem &W = find_item(items, H.fin_first, H.fin_count, blockIdx.x);
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem &W = find_item(items, H.fin_first, H.fin_count, bid);
     const TileGeo &T = tiles[W.tile];
-    uint32_t r = blockIdx.x - W.wg_start;
+    uint32_t r = bid - W.wg_start;
     int cg = (int)(r % W.nch);
     uint32_t sp = r / W.nch;
     int qx0 = (int)(W.qx0 + (sp % W.ntx) * TQ), qy0 = (int)(W.qy0 + (sp / W.ntx) * TQ);
