@@ -120,15 +120,25 @@ constexpr int kCellsPT = 3;  // 3 cells per thread: 1024 threads cover a 128x128
 // Blocks are split in two classes by size: more than 768 4x4 cells (1024
 // threads) and at most 768 cells (256 threads); the plan lists the blocks of
 // each class, large ones first.
+constexpr int kPG = 4;  // phase B: planes per group (one set of barriers per group)
+
 template <int kSymNT>
 __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint8_t *__restrict__ plan,
                                                         uint8_t *__restrict__ ws, uint32_t list0,
                                                         uint32_t nlist)
 {
-    __shared__ uint32_t hist[256];
-    __shared__ int32_t wsh[kSymNT / 64];
-    __shared__ uint32_t s_zir, s_dig[kNumWz], s_F[16], s_nruns, s_zero, s_pruns;
+    constexpr int NW = kSymNT / 64;
+    // phase-B statistics, double-buffered by group parity: a group's buffers
+    // are read out after its second barrier and cleared during the next
+    // group, so consecutive groups never touch the same words unsynchronised
+    __shared__ uint32_t hist[2][kPG][256];
+    __shared__ int32_t wmax[kPG][NW];
+    __shared__ uint32_t s_zero[2][kPG], s_zir[2][kPG], s_pruns[2][kPG], s_dig[2][kPG][kNumWz];
+    __shared__ uint32_t s_F[16];
+    __shared__ uint32_t s_gb[2][kPG];  // the group's planes, for the read-out
     const uint32_t *list = (const uint32_t *)(plan + H.list_off) + list0;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    for (uint32_t i = tid; i < 2 * kPG * 256; i += kSymNT) (&hist[0][0][0])[i] = 0;
     for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
     const uint32_t blk = list[li];
     __syncthreads();
@@ -140,7 +150,6 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
     SegStat *segstat = (SegStat *)(ws + H.ws_segstat);
     const int32_t *wsi = (const int32_t *)ws;
     const uint32_t p = B.p, wb = B.wb, hb = B.hb, n = wb * hb / 8, cpt = n / 2, wq = wb / 4;
-    const uint32_t tid = threadIdx.x;
 
     uint32_t orall = A.or_mag[0] | A.or_mag[1] | A.or_mag[2];
     uint32_t d = 1 + bitlen32(orall);
@@ -213,105 +222,165 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
         cci[k] = cell < ncell ? cell % cpt : 0u;
     }
     __threadfence_block();
-
-    for (uint32_t i = tid; i < 256; i += kSymNT) hist[i] = 0;
-    if (tid < kNumWz) s_dig[tid] = 0;
+    // kept planes (a plane where no type is present is removed, Sec. 4)
+    uint32_t keep = 0;
+    for (int b = (int)d - 1; b >= 0; b--) {
+        const uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
+        if (pm) keep |= 1u << b;
+    }
+    for (uint32_t i = tid; i < 2 * kPG * (3 + kNumWz); i += kSymNT) {
+        const uint32_t g = i / (3 + kNumWz), f = i % (3 + kNumWz);
+        uint32_t *row = f == 0 ? &s_zero[0][0] : (f == 1 ? &s_zir[0][0] : (f == 2 ? &s_pruns[0][0] : &s_dig[0][0][f - 3]));
+        row[f < 3 ? g : g * kNumWz] = 0;
+    }
     if (tid < 16) s_F[tid] = 0;
-    if (tid == 0) { s_zir = 0; s_nruns = 0; s_zero = 0; s_pruns = 0; }
     __syncthreads();
 
-    uint32_t nseg = 0;
-    for (int b = (int)d - 1; b >= 0; b--) {
-        uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
-        if (!pm) continue;
-        uint32_t M = n * __popc(pm);
-        uint8_t *segp = ws + B.sym_off + (uint64_t)b * plane_stride(p * n);
-        // symbols of own cells (written in phase A)
-        uint32_t sy[kCellsPT], pos[kCellsPT];
-        int32_t lastnz = -1;
-        uint32_t zeros = 0;
+    uint32_t nseg = 0, nruns = 0, par = 0;
+    while (keep) {
+        // the group: up to kPG planes from the top
+        uint32_t gb[kPG], gn = 0;
+        {
+            uint32_t r = keep;
 #pragma unroll
-        for (int k = 0; k < kCellsPT; k++) {
-            sy[k] = 0;
-            pos[k] = 0xffffffffu;
-            const uint32_t t = ctype[k];
-            if (t > 2 || !((pm >> t) & 1u)) continue;
-            const uint32_t rank = __popc(pm & ((1u << t) - 1u));
-            pos[k] = rank * n + 2 * cci[k];
-            sy[k] = *(const uint16_t *)(segp + pos[k]);
+            for (int g = 0; g < kPG; g++) {
+                gb[g] = r ? 31u - (uint32_t)__builtin_clz(r) : 0u;
+                if (r) { r &= ~(1u << gb[g]); gn++; }
+            }
+            keep = r;
         }
+        if (tid < kPG) s_gb[par][tid] = gb[0];
 #pragma unroll
-        for (int k = 0; k < kCellsPT; k++) {
-            if (pos[k] == 0xffffffffu) continue;
-            const uint32_t v = sy[k], ps = pos[k];
-            const uint32_t top = v & 0xffu, bot = v >> 8;
-            if (top) { atomicAdd(&hist[top], 1u); lastnz = (int32_t)ps; } else zeros++;
-            if (bot) { atomicAdd(&hist[bot], 1u); lastnz = (int32_t)ps + 1; } else zeros++;
+        for (int g = 1; g < kPG; g++)
+            if (tid == (uint32_t)g) s_gb[par][g] = gb[g];
+        // pass 1: symbols of own cells, histograms, zero counts, and the
+        // wave-level scan of the last non-zero position
+        int32_t ex[kPG];
+#pragma unroll
+        for (int g = 0; g < kPG; g++) {
+            ex[g] = -1;
+            if ((uint32_t)g >= gn) continue;
+            const uint32_t b = gb[g];
+            const uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
+            const uint8_t *segp = symb + (uint64_t)b * pstr;
+            int32_t lastnz = -1;
+            uint32_t zeros = 0;
+#pragma unroll
+            for (int k = 0; k < kCellsPT; k++) {
+                const uint32_t t = ctype[k];
+                if (t > 2 || !((pm >> t) & 1u)) continue;
+                const uint32_t ps = __popc(pm & ((1u << t) - 1u)) * n + 2 * cci[k];
+                const uint32_t v = *(const uint16_t *)(segp + ps);
+                const uint32_t top = v & 0xffu, bot = v >> 8;
+                if (top) { atomicAdd(&hist[par][g][top], 1u); lastnz = (int32_t)ps; } else zeros++;
+                if (bot) { atomicAdd(&hist[par][g][bot], 1u); lastnz = (int32_t)ps + 1; } else zeros++;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) zeros += __shfl_xor(zeros, o, 64);
+            if (lane == 0 && zeros) atomicAdd(&s_zero[par][g], zeros);
+            int32_t x = lastnz;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t y = __shfl_up(x, o, 64);
+                if ((int)lane >= o) x = max(x, y);
+            }
+            ex[g] = __shfl_up(x, 1, 64);
+            if (lane == 0) ex[g] = -1;
+            if (lane == 63) wmax[g][wave] = x;
         }
-        // zeros: one atomic per wave
-        for (int o = 32; o >= 1; o >>= 1) zeros += __shfl_xor(zeros, o, 64);
-        if ((tid & 63) == 0 && zeros) atomicAdd(&s_zero, zeros);
-        int32_t prev = block_excl_max_i32<kSymNT>(lastnz, wsh);
-        // runs terminated inside this thread (by a non-zero symbol or the
-        // segment end); per-thread sums, then one atomic per wave
-        int32_t cur = prev;
-        uint32_t rz = 0, rn = 0;
+        __syncthreads();
+        // the previous group's small statistics are read out: clear them
+        if (tid < kPG * (3 + kNumWz)) {
+            const uint32_t g = tid / (3 + kNumWz), f = tid % (3 + kNumWz);
+            if (f == 0) s_zero[par ^ 1][g] = 0;
+            else if (f == 1) s_zir[par ^ 1][g] = 0;
+            else if (f == 2) s_pruns[par ^ 1][g] = 0;
+            else s_dig[par ^ 1][g][f - 3] = 0;
+        }
+        // pass 2: runs terminated inside this thread (by a non-zero symbol
+        // or the segment end), per-thread sums, then one atomic per wave
 #pragma unroll
-        for (int k = 0; k < kCellsPT; k++) {
-            if (pos[k] == 0xffffffffu) continue;
+        for (int g = 0; g < kPG; g++) {
+            if ((uint32_t)g >= gn) continue;
+            const uint32_t b = gb[g];
+            const uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
+            const uint32_t M = n * __popc(pm);
+            const uint8_t *segp = symb + (uint64_t)b * pstr;
+            uint32_t sy[kCellsPT];  // own symbols again (cache hits)
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                uint32_t s = h ? (sy[k] >> 8) : (sy[k] & 0xffu);
-                int32_t ps = (int32_t)pos[k] + h;
-                bool endseg = (uint32_t)ps == M - 1;
-                if (s || endseg) {
-                    int32_t L = s ? (ps - cur - 1) : (ps - cur);
-                    if (L >= 2) {
-                        atomicAdd(&s_F[bitlen32((uint32_t)L)], 1u);
-                        rz += (uint32_t)L;
-                        rn++;
-                        // digits beyond the first, for the widths whose base 2^w-1 < L
-                        for (int i = 0; i < kNumWz && ((1u << (i + 2)) - 1u) < (uint32_t)L; i++)
-                            atomicAdd(&s_dig[i], bij_digits((uint32_t)L, (1u << (i + 2)) - 1u) - 1u);
+            for (int k = 0; k < kCellsPT; k++) {
+                const uint32_t t = ctype[k];
+                sy[k] = (t <= 2 && ((pm >> t) & 1u))
+                            ? (0x10000u | *(const uint16_t *)(segp + __popc(pm & ((1u << t) - 1u)) * n + 2 * cci[k]))
+                            : 0u;
+            }
+            int32_t cur = ex[g];
+            for (uint32_t w = 0; w < wave; w++) cur = max(cur, wmax[g][w]);
+            uint32_t rz = 0, rn = 0;
+#pragma unroll
+            for (int k = 0; k < kCellsPT; k++) {
+                if (!(sy[k] >> 16)) continue;
+                const uint32_t t = ctype[k];
+                const uint32_t ps0 = __popc(pm & ((1u << t) - 1u)) * n + 2 * cci[k];
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const uint32_t sv = h ? ((sy[k] >> 8) & 0xffu) : (sy[k] & 0xffu);
+                    const int32_t ps = (int32_t)ps0 + h;
+                    const bool endseg = (uint32_t)ps == M - 1;
+                    if (sv || endseg) {
+                        const int32_t L = sv ? (ps - cur - 1) : (ps - cur);
+                        if (L >= 2) {
+                            atomicAdd(&s_F[bitlen32((uint32_t)L)], 1u);
+                            rz += (uint32_t)L;
+                            rn++;
+                            // digits beyond the first, for the widths whose base 2^w-1 < L
+                            for (int i = 0; i < kNumWz && ((1u << (i + 2)) - 1u) < (uint32_t)L; i++)
+                                atomicAdd(&s_dig[par][g][i], bij_digits((uint32_t)L, (1u << (i + 2)) - 1u) - 1u);
+                        }
+                        if (sv) cur = ps;
                     }
-                    if (s) cur = ps;
+                }
+            }
+            if (__any(rn)) {
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    rz += __shfl_xor(rz, o, 64);
+                    rn += __shfl_xor(rn, o, 64);
+                }
+                if (lane == 0 && rn) {
+                    atomicAdd(&s_zir[par][g], rz);
+                    atomicAdd(&s_pruns[par][g], rn);
                 }
             }
         }
-        if (__any(rn)) {
-            for (int o = 32; o >= 1; o >>= 1) {
-                rz += __shfl_xor(rz, o, 64);
-                rn += __shfl_xor(rn, o, 64);
-            }
-            if ((tid & 63) == 0 && rn) {
-                atomicAdd(&s_zir, rz);
-                atomicAdd(&s_pruns, rn);
-            }
-        }
         __syncthreads();
-        uint32_t slot = B.slot + (uint32_t)b;
-        for (uint32_t i = tid; i < 256; i += kSymNT) {
-            uint32_t hv = hist[i];
-            if (i == 0) hv = s_zero;
-            seghist[(uint64_t)slot * 256 + i] = (uint16_t)hv;
-            hist[i] = 0;
+        // write-out of the group: per plane the 256-bin histogram (bin 0 =
+        // zero symbols), the run sums per counter width and the plane list
+        for (uint32_t i = tid; i < gn * 256; i += kSymNT) {
+            const uint32_t g = i >> 8, sidx = i & 255u;
+            const uint32_t hv = sidx ? hist[par][g][sidx] : s_zero[par][g];
+            seghist[(uint64_t)(B.slot + s_gb[par][g]) * 256 + sidx] = (uint16_t)hv;
+            hist[par][g][sidx] = 0;
         }
-        if (tid < kNumWz) { segstat[slot].dig[tid] = s_dig[tid] + s_pruns; }
-        if (tid == 0) {
-            segstat[slot].zir = s_zir;
-            s_nruns += s_pruns;
-            P.seg_plane[nseg] = (uint8_t)b;
-            P.seg_M[nseg] = M;
+        for (uint32_t i = tid; i < gn * kNumWz; i += kSymNT) {
+            const uint32_t g = i / kNumWz, k = i % kNumWz;
+            segstat[B.slot + s_gb[par][g]].dig[k] = s_dig[par][g][k] + s_pruns[par][g];
         }
-        __syncthreads();
-        if (tid < kNumWz) s_dig[tid] = 0;
-        if (tid == 0) { s_zir = 0; s_zero = 0; s_pruns = 0; }
-        nseg++;
-        __syncthreads();
+        if (tid < gn) {
+            const uint32_t b = s_gb[par][tid];
+            segstat[B.slot + b].zir = s_zir[par][tid];
+            P.seg_plane[nseg + tid] = (uint8_t)b;
+            P.seg_M[nseg + tid] = n * (((pres[0] >> b) & 1u) + ((pres[1] >> b) & 1u) + ((pres[2] >> b) & 1u));
+        }
+        if (tid == 0)
+            for (uint32_t g = 0; g < gn; g++) nruns += s_pruns[par][g];
+        nseg += gn;
+        par ^= 1u;
     }
+    __syncthreads();
     if (tid < 16) S.F[tid] = s_F[tid];
     if (tid == 0) {
-        S.nruns = s_nruns;
+        S.nruns = nruns;
         S.err = err;
         P.d = d;
         P.nseg = nseg;
@@ -897,10 +966,17 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
         flush_bits(st, bit0, nbits, outw);
         return;
     }
-    // segment y-1: tokens of the plane's symbols
+    // segment y-1: tokens of the plane's symbols; its start = header + the
+    // lengths of the segments before it (a wave sum in every wave)
     const uint32_t s = y - 1;
-    uint32_t start = P.hdr_bits;
-    for (uint32_t i = 0; i < s; i++) start += P.seg_bits[i];
+    uint32_t start;
+    {
+        const uint32_t lane = tid & 63u;
+        uint32_t v = lane < s ? P.seg_bits[lane] : 0u;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        start = P.hdr_bits + v;
+    }
     const uint32_t nbits = P.seg_bits[s];
     const uint64_t abit = bit0 + start;
     const uint32_t o = (uint32_t)(abit & 31u);
@@ -915,20 +991,22 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
     const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride(P.p * P.n);
     const uint32_t czr = P.czr, wz = P.wz, Bb = (1u << wz) - 1u;
     const uint32_t lz = s_len[czr];
-    const uint32_t chunk = (M + kPackNT - 1) / kPackNT;  // <= kPackPT for M <= 6144
+    // a multiple of 4 symbols per thread, <= kPackPT for M <= 6144: the
+    // thread's symbols are whole aligned words of the plane (its stride is
+    // padded to 16 bytes, so the last word stays inside it)
+    const uint32_t chunk = (((M + kPackNT - 1) / kPackNT) + 3u) & ~3u;
     const uint32_t lo = tid * chunk;
     uint32_t hi = lo + chunk;
     if (hi > M) hi = M;
     uint32_t lw[kPackPT / 4];  // the thread's symbols, 4 per register
     int32_t lastnz = -1;
 #pragma unroll
-    for (uint32_t k = 0; k < kPackPT / 4; k++) lw[k] = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < kPackPT; i++) {
-        const uint32_t ps = lo + i;
-        const uint32_t b = (ps < hi) ? syms[ps] : 0u;
-        lw[i / 4] |= b << (8 * (i % 4));
-        if (b) lastnz = (int32_t)ps;
+    for (uint32_t k = 0; k < kPackPT / 4; k++) {
+        const uint32_t ps = lo + 4 * k;
+        uint32_t w = (4 * k < chunk && ps < hi) ? *(const uint32_t *)(syms + ps) : 0u;
+        if (ps + 4 > hi) w &= ps < hi ? (1u << (8 * (hi - ps))) - 1u : 0u;  // hi - ps <= 3 here
+        lw[k] = w;
+        if (w) lastnz = (int32_t)(ps + (31u - (uint32_t)__builtin_clz(w)) / 8u);
     }
 #define LOC(i) ((lw[(i) / 4] >> (8 * ((i) % 4))) & 0xffu)
     int32_t prev = block_excl_max_i32<kPackNT>(lastnz, shi);

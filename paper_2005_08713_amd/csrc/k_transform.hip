@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(256) k_fwd_level0(PlanHdr H, const uint8_t *__
 // Stage the interleaved window of level `level` for channel c: position
 // (gy, gx) of LL_{level-1}, reflected, maps to LL/HL/LH/HH by parity.
 // rmap/cmap hold the reflected coordinates of the window rows/columns.
-template <int TQ>
+template <int TQ, int KB>
 __device__ inline void stage_inverse(const TileGeo &T, int level, int c, const int32_t *rmap,
                                      const int32_t *cmap, const int32_t *wsi, int32_t *win)
 {
@@ -322,15 +322,43 @@ __device__ inline void stage_inverse(const TileGeo &T, int level, int c, const i
     const int32_t *lh = wsi + G.off[0] + (uint64_t)c * T.chan_elems;
     const int32_t *hl = wsi + G.off[1] + (uint64_t)c * T.chan_elems;
     const int32_t *hh = wsi + G.off[2] + (uint64_t)c * T.chan_elems;
-    for (int i = threadIdx.x; i < WN * WN; i += blockDim.x) {
-        int lr = i / WN, lc = i % WN;
-        int gy = rmap[lr], gx = cmap[lc];
-        int py = gy & 1, px = gx & 1;
-        uint64_t ry = (uint64_t)(gy >> 1);
-        int32_t v;
-        if (!py) v = !px ? ll[ry * llp + (gx >> 1)] : hl[ry * G.pitch[1] + (gx >> 1)];
-        else v = !px ? lh[ry * G.pitch[0] + (gx >> 1)] : hh[ry * G.pitch[2] + (gx >> 1)];
-        win[lr * WP + lc] = v;
+    if (KB == 0) {  // element by element (fewest registers)
+        for (int i = threadIdx.x; i < WN * WN; i += blockDim.x) {
+            int lr = i / WN, lc = i % WN;
+            int gy = rmap[lr], gx = cmap[lc];
+            int py = gy & 1, px = gx & 1;
+            uint64_t ry = (uint64_t)(gy >> 1);
+            int32_t v;
+            if (!py) v = !px ? ll[ry * llp + (gx >> 1)] : hl[ry * G.pitch[1] + (gx >> 1)];
+            else v = !px ? lh[ry * G.pitch[0] + (gx >> 1)] : hh[ry * G.pitch[2] + (gx >> 1)];
+            win[lr * WP + lc] = v;
+        }
+        return;
+    }
+    // band by band (window row/column parity = band type, as the window
+    // starts at an even position and reflection keeps parity): a wave reads
+    // consecutive elements of one band row; KB loads in flight per thread
+    constexpr int HN = WN / 2, NB = HN * HN, NT = 4 * NB, KBn = KB > 0 ? KB : 1;
+    for (int base = 0; base < NT; base += 256 * KBn) {
+        int32_t v[KBn];
+        int dst[KBn];
+#pragma unroll
+        for (int k = 0; k < KBn; k++) {
+            const int i = base + (int)threadIdx.x + 256 * k;
+            dst[k] = -1;
+            if (i < NT) {
+                const int b = i / NB, j = i - b * NB;  // 0 LL, 1 HL, 2 LH, 3 HH
+                const int br = j / HN, bc = j - br * HN;
+                const int lr = 2 * br + (b >> 1), lc = 2 * bc + (b & 1);
+                const int32_t *src = b == 0 ? ll : (b == 1 ? hl : (b == 2 ? lh : hh));
+                const uint32_t pitch = b == 0 ? llp : G.pitch[b == 1 ? 1 : (b == 2 ? 0 : 2)];
+                v[k] = src[(uint64_t)(rmap[lr] >> 1) * pitch + (cmap[lc] >> 1)];
+                dst[k] = lr * WP + lc;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KBn; k++)
+            if (dst[k] >= 0) win[dst[k]] = v[k];
     }
 }
 
@@ -411,7 +439,7 @@ __global__ void __launch_bounds__(256) k_inv_level(PlanHdr H, const uint8_t *__r
     const LevelGeo &G = T.lv[level];
     fill_maps<TQ>(rmap, cmap, qx0, qy0, (int)G.w, (int)G.h, G);
     __syncthreads();
-    stage_inverse<TQ>(T, level, c, rmap, cmap, wsi, win);
+    stage_inverse<TQ, 6>(T, level, c, rmap, cmap, wsi, win);
     __syncthreads();
     inverse_window<TQ>(win, G.h > 1, G.w > 1);
     // LL_{level-1} is the low band of level-1: store the part inside that
@@ -478,7 +506,7 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
         }
         __syncthreads();
         if (fused) {
-            stage_inverse<TQ>(T, z + 1, c0 + k, rmap, cmap, wsi, win);
+            stage_inverse<TQ, 0>(T, z + 1, c0 + k, rmap, cmap, wsi, win);
             __syncthreads();
             inverse_window<TQ>(win, oh > 1, ow > 1);
         } else {
