@@ -315,7 +315,7 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     }
     if (mode == MODE_DECODE) {
         H.ws_lut = o; o = al(o + total_blocks * kLutStride);
-        H.ws_items = o; o = al(o + 64 + 2 * total_blocks * 32 * sizeof(uint32_t));
+        H.ws_items = o; o = al(o + kItemsHdr + 2 * total_blocks * 32 * sizeof(uint32_t));
     }
     H.ws_tileout = o; o = al(o + (uint64_t)n * sizeof(TileOut));
     for (int32_t i = 0; i < n; i++) {

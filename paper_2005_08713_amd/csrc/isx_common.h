@@ -165,6 +165,10 @@ constexpr uint32_t kMaxSeg = 3 * 128 * 128 / 8;  // symbols in the largest segme
 constexpr uint32_t kSegWords = 2048;             // segment bits staged in LDS (larger: read from HBM)
 constexpr uint32_t kBigSegBits = 16384;          // queue class of a segment
 constexpr uint32_t kSegWavesPerCu = 8;
+// Segment work queue header: the large-list length, the small-list length
+// and the take counter, each in a 128-byte line of its own (atomics of
+// thousands of waves on one shared line contend); the lists follow.
+constexpr uint32_t kQBig = 0, kQSmall = 32, kQTake = 64, kItemsHdr = 384;
 struct TileOut {
     uint64_t size;
     uint64_t offset;

@@ -64,7 +64,8 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
     BlockDesc *descs = (BlockDesc *)(ws + H.ws_blockdesc);
     const uint8_t *base = enc + T.enc_offset;
     const uint64_t avail = T.enc_bytes;
-    if (job == 0 && threadIdx.x < 16) ((uint32_t *)(ws + H.ws_items))[threadIdx.x] = 0;  // segment queue
+    if (job == 0)  // segment queue
+        for (uint32_t i = threadIdx.x; i < kItemsHdr / 4; i += blockDim.x) ((uint32_t *)(ws + H.ws_items))[i] = 0;
     if (threadIdx.x == 0) {
         int32_t st = D_OK;
         if (avail < 24) st = D_TRUNC;
@@ -362,15 +363,15 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
     const uint32_t nbig = __popcll(bm), nsmall = nkeep - nbig;
     uint32_t bb = 0, sb = 0;
     if (lane == 0) {
-        if (nbig) bb = atomicAdd(&ctr[0], nbig);
-        if (nsmall) sb = atomicAdd(&ctr[1], nsmall);
+        if (nbig) bb = atomicAdd(&ctr[kQBig], nbig);
+        if (nsmall) sb = atomicAdd(&ctr[kQSmall], nsmall);
     }
     bb = __shfl(bb, 0, 64);
     sb = __shfl(sb, 0, 64);
     if (lane < nkeep) {
         const uint64_t below = (1ull << lane) - 1ull;
         const uint32_t item = (blk << 5) | lane;
-        uint32_t *list = (uint32_t *)(ws + H.ws_items + 64);
+        uint32_t *list = (uint32_t *)(ws + H.ws_items + kItemsHdr);
         if (big) list[bb + __popcll(bm & below)] = item;
         else list[H.total_blocks * 32ull + sb + (lane - __popcll(bm & below))] = item;
     }
@@ -655,12 +656,12 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
     __shared__ SegShared S;
     const uint32_t lane = threadIdx.x;
     uint32_t *ctr = (uint32_t *)(ws + H.ws_items);
-    const uint32_t nbig = __builtin_amdgcn_readfirstlane(ctr[0]);
-    const uint32_t ntot = nbig + __builtin_amdgcn_readfirstlane(ctr[1]);
-    const uint32_t *list = (const uint32_t *)(ws + H.ws_items + 64);
+    const uint32_t nbig = __builtin_amdgcn_readfirstlane(ctr[kQBig]);
+    const uint32_t ntot = nbig + __builtin_amdgcn_readfirstlane(ctr[kQSmall]);
+    const uint32_t *list = (const uint32_t *)(ws + H.ws_items + kItemsHdr);
     for (;;) {
         uint32_t idx = 0;
-        if (lane == 0) idx = atomicAdd(&ctr[2], 1u);
+        if (lane == 0) idx = atomicAdd(&ctr[kQTake], 1u);
         idx = __builtin_amdgcn_readfirstlane(idx);
         if (idx >= ntot) break;
         const uint32_t item =
