@@ -770,6 +770,10 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
 }
 
 // ---------------------------------------------------------------- offsets
+// Four consecutive blocks per thread and iteration: one workgroup scan per
+// 1024 blocks.
+constexpr uint32_t kPrepPT = 4;
+
 __global__ void __launch_bounds__(256) k_enc_block_offsets(PlanHdr H, const uint8_t *__restrict__ plan,
                                                            uint8_t *__restrict__ ws)
 {
@@ -779,16 +783,25 @@ __global__ void __launch_bounds__(256) k_enc_block_offsets(PlanHdr H, const uint
     TileOut *to = (TileOut *)(ws + H.ws_tileout);
     uint64_t carry = 24 + 4ull * T.nblocks_stream;
     uint32_t err = 0;
-    for (uint32_t base = 0; base < T.nblocks; base += 256) {
-        uint32_t local = base + threadIdx.x;
-        uint64_t sz = 0;
-        if (local < T.nblocks) {
-            sz = plans[T.block_base + local].bytes;
-            err |= plans[T.block_base + local].err;
+    for (uint32_t base = 0; base < T.nblocks; base += 256 * kPrepPT) {
+        const uint32_t l0 = base + threadIdx.x * kPrepPT;
+        uint64_t sz[kPrepPT], own = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kPrepPT; k++) {
+            sz[k] = 0;
+            if (l0 + k < T.nblocks) {
+                sz[k] = plans[T.block_base + l0 + k].bytes;
+                err |= plans[T.block_base + l0 + k].err;
+            }
+            own += sz[k];
         }
         uint64_t tot;
-        uint64_t ex = block_excl_sum_u64<256>(sz, sh, &tot);
-        if (local < T.nblocks) plans[T.block_base + local].byte_off = carry + ex;
+        uint64_t ex = block_excl_sum_u64<256>(own, sh, &tot);
+#pragma unroll
+        for (uint32_t k = 0; k < kPrepPT; k++) {
+            if (l0 + k < T.nblocks) plans[T.block_base + l0 + k].byte_off = carry + ex;
+            ex += sz[k];
+        }
         carry += tot;
     }
     err = __syncthreads_or(err);
@@ -827,49 +840,66 @@ __global__ void __launch_bounds__(1024) k_enc_tile_offsets(PlanHdr H, uint8_t *_
     }
 }
 
-// Tile header (little endian) + block size table, and zero the words that the
-// packers OR into: the first and last word of every block header and every
-// segment (neighbouring regions share those words; all other words are
-// written whole by exactly one packer).
+// Workgroups [0, n_tiles): tile header (little endian) + block size table.
+// The rest, one wave per block: zero the words that the packers OR into --
+// the first and last word of every block header and every segment
+// (neighbouring regions share those words; all other words are written whole
+// by exactly one packer).
 __global__ void __launch_bounds__(256) k_enc_tile_finish(PlanHdr H, const uint8_t *__restrict__ plan,
                                                          const uint8_t *__restrict__ ws,
                                                          uint8_t *__restrict__ out)
 {
-    const TileGeo &T = ((const TileGeo *)(plan + H.tiles_off))[blockIdx.x];
-    const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[blockIdx.x];
-    if (O.status != ISX_STATUS_OK) return;
     const BlkPlan *plans = (const BlkPlan *)(ws + H.ws_blkplan);
-    uint32_t *w = (uint32_t *)(out + O.offset);
-    uint32_t hdrw = 6 + T.nblocks_stream;
-    for (uint32_t i = threadIdx.x; i < hdrw; i += blockDim.x) {
-        uint32_t x = 0;
-        if (i == 0) x = 0x31585349u;  // "ISX1"
-        else if (i == 1) x = 1u | ((uint32_t)T.ct << 8) | ((uint32_t)T.channels << 16) | ((uint32_t)T.bits << 24);
-        else if (i == 2) x = (uint32_t)T.bps | ((uint32_t)T.levels << 8) | ((uint32_t)T.qstep << 16);
-        else if (i == 3) x = T.width;
-        else if (i == 4) x = T.height;
-        else if (i == 5) x = T.nblocks_stream;
-        else x = plans[T.block_base + (i - 6)].bytes;
-        w[i] = x;
-    }
-    for (uint32_t b = threadIdx.x; b < T.nblocks; b += blockDim.x) {
-        const BlkPlan &P = plans[T.block_base + b];
-        uint64_t a = P.byte_off * 8;
-        uint64_t e = a + P.hdr_bits;
-        w[a >> 5] = 0;
-        w[(e - 1) >> 5] = 0;
-        for (uint32_t s = 0; s < P.nseg; s++) {
-            uint32_t nb = P.seg_bits[s];
-            if (nb) {
-                w[e >> 5] = 0;
-                w[(e + nb - 1) >> 5] = 0;
-            }
-            e += nb;
+    const TileOut *tos = (const TileOut *)(ws + H.ws_tileout);
+    if (blockIdx.x < H.n_tiles) {
+        const TileGeo &T = ((const TileGeo *)(plan + H.tiles_off))[blockIdx.x];
+        const TileOut &O = tos[blockIdx.x];
+        if (O.status != ISX_STATUS_OK) return;
+        uint32_t *w = (uint32_t *)(out + O.offset);
+        uint32_t hdrw = 6 + T.nblocks_stream;
+        for (uint32_t i = threadIdx.x; i < hdrw; i += blockDim.x) {
+            uint32_t x = 0;
+            if (i == 0) x = 0x31585349u;  // "ISX1"
+            else if (i == 1) x = 1u | ((uint32_t)T.ct << 8) | ((uint32_t)T.channels << 16) | ((uint32_t)T.bits << 24);
+            else if (i == 2) x = (uint32_t)T.bps | ((uint32_t)T.levels << 8) | ((uint32_t)T.qstep << 16);
+            else if (i == 3) x = T.width;
+            else if (i == 4) x = T.height;
+            else if (i == 5) x = T.nblocks_stream;
+            else x = plans[T.block_base + (i - 6)].bytes;
+            w[i] = x;
         }
-        // the byte padding after the last region
-        uint64_t end = (P.byte_off + P.bytes) * 8;
-        if (end > e) w[(end - 1) >> 5] = 0;
+        return;
     }
+    const uint32_t blk = (blockIdx.x - H.n_tiles) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (blk >= H.total_blocks) return;
+    const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+    const TileOut &O = tos[B.tile];
+    if (O.status != ISX_STATUS_OK) return;
+    const BlkPlan &P = plans[blk];
+    uint32_t *w = (uint32_t *)(out + O.offset);
+    const uint64_t a = P.byte_off * 8, e0 = a + P.hdr_bits;
+    // segment s starts after the header and segments 0 .. s-1 (wave scan)
+    const uint32_t nseg = P.nseg;
+    const uint32_t nb = lane < nseg ? P.seg_bits[lane] : 0u;
+    uint32_t x = nb;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if ((int)lane >= o) x += y;
+    }
+    const uint64_t st = e0 + (x - nb);
+    if (nb) {
+        w[st >> 5] = 0;
+        w[(st + nb - 1) >> 5] = 0;
+    }
+    if (lane == 0) {
+        w[a >> 5] = 0;
+        w[(e0 - 1) >> 5] = 0;
+    }
+    // the byte padding after the last region
+    const uint64_t eall = e0 + (uint64_t)__shfl(x, 63, 64);
+    const uint64_t end = (P.byte_off + P.bytes) * 8;
+    if (lane == 0 && end > eall) w[(end - 1) >> 5] = 0;
 }
 
 // ---------------------------------------------------------------- pack
@@ -1149,7 +1179,8 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             hipLaunchKernelGGL(k_enc_tile_offsets, dim3(1), dim3(1024), 0, stream, H, d_ws, out_capacity,
                                d_tile_offsets, d_tile_sizes, d_status);
         } else if (st == ENC_FIN) {
-            hipLaunchKernelGGL(k_enc_tile_finish, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws, d_out);
+            hipLaunchKernelGGL(k_enc_tile_finish, dim3(H.n_tiles + (H.total_blocks + 3) / 4), dim3(256), 0, stream, H,
+                               d_plan, d_ws, d_out);
         } else if (st == ENC_PACK) {
             if (H.total_blocks)
             {
