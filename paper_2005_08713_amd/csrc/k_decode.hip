@@ -157,6 +157,18 @@ struct UBits {
         pre = load(2);
         avail = 64; nx = 3; pos = 0;
     }
+    // restart at bit `b` of the words
+    __device__ inline void init_at(const uint32_t *words, uint32_t n, uint32_t b)
+    {
+        w = words; nw = n;
+        const uint32_t i = b >> 5, o = b & 31u;
+        const uint64_t x = ((uint64_t)rfl(load(i)) << 32) | rfl(load(i + 1));
+        buf = x << o;
+        avail = 64 - o;
+        pre = load(i + 2);
+        nx = i + 3;
+        pos = b;
+    }
     __device__ inline uint32_t peek() const { return (uint32_t)(buf >> 32); }
     __device__ inline void skip(uint32_t k)  // k <= 32
     {
@@ -177,6 +189,27 @@ struct UBits {
     }
 };
 
+// 64 header bits from bit b on (words w[b / 32 ..] big-endian, MSB first).
+__device__ inline uint64_t hbits64(const uint32_t *w, uint32_t b)
+{
+    const uint32_t i = b >> 5, o = b & 31u;
+    const uint64_t x = ((uint64_t)w[i] << 32) | w[i + 1];
+    return o ? (x << o) | ((uint64_t)w[i + 2] >> (32 - o)) : x;
+}
+
+// Token walk over one 64-bit chunk of the serialised tree (0 = internal
+// node, one bit; 1 + 8 bits = leaf): from the token start `pos` < 64, the
+// first token start at or after bit 64, minus 64 (0..8).
+__device__ inline uint32_t tree_chunk_exit(uint64_t W, uint32_t pos)
+{
+    while (pos < 64) {
+        const uint64_t rest = W << pos;
+        if (!rest) return 0;  // internal nodes up to the chunk end
+        pos += (uint32_t)__builtin_clzll(rest) + 9;
+    }
+    return pos - 64;
+}
+
 // Per block, one wave: header (layout of Fig. 3 as read: d, masks, C_zr, wz,
 // pre-order code tree with 0 = internal node and 1 + 8 bits = leaf, seek
 // table), then the prefix table and sorted left-aligned codes of the tree
@@ -186,7 +219,9 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
                                                    uint8_t *__restrict__ ws,
                                                    int32_t *__restrict__ status)
 {
-    __shared__ uint32_t hw[132];
+    __shared__ uint32_t hw[136];
+    __shared__ uint16_t s_lzb[256], s_lend[256];  // per tokenised leaf: 0-tokens before it, end bit
+    __shared__ uint8_t s_lsym[256];
     __shared__ uint32_t s_acode[256];
     __shared__ uint8_t s_len[256], s_sym[256];
     __shared__ uint32_t s_bits[32], s_M[32];
@@ -210,12 +245,12 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         for (int k = 0; k < 4; k++) x = (x << 8) | rd_byte(src, blen, 4 * i + k);
         hw[i] = x;
     }
-    if (lane < 4) hw[128 + lane] = 0;
+    if (lane < 8) hw[128 + lane] = 0;
     __syncthreads();
     const uint32_t p = B.p, n = (uint32_t)B.wb * B.hb / 8;
     const uint32_t lim = (blen < 512 ? blen : 512) * 8;
     UBits r;
-    r.init(hw, 130);
+    r.init(hw, 136);
     int32_t err = 0;
     const uint32_t d = r.get(5);
     uint32_t masks[3] = {0, 0, 0};
@@ -242,40 +277,140 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         wz = r.get(4);
         const uint32_t beta = bitlen32(p * n - 1), wzhi = beta > 2 ? beta : 2;
         if (wz < 2 || wz > wzhi) err = D_CORRUPT;
-        // walk with the left-aligned code A and depth of the current node: a
-        // run of z 0-bits is a chain of internal nodes, then a leaf; after a
-        // leaf the next node is at A + 2^(32-depth), depth 32 - ctz.  Every
-        // violation (internal node at depth 32, more than 511 nodes, bits
-        // past the header, a 257th leaf, a repeated symbol) is the same
+        // The tree, in two steps.  (1) Tokens in parallel: lane c takes bits
+        // [64c, 64c + 64) of the tree; for each of the 9 places its first
+        // token can start (a leaf from the previous chunk reaches up to 8
+        // bits in) it finds where its last token ends; composing these maps
+        // over the lanes gives every lane its true first token, and each
+        // lane lists its leaves with the number of 0-tokens (internal
+        // nodes) before them.  (2) The pre-order walk itself, on the scalar
+        // unit, leaf by leaf: a run of z internal nodes deepens the current
+        // node by z; after a leaf with left-aligned code A and depth d the
+        // next node is at A + 2^(32-d), depth 32 - ctz.  Every violation
+        // (a node deeper than 32, more than 511 nodes, bits past the header,
+        // a 257th leaf, a repeated symbol, no closing leaf) is the same
         // error, so the checks are grouped.
-        uint64_t A = 0;
-        uint32_t depth = 0, nodes = 0;
+        const uint32_t t0 = r.pos;
         if (lane < 8) s_seen[lane] = 0;
-        while (!err) {
-            const uint32_t pk = r.peek();
-            if (pk == 0) {  // 32 internal nodes
-                depth += 32; nodes += 32;
-                r.skip(32);
-                if (depth > 32 || nodes > 511 || r.pos > lim) err = D_CORRUPT;
-                continue;
+        const uint64_t W = hbits64(hw, t0 + 64 * lane);
+        uint64_t f = 0;  // 9 exits, 4 bits each
+#pragma unroll 1
+        for (uint32_t e = 0; e < 9; e++) f |= (uint64_t)tree_chunk_exit(W, e) << (4 * e);
+        // inclusive scan of the maps (F_c = f_c o ... o f_0), then the entry
+        // of chunk c = F_{c-1}(0)
+        uint64_t F = f;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t G = __shfl_up(F, o, 64);
+            if ((int)lane >= o) {
+                uint64_t h = 0;
+#pragma unroll
+                for (uint32_t e = 0; e < 9; e++) h |= ((F >> (4 * ((G >> (4 * e)) & 15u))) & 15u) << (4 * e);
+                F = h;
             }
-            const uint32_t z = (uint32_t)__builtin_clz(pk);
-            depth += z;
-            nodes += z + 1;
-            r.skip(z);
-            const uint32_t sym = r.peek() >> 23 & 0xffu;
-            r.skip(9);
-            if (depth > 32 || nodes > 511 || r.pos > lim) { err = D_CORRUPT; break; }
-            s_acode[m] = (uint32_t)A;
-            s_len[m] = (uint8_t)depth;
-            s_sym[m] = (uint8_t)sym;
-            m++;
-            if (depth == 0) break;  // a lone leaf is the whole tree
-            A += 1ull << (32 - depth);
-            if (A >= (1ull << 32)) break;  // the rightmost leaf closes the tree
-            if (m == 256) { err = D_CORRUPT; break; }  // more leaves: a symbol repeats
-            depth = 32 - (uint32_t)__builtin_ctzll(A);
         }
+        const uint64_t Fp = __shfl_up(F, 1, 64);
+        uint32_t pos = lane == 0 ? 0u : (uint32_t)(Fp & 15u);
+        // this lane's leaves (at most 8 in 64 bits)
+        uint32_t lq[8], lz[8], nl = 0, nz = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) { lq[k] = 0; lz[k] = 0; }
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if (pos < 64) {
+                const uint64_t rest = W << pos;
+                const uint32_t z = rest ? (uint32_t)__builtin_clzll(rest) : 64u - pos;
+                if (pos + z < 64) {
+                    nz += z;
+                    lq[k] = pos + z;
+                    lz[k] = nz;
+                    nl++;
+                    pos += z + 9;
+                } else {
+                    nz += 64 - pos;
+                    pos = 64;
+                }
+            }
+        }
+        if (pos < 64) nz += 64 - pos;  // unreachable: 8 leaves fill 72 bits
+        uint32_t Lx = nl, Zx = nz;  // inclusive scans over the lanes
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t a = __shfl_up(Lx, o, 64), b = __shfl_up(Zx, o, 64);
+            if ((int)lane >= o) { Lx += a; Zx += b; }
+        }
+        const uint32_t NL = __builtin_amdgcn_readlane(Lx, 63);
+        const uint32_t Lpre = Lx - nl, Zpre = Zx - nz;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint32_t j = Lpre + (uint32_t)k;
+            if ((uint32_t)k < nl && j < 256) {
+                const uint32_t a = t0 + 64 * lane + lq[k];
+                s_lzb[j] = (uint16_t)(Zpre + lz[k]);
+                s_lend[j] = (uint16_t)(a + 9);
+                s_lsym[j] = (uint8_t)(hbits64(hw, a + 1) >> 56);
+            }
+        }
+        __syncthreads();
+        // leaf j's record in lane j % 64 of R[j / 64]: the 0-tokens since the
+        // previous leaf (bits 0-5, at most 63: more is a depth error anyway),
+        // its symbol (6-13), a node-count or header-end violation (14), the
+        // bit after it (15-27), and bit 31 for "no such leaf"
+        uint32_t R0, R1, R2, R3;
+        {
+            const uint32_t nlc = NL < 256 ? NL : 256;
+            auto rec = [&](uint32_t j) -> uint32_t {
+                if (j >= nlc) return 1u << 31;
+                const uint32_t zb = s_lzb[j], end = s_lend[j];
+                const uint32_t z = zb - (j ? (uint32_t)s_lzb[j - 1] : 0u);
+                const uint32_t bad = (zb + j + 1 > 511 || end > lim) ? 1u : 0u;
+                return (z < 63 ? z : 63u) | ((uint32_t)s_lsym[j] << 6) | (bad << 14) | (end << 15);
+            };
+            R0 = rec(lane); R1 = rec(64 + lane); R2 = rec(128 + lane); R3 = rec(192 + lane);
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the records are in registers
+        // the walk: leaf j's code and (length | symbol << 8) go to lane j % 64
+        // of Aq, Lq (q = j / 64)
+        uint32_t A0 = 0, A1 = 0, A2 = 0, A3 = 0, L0 = 0, L1 = 0, L2 = 0, L3 = 0;
+        uint32_t A = 0, base = 0;
+        bool done = false;
+        auto walk = [&](uint32_t Rq, uint32_t &Aq, uint32_t &Lq) {
+            for (uint32_t ln = 0; ln < 64; ln++) {
+                const uint32_t v = __builtin_amdgcn_readlane(Rq, ln);
+                const uint32_t d = base + (v & 63u);
+                if ((v >> 31) || ((v >> 14) & 1u) || d > 32) { err = D_CORRUPT; return; }
+                const bool mine = lane == ln;
+                Aq = mine ? A : Aq;
+                Lq = mine ? (d | (((v >> 6) & 255u) << 8)) : Lq;
+                m++;
+                if (d == 0) { done = true; return; }  // a lone leaf is the whole tree
+                const uint32_t An = A + (1u << (32 - d));
+                if (An < A) { done = true; return; }  // carry out: the rightmost leaf closes the tree
+                A = An;
+                base = 32 - (uint32_t)__builtin_ctz(A);
+            }
+        };
+        walk(R0, A0, L0);
+        if (!done && !err) walk(R1, A1, L1);
+        if (!done && !err) walk(R2, A2, L2);
+        if (!done && !err) walk(R3, A3, L3);
+        if (!done && !err) err = D_CORRUPT;  // 256 leaves and open: a symbol repeats
+        uint32_t tend = t0;
+        if (!err) {
+            const uint32_t q = (m - 1) >> 6, ln = (m - 1) & 63u;
+            const uint32_t Rl = q == 0 ? R0 : (q == 1 ? R1 : (q == 2 ? R2 : R3));
+            tend = ((uint32_t)__builtin_amdgcn_readlane(Rl, ln) >> 15) & 0x1fffu;
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++) {
+                const uint32_t j = 64 * k + lane;
+                const uint32_t Av = k == 0 ? A0 : (k == 1 ? A1 : (k == 2 ? A2 : A3));
+                const uint32_t Lv = k == 0 ? L0 : (k == 1 ? L1 : (k == 2 ? L2 : L3));
+                if (j < m) {
+                    s_acode[j] = Av;
+                    s_len[j] = (uint8_t)(Lv & 0xffu);
+                    s_sym[j] = (uint8_t)(Lv >> 8);
+                }
+            }
+        }
+        if (!err) r.init_at(hw, 136, tend);
         __syncthreads();
         if (!err) {  // repeated symbols
             bool dup = false;

@@ -168,6 +168,50 @@ def test_corrupt_segments_detected_like_oracle():
     assert n_err > len(blobs) // 4
 
 
+def test_corrupt_code_trees_detected_like_oracle():
+    """Bit flips inside the serialised code trees of block headers (one or
+    two bits, or a byte's worth): the GPU decoder rejects a stream exactly
+    when the oracle does, and otherwise decodes the same pixels.  Flips turn
+    leaves into internal nodes and back, so trees end early, run past the
+    header, grow past 32 levels or repeat symbols."""
+    from tests import format_reader as fr
+    rng = np.random.default_rng(78)
+    cases = [(96, 80, 3, 3, 1, 911), (64, 64, 1, 2, 1, 912), (140, 130, 3, 4, 4, 913), (40, 36, 1, 1, 1, 914)]
+    blobs = []
+    for w, h, c, lv, q, seed in cases:
+        img = synth.he_like(w, h, seed, sigma=(60.0, 300.0)) if c == 3 else \
+            synth.random_image(w, h, 1, 8, seed=seed, kind="uniform" if seed % 2 else "ramp")
+        blob = oracle.encode_tile(img, lv, qstep=q)
+        hdr, blocks = fr.parse_tile(blob)
+        off = 24 + 4 * hdr["nblocks"]
+        trees = []
+        for g, data in blocks:
+            r = fr.block_payload_bits(data, g[4], g[5], g[6])
+            if r is not None:
+                d = data[0] >> 3
+                t0 = 5 + g[4] * d + 12
+                trees.append((off * 8 + t0, off * 8 + r[0]))
+            off += len(data)
+        for k in range(30):
+            lo, hi = trees[int(rng.integers(len(trees)))]
+            b = bytearray(blob)
+            nflip = [1, 2, 8][k % 3]
+            for bit in rng.integers(lo, hi, size=nflip):
+                b[int(bit) >> 3] ^= 0x80 >> (int(bit) & 7)
+            blobs.append(bytes(b))
+    print("corrupt trees", len(blobs), flush=True)
+    got, st = isx.decode_streams(blobs, return_status=True)
+    n_err = 0
+    for i, blob in enumerate(blobs):
+        ost = oracle.decode_status(blob)
+        assert (st[i] != 0) == (ost != 0), (i, st[i], ost)
+        if ost == 0:
+            assert np.array_equal(got[i], oracle.decode_tile(blob, 0)), i
+        else:
+            n_err += 1
+    assert n_err > len(blobs) // 2
+
+
 def test_progressive_decode_matches_oracle():
     """Quality-progressive decode (r magnitude planes left out of every block,
     midpoint reconstruction) at several resolution levels, in one mixed
