@@ -650,19 +650,21 @@ __device__ inline void xf_push(RunXf &f, bool dig, uint32_t c, uint32_t wz)
     f.lit = dig ? f.lit : 1u;
 }
 
-constexpr uint32_t kSyncWin = 128;  // phase-1 bits before the resynchronisation point
+// Phase-1 bits before the first and the second resynchronisation point.
+constexpr uint32_t kSyncWin = 128, kSyncWin2 = 384;
 
 // Decode of one segment by one wave: the segment's N bits are split into 64
 // chunks.  Phase 1: every lane decodes its chunk from the chunk start
-// (speculatively, for lanes > 0), keeping the run map of the tokens before
-// and from the first token start sw at or after kSyncWin bits, and its exit
+// (speculatively, for lanes > 0), keeping the run maps of the tokens before
+// the first token start sw1 at or after kSyncWin bits, from sw1 to the first
+// token start sw2 at or after kSyncWin2 bits, and from sw2 on, and its exit
 // (first token start at or after the chunk end).  Phase 2: a lane whose
 // start differs from its left neighbour's exit decodes again from that exit;
-// on reaching sw the rest of phase 1 stands (Huffman codes resynchronise),
-// else it decodes the whole chunk; repeated until no lane changes.  A wave
-// scan of the run maps gives each lane its output position and pending run;
-// phase 3 decodes again and writes the non-zero symbols (the plane was
-// zeroed, so runs write nothing).
+// on reaching sw1, or else sw2, the rest of phase 1 stands (Huffman codes
+// resynchronise), else it decodes the whole chunk; repeated until no lane
+// changes.  A wave scan of the run maps gives each lane its output position
+// and pending run; phase 3 decodes again and writes the non-zero symbols
+// (the plane was zeroed, so runs write nothing).
 template <class Src>
 __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uint32_t M, uint8_t *out)
 {
@@ -675,7 +677,7 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
     const bool active = cs < N;
     const uint32_t ce = active ? (cs + chunk < N ? cs + chunk : N) : cs;
     // phase 1
-    RunXf fpre = xf_id(), G = xf_id();
+    RunXf fpre = xf_id(), G1 = xf_id(), G2 = xf_id();
     uint32_t r = cs;
     {
         const uint32_t l1 = (cs + kSyncWin < ce) ? cs + kSyncWin : ce;
@@ -686,15 +688,26 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
             xf_push(fpre, v == czr && c, c, wz);
         }
     }
-    const uint32_t sw = r;
+    const uint32_t sw1 = r;
+    {
+        const uint32_t l2 = (cs + kSyncWin2 < ce) ? cs + kSyncWin2 : ce;
+        while (r < l2) {
+            uint32_t c, adv;
+            const uint32_t v = dec_token(S, T, r, c, adv);
+            r += adv;
+            xf_push(G1, v == czr && c, c, wz);
+        }
+    }
+    const uint32_t sw2 = r;
     while (r < ce) {
         uint32_t c, adv;
         const uint32_t v = dec_token(S, T, r, c, adv);
         r += adv;
-        xf_push(G, v == czr && c, c, wz);
+        xf_push(G2, v == czr && c, c, wz);
     }
     const uint32_t exit1 = r;
-    RunXf f = xf_combine(fpre, G);
+    const RunXf G12 = xf_combine(G1, G2);
+    RunXf f = xf_combine(fpre, G12);
     uint32_t start = cs, exitc = exit1;
     // phase 2
     for (int it = 0; it < 64; it++) {
@@ -706,24 +719,35 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
             start = want;
             RunXf Pm = xf_id();
             uint32_t q = want;
-            while (q < sw && q < ce) {
+            while (q < sw1 && q < ce) {
                 uint32_t c, adv;
                 const uint32_t v = dec_token(S, T, q, c, adv);
                 q += adv;
                 xf_push(Pm, v == czr && c, c, wz);
             }
-            if (q == sw) {
-                f = xf_combine(Pm, G);
+            if (q == sw1) {
+                f = xf_combine(Pm, G12);
                 exitc = exit1;
             } else {
-                while (q < ce) {
+                while (q < sw2 && q < ce) {
                     uint32_t c, adv;
                     const uint32_t v = dec_token(S, T, q, c, adv);
                     q += adv;
                     xf_push(Pm, v == czr && c, c, wz);
                 }
-                f = Pm;
-                exitc = q;
+                if (q == sw2) {
+                    f = xf_combine(Pm, G2);
+                    exitc = exit1;
+                } else {
+                    while (q < ce) {
+                        uint32_t c, adv;
+                        const uint32_t v = dec_token(S, T, q, c, adv);
+                        q += adv;
+                        xf_push(Pm, v == czr && c, c, wz);
+                    }
+                    f = Pm;
+                    exitc = q;
+                }
             }
         }
     }
