@@ -80,6 +80,13 @@ int tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb, const
     T.width = d.width; T.height = d.height;
     T.channels = d.channels; T.bps = d.bytes_per_sample; T.bits = d.bits; T.levels = d.levels;
     T.ct = d.colour_transform; T.target_level = (uint8_t)target_level; T.qstep = d.qstep;
+    {   // division by the invariant step (Granlund and Montgomery 1994): with
+        // l = ceil(log2 step), qmul = floor(2^32 (2^l - step) / step) + 1
+        uint32_t l = 0;
+        while ((1ull << l) < d.qstep) l++;
+        T.qmul = (uint32_t)(((1ull << 32) * ((1ull << l) - d.qstep)) / d.qstep + 1);
+        T.qsh = l ? l - 1 : 0;
+    }
     T.dmax = (uint8_t)dmax_bound(d.bits, d.levels);
     T.first_level = (uint8_t)(target_level + 1);
     uint32_t w = d.width, h = d.height;

@@ -41,6 +41,7 @@ struct TileGeo {
     uint8_t channels, bps, bits, levels;
     uint8_t ct, target_level, dmax, first_level;  // first_level: lowest level reconstructed
     uint32_t qstep;
+    uint32_t qmul, qsh;    // n / qstep = (t + ((n - t) >> 1)) >> qsh, t = mulhi(qmul, n), for qstep > 1
     uint64_t enc_offset;   // decode: encoded tile offset in d_encoded
     uint64_t enc_bytes;    // decode: bytes available
     uint64_t chan_elems;   // int32 elements between channels of the coefficient arena

@@ -6,9 +6,11 @@
 //   d[n] = x[2n+1] - floor((x[2n] + x[2n+2]) / 2)
 //   s[n] = x[2n]   + floor((d[n-1] + d[n] + 2) / 4)
 // with whole-sample symmetric extension at the borders.  A workgroup owns a
-// 32x32-quad output tile (64x64 input samples); it stages the input plus a
-// 2/1-sample halo (reflected at the image border) in LDS, lifts the rows,
-// then the columns, and writes the four subbands.  Level 1 reads the
+// TQ x TQ-quad output tile (2TQ x 2TQ input samples); it stages the input
+// plus a 2-sample halo (reflected at the image border) in LDS, lifts the
+// rows, then the columns, and writes the four subbands.  Two implementations:
+// element-wise LDS passes (TQ = 16) and, for TQ = 32, the strip kernels at
+// the end of this file, which lift whole lines in registers.  Level 1 reads the
 // interleaved uint8/uint16 pixels and applies the reversible colour
 // transform on load (Sec. 3's optional colour stage).  The high-pass bands
 // are quantised on store (Sec. 3: JPEG2000-style dead-zone quantiser) and the
@@ -604,6 +606,597 @@ __global__ void __launch_bounds__(256) k_inv_final(PlanHdr H, const uint8_t *__r
     (void)status;
 }
 
+// ------------------------------------------------------------------ strips
+// The 32x32-quad tile kernels below lift whole lines in registers.  The
+// window is split into four strips of 16 outputs, one per wave.  In a row
+// pass each lane owns one window row of its wave's strip; in a column pass
+// each lane owns one window column.  A line of a strip takes 19 window
+// samples and gives the 16 outputs at window positions 16s+2 .. 16s+17
+// (s = strip), which is the 2-sample halo of the 5/3 filter on each side.
+namespace strips {
+constexpr int TQ = 32, WN = 2 * TQ + 4, WP = WN + 1;  // odd pitch: a column is bank-conflict free
+
+// Forward lifting of the samples at positions p .. p+18 (p even): outputs at
+// p+2 .. p+17, low-pass s at even positions, high-pass d at odd ones.
+__device__ inline void lift_fwd16(const int32_t (&x)[19], int32_t (&o)[16])
+{
+    int32_t d[9];  // d at p+1, p+3, .., p+17
+#pragma unroll
+    for (int k = 0; k < 9; k++) d[k] = x[2 * k + 1] - floor_half(x[2 * k] + x[2 * k + 2]);
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        o[2 * k] = x[2 * k + 2] + floor_quarter_r(d[k] + d[k + 1]);
+        o[2 * k + 1] = d[k + 1];
+    }
+}
+
+// Inverse lifting of the interleaved coefficients at positions p+1 .. p+19
+// (x[j] at p+1+j: odd j hold s, even j hold d): samples at p+2 .. p+17.
+__device__ inline void lift_inv16(const int32_t (&x)[19], int32_t (&o)[16])
+{
+    int32_t e[9];  // samples at p+2, p+4, .., p+18
+#pragma unroll
+    for (int k = 0; k < 9; k++) e[k] = x[2 * k + 1] - floor_quarter_r(x[2 * k] + x[2 * k + 2]);
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        o[2 * k] = e[k];
+        o[2 * k + 1] = x[2 * k + 2] + floor_half(e[k] + e[k + 1]);
+    }
+}
+
+// Forward row lifting at one position from the raw samples p[-2..2] of its
+// row (for window rows the row pass leaves out).
+__device__ inline int32_t row_lift_fwd_at(const int32_t *p, bool odd)
+{
+    const int32_t xm2 = p[-2], xm1 = p[-1], x0 = p[0], xp1 = p[1], xp2 = p[2];
+    const int32_t hv = x0 - floor_half(xm1 + xp1);
+    const int32_t dm = xm1 - floor_half(xm2 + x0), dp = xp1 - floor_half(x0 + xp2);
+    const int32_t lv = x0 + floor_quarter_r(dm + dp);
+    return odd ? hv : lv;
+}
+
+// Inverse column lifting at one position from the coefficients p[-2WP..2WP]
+// of its column (for window columns the column pass leaves out).
+__device__ inline int32_t col_lift_inv_at(const int32_t *p, bool odd)
+{
+    const int32_t xm2 = p[-2 * WP], xm1 = p[-WP], x0 = p[0], xp1 = p[WP], xp2 = p[2 * WP];
+    const int32_t ev = x0 - floor_quarter_r(xm1 + xp1);
+    const int32_t em = xm1 - floor_quarter_r(xm2 + x0), ep = xp1 - floor_quarter_r(x0 + xp2);
+    const int32_t ov = x0 + floor_half(em + ep);
+    return odd ? ov : ev;
+}
+
+// |v| / step with the sign of v (dead-zone quantiser), the division by the
+// tile's precomputed multiplier.
+__device__ inline int32_t quantise(int32_t v, uint32_t qmul, uint32_t qsh)
+{
+    const uint32_t a = v < 0 ? 0u - (uint32_t)v : (uint32_t)v;
+    const uint32_t t = __umulhi(qmul, a);
+    const uint32_t q = (t + ((a - t) >> 1)) >> qsh;
+    return v < 0 ? -(int32_t)q : (int32_t)q;
+}
+
+// Interleaved RGB u8: the colour-transformed channel of 4 pixels held in 3
+// little-endian dwords.
+template <int CT, int CH>
+__device__ inline int32_t rgb_channel(uint32_t R, uint32_t G, uint32_t B)
+{
+    const int32_t r = (int32_t)R, g = (int32_t)G, b = (int32_t)B;
+    if (CT == 1) return CH == 0 ? ((r + 2 * g + b) >> 2) : (CH == 1 ? b - g : r - g);
+    const int32_t co = r - b, t = b + (co >> 1), cg = g - t;
+    return CH == 0 ? t + (cg >> 1) : (CH == 1 ? co : cg);
+}
+
+// Window of an interior tile at level 1 from interleaved RGB u8 pixels: each
+// task loads 12 bytes (4 pixels) of a window row; the window starts at pixel
+// 2 qx0 - 2 and the loads at 2 qx0 - 4, so every load is dword aligned.
+template <int CT, int CH>
+__device__ inline void stage_rgb8(const uint8_t *base, uint32_t stride, int32_t *win)
+{
+    constexpr int NG = 18, NT = WN * NG, NK = (NT + 255) / 256;
+    uint32_t d[NK][3];
+#pragma unroll
+    for (int k = 0; k < NK; k++) {
+        const int t = (int)threadIdx.x + 256 * k;
+        if (t < NT) {
+            const int lr = t / NG, g = t - lr * NG;
+            const uint32_t *p = (const uint32_t *)(base + (uint64_t)lr * stride + 12 * g);
+            d[k][0] = p[0]; d[k][1] = p[1]; d[k][2] = p[2];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NK; k++) {
+        const int t = (int)threadIdx.x + 256 * k;
+        if (t < NT) {
+            const int lr = t / NG, g = t - lr * NG;
+            const uint32_t a = d[k][0], b = d[k][1], c = d[k][2];
+            int32_t v[4];
+            v[0] = rgb_channel<CT, CH>(a & 0xff, (a >> 8) & 0xff, (a >> 16) & 0xff);
+            v[1] = rgb_channel<CT, CH>(a >> 24, b & 0xff, (b >> 8) & 0xff);
+            v[2] = rgb_channel<CT, CH>((b >> 16) & 0xff, b >> 24, c & 0xff);
+            v[3] = rgb_channel<CT, CH>((c >> 8) & 0xff, (c >> 16) & 0xff, c >> 24);
+            int32_t *row = win + lr * WP + 4 * g - 2;
+            if (g > 0) { row[0] = v[0]; row[1] = v[1]; }          // columns -2, -1 are outside
+            if (g < NG - 1) { row[2] = v[2]; row[3] = v[3]; }     // columns 68, 69 are outside
+        }
+    }
+}
+}  // namespace strips
+
+// One forward 2-D level over a 32x32-quad tile of one channel, by strips:
+// stage the reflected 68x68 window, lift window rows 1..64 (a lane per row),
+// then window columns 2..65 (a lane per column) and store the coefficients
+// from the column pass: a wave stores 32 consecutive coefficients of two
+// bands per instruction.  Rows 0, 65 and 66 are row-lifted where the column
+// pass needs them.  Same results as the element-wise kernel above.
+__global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                    const uint8_t *__restrict__ pix,
+                                                    uint8_t *__restrict__ ws, int level)
+{
+    using namespace strips;
+    __shared__ int32_t win[WN * WP];
+    __shared__ int32_t rmap[WN], cmap[WN];
+    const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
+    const WorkItem *items = (const WorkItem *)(plan + H.work_off);
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem &W = find_item(items, H.lvl_first[level], H.lvl_count[level], bid);
+    const TileGeo &T = tiles[W.tile];
+    const uint32_t r = bid - W.wg_start;
+    const int c = (int)(r % W.nch);
+    const uint32_t sp = r / W.nch;
+    const int qx0 = (int)(sp % W.ntx) * TQ, qy0 = (int)(sp / W.ntx) * TQ;
+    const LevelGeo &G = T.lv[level];
+    const int w = (int)G.w, h = (int)G.h;
+    int32_t *wsi = (int32_t *)ws;
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (threadIdx.x < WN) rmap[threadIdx.x] = reflect_idx(2 * qy0 - 2 + (int)threadIdx.x, h);
+    else if (threadIdx.x < 2 * WN) cmap[threadIdx.x - WN] = reflect_idx(2 * qx0 - 2 + (int)threadIdx.x - WN, w);
+    __syncthreads();
+    // ---- stage the window (rows and columns 0..67)
+    if (level == 1) {
+        const uint32_t C = T.channels, bps = T.bps;
+        const uint8_t *tb = pix + T.pix_offset;
+        const bool fast = bps == 1 && C == 3 && T.ct != 0 && qx0 >= 2 && 2 * qx0 + 68 <= w && qy0 >= 1 &&
+                          2 * qy0 + 66 <= h && ((((uintptr_t)tb) | T.pix_stride) & 3u) == 0;
+        if (fast) {
+            const uint8_t *base = tb + (uint64_t)(2 * qy0 - 2) * T.pix_stride + (uint32_t)(6 * qx0 - 12);
+            if (T.ct == 1) {
+                if (c == 0) stage_rgb8<1, 0>(base, T.pix_stride, win);
+                else if (c == 1) stage_rgb8<1, 1>(base, T.pix_stride, win);
+                else stage_rgb8<1, 2>(base, T.pix_stride, win);
+            } else {
+                if (c == 0) stage_rgb8<2, 0>(base, T.pix_stride, win);
+                else if (c == 1) stage_rgb8<2, 1>(base, T.pix_stride, win);
+                else stage_rgb8<2, 2>(base, T.pix_stride, win);
+            }
+        } else {
+            // any format, or a tile at the image border: element by element,
+            // six loads in flight per thread
+            constexpr int NI = (WN * WN + 255) / 256, KB = 6;
+            for (int k0 = 0; k0 < NI; k0 += KB) {
+                int32_t vals[KB];
+#pragma unroll
+                for (int k = 0; k < KB; k++) {
+                    const int i = (int)threadIdx.x + 256 * (k0 + k);
+                    if (i < WN * WN) {
+                        const int lr = i / WN, lc = i % WN;
+                        const uint8_t *px = tb + (uint64_t)rmap[lr] * T.pix_stride + (uint32_t)cmap[lc] * C * bps;
+                        vals[k] = T.ct ? colour_fwd(sample_at(px, bps, 0), sample_at(px, bps, 1), sample_at(px, bps, 2),
+                                                    T.ct, c)
+                                       : sample_at(px, bps, (uint32_t)c);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < KB; k++) {
+                    const int i = (int)threadIdx.x + 256 * (k0 + k);
+                    if (i < WN * WN) win[(i / WN) * WP + (i % WN)] = vals[k];
+                }
+            }
+        }
+    } else {
+        // LL of the previous level: a lane per window column (0..63), a wave
+        // per fourth row; then columns 64..67
+        const int which = ((level - 1) & 1) ? 0 : 1;
+        const int32_t *src = wsi + T.tmp_off[which] + (uint64_t)c * T.tmp_chan[which];
+        const uint32_t spitch = T.tmp_pitch[which];
+        constexpr int NR = WN / 4;
+        int32_t v[NR];
+        const int32_t *sc = src + cmap[lane];
+#pragma unroll
+        for (int k = 0; k < NR; k++) v[k] = sc[(uint64_t)rmap[wv + 4 * k] * spitch];
+        int32_t e[2];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int t = (int)threadIdx.x + 256 * k;
+            if (t < 4 * WN) e[k] = src[(uint64_t)rmap[t >> 2] * spitch + cmap[64 + (t & 3)]];
+        }
+#pragma unroll
+        for (int k = 0; k < NR; k++) win[(wv + 4 * k) * WP + lane] = v[k];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int t = (int)threadIdx.x + 256 * k;
+            if (t < 4 * WN) win[(t >> 2) * WP + 64 + (t & 3)] = e[k];
+        }
+    }
+    __syncthreads();
+    // ---- row pass: window rows 1..64, columns 16wv .. 16wv+18 -> 16wv+2 ..
+    {
+        int32_t x[19], o[16];
+        int32_t *row = win + (1 + lane) * WP + 16 * wv;
+#pragma unroll
+        for (int j = 0; j < 19; j++) x[j] = row[j];
+        lift_fwd16(x, o);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; j++) row[2 + j] = o[j];
+    }
+    __syncthreads();
+    // ---- column pass: window column 2 + lane, rows 16wv .. 16wv+18
+    const int cc = 2 + lane;
+    const bool odd = (lane & 1) != 0;  // column parity: high-pass column
+    int32_t o[16];
+    {
+        int32_t x[19];
+        const int32_t *col = win + 16 * wv * WP + cc;
+#pragma unroll
+        for (int j = 0; j < 19; j++) x[j] = col[j * WP];
+        if (wv == 0) x[0] = row_lift_fwd_at(win + cc, odd);
+        if (wv == 3) {
+            x[17] = row_lift_fwd_at(win + 65 * WP + cc, odd);
+            x[18] = row_lift_fwd_at(win + 66 * WP + cc, odd);
+        }
+        lift_fwd16(x, o);
+    }
+    // ---- outputs: even window rows of the strip give L rows, odd ones H rows
+    const int llw = (w + 1) / 2, llh = (h + 1) / 2, hw = w / 2, hh = h / 2;
+    const bool last = (level == T.levels);
+    int32_t *llout;
+    uint32_t llpitch;
+    if (last) {
+        llout = wsi + T.ll_off + (uint64_t)c * T.chan_elems;
+        llpitch = T.ll_pitch;
+    } else {
+        const int which = (level & 1) ? 0 : 1;
+        llout = wsi + T.tmp_off[which] + (uint64_t)c * T.tmp_chan[which];
+        llpitch = T.tmp_pitch[which];
+    }
+    const int qx = qx0 + (lane >> 1);
+    int32_t *pe = odd ? wsi + G.off[1] + (uint64_t)c * T.chan_elems : llout;   // HL | LL
+    int32_t *po = wsi + G.off[odd ? 2 : 0] + (uint64_t)c * T.chan_elems;     // HH | LH
+    const uint32_t pitch_e = odd ? G.pitch[1] : llpitch, pitch_o = G.pitch[odd ? 2 : 0];
+    const bool xin = qx < (odd ? hw : llw);
+    pe += qx; po += qx;
+    const uint32_t step = T.qstep, qmul = T.qmul, qsh = T.qsh;
+    uint32_t or_e = 0, or_o = 0, negs = 0;
+    const int qyb = qy0 + 8 * wv;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const int qy = qyb + (j >> 1);
+        int32_t v = o[j];
+        if (j & 1) {
+            if (step > 1) v = quantise(v, qmul, qsh);
+            if (xin && qy < hh) {
+                po[(uint64_t)qy * pitch_o] = v;
+                or_o |= v < 0 ? 0u - (uint32_t)v : (uint32_t)v;
+                negs |= v < 0 ? 2u : 0u;
+            }
+        } else {
+            if (step > 1 && odd) v = quantise(v, qmul, qsh);
+            if (xin && qy < llh) {
+                pe[(uint64_t)qy * pitch_e] = v;
+                or_e |= v < 0 ? 0u - (uint32_t)v : (uint32_t)v;
+                negs |= v < 0 ? 1u : 0u;
+            }
+        }
+    }
+    // per-block accumulation over the lanes of one column parity (the whole
+    // quad tile lies in one 128 cell): lane 0 gets LL and LH, lane 1 HL and HH
+#pragma unroll
+    for (int s = 2; s <= 32; s <<= 1) {
+        or_e |= __shfl_xor(or_e, s, 64);
+        or_o |= __shfl_xor(or_o, s, 64);
+        negs |= __shfl_xor(negs, s, 64);
+    }
+    if (lane < 2) {
+        BlkAcc *acc = (BlkAcc *)(ws + H.ws_acc);
+        const int bx = qx0 / kBlock, by = qy0 / kBlock;
+        const int32_t hwc = hw - bx * kBlock, hhc = hh - by * kBlock;
+        if (hwc > 0 || hhc > 0) {  // the cell holds at least one H coefficient
+            const uint32_t local = G.group_start + (uint32_t)c * G.blocks_per_chan + (uint32_t)by * G.gx + bx;
+            BlkAcc *a = acc + T.block_base + local;
+            if (lane == 0) {
+                if (or_o) atomicOr(&a->or_mag[0], or_o);
+                if (negs & 2u) atomicOr(&a->neg, 1u);
+            } else {
+                if (or_e) atomicOr(&a->or_mag[1], or_e);
+                if (or_o) atomicOr(&a->or_mag[2], or_o);
+                const uint32_t nb = ((negs & 1u) ? 2u : 0u) | ((negs & 2u) ? 4u : 0u);
+                if (nb) atomicOr(&a->neg, nb);
+            }
+        }
+        if (last && lane == 0) {
+            const uint32_t local = (uint32_t)c * T.ll_gx * T.ll_gy + (uint32_t)by * T.ll_gx + bx;
+            BlkAcc *a = acc + T.block_base + local;
+            if (or_e) atomicOr(&a->or_mag[0], or_e);
+            if (negs & 1u) atomicOr(&a->neg, 1u);
+        }
+    }
+}
+
+// Inverse of level `level` for channel ch over the window of the maps rmap /
+// cmap, by strips.  The column pass loads the interleaved coefficients of
+// window column 2 + lane, rows 1 + 16wv .. 19 + 16wv, straight from the bands
+// into registers; the halo columns 1, 66 and 67 are staged raw and lifted
+// where the row pass needs them.  o receives window row 2 + lane, columns
+// 16wv + 2 .. 16wv + 17.  The caller synchronises before the window is
+// written again.
+__device__ inline void inv_strips_channel(const TileGeo &T, int level, int ch, const int32_t *rmap,
+                                          const int32_t *cmap, const int32_t *wsi, int32_t *win, int lane,
+                                          int wv, bool do_cols, bool do_rows, int32_t (&o)[16])
+{
+    using namespace strips;
+    const LevelGeo &G = T.lv[level];
+    const int32_t *ll;
+    uint32_t llp;
+    if (level == T.levels) { ll = wsi + T.ll_off + (uint64_t)ch * T.chan_elems; llp = T.ll_pitch; }
+    else {
+        const int which = (level & 1) ? 0 : 1;
+        ll = wsi + T.tmp_off[which] + (uint64_t)ch * T.tmp_chan[which];
+        llp = T.tmp_pitch[which];
+    }
+    const int32_t *lh = wsi + G.off[0] + (uint64_t)ch * T.chan_elems;
+    const int32_t *hl = wsi + G.off[1] + (uint64_t)ch * T.chan_elems;
+    const int32_t *hh = wsi + G.off[2] + (uint64_t)ch * T.chan_elems;
+    // halo columns, window rows 0..67
+    const int t = (int)threadIdx.x;
+    int32_t hv = 0;
+    int hdst = -1;
+    if (t < 3 * WN) {
+        const int k = t / WN, lr = t - k * WN;
+        const int lc = k == 0 ? 1 : 65 + k;
+        const int gy = rmap[lr], gx = cmap[lc];
+        const int32_t *src = (gy & 1) ? ((gx & 1) ? hh : lh) : ((gx & 1) ? hl : ll);
+        const uint32_t pitch = (gy & 1) ? G.pitch[(gx & 1) ? 2 : 0] : ((gx & 1) ? G.pitch[1] : llp);
+        hv = src[(uint64_t)(gy >> 1) * pitch + (gx >> 1)];
+        hdst = lr * WP + lc;
+    }
+    // column pass: window column 2 + lane (even rows LL | HL, odd rows LH | HH)
+    const int gx = cmap[2 + lane];
+    const bool xo = (gx & 1) != 0;
+    const int32_t *pe = (xo ? hl : ll) + (gx >> 1);
+    const int32_t *po = (xo ? hh : lh) + (gx >> 1);
+    const uint32_t pitch_e = xo ? G.pitch[1] : llp, pitch_o = G.pitch[xo ? 2 : 0];
+    int32_t x[19];
+#pragma unroll
+    for (int j = 0; j < 19; j++) {
+        const int gy = __builtin_amdgcn_readfirstlane(rmap[1 + 16 * wv + j]);
+        const int32_t *p = (gy & 1) ? po : pe;
+        const uint32_t pitch = (gy & 1) ? pitch_o : pitch_e;
+        x[j] = p[(uint64_t)(gy >> 1) * pitch];
+    }
+    if (hdst >= 0) win[hdst] = hv;
+    {
+        int32_t y[16];
+        if (do_cols) lift_inv16(x, y);
+        else {
+#pragma unroll
+            for (int j = 0; j < 16; j++) y[j] = x[j + 1];
+        }
+        int32_t *colw = win + (2 + 16 * wv) * WP + 2 + lane;
+#pragma unroll
+        for (int j = 0; j < 16; j++) colw[j * WP] = y[j];
+    }
+    __syncthreads();
+    // row pass: window row 2 + lane, columns 1 + 16wv .. 19 + 16wv
+    int32_t *rw = win + (2 + lane) * WP;
+#pragma unroll
+    for (int j = 0; j < 19; j++) x[j] = rw[1 + 16 * wv + j];
+    if (do_cols) {
+        const bool ro = (lane & 1) != 0;  // window row parity
+        if (wv == 0) x[0] = col_lift_inv_at(rw + 1, ro);
+        if (wv == 3) {
+            x[17] = col_lift_inv_at(rw + 66, ro);
+            x[18] = col_lift_inv_at(rw + 67, ro);
+        }
+    }
+    if (do_rows) lift_inv16(x, o);
+    else {
+#pragma unroll
+        for (int j = 0; j < 16; j++) o[j] = x[j + 1];
+    }
+}
+
+// Inverse of level `level` into LL_{level-1} (an intermediate level), by
+// strips; the outputs go back through the window so that a wave stores whole
+// rows.
+__global__ void __launch_bounds__(256) k_inv_level_strips(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                          uint8_t *__restrict__ ws, int level)
+{
+    using namespace strips;
+    __shared__ int32_t win[WN * WP];
+    __shared__ int32_t rmap[WN], cmap[WN];
+    const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
+    const WorkItem *items = (const WorkItem *)(plan + H.work_off);
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem &W = find_item(items, H.lvl_first[level], H.lvl_count[level], bid);
+    const TileGeo &T = tiles[W.tile];
+    const uint32_t r = bid - W.wg_start;
+    const int c = (int)(r % W.nch);
+    const uint32_t sp = r / W.nch;
+    const int qx0 = (int)(W.qx0 + (sp % W.ntx) * TQ), qy0 = (int)(W.qy0 + (sp / W.ntx) * TQ);
+    int32_t *wsi = (int32_t *)ws;
+    const LevelGeo &G = T.lv[level];
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    fill_maps<TQ>(rmap, cmap, qx0, qy0, (int)G.w, (int)G.h, G);
+    __syncthreads();
+    int32_t o[16];
+    inv_strips_channel(T, level, c, rmap, cmap, wsi, win, lane, wv, G.h > 1, G.w > 1, o);
+    __syncthreads();
+    int32_t *rowp = win + (2 + lane) * WP + 2 + 16 * wv;
+#pragma unroll
+    for (int j = 0; j < 16; j++) rowp[j] = o[j];
+    __syncthreads();
+    // LL_{level-1} is the low band of level-1: store the part inside that
+    // level's window, a lane per column, a wave per fourth row
+    const int k = level - 1, which = (k & 1) ? 0 : 1;
+    const LevelGeo &D = T.lv[k];
+    int32_t *dst = wsi + T.tmp_off[which] + (uint64_t)c * T.tmp_chan[which];
+    const uint32_t dp = T.tmp_pitch[which];
+    const int x = 2 * qx0 + lane - (int)D.wx0;
+#pragma unroll
+    for (int m = 0; m < 16; m++) {
+        const int ly = wv + 4 * m;
+        const int y = 2 * qy0 + ly - (int)D.wy0;
+        if ((uint32_t)x < D.ww && (uint32_t)y < D.wh) dst[(uint64_t)y * dp + x] = win[(2 + ly) * WP + 2 + lane];
+    }
+}
+
+// Final stage of a decode job by strips: LL_z (z = target level), fusing the
+// inverse of level z+1 if z < levels, then the inverse colour transform,
+// clamping and the interleaved pixel stores.  The channels of a group (3
+// with the colour transform) go through the window in turn; a thread keeps
+// its 16 pixels of one output row per channel in registers.  Formats of at
+// most 4 bytes per pixel in one channel group are staged in LDS as output
+// bytes and stored by whole rows.
+__global__ void __launch_bounds__(256) k_inv_final_strips(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                          uint8_t *__restrict__ ws, uint8_t *__restrict__ pix)
+{
+    using namespace strips;
+    __shared__ __align__(16) int32_t win[WN * WP];
+    __shared__ int32_t rmap[WN], cmap[WN];
+    const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
+    const WorkItem *items = (const WorkItem *)(plan + H.work_off);
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const WorkItem &W = find_item(items, H.fin_first, H.fin_count, bid);
+    const TileGeo &T = tiles[W.tile];
+    const uint32_t r = bid - W.wg_start;
+    const int cg = (int)(r % W.nch);
+    const uint32_t sp = r / W.nch;
+    const int qx0 = (int)(W.qx0 + (sp % W.ntx) * TQ), qy0 = (int)(W.qy0 + (sp / W.ntx) * TQ);
+    int32_t *wsi = (int32_t *)ws;
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int z = T.target_level;
+    const int c0 = cg * 3;
+    const int nc = min((int)T.channels - c0, 3);
+    const bool fused = z < T.levels;
+    int ow = 0, oh = 0;
+    if (fused) {
+        ow = (int)T.lv[z + 1].w; oh = (int)T.lv[z + 1].h;
+        fill_maps<TQ>(rmap, cmap, qx0, qy0, ow, oh, T.lv[z + 1]);
+        __syncthreads();
+    }
+    // output region of the level-z image (all of it for a full decode)
+    const int rx0 = (int)T.rx0, ry0 = (int)T.ry0, rx1 = (int)T.rx1, ry1 = (int)T.ry1;
+    const int y = 2 * qy0 + lane;      // this thread's output row
+    const int xs = 2 * qx0 + 16 * wv;  // its first output column
+    int32_t v[3][16];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        if (k >= nc) {
+#pragma unroll
+            for (int j = 0; j < 16; j++) v[k][j] = 0;
+            continue;
+        }
+        if (fused) {
+            if (k) __syncthreads();
+            inv_strips_channel(T, z + 1, c0 + k, rmap, cmap, wsi, win, lane, wv, oh > 1, ow > 1, v[k]);
+        } else {
+            const int32_t *ll = wsi + T.ll_off + (uint64_t)(c0 + k) * T.chan_elems;
+            const bool yin = y >= ry0 && y < ry1;
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const int x = xs + j;
+                v[k][j] = (yin && x >= rx0 && x < rx1)
+                              ? ll[(uint64_t)(y - (int)T.ll_wy0) * T.ll_pitch + (x - (int)T.ll_wx0)] : 0;
+            }
+        }
+    }
+    const int32_t top = (1 << T.bits) - 1;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        if (T.ct) colour_inv(T.ct, v[0][j], v[1][j], v[2][j]);
+#pragma unroll
+        for (int k = 0; k < 3; k++) v[k][j] = v[k][j] < 0 ? 0 : (v[k][j] > top ? top : v[k][j]);
+    }
+    const uint32_t C = T.channels, bps = T.bps, sb = C * bps;
+    const uint64_t rowbase0 = T.pix_offset + (uint64_t)(2 * qx0 - rx0) * sb;
+    const bool staged = nc == (int)C && sb <= 4 && 2 * qx0 >= rx0 &&
+                        ((rowbase0 | T.pix_stride | (uint64_t)(uintptr_t)pix) & 3u) == 0;
+    if (staged) {
+        __syncthreads();  // every row pass has read the window
+        uint8_t *ob = (uint8_t *)win;  // 64 rows x 64 * sb bytes
+        const int RB = 64 * (int)sb;
+        uint8_t *mine = ob + lane * RB + 16 * wv * (int)sb;
+        if (sb == 3) {
+            uint32_t dw[12];
+#pragma unroll
+            for (int i = 0; i < 12; i++) dw[i] = 0;
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    const int b = 3 * j + k;
+                    dw[b >> 2] |= (uint32_t)v[k][j] << (8 * (b & 3));
+                }
+            uint4 *q = (uint4 *)mine;
+            q[0] = make_uint4(dw[0], dw[1], dw[2], dw[3]);
+            q[1] = make_uint4(dw[4], dw[5], dw[6], dw[7]);
+            q[2] = make_uint4(dw[8], dw[9], dw[10], dw[11]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) {  // constant indices keep v in registers
+                    if (k >= nc) break;
+                    uint8_t *q = mine + (j * (int)C + k) * (int)bps;
+                    if (bps == 1) *q = (uint8_t)v[k][j];
+                    else if (bps == 2) *(uint16_t *)q = (uint16_t)v[k][j];
+                    else *(uint32_t *)q = (uint32_t)v[k][j];
+                }
+        }
+        __syncthreads();
+        // 16-byte pieces: 16 lanes per row, four rows per wave and pass
+        const int nq = RB / 16;
+        const int nbytes = min(64, rx1 - 2 * qx0) * (int)sb;
+        const bool a16 = ((rowbase0 | T.pix_stride | (uint64_t)(uintptr_t)pix) & 15u) == 0;
+        const int k = lane & 15;
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            const int ly = 4 * (wv + 4 * m) + (lane >> 4);
+            const int yy = 2 * qy0 + ly;
+            const int nb = min(16, nbytes - 16 * k);
+            if (k >= nq || nb <= 0 || yy < ry0 || yy >= ry1) continue;
+            uint8_t *dst = pix + rowbase0 + (uint64_t)(yy - ry0) * T.pix_stride + 16 * k;
+            const uint8_t *src = ob + ly * RB + 16 * k;
+            if (nb == 16 && a16) *(uint4 *)dst = *(const uint4 *)src;
+            else {
+                const int nw = nb >> 2;
+                for (int i = 0; i < nw; i++) ((uint32_t *)dst)[i] = ((const uint32_t *)src)[i];
+                for (int b = 4 * nw; b < nb; b++) dst[b] = src[b];
+            }
+        }
+        return;
+    }
+    if (y < ry0 || y >= ry1) return;
+    uint8_t *row = pix + T.pix_offset + (uint64_t)(y - ry0) * T.pix_stride;  // region row
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const int x = xs + j;
+        if (x < rx0 || x >= rx1) continue;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            if (k >= nc) break;
+            const uint32_t e = ((uint32_t)(x - rx0) * C + c0 + k) * bps;
+            if (bps == 1) row[e] = (uint8_t)v[k][j];
+            else if (bps == 2) *(uint16_t *)(row + e) = (uint16_t)v[k][j];
+            else *(uint32_t *)(row + e) = (uint32_t)v[k][j];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launch
 hipError_t launch_forward_level(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
                                 uint8_t *d_ws, int level, hipStream_t stream)
@@ -614,7 +1207,7 @@ hipError_t launch_forward_level(const PlanHdr &H, const uint8_t *d_plan, const u
     else if (H.tq == 16)
         hipLaunchKernelGGL(k_fwd_level<16>, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws, level);
     else
-        hipLaunchKernelGGL(k_fwd_level<32>, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws, level);
+        hipLaunchKernelGGL(k_fwd_strips, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_pixels, d_ws, level);
     return hipGetLastError();
 }
 
@@ -627,12 +1220,12 @@ hipError_t launch_inverse_level(const PlanHdr &H, const uint8_t *d_plan, uint8_t
         if (H.tq == 16)
             hipLaunchKernelGGL(k_inv_final<16>, dim3(H.fin_wgs), dim3(256), 0, stream, H, d_plan, d_ws, d_pixels_out, d_status);
         else
-            hipLaunchKernelGGL(k_inv_final<32>, dim3(H.fin_wgs), dim3(256), 0, stream, H, d_plan, d_ws, d_pixels_out, d_status);
+            hipLaunchKernelGGL(k_inv_final_strips, dim3(H.fin_wgs), dim3(256), 0, stream, H, d_plan, d_ws, d_pixels_out);
     } else if (level <= (int)H.max_levels && H.lvl_wgs[level]) {
         if (H.tq == 16)
             hipLaunchKernelGGL(k_inv_level<16>, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_ws, level);
         else
-            hipLaunchKernelGGL(k_inv_level<32>, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_ws, level);
+            hipLaunchKernelGGL(k_inv_level_strips, dim3(H.lvl_wgs[level]), dim3(256), 0, stream, H, d_plan, d_ws, level);
     }
     return hipGetLastError();
 }

@@ -250,9 +250,33 @@ def test_generality_matches_oracle(case):
     """Forward coefficients, stream bytes, every resolution level and a
     reduced-quality decode equal the oracle's for the alternative colour
     transform, deep samples and many channels."""
+    print("general", case, flush=True)
+    _check_everything(case)
+
+
+INTERIOR = [
+    # (w, h, c, bits, levels, qstep, ct, kind): images of several 64x64
+    # transform tiles with interior tiles (no reflection in the window), ragged
+    # right and bottom tiles, and steps that are not powers of two; the output
+    # formats cover 1, 2, 3 and 4 bytes per pixel and two channel groups
+    (640, 456, 3, 8, 3, 1, 1, "uniform"), (517, 389, 3, 8, 5, 7, 1, "sparse"),
+    (520, 390, 3, 8, 4, 3, 2, "ramp"), (600, 330, 1, 16, 3, 5, 0, "uniform"),
+    (330, 300, 2, 8, 2, 1, 0, "uniform"), (300, 280, 1, 24, 3, 1, 0, "uniform"),
+    (400, 200, 4, 8, 2, 2, 0, "uniform"), (384, 320, 1, 8, 1, 1, 0, "checker"),
+]
+
+
+@pytest.mark.parametrize("case", INTERIOR, ids=lambda c: "x".join(map(str, c)))
+def test_interior_tiles_match_oracle(case):
+    """The same checks on images large enough for the transform kernels' fast
+    paths (aligned interior windows, whole-row output staging)."""
+    print("interior", case, flush=True)
+    _check_everything(case)
+
+
+def _check_everything(case):
     w, h, c, bits, lv, q, ct, kind = case
     img = synth.random_image(w, h, c, bits, seed=w * 5 + h, kind=kind)
-    print("general", case, flush=True)
     got = isx.debug_forward(img, lv, bits=bits, ct=ct, qstep=q)
     ref = oracle.forward_dump(img, lv, bits=bits, ct=ct, qstep=q)
     for ch in range(c):
