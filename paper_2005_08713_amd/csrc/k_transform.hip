@@ -924,16 +924,24 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
     }
 }
 
-// Inverse of level `level` for channel ch over the window of the maps rmap /
-// cmap, by strips.  The column pass loads the interleaved coefficients of
-// window column 2 + lane, rows 1 + 16wv .. 19 + 16wv, straight from the bands
-// into registers; the halo columns 1, 66 and 67 are staged raw and lifted
-// where the row pass needs them.  o receives window row 2 + lane, columns
-// 16wv + 2 .. 16wv + 17.  The caller synchronises before the window is
-// written again.
-__device__ inline void inv_strips_channel(const TileGeo &T, int level, int ch, const int32_t *rmap,
-                                          const int32_t *cmap, const int32_t *wsi, int32_t *win, int lane,
-                                          int wv, bool do_cols, bool do_rows, int32_t (&o)[16])
+// Inverse of level `level` for one channel over the window of the maps rmap /
+// cmap, by strips, in three steps so that a caller can have the next
+// channel's loads in flight while it finishes the current one:
+//  1. inv_strips_load: the column pass's coefficients of window column
+//     2 + lane, rows 1 + 16wv .. 19 + 16wv, straight from the bands into
+//     registers, and one coefficient of the halo columns 1, 66, 67;
+//  2. inv_strips_cols: the column lifting, its outputs (and the raw halo)
+//     into the window;
+//  3. after a barrier, inv_strips_rows: the row pass of window row 2 + lane,
+//     columns 16wv + 2 .. 16wv + 17, lifting the halo columns where needed.
+struct InvLoad {
+    int32_t x[19];
+    int32_t hv;
+    int hdst;
+};
+
+__device__ inline void inv_strips_load(const TileGeo &T, int level, int ch, const int32_t *rmap, const int32_t *cmap,
+                                       const int32_t *wsi, int lane, int wv, InvLoad &L)
 {
     using namespace strips;
     const LevelGeo &G = T.lv[level];
@@ -950,49 +958,56 @@ __device__ inline void inv_strips_channel(const TileGeo &T, int level, int ch, c
     const int32_t *hh = wsi + G.off[2] + (uint64_t)ch * T.chan_elems;
     // halo columns, window rows 0..67
     const int t = (int)threadIdx.x;
-    int32_t hv = 0;
-    int hdst = -1;
+    L.hv = 0;
+    L.hdst = -1;
     if (t < 3 * WN) {
         const int k = t / WN, lr = t - k * WN;
         const int lc = k == 0 ? 1 : 65 + k;
         const int gy = rmap[lr], gx = cmap[lc];
         const int32_t *src = (gy & 1) ? ((gx & 1) ? hh : lh) : ((gx & 1) ? hl : ll);
         const uint32_t pitch = (gy & 1) ? G.pitch[(gx & 1) ? 2 : 0] : ((gx & 1) ? G.pitch[1] : llp);
-        hv = src[(uint64_t)(gy >> 1) * pitch + (gx >> 1)];
-        hdst = lr * WP + lc;
+        L.hv = src[(uint64_t)(gy >> 1) * pitch + (gx >> 1)];
+        L.hdst = lr * WP + lc;
     }
-    // column pass: window column 2 + lane (even rows LL | HL, odd rows LH | HH)
+    // window column 2 + lane: even rows LL | HL, odd rows LH | HH
     const int gx = cmap[2 + lane];
     const bool xo = (gx & 1) != 0;
     const int32_t *pe = (xo ? hl : ll) + (gx >> 1);
     const int32_t *po = (xo ? hh : lh) + (gx >> 1);
     const uint32_t pitch_e = xo ? G.pitch[1] : llp, pitch_o = G.pitch[xo ? 2 : 0];
-    int32_t x[19];
 #pragma unroll
     for (int j = 0; j < 19; j++) {
         const int gy = __builtin_amdgcn_readfirstlane(rmap[1 + 16 * wv + j]);
         const int32_t *p = (gy & 1) ? po : pe;
         const uint32_t pitch = (gy & 1) ? pitch_o : pitch_e;
-        x[j] = p[(uint64_t)(gy >> 1) * pitch];
+        L.x[j] = p[(uint64_t)(gy >> 1) * pitch];
     }
-    if (hdst >= 0) win[hdst] = hv;
-    {
-        int32_t y[16];
-        if (do_cols) lift_inv16(x, y);
-        else {
+}
+
+__device__ inline void inv_strips_cols(const InvLoad &L, int32_t *win, int lane, int wv, bool do_cols)
+{
+    using namespace strips;
+    if (L.hdst >= 0) win[L.hdst] = L.hv;
+    int32_t y[16];
+    if (do_cols) lift_inv16(L.x, y);
+    else {
 #pragma unroll
-            for (int j = 0; j < 16; j++) y[j] = x[j + 1];
-        }
-        int32_t *colw = win + (2 + 16 * wv) * WP + 2 + lane;
-#pragma unroll
-        for (int j = 0; j < 16; j++) colw[j * WP] = y[j];
+        for (int j = 0; j < 16; j++) y[j] = L.x[j + 1];
     }
-    __syncthreads();
-    // row pass: window row 2 + lane, columns 1 + 16wv .. 19 + 16wv
-    int32_t *rw = win + (2 + lane) * WP;
+    int32_t *colw = win + (2 + 16 * wv) * WP + 2 + lane;
+#pragma unroll
+    for (int j = 0; j < 16; j++) colw[j * WP] = y[j];
+}
+
+__device__ inline void inv_strips_rows(const int32_t *win, int lane, int wv, bool do_cols, bool do_rows,
+                                       int32_t (&o)[16])
+{
+    using namespace strips;
+    int32_t x[19];
+    const int32_t *rw = win + (2 + lane) * WP;
 #pragma unroll
     for (int j = 0; j < 19; j++) x[j] = rw[1 + 16 * wv + j];
-    if (do_cols) {
+    if (do_cols) {  // the halo columns were left raw by the column pass
         const bool ro = (lane & 1) != 0;  // window row parity
         if (wv == 0) x[0] = col_lift_inv_at(rw + 1, ro);
         if (wv == 3) {
@@ -1032,7 +1047,13 @@ __global__ void __launch_bounds__(256) k_inv_level_strips(PlanHdr H, const uint8
     fill_maps<TQ>(rmap, cmap, qx0, qy0, (int)G.w, (int)G.h, G);
     __syncthreads();
     int32_t o[16];
-    inv_strips_channel(T, level, c, rmap, cmap, wsi, win, lane, wv, G.h > 1, G.w > 1, o);
+    {
+        InvLoad L;
+        inv_strips_load(T, level, c, rmap, cmap, wsi, lane, wv, L);
+        inv_strips_cols(L, win, lane, wv, G.h > 1);
+    }
+    __syncthreads();
+    inv_strips_rows(win, lane, wv, G.h > 1, G.w > 1, o);
     __syncthreads();
     int32_t *rowp = win + (2 + lane) * WP + 2 + 16 * wv;
 #pragma unroll
@@ -1093,6 +1114,8 @@ __global__ void __launch_bounds__(256) k_inv_final_strips(PlanHdr H, const uint8
     const int y = 2 * qy0 + lane;      // this thread's output row
     const int xs = 2 * qx0 + 16 * wv;  // its first output column
     int32_t v[3][16];
+    InvLoad L;  // the coefficients of the channel the window takes next
+    if (fused) inv_strips_load(T, z + 1, c0, rmap, cmap, wsi, lane, wv, L);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         if (k >= nc) {
@@ -1101,8 +1124,12 @@ __global__ void __launch_bounds__(256) k_inv_final_strips(PlanHdr H, const uint8
             continue;
         }
         if (fused) {
-            if (k) __syncthreads();
-            inv_strips_channel(T, z + 1, c0 + k, rmap, cmap, wsi, win, lane, wv, oh > 1, ow > 1, v[k]);
+            if (k) __syncthreads();  // the previous row pass has read the window
+            inv_strips_cols(L, win, lane, wv, oh > 1);
+            // the next channel's loads are in flight during this row pass
+            if (k + 1 < nc) inv_strips_load(T, z + 1, c0 + k + 1, rmap, cmap, wsi, lane, wv, L);
+            __syncthreads();
+            inv_strips_rows(win, lane, wv, oh > 1, ow > 1, v[k]);
         } else {
             const int32_t *ll = wsi + T.ll_off + (uint64_t)(c0 + k) * T.chan_elems;
             const bool yin = y >= ry0 && y < ry1;
