@@ -928,6 +928,11 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
                                                     uint8_t *__restrict__ ws,
                                                     const int32_t *__restrict__ status)
 {
+    // per kept plane s of the block: its bit b and, per type t, the byte
+    // offset of the type's symbols in the plane (~0: the type skips it), so
+    // that the plane loop issues only independent symbol loads
+    __shared__ uint32_t s_off[32][3];
+    __shared__ uint32_t s_bit[32];
     const uint32_t tid = threadIdx.x;
     for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
@@ -940,27 +945,41 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
     int32_t *wsi = (int32_t *)ws;
     const uint8_t *sym = ws + B.sym_off;
     const uint32_t pstr = plane_stride(p * n);
+    __syncthreads();  // the previous block's table has been read
+    if (tid < nseg) {
+        const uint32_t b = P.seg_plane[tid];
+        uint32_t pm = 0;
+        for (uint32_t u = 0; u < p; u++) pm |= (((P.masks[u] >> b) & 1u) ^ 1u) << u;
+        s_bit[tid] = b;
+        for (uint32_t u = 0; u < 3; u++)
+            s_off[tid][u] = ((pm >> u) & 1u) ? b * pstr + (uint32_t)__popc(pm & ((1u << u) - 1u)) * n : ~0u;
+    }
+    __syncthreads();
     for (uint32_t cell = tid; cell < p * cpt; cell += blockDim.x) {
         const uint32_t t = cell / cpt, ci = cell % cpt;
         uint32_t mag[16];
 #pragma unroll
         for (int i = 0; i < 16; i++) mag[i] = 0;
         uint32_t sgn = 0;
-        // predicated loads, several planes in flight
-#pragma unroll 4
-        for (uint32_t s = 0; s < nseg; s++) {
-            const uint32_t b = P.seg_plane[s];
-            uint32_t pm = 0;
-            for (uint32_t u = 0; u < p; u++) pm |= (((P.masks[u] >> b) & 1u) ^ 1u) << u;
-            uint32_t v = 0;
-            if ((pm >> t) & 1u) {
-                const uint32_t rank = __popc(pm & ((1u << t) - 1u));
-                v = *(const uint16_t *)(sym + (uint64_t)b * pstr + rank * n + 2 * ci);
-            }
-            if (b == d - 1) sgn = v;
-            else {
+        // eight planes' loads in flight, then their bits; a type that skips
+        // a plane (and a plane past the last) reads plane 0 and contributes 0
+        for (uint32_t s0 = 0; s0 < nseg; s0 += 8) {
+            uint32_t w[8], bb[8];
 #pragma unroll
-                for (int i = 0; i < 16; i++) mag[i] |= ((v >> i) & 1u) << b;
+            for (int k = 0; k < 8; k++) {
+                const uint32_t s = s0 + k;
+                const uint32_t o = s < nseg ? s_off[s][t] : ~0u;
+                bb[k] = s < nseg && o != ~0u ? s_bit[s] : 32u;
+                w[k] = *(const uint16_t *)(sym + (o != ~0u ? o : 0u) + 2 * ci);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const bool sign_plane = bb[k] == d - 1;
+                const uint32_t v = (sign_plane || bb[k] >= 32u) ? 0u : w[k];
+                sgn = sign_plane ? w[k] : sgn;
+                const uint32_t sh = bb[k] & 31u;
+#pragma unroll
+                for (int i = 0; i < 16; i++) mag[i] |= ((v >> i) & 1u) << sh;
             }
         }
         if (B.drop) {  // midpoint of the dropped magnitude bits
