@@ -951,12 +951,24 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
     const uint32_t tid = threadIdx.x;
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
-    const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[B.tile];
-    if (O.status != ISX_STATUS_OK) return;
-    const uint32_t nseg = P.nseg;
+    // the plan fields a segment needs are loaded together, before the checks
+    // that depend on them, so that they cost one round trip to memory
+    const uint32_t s = y ? y - 1 : 0;
+    const uint32_t lane = tid & 63u;
+    const uint32_t tile = B.tile;
+    const uint64_t sym_off = B.sym_off;
+    const uint32_t nseg = P.nseg, hdr_bits = P.hdr_bits, czr = P.czr, wz = P.wz, pp = P.p, pn = P.n;
+    const uint32_t seg_lane = P.seg_bits[lane & 31u];
+    const uint32_t nbits_s = P.seg_bits[s], M = P.seg_M[s], plane = P.seg_plane[s];
+    const uint64_t byte_off = P.byte_off;
+    const uint32_t code_t = P.code[tid & 255u], len_t = P.len[tid & 255u];
+    const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[tile];
+    const uint32_t status = O.status;
+    const uint64_t toff = O.offset;
+    if (status != ISX_STATUS_OK) return;
     if (y > nseg) return;
     uint32_t *outw = (uint32_t *)out;
-    const uint64_t bit0 = (O.offset + P.byte_off) * 8;
+    const uint64_t bit0 = (toff + byte_off) * 8;
     if (y == 0) {
         // header: d | masks | C_zr | wz | tree | seek table (Fig. 3)
         const uint32_t nbits = P.hdr_bits;
@@ -996,30 +1008,27 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
         flush_bits(st, bit0, nbits, outw);
         return;
     }
-    // segment y-1: tokens of the plane's symbols; its start = header + the
-    // lengths of the segments before it (a wave sum in every wave)
-    const uint32_t s = y - 1;
+    // segment s = y-1: tokens of the plane's symbols; its start = header +
+    // the lengths of the segments before it (a wave sum in every wave)
     uint32_t start;
     {
-        const uint32_t lane = tid & 63u;
-        uint32_t v = lane < s ? P.seg_bits[lane] : 0u;
+        uint32_t v = lane < s ? seg_lane : 0u;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        start = P.hdr_bits + v;
+        start = hdr_bits + v;
     }
-    const uint32_t nbits = P.seg_bits[s];
+    const uint32_t nbits = nbits_s;
     const uint64_t abit = bit0 + start;
     const uint32_t o = (uint32_t)(abit & 31u);
     const uint32_t nw = (o + nbits + 31) >> 5;
     for (uint32_t i = tid; i < nw + 1; i += blockDim.x) st[i] = 0;
     if (tid < 256) {
-        s_code[tid] = P.code[tid];
-        s_len[tid] = P.len[tid];
+        s_code[tid] = code_t;
+        s_len[tid] = (uint8_t)len_t;
     }
+    const uint8_t *syms = ws + sym_off + (uint64_t)plane * plane_stride(pp * pn);
     __syncthreads();
-    const uint32_t M = P.seg_M[s];
-    const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride(P.p * P.n);
-    const uint32_t czr = P.czr, wz = P.wz, Bb = (1u << wz) - 1u;
+    const uint32_t Bb = (1u << wz) - 1u;
     const uint32_t lz = s_len[czr];
     // a multiple of 4 symbols per thread, <= kPackPT for M <= 6144: the
     // thread's symbols are whole aligned words of the plane (its stride is
