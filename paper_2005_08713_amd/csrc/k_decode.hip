@@ -924,15 +924,32 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
 }
 
 // ------------------------------------------------------------------ reassembly
+// 16x16 bit-matrix transpose: bit j of r[i] moves to bit i of r[j] (rows of
+// 16 bits in the low halves), by the recursive block transpose (blocks of 8,
+// 4, 2 and 1 bits swapped between rows i and i + s).
+__device__ inline void transpose16(uint32_t (&r)[16])
+{
+#pragma unroll
+    for (int s = 8, k = 0; s >= 1; s >>= 1, k++) {
+        const uint32_t m = k == 0 ? 0x00ffu : (k == 1 ? 0x0f0fu : (k == 2 ? 0x3333u : 0x5555u));
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            if (i & s) continue;
+            const uint32_t x = ((r[i] >> s) ^ r[i + s]) & m;
+            r[i + s] ^= x;
+            r[i] ^= x << s;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__restrict__ plan,
                                                     uint8_t *__restrict__ ws,
                                                     const int32_t *__restrict__ status)
 {
-    // per kept plane s of the block: its bit b and, per type t, the byte
-    // offset of the type's symbols in the plane (~0: the type skips it), so
-    // that the plane loop issues only independent symbol loads
+    // per plane b of the block and type t: the byte offset of the type's
+    // symbols in the plane (~0: not decoded for the type), so that the cell
+    // loop issues only independent symbol loads
     __shared__ uint32_t s_off[32][3];
-    __shared__ uint32_t s_bit[32];
     const uint32_t tid = threadIdx.x;
     for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
@@ -946,41 +963,43 @@ __global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__
     const uint8_t *sym = ws + B.sym_off;
     const uint32_t pstr = plane_stride(p * n);
     __syncthreads();  // the previous block's table has been read
+    if (tid < 96) (&s_off[0][0])[tid] = ~0u;
+    __syncthreads();
     if (tid < nseg) {
         const uint32_t b = P.seg_plane[tid];
         uint32_t pm = 0;
         for (uint32_t u = 0; u < p; u++) pm |= (((P.masks[u] >> b) & 1u) ^ 1u) << u;
-        s_bit[tid] = b;
         for (uint32_t u = 0; u < 3; u++)
-            s_off[tid][u] = ((pm >> u) & 1u) ? b * pstr + (uint32_t)__popc(pm & ((1u << u) - 1u)) * n : ~0u;
+            s_off[b][u] = ((pm >> u) & 1u) ? b * pstr + (uint32_t)__popc(pm & ((1u << u) - 1u)) * n : ~0u;
     }
     __syncthreads();
     for (uint32_t cell = tid; cell < p * cpt; cell += blockDim.x) {
         const uint32_t t = cell / cpt, ci = cell % cpt;
+        // the 16 low magnitude planes and the sign plane (d - 1) in flight
+        // together (a plane the type skips reads plane 0 and counts as 0),
+        // then one 16x16 bit-matrix transpose turns plane words into the
+        // cell's magnitudes
         uint32_t mag[16];
 #pragma unroll
-        for (int i = 0; i < 16; i++) mag[i] = 0;
-        uint32_t sgn = 0;
-        // eight planes' loads in flight, then their bits; a type that skips
-        // a plane (and a plane past the last) reads plane 0 and contributes 0
-        for (uint32_t s0 = 0; s0 < nseg; s0 += 8) {
-            uint32_t w[8], bb[8];
+        for (int b = 0; b < 16; b++) {
+            const uint32_t o = (uint32_t)b + 1 < d ? s_off[b][t] : ~0u;
+            const uint32_t v = *(const uint16_t *)(sym + (o != ~0u ? o : 0u) + 2 * ci);
+            mag[b] = o != ~0u ? v : 0u;
+        }
+        uint32_t sgn;
+        {
+            const uint32_t o = d ? s_off[d - 1][t] : ~0u;
+            const uint32_t v = *(const uint16_t *)(sym + (o != ~0u ? o : 0u) + 2 * ci);
+            sgn = o != ~0u ? v : 0u;
+        }
+        transpose16(mag);
+        // magnitude planes 16 .. d-2 (samples deeper than 16 bits)
+        for (uint32_t b = 16; b + 1 < d; b++) {
+            const uint32_t o = s_off[b][t];
+            if (o == ~0u) continue;
+            const uint32_t v = *(const uint16_t *)(sym + o + 2 * ci);
 #pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const uint32_t s = s0 + k;
-                const uint32_t o = s < nseg ? s_off[s][t] : ~0u;
-                bb[k] = s < nseg && o != ~0u ? s_bit[s] : 32u;
-                w[k] = *(const uint16_t *)(sym + (o != ~0u ? o : 0u) + 2 * ci);
-            }
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const bool sign_plane = bb[k] == d - 1;
-                const uint32_t v = (sign_plane || bb[k] >= 32u) ? 0u : w[k];
-                sgn = sign_plane ? w[k] : sgn;
-                const uint32_t sh = bb[k] & 31u;
-#pragma unroll
-                for (int i = 0; i < 16; i++) mag[i] |= ((v >> i) & 1u) << sh;
-            }
+            for (int i = 0; i < 16; i++) mag[i] |= ((v >> i) & 1u) << b;
         }
         if (B.drop) {  // midpoint of the dropped magnitude bits
             const uint32_t half = 1u << (B.drop - 1);

@@ -122,6 +122,24 @@ constexpr int kCellsPT = 3;  // 3 cells per thread: 1024 threads cover a 128x128
 // each class, large ones first.
 constexpr int kPG = 4;  // phase B: planes per group (one set of barriers per group)
 
+// 16x16 bit-matrix transpose: bit j of r[i] moves to bit i of r[j] (rows of
+// 16 bits in the low halves).  Four rounds swap blocks of 8, 4, 2 and 1 bits
+// between rows i and i + s (the recursive block transpose).
+__device__ inline void transpose16(uint32_t (&r)[16])
+{
+#pragma unroll
+    for (int s = 8, k = 0; s >= 1; s >>= 1, k++) {
+        const uint32_t m = k == 0 ? 0x00ffu : (k == 1 ? 0x0f0fu : (k == 2 ? 0x3333u : 0x5555u));
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            if (i & s) continue;
+            const uint32_t x = ((r[i] >> s) ^ r[i + s]) & m;
+            r[i + s] ^= x;
+            r[i] ^= x << s;
+        }
+    }
+}
+
 template <int kSymNT>
 __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint8_t *__restrict__ plan,
                                                         uint8_t *__restrict__ ws, uint32_t list0,
@@ -200,18 +218,27 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
                 sgn |= (v[cc] < 0 ? 1u : 0u) << (rr * 4 + cc);
             }
         }
-        for (int b = (int)d - 1; b >= 0; b--) {
+        auto put_plane = [&](int b, uint32_t v) {
             const uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
-            if (!((pm >> t) & 1u)) continue;
-            uint32_t v = 0;
-            if ((uint32_t)b == d - 1) v = sgn;
-            else {
-#pragma unroll
-                for (int i = 0; i < 16; i++) v |= ((mag[i] >> b) & 1u) << i;
-            }
+            if (!((pm >> t) & 1u)) return;
             const uint32_t rank = __popc(pm & ((1u << t) - 1u));
             *(uint16_t *)(symb + (uint64_t)b * pstr + rank * n + 2 * ci) = (uint16_t)v;
+        };
+        put_plane((int)d - 1, sgn);
+        // magnitude planes 16 .. d-2 (samples deeper than 16 bits): bit gathers
+        for (int b = (int)d - 2; b >= 16; b--) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int i = 0; i < 16; i++) v |= ((mag[i] >> b) & 1u) << i;
+            put_plane(b, v);
         }
+        // planes 0 .. 15: one 16x16 bit-matrix transpose of the low halves
+#pragma unroll
+        for (int i = 0; i < 16; i++) mag[i] &= 0xffffu;
+        transpose16(mag);
+#pragma unroll
+        for (int b = 0; b < 16; b++)
+            if (b + 1 < (int)d) put_plane(b, mag[b]);
     }
     // phase B reads the planes back with a thread-contiguous cell layout
     uint32_t ctype[kCellsPT], cci[kCellsPT];
