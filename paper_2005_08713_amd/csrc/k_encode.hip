@@ -280,8 +280,26 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
 #pragma unroll
         for (int g = 1; g < kPG; g++)
             if (tid == (uint32_t)g) s_gb[par][g] = gb[g];
-        // pass 1: symbols of own cells, histograms, zero counts, and the
-        // wave-level scan of the last non-zero position
+        // the group's symbols of the thread's cells, all loads in flight at
+        // once (a cell the plane skips reads the plane start and is masked
+        // out); both passes use them
+        uint32_t sy[kPG][kCellsPT];
+#pragma unroll
+        for (int g = 0; g < kPG; g++) {
+            const uint32_t b = gb[g];
+            const uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
+            const uint8_t *segp = symb + (uint64_t)b * pstr;
+#pragma unroll
+            for (int k = 0; k < kCellsPT; k++) {
+                const uint32_t t = ctype[k];
+                const bool in = (uint32_t)g < gn && t <= 2 && ((pm >> t) & 1u);
+                const uint32_t ps = in ? __popc(pm & ((1u << t) - 1u)) * n + 2 * cci[k] : 0u;
+                const uint32_t v = *(const uint16_t *)(segp + ps);
+                sy[g][k] = in ? (0x10000u | v) : 0u;
+            }
+        }
+        // pass 1: histograms, zero counts, and the wave-level scan of the
+        // last non-zero position
         int32_t ex[kPG];
 #pragma unroll
         for (int g = 0; g < kPG; g++) {
@@ -289,16 +307,14 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
             if ((uint32_t)g >= gn) continue;
             const uint32_t b = gb[g];
             const uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
-            const uint8_t *segp = symb + (uint64_t)b * pstr;
             int32_t lastnz = -1;
             uint32_t zeros = 0;
 #pragma unroll
             for (int k = 0; k < kCellsPT; k++) {
+                if (!(sy[g][k] >> 16)) continue;
                 const uint32_t t = ctype[k];
-                if (t > 2 || !((pm >> t) & 1u)) continue;
                 const uint32_t ps = __popc(pm & ((1u << t) - 1u)) * n + 2 * cci[k];
-                const uint32_t v = *(const uint16_t *)(segp + ps);
-                const uint32_t top = v & 0xffu, bot = v >> 8;
+                const uint32_t top = sy[g][k] & 0xffu, bot = (sy[g][k] >> 8) & 0xffu;
                 if (top) { atomicAdd(&hist[par][g][top], 1u); lastnz = (int32_t)ps; } else zeros++;
                 if (bot) { atomicAdd(&hist[par][g][bot], 1u); lastnz = (int32_t)ps + 1; } else zeros++;
             }
@@ -332,26 +348,17 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
             const uint32_t b = gb[g];
             const uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
             const uint32_t M = n * __popc(pm);
-            const uint8_t *segp = symb + (uint64_t)b * pstr;
-            uint32_t sy[kCellsPT];  // own symbols again (cache hits)
-#pragma unroll
-            for (int k = 0; k < kCellsPT; k++) {
-                const uint32_t t = ctype[k];
-                sy[k] = (t <= 2 && ((pm >> t) & 1u))
-                            ? (0x10000u | *(const uint16_t *)(segp + __popc(pm & ((1u << t) - 1u)) * n + 2 * cci[k]))
-                            : 0u;
-            }
             int32_t cur = ex[g];
             for (uint32_t w = 0; w < wave; w++) cur = max(cur, wmax[g][w]);
             uint32_t rz = 0, rn = 0;
 #pragma unroll
             for (int k = 0; k < kCellsPT; k++) {
-                if (!(sy[k] >> 16)) continue;
+                if (!(sy[g][k] >> 16)) continue;
                 const uint32_t t = ctype[k];
                 const uint32_t ps0 = __popc(pm & ((1u << t) - 1u)) * n + 2 * cci[k];
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
-                    const uint32_t sv = h ? ((sy[k] >> 8) & 0xffu) : (sy[k] & 0xffu);
+                    const uint32_t sv = h ? ((sy[g][k] >> 8) & 0xffu) : (sy[g][k] & 0xffu);
                     const int32_t ps = (int32_t)ps0 + h;
                     const bool endseg = (uint32_t)ps == M - 1;
                     if (sv || endseg) {
