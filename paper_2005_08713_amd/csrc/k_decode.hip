@@ -52,12 +52,13 @@ __device__ inline uint64_t dblock_excl_sum(uint64_t v, uint64_t *sh, uint64_t *t
     return base + x - v;
 }
 
-__global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__restrict__ plan,
-                                                  const uint8_t *__restrict__ enc,
-                                                  uint8_t *__restrict__ ws,
-                                                  int32_t *__restrict__ status)
+template <int NT>  // 256, or 1024 for tiles of many blocks
+__global__ void __launch_bounds__(NT) k_dec_prep(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                 const uint8_t *__restrict__ enc,
+                                                 uint8_t *__restrict__ ws,
+                                                 int32_t *__restrict__ status)
 {
-    __shared__ uint64_t sh[8];
+    __shared__ uint64_t sh[NT / 64];
     __shared__ int32_t s_st;
     const uint32_t job = blockIdx.x;
     const TileGeo &T = ((const TileGeo *)(plan + H.tiles_off))[job];
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
     const uint64_t table_end = 24 + 4ull * T.nblocks_stream;
     uint64_t carry = table_end, scarry = 0;
     uint32_t bad = 0;
-    for (uint32_t b0 = 0; b0 < T.nblocks; b0 += 256) {
+    for (uint32_t b0 = 0; b0 < T.nblocks; b0 += NT) {
         const uint32_t i = b0 + threadIdx.x;
         const uint32_t local = (sel && i < T.nblocks) ? sel[i].local : i;
         BlockDesc B;
@@ -109,8 +110,8 @@ __global__ void __launch_bounds__(256) k_dec_prep(PlanHdr H, const uint8_t *__re
             }
         }
         uint64_t tot, stot;
-        uint64_t ex = sel ? 0 : dblock_excl_sum<256>(sz, sh, &tot);
-        uint64_t sex = dblock_excl_sum<256>(ssz, sh, &stot);
+        uint64_t ex = sel ? 0 : dblock_excl_sum<NT>(sz, sh, &tot);
+        uint64_t sex = dblock_excl_sum<NT>(ssz, sh, &stot);
         if (i < T.nblocks) {
             uint64_t off = sel ? sel[i].off : carry + ex;
             bool ok = sz > 0 && off >= table_end && off + sz <= avail;
@@ -1045,7 +1046,12 @@ hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
 {
     for (int st = first; st <= last; st++) {
         if (st == DEC_PREP) {
-            hipLaunchKernelGGL(k_dec_prep, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_encoded, d_ws, d_status);
+            if (H.max_nblocks > 512)
+                hipLaunchKernelGGL(k_dec_prep<1024>, dim3(H.n_tiles), dim3(1024), 0, stream, H, d_plan, d_encoded, d_ws,
+                                   d_status);
+            else
+                hipLaunchKernelGGL(k_dec_prep<256>, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_encoded, d_ws,
+                                   d_status);
         } else if (st == DEC_HDR) {
             if (H.total_blocks)
                 hipLaunchKernelGGL(k_dec_header, dim3(H.total_blocks), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);

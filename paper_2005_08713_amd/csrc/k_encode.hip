@@ -81,15 +81,16 @@ __device__ inline uint32_t bij_digits(uint32_t L, uint32_t B)
 
 // ---------------------------------------------------------------- prep
 // Per tile: block descriptors, symbol-area offsets, zeroed accumulators.
-__global__ void __launch_bounds__(256) k_prep_blocks(PlanHdr H, const uint8_t *__restrict__ plan,
-                                                     uint8_t *__restrict__ ws)
+template <int NT>  // 256, or 1024 for tiles of many blocks
+__global__ void __launch_bounds__(NT) k_prep_blocks(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                    uint8_t *__restrict__ ws)
 {
-    __shared__ uint64_t sh[8];
+    __shared__ uint64_t sh[NT / 64 + 1];
     const TileGeo &T = ((const TileGeo *)(plan + H.tiles_off))[blockIdx.x];
     BlockDesc *descs = (BlockDesc *)(ws + H.ws_blockdesc);
     BlkAcc *acc = (BlkAcc *)(ws + H.ws_acc);
     uint64_t carry = 0;
-    for (uint32_t base = 0; base < T.nblocks; base += 256) {
+    for (uint32_t base = 0; base < T.nblocks; base += NT) {
         uint32_t local = base + threadIdx.x;
         BlockDesc B;
         uint64_t sz = 0;
@@ -98,7 +99,7 @@ __global__ void __launch_bounds__(256) k_prep_blocks(PlanHdr H, const uint8_t *_
             sz = block_sym_bytes(B, T.dmax);
         }
         uint64_t tot;
-        uint64_t ex = block_excl_sum_u64<256>(sz, sh, &tot);
+        uint64_t ex = block_excl_sum_u64<NT>(sz, sh, &tot);
         if (local < T.nblocks) {
             B.tile = blockIdx.x;
             B.sym_off = T.sym_base + carry + ex;
@@ -1201,7 +1202,10 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
 {
     for (int st = first; st <= last; st++) {
         if (st == ENC_PREP) {
-            hipLaunchKernelGGL(k_prep_blocks, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
+            if (H.max_nblocks > 512)
+                hipLaunchKernelGGL(k_prep_blocks<1024>, dim3(H.n_tiles), dim3(1024), 0, stream, H, d_plan, d_ws);
+            else
+                hipLaunchKernelGGL(k_prep_blocks<256>, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
         } else if (st >= ENC_FWD0 && st <= ENC_FWD0 + kMaxLevels) {
             hipError_t e = launch_forward_level(H, d_plan, d_pixels, d_ws, st - ENC_FWD0, stream);
             if (e != hipSuccess) return e;
