@@ -208,7 +208,9 @@ def main():
         raise SystemExit("decoded pixels changed between runs")
     px = W * H
     raw = px * C
-    # algorithmic bytes per launch of the dominant kernel (both images):
+    # algorithmic bytes per launch of the dominant kernel, both images: what it
+    # must read and write once (stream bytes S, symbol-plane bytes Y, pixels
+    # N*C at one byte, int32 coefficients 4*N*C)
     s_tot = float(sum(stream_bytes.values()))
     sym_tot = float(sum(stream_symbol_count(streams[q]) for q in modes))
     nm = len(modes)

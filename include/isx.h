@@ -38,7 +38,7 @@ extern "C" {
 #define ISX_E_CAPACITY (-2)      /* (device status) output arena too small for a tile   */
 #define ISX_E_CORRUPT (-3)       /* (device status) malformed encoded stream            */
 #define ISX_E_TRUNCATED (-4)     /* (device status) encoded stream shorter than needed  */
-#define ISX_E_UNSUPPORTED (-5)   /* parameters outside what this build implements       */
+#define ISX_E_UNSUPPORTED (-5)   /* parameters outside what the library implements      */
 #define ISX_E_WORKSPACE (-6)     /* workspace smaller than the *_workspace_bytes figure */
 #define ISX_E_HIP (-7)           /* a HIP runtime call failed                           */
 #define ISX_E_PENDING 1          /* (device status) initial value before completion     */
