@@ -372,28 +372,36 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         // of Aq, Lq (q = j / 64)
         uint32_t A0 = 0, A1 = 0, A2 = 0, A3 = 0, L0 = 0, L1 = 0, L2 = 0, L3 = 0;
         uint32_t A = 0, base = 0;
-        bool done = false;
+        // branch-free per leaf: `live` ends at the leaf that closes the tree
+        // (a lone leaf of depth 0, or the carry out of the rightmost leaf) or
+        // at a violation; a leaf after that changes only its own output
+        // lane, which nobody reads (leaves past m)
+        uint32_t live = 1u, bad = 0u, done = 0u;
         auto walk = [&](uint32_t Rq, uint32_t &Aq, uint32_t &Lq) {
+#pragma unroll 16
             for (uint32_t ln = 0; ln < 64; ln++) {
                 const uint32_t v = __builtin_amdgcn_readlane(Rq, ln);
                 const uint32_t d = base + (v & 63u);
-                if ((v >> 31) || ((v >> 14) & 1u) || d > 32) { err = D_CORRUPT; return; }
+                const uint32_t fail = (v >> 31) | ((v >> 14) & 1u) | (d > 32u ? 1u : 0u);
+                bad |= live & fail;
+                live &= fail ^ 1u;
                 const bool mine = lane == ln;
                 Aq = mine ? A : Aq;
                 Lq = mine ? (d | (((v >> 6) & 255u) << 8)) : Lq;
-                m++;
-                if (d == 0) { done = true; return; }  // a lone leaf is the whole tree
-                const uint32_t An = A + (1u << (32 - d));
-                if (An < A) { done = true; return; }  // carry out: the rightmost leaf closes the tree
-                A = An;
-                base = 32 - (uint32_t)__builtin_ctz(A);
+                m += live;
+                const uint32_t An = A + (d ? 1u << ((32u - d) & 31u) : 0u);
+                const uint32_t stop = (d == 0u ? 1u : 0u) | (An < A ? 1u : 0u);
+                done |= live & stop;
+                live &= stop ^ 1u;
+                A = live ? An : A;
+                base = (live && A) ? 32u - (uint32_t)__builtin_ctz(A) : base;
             }
         };
         walk(R0, A0, L0);
-        if (!done && !err) walk(R1, A1, L1);
-        if (!done && !err) walk(R2, A2, L2);
-        if (!done && !err) walk(R3, A3, L3);
-        if (!done && !err) err = D_CORRUPT;  // 256 leaves and open: a symbol repeats
+        if (live) walk(R1, A1, L1);
+        if (live) walk(R2, A2, L2);
+        if (live) walk(R3, A3, L3);
+        if (bad || !done) err = D_CORRUPT;  // a violation, or 256 leaves and open: a symbol repeats
         uint32_t tend = t0;
         if (!err) {
             const uint32_t q = (m - 1) >> 6, ln = (m - 1) & 63u;
