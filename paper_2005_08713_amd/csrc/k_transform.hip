@@ -734,7 +734,7 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
                                                     uint8_t *__restrict__ ws, int level)
 {
     using namespace strips;
-    __shared__ int32_t win[WN * WP];
+    __shared__ __align__(16) int32_t win[WN * WP];
     __shared__ int32_t rmap[WN], cmap[WN];
     const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
     const WorkItem *items = (const WorkItem *)(plan + H.work_off);
@@ -862,11 +862,7 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
         llpitch = T.tmp_pitch[which];
     }
     const int qx = qx0 + (lane >> 1);
-    int32_t *pe = odd ? wsi + G.off[1] + (uint64_t)c * T.chan_elems : llout;   // HL | LL
-    int32_t *po = wsi + G.off[odd ? 2 : 0] + (uint64_t)c * T.chan_elems;     // HH | LH
-    const uint32_t pitch_e = odd ? G.pitch[1] : llpitch, pitch_o = G.pitch[odd ? 2 : 0];
     const bool xin = qx < (odd ? hw : llw);
-    pe += qx; po += qx;
     const uint32_t step = T.qstep, qmul = T.qmul, qsh = T.qsh;
     uint32_t or_e = 0, or_o = 0, negs = 0;
     const int qyb = qy0 + 8 * wv;
@@ -877,17 +873,46 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
         if (j & 1) {
             if (step > 1) v = quantise(v, qmul, qsh);
             if (xin && qy < hh) {
-                po[(uint64_t)qy * pitch_o] = v;
                 or_o |= v < 0 ? 0u - (uint32_t)v : (uint32_t)v;
                 negs |= v < 0 ? 2u : 0u;
             }
         } else {
             if (step > 1 && odd) v = quantise(v, qmul, qsh);
             if (xin && qy < llh) {
-                pe[(uint64_t)qy * pitch_e] = v;
                 or_e |= v < 0 ? 0u - (uint32_t)v : (uint32_t)v;
                 negs |= v < 0 ? 1u : 0u;
             }
+        }
+        o[j] = v;
+    }
+    // the four 32x32 bands of the tile go through LDS (the window is free
+    // once every column pass has read it) and out in 16-byte pieces: a wave
+    // stores eight whole band rows per instruction
+    constexpr int BP = 36, BS = 32 * BP + 4;  // row and band pitch of the staging (16-byte rows)
+    __syncthreads();
+    {
+        int32_t *stg = win + (odd ? BS : 0) + (lane >> 1);  // LL | HL, then + 2 BS: LH | HH
+#pragma unroll
+        for (int j = 0; j < 16; j++) stg[((j & 1) ? 2 * BS : 0) + (8 * wv + (j >> 1)) * BP] = o[j];
+    }
+    __syncthreads();
+    {
+        int32_t *const bptr[4] = {llout, wsi + G.off[1] + (uint64_t)c * T.chan_elems,
+                                  wsi + G.off[0] + (uint64_t)c * T.chan_elems,
+                                  wsi + G.off[2] + (uint64_t)c * T.chan_elems};
+        const uint32_t bpitch[4] = {llpitch, G.pitch[1], G.pitch[0], G.pitch[2]};
+        const int bw[4] = {llw, hw, llw, hw}, bh[4] = {llh, llh, hh, hh};
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int b = k;  // band of this pass: thread t stores row t >> 3, piece t & 7
+            const int row = (int)threadIdx.x >> 3, part = (int)threadIdx.x & 7;
+            const int qy = qy0 + row, qxs = qx0 + 4 * part;
+            if (qy >= bh[b] || qxs >= bw[b]) continue;
+            const int32_t *src = win + b * BS + row * BP + 4 * part;
+            int32_t *dst = bptr[b] + (uint64_t)qy * bpitch[b] + qxs;
+            if (qxs + 3 < bw[b]) *(int4 *)dst = *(const int4 *)src;
+            else
+                for (int e = 0; e < 4 && qxs + e < bw[b]; e++) dst[e] = src[e];
         }
     }
     // per-block accumulation over the lanes of one column parity (the whole
