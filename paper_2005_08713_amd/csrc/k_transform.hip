@@ -1054,7 +1054,7 @@ __global__ void __launch_bounds__(256) k_inv_level_strips(PlanHdr H, const uint8
                                                           uint8_t *__restrict__ ws, int level)
 {
     using namespace strips;
-    __shared__ int32_t win[WN * WP];
+    __shared__ __align__(16) int32_t win[WN * WP];
     __shared__ int32_t rmap[WN], cmap[WN];
     const TileGeo *tiles = (const TileGeo *)(plan + H.tiles_off);
     const WorkItem *items = (const WorkItem *)(plan + H.work_off);
@@ -1079,23 +1079,44 @@ __global__ void __launch_bounds__(256) k_inv_level_strips(PlanHdr H, const uint8
     }
     __syncthreads();
     inv_strips_rows(win, lane, wv, G.h > 1, G.w > 1, o);
+    // the 64x64 outputs go through LDS (rows of 68 words, 16-byte aligned)
+    constexpr int OP = 68;
     __syncthreads();
-    int32_t *rowp = win + (2 + lane) * WP + 2 + 16 * wv;
+    {
+        int32_t *rowp = win + lane * OP + 16 * wv;
 #pragma unroll
-    for (int j = 0; j < 16; j++) rowp[j] = o[j];
+        for (int j = 0; j < 16; j++) rowp[j] = o[j];
+    }
     __syncthreads();
     // LL_{level-1} is the low band of level-1: store the part inside that
-    // level's window, a lane per column, a wave per fourth row
+    // level's window; 16-byte pieces (a wave stores four whole rows) when the
+    // tile's columns are 4-aligned in it, else a lane per column
     const int k = level - 1, which = (k & 1) ? 0 : 1;
     const LevelGeo &D = T.lv[k];
     int32_t *dst = wsi + T.tmp_off[which] + (uint64_t)c * T.tmp_chan[which];
     const uint32_t dp = T.tmp_pitch[which];
-    const int x = 2 * qx0 + lane - (int)D.wx0;
+    const int xb = 2 * qx0 - (int)D.wx0, yb = 2 * qy0 - (int)D.wy0;
+    if (((xb | (int)dp) & 3) == 0) {
 #pragma unroll
-    for (int m = 0; m < 16; m++) {
-        const int ly = wv + 4 * m;
-        const int y = 2 * qy0 + ly - (int)D.wy0;
-        if ((uint32_t)x < D.ww && (uint32_t)y < D.wh) dst[(uint64_t)y * dp + x] = win[(2 + ly) * WP + 2 + lane];
+        for (int m = 0; m < 4; m++) {
+            const int ch = (int)threadIdx.x + 256 * m, row = ch >> 4, part = ch & 15;
+            const int y = yb + row, x = xb + 4 * part;
+            if ((uint32_t)y >= D.wh) continue;
+            const int32_t *src = win + row * OP + 4 * part;
+            int32_t *d = dst + (uint64_t)y * dp;
+            if (x >= 0 && x + 3 < (int)D.ww) *(int4 *)(d + x) = *(const int4 *)src;
+            else
+                for (int e = 0; e < 4; e++)
+                    if ((uint32_t)(x + e) < D.ww) d[x + e] = src[e];
+        }
+    } else {
+        const int x = xb + lane;
+#pragma unroll
+        for (int m = 0; m < 16; m++) {
+            const int ly = wv + 4 * m;
+            const int y = yb + ly;
+            if ((uint32_t)x < D.ww && (uint32_t)y < D.wh) dst[(uint64_t)y * dp + x] = win[ly * OP + lane];
+        }
     }
 }
 
