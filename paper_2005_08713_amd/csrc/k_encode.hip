@@ -657,7 +657,6 @@ __device__ void canonical(const uint8_t *len, uint32_t *code, uint8_t *order, ui
 struct CodeShared {
     uint16_t sh_hist[kMaxPlanes][256];
     uint32_t f[256];
-    uint32_t lit[256];
     uint8_t len[256];
     uint32_t code[256];
     uint8_t order[256];
@@ -667,7 +666,7 @@ struct CodeShared {
     uint64_t red[4];
     uint32_t plane[32];             // kept planes, segment order
     uint32_t zir[32];               // per segment: zeros inside runs
-    uint32_t dig[32][kNumWz];       // per segment: run digits per counter width
+    uint16_t dig[32][kNumWz];       // per segment: run digits per counter width (< 8 * 3073)
     HuffScratch hs;
 };
 
@@ -690,7 +689,11 @@ __device__ void seg_lengths(CodeShared &C, uint32_t nseg, uint32_t czr, uint32_t
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict__ ws)
+// five workgroups per CU (at most 96 VGPRs and 31.25 KB of LDS, as LDS is
+// allocated in 1280-byte units): a batch of two 4096x4096 RGB images has
+// 2052 blocks, which then take two rounds of the 256 CUs instead of three
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_enc_code(PlanHdr H,
+                                                                                         uint8_t *__restrict__ ws)
 {
     __shared__ CodeShared C;
     __shared__ PMScratch Q;
@@ -720,7 +723,7 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
         const uint32_t sg = i / (kNumWz + 1), k = i % (kNumWz + 1);
         const SegStat &st = segstat[slot + C.plane[sg]];
         if (k == kNumWz) C.zir[sg] = st.zir;
-        else C.dig[sg][k] = st.dig[k];
+        else C.dig[sg][k] = (uint16_t)st.dig[k];
     }
     // per-segment histograms into LDS, block histogram
     uint32_t h = 0;
@@ -742,7 +745,6 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
     for (int i = 1; i < 4; i++) kmin = C.red[i] < kmin ? C.red[i] : kmin;
     const uint32_t czr = (uint32_t)(kmin & 0xff);
     uint32_t lit = h - (v == 0 ? Z : 0u);
-    C.lit[v] = lit;
     C.f[v] = lit + (v == czr ? S.nruns : 0u);
     __syncthreads();
     // provisional code (each run one C_zr token) -> l
@@ -771,7 +773,7 @@ __global__ void __launch_bounds__(256) k_enc_code(PlanHdr H, uint8_t *__restrict
     }
     __syncthreads();
     const uint32_t wz = C.scal[1];
-    C.f[v] = C.lit[v] + (v == czr ? C.scal[2] : 0u);
+    C.f[v] = lit + (v == czr ? C.scal[2] : 0u);
     __syncthreads();
     huff_lengths(C.f, C.len, C.hs);
     seg_lengths(C, nseg, czr, wz);
