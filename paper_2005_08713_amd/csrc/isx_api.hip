@@ -301,6 +301,7 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         if (total_blocks > 0x7fffffffull || total_slots > 0x7fffffffull) return ISX_E_UNSUPPORTED;
         if (T.levels > H.max_levels) H.max_levels = T.levels;
         if (T.nblocks > H.max_nblocks) H.max_nblocks = T.nblocks;
+        if (T.dmax > H.max_dmax) H.max_dmax = T.dmax;
     }
     if (mode == MODE_DECODE && total_blocks >= (1ull << 27)) return ISX_E_UNSUPPORTED;  // segment item = block << 5 | segment
     H.total_blocks = (uint32_t)total_blocks;

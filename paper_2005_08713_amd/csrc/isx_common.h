@@ -83,7 +83,7 @@ struct SelBlock {          // a block of a region decode: stream index, bytes
 
 struct PlanHdr {
     uint32_t magic, mode, n_tiles, total_blocks;
-    uint32_t total_slots, max_levels, max_nblocks, pad0;
+    uint32_t total_slots, max_levels, max_nblocks, max_dmax;  // max_dmax: largest plane bound of any tile
     uint64_t plan_bytes;
     uint64_t ws_bytes;
     // workspace regions (byte offsets from ws base)

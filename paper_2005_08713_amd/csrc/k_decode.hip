@@ -659,6 +659,33 @@ __device__ inline void xf_push(RunXf &f, bool dig, uint32_t c, uint32_t wz)
     f.lit = dig ? f.lit : 1u;
 }
 
+// Tokens from r up to the first token start at or after lim, appended to f.
+// Once f holds a literal only mid and V1 change (a digit extends the pending
+// run, a symbol closes it), so the rest of the range takes a shorter update.
+template <class Src>
+__device__ inline uint32_t run_tokens(const Src &S, const DecTab &T, uint32_t r, uint32_t lim, RunXf &f)
+{
+    const uint32_t czr = T.czr, wz = T.wz;
+    while (r < lim && !f.lit) {
+        uint32_t c, adv;
+        const uint32_t v = dec_token(S, T, r, c, adv);
+        r += adv;
+        xf_push(f, v == czr && c, c, wz);
+    }
+    uint32_t mid = f.mid, V1 = f.V1;
+    while (r < lim) {
+        uint32_t c, adv;
+        const uint32_t v = dec_token(S, T, r, c, adv);
+        r += adv;
+        const bool dig = v == czr && c;
+        mid = dig ? mid : min(mid + V1 + 1u, kSat);
+        V1 = dig ? run_push(V1, c, wz) : 0u;
+    }
+    f.mid = mid;
+    f.V1 = V1;
+    return r;
+}
+
 // Phase-1 bits before the first and the second resynchronisation point.
 constexpr uint32_t kSyncWin = 128, kSyncWin2 = 384;
 
@@ -687,34 +714,11 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
     const uint32_t ce = active ? (cs + chunk < N ? cs + chunk : N) : cs;
     // phase 1
     RunXf fpre = xf_id(), G1 = xf_id(), G2 = xf_id();
-    uint32_t r = cs;
-    {
-        const uint32_t l1 = (cs + kSyncWin < ce) ? cs + kSyncWin : ce;
-        while (r < l1) {
-            uint32_t c, adv;
-            const uint32_t v = dec_token(S, T, r, c, adv);
-            r += adv;
-            xf_push(fpre, v == czr && c, c, wz);
-        }
-    }
-    const uint32_t sw1 = r;
-    {
-        const uint32_t l2 = (cs + kSyncWin2 < ce) ? cs + kSyncWin2 : ce;
-        while (r < l2) {
-            uint32_t c, adv;
-            const uint32_t v = dec_token(S, T, r, c, adv);
-            r += adv;
-            xf_push(G1, v == czr && c, c, wz);
-        }
-    }
-    const uint32_t sw2 = r;
-    while (r < ce) {
-        uint32_t c, adv;
-        const uint32_t v = dec_token(S, T, r, c, adv);
-        r += adv;
-        xf_push(G2, v == czr && c, c, wz);
-    }
-    const uint32_t exit1 = r;
+    const uint32_t l1 = (cs + kSyncWin < ce) ? cs + kSyncWin : ce;
+    const uint32_t sw1 = run_tokens(S, T, cs, l1, fpre);
+    const uint32_t l2 = (cs + kSyncWin2 < ce) ? cs + kSyncWin2 : ce;
+    const uint32_t sw2 = run_tokens(S, T, sw1, l2, G1);
+    const uint32_t exit1 = run_tokens(S, T, sw2, ce, G2);
     const RunXf G12 = xf_combine(G1, G2);
     RunXf f = xf_combine(fpre, G12);
     uint32_t start = cs, exitc = exit1;
@@ -727,33 +731,17 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
         if (chg) {
             start = want;
             RunXf Pm = xf_id();
-            uint32_t q = want;
-            while (q < sw1 && q < ce) {
-                uint32_t c, adv;
-                const uint32_t v = dec_token(S, T, q, c, adv);
-                q += adv;
-                xf_push(Pm, v == czr && c, c, wz);
-            }
+            uint32_t q = run_tokens(S, T, want, min(sw1, ce), Pm);
             if (q == sw1) {
                 f = xf_combine(Pm, G12);
                 exitc = exit1;
             } else {
-                while (q < sw2 && q < ce) {
-                    uint32_t c, adv;
-                    const uint32_t v = dec_token(S, T, q, c, adv);
-                    q += adv;
-                    xf_push(Pm, v == czr && c, c, wz);
-                }
+                q = run_tokens(S, T, q, min(sw2, ce), Pm);
                 if (q == sw2) {
                     f = xf_combine(Pm, G2);
                     exitc = exit1;
                 } else {
-                    while (q < ce) {
-                        uint32_t c, adv;
-                        const uint32_t v = dec_token(S, T, q, c, adv);
-                        q += adv;
-                        xf_push(Pm, v == czr && c, c, wz);
-                    }
+                    q = run_tokens(S, T, q, ce, Pm);
                     f = Pm;
                     exitc = q;
                 }

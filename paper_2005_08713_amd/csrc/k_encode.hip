@@ -999,11 +999,11 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
     const uint32_t nbits_s = P.seg_bits[s], M = P.seg_M[s], plane = P.seg_plane[s];
     const uint64_t byte_off = P.byte_off;
     const uint32_t code_t = P.code[tid & 255u], len_t = P.len[tid & 255u];
+    if (y > nseg) return;  // no such segment: leave before the tile's status is read
     const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[tile];
     const uint32_t status = O.status;
     const uint64_t toff = O.offset;
     if (status != ISX_STATUS_OK) return;
-    if (y > nseg) return;
     uint32_t *outw = (uint32_t *)out;
     const uint64_t bit0 = (toff + byte_off) * 8;
     if (y == 0) {
@@ -1172,7 +1172,7 @@ __global__ void __launch_bounds__(kPackNT) k_enc_pack_pers(PlanHdr H, const uint
                                                        uint8_t *__restrict__ out)
 {
     __shared__ PackShared S;
-    const uint64_t nitems = (uint64_t)H.total_blocks * 33;
+    const uint64_t nitems = (uint64_t)H.total_blocks * (H.max_dmax + 1);
     for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const uint32_t blk = (uint32_t)(item % H.total_blocks), y = (uint32_t)(item / H.total_blocks);
         const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
@@ -1236,7 +1236,9 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
                 if (H.blocks_per_cu)
                     hipLaunchKernelGGL(k_enc_pack_pers, dim3(H.blk_grid), dim3(kPackNT), 0, stream, H, d_ws, d_out);
                 else
-                    hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, 33), dim3(kPackNT), 0, stream, H, d_ws, d_out);
+                    // item y = 0 is the header, y = 1 .. nseg the segments; nseg <= d <= the tile's plane bound
+                    hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, H.max_dmax + 1), dim3(kPackNT), 0, stream, H,
+                                       d_ws, d_out);
             }
         }
     }
