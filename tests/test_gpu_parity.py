@@ -128,6 +128,28 @@ def test_batch_of_uneven_tiles_matches_per_tile_oracle():
         assert np.array_equal(dec[i], oracle.decode_tile(got[i], zs[i])), i
 
 
+def test_mixed_depth_batch_matches_per_tile_oracle():
+    """Tiles of 8 and 16 bits and different level counts in one plan: the
+    per-block kernels are sized by the plan's largest plane bound, which the
+    8-bit tiles do not reach."""
+    imgs = [synth.he_like(200, 150, 31),
+            synth.random_image(170, 130, 1, 16, 32, kind="uniform"),
+            synth.he_like(96, 72, 33),
+            synth.random_image(140, 90, 3, 16, 34, kind="max")]
+    levels = [3, 4, 1, 2]
+    qs = [1, 1, 4, 2]
+    print("mixed-depth batch encode", flush=True)
+    got = isx.encode_images(imgs, levels, qs)
+    for i, img in enumerate(imgs):
+        assert got[i] == oracle.encode_tile(img, levels[i], qstep=qs[i]), i
+    print("mixed-depth batch decode", flush=True)
+    dec = isx.decode_streams(got)
+    for i, img in enumerate(imgs):
+        assert np.array_equal(dec[i], oracle.decode_tile(got[i], 0)), i
+        if qs[i] == 1:
+            assert np.array_equal(dec[i].reshape(img.shape), img), i
+
+
 def test_corrupt_segments_detected_like_oracle():
     """Bit flips in seek tables and segment payloads: the GPU decoder reports
     an error exactly when the oracle does, and decodes the same pixels when
