@@ -764,10 +764,17 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
     uint32_t op, run;
     if (ex.lit) { op = sadd(ex.V0, ex.mid); run = ex.V1; }
     else { op = 0; run = ex.V0; }
-    // phase 3: write
+    // phase 3: write.  A lane's output positions only grow, so its non-zero
+    // symbols are gathered into 32-bit words of the (zeroed, 4-byte aligned)
+    // plane: a word left behind lies inside the lane's range and is stored
+    // whole; the first word written and the last may be shared with the
+    // neighbouring lanes and are ORed in.
     int32_t err = 0;
     const bool last = active && (lane == 63 || cs + chunk >= N);
     if (active) {
+        uint32_t *outw = (uint32_t *)out;
+        uint32_t wcur = ~0u, wacc = 0;
+        bool wfirst = true;
         uint32_t q = start;
         bool bad = false;
         while (q < ce) {
@@ -777,10 +784,23 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
             const bool dig = (v == czr) && c;
             const uint32_t opr = sadd(op, run);
             bad |= !dig && (run == 1 || opr >= M);
-            if (!dig && v && opr < M) out[opr] = (uint8_t)v;
+            if (!dig && v && opr < M) {
+                const uint32_t wi = opr >> 2;
+                if (wi != wcur) {
+                    if (wacc) {
+                        if (wfirst) atomicOr(&outw[wcur], wacc);
+                        else outw[wcur] = wacc;
+                    }
+                    wfirst = wcur == ~0u;
+                    wcur = wi;
+                    wacc = 0;
+                }
+                wacc |= v << (8 * (opr & 3u));
+            }
             op = dig ? op : opr + 1;
             run = dig ? run_push(run, c, wz) : 0u;
         }
+        if (wacc) atomicOr(&outw[wcur], wacc);
         if (last) {
             if (run) {
                 bad |= run < 2;
@@ -799,12 +819,12 @@ struct SegShared {
     uint32_t acode[256];
     uint8_t llen[256], lsym[256];
     uint32_t bits[kSegWords + 2];
-    uint4 stg[kMaxSeg / 16];
 };
 
 // Persistent waves taking (block, segment) items from the two lists (large
-// segments first); per item: code tables and the segment's bits to LDS, the
-// symbol plane built in LDS and copied out.
+// segments first); per item: the symbol plane zeroed in place, code tables
+// and the segment's bits to LDS, then the non-zero symbols written straight
+// to the plane (13.8 KB of LDS per wave: eleven waves per CU).
 __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
                                                      uint8_t *__restrict__ ws,
                                                      int32_t *__restrict__ status)
@@ -835,6 +855,10 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
             continue;
         }
         const uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
+        // the plane starts as zeros (16-byte aligned, its stride padded to 16
+        // bytes); the decode writes only non-zero symbols over them
+        const uint32_t M16 = (M + 15) / 16;
+        for (uint32_t i = lane; i < M16; i += 64) gout[i] = make_uint4(0, 0, 0, 0);
         __syncthreads();  // the previous item is done with S
         {
             // code tables (352 x 16 bytes): all loads of a lane first
@@ -893,13 +917,12 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
             }
             if (lane < 2) S.bits[nw + lane] = 0u;
         }
-        const uint32_t M16 = (M + 15) / 16;
-        for (uint32_t i = lane; i < M16; i += 64) S.stg[i] = make_uint4(0, 0, 0, 0);
+        __threadfence_block();  // the zero stores are complete before any symbol store
         __syncthreads();
         DecTab T;
         T.lut = S.lut; T.acode = S.acode; T.llen = S.llen; T.lsym = S.lsym;
         T.m = P.m; T.czr = P.czr; T.wz = P.wz;
-        uint8_t *out = (uint8_t *)S.stg;
+        uint8_t *out = (uint8_t *)gout;
         int32_t err = 0;
         if (T.m == 1 && S.lsym[0] != T.czr) {
             // zero-length codewords: the segment is M copies of the leaf
@@ -914,8 +937,6 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
             src.enc = enc; src.lo = lo; src.hi = hi; src.w0 = w0; src.off = off;
             err = decode_segment(src, T, N, M, out);
         }
-        __syncthreads();
-        for (uint32_t i = lane; i < M16; i += 64) gout[i] = S.stg[i];
         if (err) atomicMin(&status[B.tile], err);
     }
 }
