@@ -368,40 +368,48 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
             R0 = rec(lane); R1 = rec(64 + lane); R2 = rec(128 + lane); R3 = rec(192 + lane);
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the records are in registers
-        // the walk: leaf j's code and (length | symbol << 8) go to lane j % 64
-        // of Aq, Lq (q = j / 64)
-        uint32_t A0 = 0, A1 = 0, A2 = 0, A3 = 0, L0 = 0, L1 = 0, L2 = 0, L3 = 0;
+        // the walk: leaf j's code and depth go to lane j % 64 of Aq, Dq (q =
+        // j / 64).  The serial part carries only what the next leaf needs:
+        // its depth (the deepest open right branch, 32 - ctz of the running
+        // code, plus the leaf's 0-tokens) and the running code.  Where the
+        // tree closes (a lone leaf of depth 0, or the carry out of the
+        // rightmost leaf) and whether a leaf up to there breaks a rule is
+        // found afterwards, 64 leaves at a time; leaves after the close are
+        // computed but never read.
+        uint32_t A0 = 0, A1 = 0, A2 = 0, A3 = 0, D0 = 0, D1 = 0, D2 = 0, D3 = 0;
         uint32_t A = 0, base = 0;
-        // branch-free per leaf: `live` ends at the leaf that closes the tree
-        // (a lone leaf of depth 0, or the carry out of the rightmost leaf) or
-        // at a violation; a leaf after that changes only its own output
-        // lane, which nobody reads (leaves past m)
-        uint32_t live = 1u, bad = 0u, done = 0u;
-        auto walk = [&](uint32_t Rq, uint32_t &Aq, uint32_t &Lq) {
+        auto walk = [&](uint32_t Rq, uint32_t &Aq, uint32_t &Dq) {
 #pragma unroll 16
             for (uint32_t ln = 0; ln < 64; ln++) {
-                const uint32_t v = __builtin_amdgcn_readlane(Rq, ln);
-                const uint32_t d = base + (v & 63u);
-                const uint32_t fail = (v >> 31) | ((v >> 14) & 1u) | (d > 32u ? 1u : 0u);
-                bad |= live & fail;
-                live &= fail ^ 1u;
+                const uint32_t d = base + (__builtin_amdgcn_readlane(Rq, ln) & 63u);
                 const bool mine = lane == ln;
                 Aq = mine ? A : Aq;
-                Lq = mine ? (d | (((v >> 6) & 255u) << 8)) : Lq;
-                m += live;
-                const uint32_t An = A + (d ? 1u << ((32u - d) & 31u) : 0u);
-                const uint32_t stop = (d == 0u ? 1u : 0u) | (An < A ? 1u : 0u);
-                done |= live & stop;
-                live &= stop ^ 1u;
-                A = live ? An : A;
-                base = (live && A) ? 32u - (uint32_t)__builtin_ctz(A) : base;
+                Dq = mine ? d : Dq;
+                A += d ? 1u << ((32u - d) & 31u) : 0u;
+                base = A ? 32u - (uint32_t)__builtin_ctz(A) : base;
             }
         };
-        walk(R0, A0, L0);
-        if (live) walk(R1, A1, L1);
-        if (live) walk(R2, A2, L2);
-        if (live) walk(R3, A3, L3);
-        if (bad || !done) err = D_CORRUPT;  // a violation, or 256 leaves and open: a symbol repeats
+        // per group of 64 leaves: walk it, then look for the close; groups
+        // after the close are not walked (and not checked)
+        uint32_t close = 256u;
+        bool bad = false;
+        auto check = [&](uint32_t q, uint32_t Rv, uint32_t Av, uint32_t Dv) {
+            const uint32_t An = Av + (Dv ? 1u << ((32u - Dv) & 31u) : 0u);
+            const bool fail = (Rv >> 31) != 0u || ((Rv >> 14) & 1u) != 0u || Dv > 32u;
+            const bool stop = !fail && (Dv == 0u || An < Av);
+            const uint64_t sm = __ballot(stop), fm = __ballot(fail);
+            // leaves of this group at or before the close
+            const uint64_t upto = sm ? (2ull << __builtin_ctzll(sm)) - 1ull : ~0ull;
+            bad |= (fm & upto) != 0ull;
+            if (sm) close = 64u * q + (uint32_t)__builtin_ctzll(sm);
+        };
+        walk(R0, A0, D0);
+        check(0, R0, A0, D0);
+        if (close == 256u) { walk(R1, A1, D1); check(1, R1, A1, D1); }
+        if (close == 256u) { walk(R2, A2, D2); check(2, R2, A2, D2); }
+        if (close == 256u) { walk(R3, A3, D3); check(3, R3, A3, D3); }
+        m = close < 256u ? close + 1u : 0u;
+        if (bad || close == 256u) err = D_CORRUPT;  // a violation, or 256 leaves and open: a symbol repeats
         uint32_t tend = t0;
         if (!err) {
             const uint32_t q = (m - 1) >> 6, ln = (m - 1) & 63u;
@@ -411,11 +419,12 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
             for (uint32_t k = 0; k < 4; k++) {
                 const uint32_t j = 64 * k + lane;
                 const uint32_t Av = k == 0 ? A0 : (k == 1 ? A1 : (k == 2 ? A2 : A3));
-                const uint32_t Lv = k == 0 ? L0 : (k == 1 ? L1 : (k == 2 ? L2 : L3));
+                const uint32_t Dv = k == 0 ? D0 : (k == 1 ? D1 : (k == 2 ? D2 : D3));
+                const uint32_t Rv = k == 0 ? R0 : (k == 1 ? R1 : (k == 2 ? R2 : R3));
                 if (j < m) {
                     s_acode[j] = Av;
-                    s_len[j] = (uint8_t)(Lv & 0xffu);
-                    s_sym[j] = (uint8_t)(Lv >> 8);
+                    s_len[j] = (uint8_t)Dv;
+                    s_sym[j] = (uint8_t)((Rv >> 6) & 255u);
                 }
             }
         }
