@@ -1082,9 +1082,12 @@ hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             if (H.total_blocks)
                 hipLaunchKernelGGL(k_dec_header, dim3(H.total_blocks), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
         } else if (st == DEC_SEG) {
-            if (H.total_blocks)
-                hipLaunchKernelGGL(k_dec_segments, dim3(H.num_cus * kSegWavesPerCu), dim3(64), 0, stream, H, d_encoded,
-                                   d_ws, d_status);
+            if (H.total_blocks) {
+                // no more waves than the plan can queue segments (a block
+                // queues at most one per plane, at most its tile's plane bound)
+                const uint32_t g = std::min<uint32_t>(H.num_cus * kSegWavesPerCu, std::max<uint32_t>(H.total_slots, 1u));
+                hipLaunchKernelGGL(k_dec_segments, dim3(g), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
+            }
         } else if (st == DEC_REASM) {
             if (H.total_blocks)
                 hipLaunchKernelGGL(k_dec_reasm, dim3(H.blk_grid), dim3(1024), 0, stream, H, d_plan, d_ws, d_status);
