@@ -1164,7 +1164,9 @@ __global__ void __launch_bounds__(kPackNT) k_enc_pack(PlanHdr H, const uint8_t *
                                                   uint8_t *__restrict__ out)
 {
     __shared__ PackShared S;
-    pack_item(H, ws, out, S, blockIdx.x, blockIdx.y);
+    // the last segments (the low, dense planes) are the longest items: they
+    // are dispatched first, the headers last
+    pack_item(H, ws, out, S, blockIdx.x, gridDim.y - 1u - blockIdx.y);
 }
 
 // Persistent variant: segment-major items over a fixed grid.
