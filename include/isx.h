@@ -72,14 +72,14 @@ typedef struct {
 
 /* One decode job: reconstruct an encoded tile at resolution level
  * target_level (0 = full size; z gives the ceil(W/2^z) x ceil(H/2^z) image
- * built from the coarser blocks only: the decompression part of Sec. 5
+ * built from the coarser blocks only: the decompression part of Sec. 4
  * leaves out the high-pass blocks of the finer levels).  `tile` repeats the
  * encoded tile's parameters (the host plans the workspace from them; the
  * device checks them against the stream header and reports ISX_E_CORRUPT on
  * mismatch); tile.pixel_offset and tile.row_stride_bytes are ignored; for
  * 16- and 32-bit samples out_offset and out_row_stride_bytes must be
  * multiples of the sample size.
- * drop_bitplanes = r > 0 asks for a lower-quality decode (Sec. 5: the seek
+ * drop_bitplanes = r > 0 asks for a lower-quality decode (Sec. 4, decompression: the seek
  * table of a block lets the decoder discard its least significant planes):
  * the magnitude planes b < r of every block are skipped (not decoded, not
  * checked; the sign plane is kept), and a coefficient whose kept magnitude
@@ -186,7 +186,7 @@ int32_t isx_decode_plan_build_tuned(const isx_decode_job *h_jobs, int32_t n_jobs
 
 /* ---- region decode (whole-slide pyramids) ----------------------------------
  * A whole slide encoded as ONE tile is one non-redundant wavelet pyramid
- * (Sec. 3: the blocks of every scale are stored separately, Sec. 5: a viewer
+ * (Sec. 3: the blocks of every scale are stored separately, Sec. 4, decompression: a viewer
  * decodes only the blocks of the scale and area it shows).  A region job
  * reconstructs the rectangle [x0, x0+width) x [y0, y0+height) of the level-z
  * image (z = job.target_level) from the blocks it depends on: at each level

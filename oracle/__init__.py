@@ -64,6 +64,10 @@ def lib():
         L.oracle_lift53_forward_1d.argtypes = [P, i32, P, P]
         L.oracle_lift53_inverse_1d.restype = None
         L.oracle_lift53_inverse_1d.argtypes = [P, P, i32, P]
+        L.oracle_quantise.restype = i32
+        L.oracle_quantise.argtypes = [i32, i32]
+        L.oracle_dequantise.restype = i32
+        L.oracle_dequantise.argtypes = [i32, i32]
         L.oracle_rct_forward.restype = None
         L.oracle_rct_forward.argtypes = [i32, i32, i32, P]
         L.oracle_rct_inverse.restype = None
@@ -171,7 +175,7 @@ def decode_tile(blob: bytes, level: int = 0, drop: int = 0) -> np.ndarray:
 
 def decode_region(blob: bytes, level: int, x0: int, y0: int, w: int, h: int, drop: int = 0) -> np.ndarray:
     """Region [x0, x0+w) x [y0, y0+h) of the level-`level` image.  By
-    definition this is the crop of the whole decode at that level (Sec. 5:
+    definition this is the crop of the whole decode at that level (Sec. 4, decompression:
     a viewer shows part of one scale); no other arithmetic."""
     full = decode_tile(blob, level, drop)
     if not (0 <= x0 and 0 <= y0 and w >= 1 and h >= 1 and x0 + w <= full.shape[1] and y0 + h <= full.shape[0]):
@@ -242,6 +246,14 @@ def lift_inverse_1d(lo, hi, n):
     x = np.zeros(n, dtype=np.int32)
     lib().oracle_lift53_inverse_1d(_ptr(lo), _ptr(hi), n, _ptr(x))
     return x
+
+
+def quantise(c: int, step: int) -> int:
+    return int(lib().oracle_quantise(int(c), int(step)))
+
+
+def dequantise(q: int, step: int) -> int:
+    return int(lib().oracle_dequantise(int(q), int(step)))
 
 
 def rct_forward(r, g, b):

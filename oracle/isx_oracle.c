@@ -374,6 +374,11 @@ static int32_t dequantise(int32_t q, int32_t step)
     return (int32_t)(q < 0 ? -r : r);
 }
 
+/* The two maps above, exported for their pins (worked values and the
+ * midpoint property of the reconstruction). */
+int32_t oracle_quantise(int32_t c, int32_t step) { return quantise(c, step); }
+int32_t oracle_dequantise(int32_t q, int32_t step) { return dequantise(q, step); }
+
 /* ================================================================== */
 /* MSB-first bit writer / reader (Fig. 3 caption: fields are not byte    */
 /* aligned; Sec. 4: counters stored big-endian).                         */
@@ -980,7 +985,7 @@ static int tree_read(BitReader *r, TNode *nodes, int *nn, int depth, int *nleave
     return OR_OK;
 }
 
-/* Quality-progressive decode (Sec. 5: the seek table lets a decoder drop
+/* Quality-progressive decode (Sec. 4, decompression: the seek table lets a decoder drop
  * any number of the least significant planes of a block).  Reading: `drop`
  * = r removes the magnitude planes b < r of every block (the sign plane is
  * always kept); their segments are skipped through the seek table and not

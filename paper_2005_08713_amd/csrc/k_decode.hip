@@ -1,5 +1,5 @@
 // k_decode.hip -- decoder of the codec for gfx950: the encode pipeline run
-// backwards (Sec. 5; lower resolutions by decoding only the coarser blocks).
+// backwards (Sec. 4, decompression; lower resolutions by decoding only the coarser blocks).
 //
 //  k_dec_prep      per job: tile header and block-size table checks, block
 //                  descriptors and byte offsets (scan) of the blocks needed

@@ -16,6 +16,7 @@ import pytest
 import oracle
 from paper_2005_08713_amd import synth
 from tests import format_reader as fr
+from tests import lift_literal as lit
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -142,6 +143,95 @@ def test_one_level_2d_rows_then_columns_near_real_filters(w, h):
     assert np.abs(c["HL"][1] - hl).max() <= 1.5 * 0.5 + 1 + 1e-9
     assert np.abs(c["LH"][1] - lh).max() <= 2 * 1 + 0.5 + 1e-9
     assert np.abs(c["HH"][1] - hh).max() <= 2 * 0.5 + 0.5 + 1e-9
+
+
+def _read_dwt2_golden():
+    cases, cur = [], None
+    with open(os.path.join(GOLDEN, "dwt2_one_level.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            key, rest = line.split(None, 1)
+            if key == "case":
+                cur = {"img": [], "bands": {}}
+                cases.append(cur)
+            elif key == "row":
+                cur["img"].append([int(v) for v in rest.split()])
+            else:
+                cur["bands"][key] = [[int(v) for v in r.split()] for r in rest.split("|")]
+    return cases
+
+
+def test_one_level_2d_golden_rows_then_columns():
+    """Hand-worked bands of one level on images where the column-first order
+    differs: pins the row-then-column order of the oracle exactly."""
+    for case in _read_dwt2_golden():
+        img = np.array(case["img"], dtype=np.uint8)
+        got = oracle.forward_dump(img, 1, bits=8, ct=0)[0]
+        for nm, rows in case["bands"].items():
+            band = got[nm] if nm == "LL" else got[nm][1]
+            assert band.tolist() == rows, nm
+        assert lit.forward_2d_level(case["img"]) == case["bands"]
+        assert lit.forward_2d_level(case["img"], rows_first=False) != case["bands"]
+
+
+def _band_eq(band, rows):
+    """An oracle band (2-D array) equals a literal band (list of rows);
+    empty bands of either shape compare equal."""
+    if band.size == 0:
+        return sum(len(r) for r in rows) == 0
+    return band.tolist() == rows
+
+
+def test_literal_lifting_checker_equals_oracle_1d():
+    """The literal checker (explicit symmetric extension, predict at every odd
+    position of the extended range) equals the oracle's band-array lifting
+    with ==, for every length 1..64 on random and extreme integers."""
+    rng = np.random.default_rng(41)
+    for n in range(1, 65):
+        for lim in (2, 256, 1 << 20):
+            for _ in range(4):
+                x = rng.integers(-lim, lim, size=n)
+                lo, hi = oracle.lift_forward_1d(x)
+                llo, lhi = lit.forward_1d(x.tolist())
+                assert lo.tolist() == llo and hi.tolist() == lhi, (n, x.tolist())
+                assert oracle.lift_inverse_1d(lo, hi, n).tolist() == lit.inverse_1d(llo, lhi)
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (1, 6), (5, 1), (2, 2), (3, 3), (2, 5), (7, 4),
+                                 (8, 8), (9, 7), (16, 5), (13, 17), (33, 30)])
+def test_one_level_2d_equals_literal_rows_then_columns(w, h):
+    """One 2-D level of the oracle equals the literal checker composed rows
+    first, then columns, with ==; the column-first composition differs on
+    every size with both sides at least 2 (so this test tells the orders
+    apart), and the literal inverse restores the image."""
+    rng = np.random.default_rng(w * 131 + h)
+    differs = 0
+    for trial in range(6):
+        img = rng.integers(0, 256, size=(h, w)).astype(np.uint8)
+        got = oracle.forward_dump(img, 1, bits=8, ct=0)[0]
+        ref = lit.forward_2d_level(img.tolist())
+        assert got["LL"].tolist() == ref["LL"]
+        for nm in ("HL", "LH", "HH"):
+            assert _band_eq(got[nm][1], ref[nm]), nm
+        differs += lit.forward_2d_level(img.tolist(), rows_first=False) != ref
+        assert lit.inverse_2d_level(ref, w, h) == img.tolist()
+    if w >= 2 and h >= 2:
+        assert differs > 0
+
+
+@pytest.mark.parametrize("w,h,levels", [(37, 29, 4), (64, 64, 3), (19, 50, 6), (5, 3, 5)])
+def test_pyramid_equals_literal_recursion(w, h, levels):
+    """Every band of an L-level oracle pyramid equals the literal checker's
+    recursion on LL (Sec. 3: the decomposition is recursive)."""
+    rng = np.random.default_rng(w + h + levels)
+    img = rng.integers(0, 4096, size=(h, w)).astype(np.uint16)
+    got = oracle.forward_dump(img, levels, bits=12, ct=0)[0]
+    ref = lit.forward_pyramid(img.tolist(), levels)
+    assert got["LL"].tolist() == ref["LL"]
+    for lv in range(1, levels + 1):
+        for nm in ("HL", "LH", "HH"):
+            assert _band_eq(got[nm][lv], ref[nm][lv]), (nm, lv)
 
 
 def test_pyramid_is_recursive_and_constant_image_has_zero_highpass():
@@ -500,6 +590,57 @@ def test_lossy_quantiser_and_reconstruction():
     _ = rng
 
 
+def _read_dequant_golden():
+    values, tiles = [], []
+    with open(os.path.join(GOLDEN, "dequant_examples.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if parts[0] == "tile":
+                tiles.append(tuple(int(v) for v in parts[1:]))
+            else:
+                values.append(tuple(int(v) for v in parts))
+    return values, tiles
+
+
+def test_dequantiser_worked_values_and_midpoint():
+    """Reconstruction of the dead-zone quantiser (Sec. 3, JPEG2000-style):
+    hand-worked values for steps 2, 3, 4, 7, both signs and q = 0; and for
+    every c the reconstruction is the middle of c's bin, floor((|q| + 1/2) step),
+    with the sign of c (exact rational arithmetic, no use of the formula)."""
+    from fractions import Fraction
+    values, _ = _read_dequant_golden()
+    for step, q, rec in values:
+        assert oracle.dequantise(q, step) == rec, (step, q)
+    for step in (1, 2, 3, 4, 5, 7, 8, 16):
+        for c in range(-300, 301):
+            q = oracle.quantise(c, step)
+            # q is the bin index: |q| step <= |c| < (|q| + 1) step, sign of c
+            assert abs(q) * step <= abs(c) < (abs(q) + 1) * step
+            assert q == 0 or (q > 0) == (c > 0)
+            rec = oracle.dequantise(q, step)
+            if step == 1:
+                assert rec == c
+            elif q == 0:
+                assert rec == 0
+            else:
+                mid = (Fraction(abs(q)) + Fraction(1, 2)) * step
+                assert abs(rec) == int(mid) and (rec > 0) == (q > 0)
+                assert oracle.quantise(rec, step) == q  # stays in its bin
+
+
+def test_lossy_tile_decode_worked_examples():
+    """Hand-worked lossy decodes of 2x1 tiles (one level, one channel): the
+    dequantised high-pass coefficient, inverse lifting and clamp, end to end
+    through the oracle's encoder and decoder."""
+    _, tiles = _read_dequant_golden()
+    for step, a, b, ra, rb in tiles:
+        img = np.array([[a, b]], dtype=np.uint8)
+        blob = oracle.encode_tile(img, 1, bits=8, ct=0, qstep=step)
+        assert oracle.decode_tile(blob)[:, :, 0].tolist() == [[ra, rb]], (step, a, b)
+
+
 def test_c1_workload_roundtrip():
     for seed in (101, 102, 103):
         img = synth.he_like(256, 256, seed)
@@ -523,7 +664,7 @@ def _drop_planes(q, r):
 def test_progressive_block_decode_matches_truncated_reader(kind):
     """Blocks decoded with r planes left out equal the independent reader's
     exact coefficients with the low r magnitude bits replaced per the
-    definition (Sec. 5: the seek table lets a decoder drop LSB planes)."""
+    definition (Sec. 4, decompression: the seek table lets a decoder drop LSB planes)."""
     if kind == "he8_lossless":
         img, lv, q = synth.he_like(150, 140, 31), 3, 1
     elif kind == "he8_step4":
