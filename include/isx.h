@@ -109,6 +109,17 @@ uint64_t isx_encode_workspace_bytes(const isx_tile_desc *h_descs, int32_t n_tile
 /* Device workspace needed by isx_decode_tiles for these jobs (bytes). */
 uint64_t isx_decode_workspace_bytes(const isx_decode_job *h_jobs, int32_t n_jobs);
 
+/* Parameters of an encoded tile, read from the first 24 bytes of its stream
+ * (host memory; the header written by isx_encode_tiles).  On ISX_OK *out
+ * holds the tile's width, height, channels, bytes_per_sample, bits, levels,
+ * colour_transform and qstep, with pixel_offset = 0 and row_stride_bytes =
+ * width * channels * bytes_per_sample: a ready `tile` for an isx_decode_job.
+ * Returns ISX_E_INVALID_ARG for null pointers, ISX_E_TRUNCATED if len < 24,
+ * ISX_E_CORRUPT if the magic, the version or a field is out of range or the
+ * block count disagrees with the geometry (Sec. 4: 128x128 blocks per band);
+ * *out is left unchanged on error. */
+int32_t isx_read_tile_header(const void *h_bytes, uint64_t len, isx_tile_desc *out);
+
 /* Number of coefficient blocks of a tile (Sec. 4: 128x128 blocks; LL blocks
  * plus one multiplexed LH/HL/HH block per non-empty grid cell per level). */
 int64_t isx_tile_block_count(const isx_tile_desc *h_desc);
@@ -125,7 +136,13 @@ int64_t isx_tile_block_count(const isx_tile_desc *h_desc);
  * d_status (int32 x n_tiles) are device arrays written by the kernels;
  * d_status[i] is ISX_OK or ISX_E_CAPACITY (nothing of tile i written).
  * d_workspace must hold isx_encode_workspace_bytes(h_descs, n_tiles) bytes.
- * Output is bit-identical for any batch composition and any run. */
+ * Output is bit-identical for any batch composition and any run.
+ * The plan of the call is copied into the workspace by a stream-ordered copy
+ * whose host source the library keeps alive until the copy has run (a host
+ * function queued on `stream` releases it).  isx_encode_tiles,
+ * isx_decode_tiles and isx_decode_regions return ISX_E_UNSUPPORTED if
+ * `stream` is being captured into a graph; capture the plan / run entry
+ * points instead. */
 int32_t isx_encode_tiles(const isx_tile_desc *h_descs, int32_t n_tiles,
                          const void *d_pixels, void *d_out, uint64_t out_capacity,
                          uint64_t *d_tile_offsets, uint64_t *d_tile_sizes, int32_t *d_status,

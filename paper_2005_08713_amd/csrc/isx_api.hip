@@ -443,12 +443,35 @@ uint64_t plan_ws_offset(const PlanHdr &H)
     return H.ws_bytes - al(H.plan_bytes);
 }
 
-int upload_plan(const Plan &P, uint8_t *d_ws, hipStream_t stream, uint8_t **d_plan)
+// Host bytes of a plan copy in flight: freed by a host function that the
+// stream runs after the copy, so the source outlives the copy whether or not
+// the runtime stages pageable memory before hipMemcpyAsync returns.
+void release_plan_bytes(void *p) { delete static_cast<std::vector<uint8_t> *>(p); }
+
+// The convenience entry points copy their plan into the workspace on
+// `stream`.  They refuse a stream under capture: a captured copy would keep a
+// host pointer whose lifetime the graph does not control (capture-safe
+// callers use the plan / run entry points, which enqueue kernels only).
+int upload_plan(Plan &P, uint8_t *d_ws, hipStream_t stream, uint8_t **d_plan)
 {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return ISX_E_HIP;
+    if (cs != hipStreamCaptureStatusNone) return ISX_E_UNSUPPORTED;
     *d_plan = d_ws + plan_ws_offset(P.H);
-    // A pageable source is staged by the runtime before hipMemcpyAsync returns.
-    hipError_t e = hipMemcpyAsync(*d_plan, P.bytes.data(), P.bytes.size(), hipMemcpyHostToDevice, stream);
-    return e == hipSuccess ? ISX_OK : ISX_E_HIP;
+    auto *held = new std::vector<uint8_t>(P.bytes);
+    hipError_t e = hipMemcpyAsync(*d_plan, held->data(), held->size(), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+        delete held;
+        return ISX_E_HIP;
+    }
+    e = hipLaunchHostFunc(stream, release_plan_bytes, held);
+    if (e != hipSuccess) {
+        // the copy is queued and its source must stay valid: wait for it
+        (void)hipStreamSynchronize(stream);
+        delete held;
+        return ISX_E_HIP;
+    }
+    return ISX_OK;
 }
 
 }  // namespace
@@ -714,6 +737,37 @@ int32_t isx_decode_tiles(const void *d_encoded, const isx_decode_job *h_jobs, in
     if (rc) return rc;
     return isx_decode_run(P.bytes.data(), d_plan, d_encoded, d_pixels_out, d_status, d_workspace,
                           workspace_bytes, stream);
+}
+
+int32_t isx_read_tile_header(const void *h_bytes, uint64_t len, isx_tile_desc *out)
+{
+    if (!h_bytes || !out) return ISX_E_INVALID_ARG;
+    const uint8_t *h = (const uint8_t *)h_bytes;
+    if (len < 24) return ISX_E_TRUNCATED;
+    if (h[0] != 'I' || h[1] != 'S' || h[2] != 'X' || h[3] != '1' || h[4] != 1) return ISX_E_CORRUPT;
+    auto u32 = [&](uint64_t o) {
+        return (uint32_t)h[o] | ((uint32_t)h[o + 1] << 8) | ((uint32_t)h[o + 2] << 16) | ((uint32_t)h[o + 3] << 24);
+    };
+    isx_tile_desc d;
+    memset(&d, 0, sizeof(d));
+    d.colour_transform = h[5];
+    d.channels = h[6];
+    d.bits = h[7];
+    d.bytes_per_sample = h[8];
+    d.levels = h[9];
+    d.qstep = (uint16_t)(h[10] | (h[11] << 8));
+    const uint32_t w = u32(12), ht = u32(16), nb = u32(20);
+    if (w > 65535 || ht > 65535) return ISX_E_CORRUPT;
+    d.width = w;
+    d.height = ht;
+    d.pixel_offset = 0;
+    d.row_stride_bytes = w * d.channels * d.bytes_per_sample;
+    if (validate_desc(d)) return ISX_E_CORRUPT;
+    TileBuild tb;
+    tile_geometry(d, 0, tb);
+    if (tb.g.nblocks_stream != nb) return ISX_E_CORRUPT;
+    *out = d;
+    return ISX_OK;
 }
 
 int32_t isx_stream_block_offsets(const void *h_head, uint64_t head_bytes, uint64_t *h_offsets, uint64_t n_offsets)

@@ -98,6 +98,7 @@ def lib():
             "isx_region_plan_bytes": (u64, [P, i32]),
             "isx_region_plan_build": (i32, [P, i32, P, P, u64]),
             "isx_decode_regions": (i32, [P, P, i32, P, P, P, u64, P]),
+            "isx_read_tile_header": (i32, [P, u64, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -114,7 +115,7 @@ EXPORTS = ["isx_max_encoded_bytes", "isx_encode_workspace_bytes", "isx_decode_wo
            "isx_debug_huffman", "isx_stage_count", "isx_stage_name", "isx_encode_run_stages",
            "isx_decode_run_stages", "isx_encode_plan_build_tuned", "isx_decode_plan_build_tuned",
            "isx_stream_block_offsets", "isx_region_workspace_bytes", "isx_region_plan_bytes",
-           "isx_region_plan_build", "isx_decode_regions"]
+           "isx_region_plan_build", "isx_decode_regions", "isx_read_tile_header"]
 
 
 def status_string(code: int) -> str:
@@ -361,13 +362,50 @@ def encode_images(imgs, levels, qsteps=None, device="cuda", bits=None):
     return enc.streams()
 
 
-def _parse_header(blob: bytes):
-    import struct
-    if len(blob) < 24:
-        raise ValueError("short stream")
-    ct, ch, bits, bps, lv = blob[5], blob[6], blob[7], blob[8], blob[9]
-    q, w, h, nb = struct.unpack_from("<HIII", blob, 10)
-    return tile_desc(w, h, ch, bps, bits, lv, ct=ct, qstep=q)
+def read_tile_header(blob: bytes) -> TileDesc:
+    """Tile parameters of an encoded stream (the library's host parser of its
+    24-byte header)."""
+    d = TileDesc()
+    head = np.frombuffer(blob[:24], np.uint8)
+    _check(lib().isx_read_tile_header(head.ctypes.data_as(ctypes.c_void_p), len(head), ctypes.byref(d)),
+           "isx_read_tile_header")
+    return d
+
+
+_parse_header = read_tile_header
+
+
+def encode_tiles(d_pixels, descs, d_out, d_offsets, d_sizes, d_status, d_ws, stream=None) -> int:
+    """One isx_encode_tiles call (plan built and copied by the library) on
+    caller-owned torch device buffers; returns the library's status."""
+    arr = desc_array(descs)
+    return int(lib().isx_encode_tiles(arr, len(descs), _ptr(d_pixels), _ptr(d_out), d_out.numel(),
+                                      _ptr(d_offsets), _ptr(d_sizes), _ptr(d_status), _ptr(d_ws),
+                                      d_ws.numel(), _stream_ptr(stream)))
+
+
+def decode_tiles(d_encoded, jobs, d_out, d_status, d_ws, stream=None) -> int:
+    """One isx_decode_tiles call on caller-owned torch device buffers."""
+    arr = (DecodeJob * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = j
+    return int(lib().isx_decode_tiles(_ptr(d_encoded), arr, len(jobs), _ptr(d_out), _ptr(d_status),
+                                      _ptr(d_ws), d_ws.numel(), _stream_ptr(stream)))
+
+
+def encode_workspace_bytes(descs) -> int:
+    return int(lib().isx_encode_workspace_bytes(desc_array(descs), len(descs)))
+
+
+def decode_workspace_bytes(jobs) -> int:
+    arr = (DecodeJob * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = j
+    return int(lib().isx_decode_workspace_bytes(arr, len(jobs)))
+
+
+def max_encoded_bytes(descs) -> int:
+    return int(lib().isx_max_encoded_bytes(desc_array(descs), len(descs)))
 
 
 def decode_streams(blobs, levels=None, device="cuda", return_status=False, drop=None):

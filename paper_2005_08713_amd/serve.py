@@ -370,17 +370,26 @@ class Server:
                                   ctypes.c_void_p(slot.stream.cuda_stream))
             if rc:
                 raise isx.IsxError(rc, "serve decode")
-            slot.event = torch.cuda.Event()
+            slot.event = torch.cuda.Event(enable_timing=True)
             slot.event.record(slot.stream)
         slot.reqs = reqs
         slot.busy = True
         slot.njobs = n
 
     def run(self, reqs, log=None, check=None):
-        """Serve `reqs` (with .arrival in seconds from start); returns stats."""
+        """Serve `reqs` (with .arrival in seconds from start); returns stats.
+
+        A request's completion time is its batch's device event: the time
+        origin is a reference event recorded on an idle stream and waited
+        for, so device event times convert to the host clock of the arrivals
+        (late by at most the wait's own latency, never early)."""
         import torch
         pending = deque(sorted(reqs, key=lambda r: r.arrival))
         ready = deque()
+        torch.cuda.synchronize()
+        ref = torch.cuda.Event(enable_timing=True)
+        ref.record(self.slots[0].stream)
+        ref.synchronize()
         t0 = time.perf_counter()
         done = 0
         batches = 0
@@ -390,7 +399,7 @@ class Server:
             # completions
             for s in self.slots:
                 if s.busy and s.event.query():
-                    tdone = time.perf_counter() - t0
+                    tdone = ref.elapsed_time(s.event) * 1e-3
                     st = s.status[:s.njobs].cpu()
                     if int(st.abs().sum()) != 0:
                         raise RuntimeError("decode error in a served batch")
@@ -420,7 +429,7 @@ class Server:
                 wait = pending[0].arrival - (time.perf_counter() - t0)
                 if wait > 2e-4 and not any(s.busy for s in self.slots):
                     time.sleep(wait - 1e-4)
-        wall = time.perf_counter() - t0
+        wall = max(time.perf_counter() - t0, max(r.done for r in reqs))
         lat = np.array([r.done - r.arrival for r in reqs]) * 1e3
         return {"requests": len(reqs), "batches": batches, "wall_s": wall,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),

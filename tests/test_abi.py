@@ -123,3 +123,41 @@ def test_stream_block_offsets_and_region_validation():
     whole = isx.region_job(d, offs, 0, 0, 0, 300, 200)
     assert L.isx_region_workspace_bytes((isx.RegionJob * 1)(small), 1) < \
         L.isx_region_workspace_bytes((isx.RegionJob * 1)(whole), 1)
+
+
+def test_read_tile_header_matches_oracle_and_rejects_bad_heads():
+    """isx_read_tile_header (host) returns the parameters the oracle wrote into
+    the 24-byte header, a decodable `tile`, and rejects short, foreign and
+    inconsistent heads without touching *out."""
+    import numpy as np
+    import oracle
+    from paper_2005_08713_amd import synth
+    L = isx.lib()
+    cases = [(synth.he_like(70, 45, 3), 3, 8, None, 4),
+             (synth.random_image(33, 17, 1, 12, 5, "uniform"), 6, 12, None, 1),
+             (synth.random_image(9, 40, 3, 8, 6, "checker"), 2, 8, 2, 3)]
+    for img, lv, bits, ct, q in cases:
+        blob = oracle.encode_tile(img, lv, bits=bits, ct=ct, qstep=q)
+        ref = oracle.read_header(blob)
+        d = isx.read_tile_header(blob)
+        assert (d.width, d.height, d.channels, d.bytes_per_sample, d.bits, d.levels,
+                d.colour_transform, d.qstep) == (ref["width"], ref["height"], ref["channels"],
+                                                 ref["bytes_per_sample"], ref["bits"], ref["levels"],
+                                                 ref["ct"], ref["qstep"])
+        assert d.pixel_offset == 0 and d.row_stride_bytes == d.width * d.channels * d.bytes_per_sample
+        assert isx.block_count(d) == ref["nblocks"]
+    blob = oracle.encode_tile(synth.he_like(40, 30, 1), 2)
+    out = isx.TileDesc()
+    out.width = 777
+
+    def rc(head):
+        b = np.frombuffer(bytes(head), np.uint8)
+        return L.isx_read_tile_header(b.ctypes.data_as(ctypes.c_void_p), len(b), ctypes.byref(out))
+
+    assert rc(blob[:23]) == isx.E_TRUNCATED
+    assert rc(b"JPEG" + blob[4:24]) == isx.E_CORRUPT
+    assert rc(blob[:4] + b"\x02" + blob[5:24]) == isx.E_CORRUPT            # version
+    assert rc(blob[:20] + (12345).to_bytes(4, "little")) == isx.E_CORRUPT  # block count
+    assert rc(blob[:6] + b"\x00" + blob[7:24]) == isx.E_CORRUPT            # zero channels
+    assert out.width == 777
+    assert L.isx_read_tile_header(None, 24, ctypes.byref(out)) == isx.E_INVALID_ARG
