@@ -42,12 +42,23 @@ class BlockInfo(ctypes.Structure):
                 ("run_hist", ctypes.c_uint64 * 40), ("total_bits", ctypes.c_uint64)]
 
 
+def build_sanitized(path: str) -> str:
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal) into `path`; a process loads it through
+    ISX_ORACLE_LIB, with the ASan runtime preloaded."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-Wall", "-Wno-alloc-size-larger-than",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-fno-omit-frame-pointer", "-shared", "-fPIC", "-o", path, _SRC])
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        path = os.environ.get("ISX_ORACLE_LIB") or _LIB
+        if path == _LIB and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         L.oracle_encode_tile.restype = i64
