@@ -41,17 +41,25 @@ def parse():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--levels", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle check and CPU baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="single: skip the high-bit-depth, batched and served legs")
+    ap.add_argument("--serve-slide", type=str, default="192x160",
+                    help="single: served leg's slide in 512-px tiles (default: 98304x81920)")
+    ap.add_argument("--serve-rate", type=float, default=10000.0, help="single: served leg's requests/s")
+    ap.add_argument("--serve-requests", type=int, default=100000, help="single: served leg's requests")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="JSON record of measured HBM bytes per launch of the dominant kernel "
                          "(used only if the kernel's source is unchanged since it was measured)")
     ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single",
                     help="single: one 4096x4096 image (default); batch: 4096 uneven tiles; "
                          "serve: tile-decode requests against an HBM-resident slide")
-    ap.add_argument("--slide", type=str, default="64x48", help="serve: slide size in 512-px tiles")
+    ap.add_argument("--slide", type=str, default="192x160",
+                    help="serve: slide size in 512-px tiles (default 98304x81920; a pyramid is one "
+                         "stream, at most 65535 px per side)")
     ap.add_argument("--layout", choices=["tiles", "pyramid"], default="tiles",
                     help="serve: the slide as independent 512-px tiles, or as one pyramid (region decode)")
     ap.add_argument("--rates", type=str, default="2000,5000,10000,20000", help="serve: requests/s")
-    ap.add_argument("--requests", type=int, default=4000, help="serve: requests per rate")
+    ap.add_argument("--requests", type=int, default=100000, help="serve: requests per rate")
     ap.add_argument("--tiles", type=int, default=4096, help="tiles of the batch workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain device copies of known size (HBM counter calibration)")
@@ -118,6 +126,7 @@ def main():
     if not args.no_cpu:
         import oracle
         log("[bench] oracle check (CPU)")
+        one = None
         for i, q in enumerate(modes):
             t0 = time.perf_counter()
             ref = oracle.encode_tile(img, L, qstep=q)
@@ -132,11 +141,9 @@ def main():
             if q == 1:
                 if not np.array_equal(refdec, img):
                     raise SystemExit("oracle lossless round trip failed")
-                cpu = {"value": round(W * H / 1e6 / (t2 - t0), 3), "unit": "MP/s", "cores": 1,
-                       "kind": "oracle",
-                       "sample": f"one lossless encode+decode of the {W}x{H} RGB image "
-                                 f"({t1 - t0:.1f} s + {t2 - t1:.1f} s, single thread)"}
+                one = (t1 - t0, t2 - t1)
         log("[bench] oracle parity ok")
+        cpu = cpu_baseline_threads(img, L, streams[1], one)
     elif not np.array_equal(decoded[:W * H * C].reshape(H, W, C), img):
         raise SystemExit("GPU lossless round trip failed")
     stream_bytes = {q: len(s) for q, s in streams.items()}
@@ -208,35 +215,7 @@ def main():
         raise SystemExit("decoded pixels changed between runs")
     px = W * H
     raw = px * C
-    # algorithmic bytes per launch of the dominant kernel, both images: what it
-    # must read and write once (stream bytes S, symbol-plane bytes Y, pixels
-    # N*C at one byte, int32 coefficients 4*N*C)
-    s_tot = float(sum(stream_bytes.values()))
-    sym_tot = float(sum(stream_symbol_count(streams[q]) for q in modes))
-    nm = len(modes)
-    alg = {
-        ("dec", "dec_segments"): s_tot + sym_tot,
-        ("enc", "enc_symbols"): nm * raw * 4 + sym_tot,
-        ("enc", "enc_pack"): sym_tot + s_tot,
-        ("enc", "forward_l1"): nm * (raw + raw * 4),
-        ("dec", "inverse_final"): nm * (raw * 4 + raw),
-        ("dec", "dec_reassemble"): sym_tot + nm * raw * 4,
-    }.get((dkind, dname), None)
-    roof = None
-    if alg is not None:
-        ach = alg / (avg_ms * 1e-3) / 1e9
-        traffic = None
-        if args.traffic and os.path.exists(args.traffic):
-            import hashlib
-            with open(args.traffic) as f:
-                tr = json.load(f)
-            src = os.path.join(ROOT, tr.get("source", ""))
-            fresh = os.path.isfile(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == tr.get("source_sha256")
-            if tr.get("kernel") == dname and fresh:
-                traffic = tr.get("bytes_per_launch")
-        roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": dname,
-                "avg_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(alg)}
+    roof = roofline(dkind, dname, avg_ms, float(sum(stream_bytes.values())), len(modes) * raw, args)
     # quality-progressive decode of the lossless stream: r magnitude planes
     # left out of every block (decode only, full resolution)
     prog = {}
@@ -289,33 +268,188 @@ def main():
         "cpu_baseline": cpu,
         "progressive_decode_mps": prog,
     }
+    del enc, dec, d_pix
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["high_bit_depth"] = leg_high_bit_depth(args)
+        torch.cuda.empty_cache()
+        out["batched"] = leg_batched(args)
+        torch.cuda.empty_cache()
+        out["served"] = leg_served(args)
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
-def calibrate_copy():
-    """Plain device-to-device copies of 256 MiB (5 dispatches), so the HBM
-    counters of a kernel of known traffic can scale FETCH_SIZE/WRITE_SIZE."""
+# Algorithmic bytes of a kernel, from the codec's per-image figures: encode
+# reads N*C*B pixel bytes and writes S stream bytes, decode reads S and
+# writes N*C*B.  Each byte is charged to the kernel that moves it between
+# the codec's own input and output: the first forward level reads the
+# pixels, the packer writes the stream, the segment decoder reads it, the
+# final inverse level writes the pixels.  Coefficients and symbol planes
+# between stages are the implementation's own traffic and count for none.
+def algorithmic_bytes(kind, name, s_bytes, raw_bytes):
+    return {("enc", "forward_l1"): raw_bytes, ("enc", "enc_pack"): s_bytes,
+            ("dec", "dec_segments"): s_bytes, ("dec", "inverse_final"): raw_bytes}.get((kind, name))
+
+
+def roofline(kind, name, avg_ms, s_bytes, raw_bytes, args):
+    alg = algorithmic_bytes(kind, name, s_bytes, raw_bytes)
+    if alg is None:
+        return None
+    ach = alg / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        import hashlib
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        src = os.path.join(ROOT, tr.get("source", ""))
+        fresh = os.path.isfile(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == tr.get("source_sha256")
+        if tr.get("kernel") == name and fresh:
+            traffic = tr.get("bytes_per_launch")
+    return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": name,
+            "avg_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(alg)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads for the CPU baseline: the cores this process may run on, at
+    most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline_threads(img, levels, lossless_stream, one):
+    """The oracle on the host's cores: T threads, each encoding and decoding
+    its own copy of the lossless image (the oracle keeps no global state and
+    ctypes releases the interpreter lock), whole-job MP/s = T images / wall
+    time.  `one` = (encode s, decode s) of the single-thread parity run."""
+    import threading
+    import oracle
+    T = host_threads()
+    H, W = img.shape[:2]
+    copies = [img.copy() for _ in range(T)]
+    errs = []
+
+    def work(k):
+        try:
+            s = oracle.encode_tile(copies[k], levels, qstep=1)
+            if s != lossless_stream or not np.array_equal(oracle.decode_tile(s, 0), copies[k]):
+                errs.append(k)
+        except Exception as e:  # noqa: BLE001 - reported below
+            errs.append(repr(e))
+    ths = [threading.Thread(target=work, args=(k,)) for k in range(T)]
+    t0 = time.perf_counter()
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    wall = time.perf_counter() - t0
+    if errs:
+        raise SystemExit(f"threaded oracle run failed: {errs[:3]}")
+    single = W * H / 1e6 / (one[0] + one[1])
+    log(f"[bench] oracle on {T} threads: {T * W * H / 1e6 / wall:.2f} MP/s ({wall:.1f} s); "
+        f"1 thread {single:.3f} MP/s; CPU {cpu_model()}")
+    return {"value": round(T * W * H / 1e6 / wall, 3), "unit": "MP/s", "cores": T, "kind": "oracle",
+            "sample": f"{T} threads, each one lossless encode+decode of its own copy of the {W}x{H} RGB image "
+                      f"({wall:.1f} s wall)",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": round(single, 3), "unit": "MP/s", "cores": 1,
+                              "sample": f"one lossless encode+decode of the {W}x{H} RGB image "
+                                        f"({one[0]:.1f} s + {one[1]:.1f} s)"}}
+
+
+def leg_high_bit_depth(args):
+    """8192x8192 single-channel uint16 with 12 significant bits (radiology
+    stand-in), 6 levels, lossless: encode + decode per step; stream equal to
+    the oracle's and lossless round trip checked first."""
     import torch
-    n = 256 << 20
-    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
-    b = torch.empty_like(a)
+    from paper_2005_08713_amd import isx, synth
+    W = H = 8192
+    L = 6
+    log("[c3] generating 8192x8192 12-bit image")
+    img = synth.rad_like(W, H, 301)
+    d_pix = torch.from_numpy(img.view(np.uint8).reshape(-1).copy()).cuda()
+    desc = isx.tile_desc(W, H, 1, 2, 12, L)
+    enc = isx.Encoder([desc])
+    enc.run(d_pix)
     torch.cuda.synchronize()
-    for _ in range(5):
-        b.copy_(a)
+    blob = enc.streams()[0]
+    job = isx.DecodeJob()
+    job.tile = desc
+    job.in_offset, job.in_bytes = int(enc.offsets[0]), len(blob)
+    job.out_offset, job.out_row_stride_bytes, job.target_level = 0, W * 2, 0
+    dec = isx.Decoder([job], W * H * 2)
+    dec.run(enc.out)
     torch.cuda.synchronize()
-    print(json.dumps({"calibration": "copy", "bytes_read": n, "bytes_written": n, "dispatches": 5}))
+    if not np.array_equal(dec.out.cpu().numpy().view(np.uint16).reshape(H, W), img):
+        raise SystemExit("high-bit-depth lossless round trip failed")
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.encode_tile(img, L, bits=12)
+        t1 = time.perf_counter()
+        if ref != blob:
+            raise SystemExit("high-bit-depth stream differs from the oracle")
+        rd = oracle.decode_tile(ref, 0)
+        t2 = time.perf_counter()
+        if not np.array_equal(rd.reshape(H, W), img):
+            raise SystemExit("oracle high-bit-depth round trip failed")
+        cpu = {"value": round(W * H / 1e6 / (t2 - t0), 3), "unit": "MP/s", "cores": 1,
+               "sample": f"one encode+decode ({t1 - t0:.1f} s + {t2 - t1:.1f} s)"}
+        log("[c3] oracle parity ok")
+    for _ in range(2):
+        enc.run(d_pix)
+        dec.run(enc.out)
+    torch.cuda.synchronize()
+    steps = 5
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        enc.run(d_pix)
+        dec.run(enc.out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    if enc.streams()[0] != blob:
+        raise SystemExit("high-bit-depth stream changed between runs")
+    s = len(blob)
+    res = {"workload": "8192x8192 uint16, 12 significant bits, radiology-like, 6 levels, lossless, "
+                       "encode+decode per step",
+           "mpx_s": round(W * H / 1e6 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4), "steps": steps,
+           "stream_bytes": s,
+           "end_to_end_hbm_frac": round(2 * (W * H * 2 + s) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5),
+           "oracle_parity": not args.no_cpu, "cpu_oracle": cpu}
+    log(f"[c3] {res['mpx_s']} MP/s, {ms:.3f} ms per step")
+    return res
 
 
-def bench_batch(args):
-    """4096 uneven RGB tiles (85% square 512/256/128, 15% ragged edge tiles),
-    levels 3-5, half lossless / half step 4: one graph replay encodes the
-    whole batch, one decodes it at full resolution."""
+def leg_batched(args):
+    """4096 uneven RGB tiles in one plan (default launch parameters), one graph
+    replay each for encode and decode; oracle sample check first."""
     from paper_2005_08713_amd import synth
-    log(f"[batch] generating {args.tiles} tiles")
-    tiles = synth.tile_batch(args.tiles, seed=401, content_seed_base=401000, workers=16)
+    log("[c4] generating 4096 tiles")
+    tiles = synth.tile_batch(4096, seed=401, content_seed_base=401000, workers=host_threads())
+    res = _batch_run(tiles, None, args, steps=5, warmup=2)
+    log(f"[c4] {res['mpx_s']} MP/s, {res['ms_per_step']:.3f} ms per step")
+    return res
+
+
+def _batch_run(tiles, best, args, steps, warmup):
     import torch
-    from paper_2005_08713_amd import autotune, isx
-    torch.cuda.set_device(0)
+    from paper_2005_08713_amd import isx
     descs, chunks, off = [], [], 0
     for t in tiles:
         a = t["pixels"]
@@ -329,10 +463,9 @@ def bench_batch(args):
     d_pix = torch.from_numpy(np.concatenate(chunks)).cuda()
     del chunks
     px = sum(d.width * d.height for d in descs)
-    log(f"[batch] {len(descs)} tiles, {px / 1e6:.1f} Mpx; autotuning")
-    best = autotune.tune(descs, d_pix, reps=2, log=log)
-    log(f"[batch] tuned: {best}")
-    enc = isx.Encoder(descs, tune=isx.tuning(*best["encode"]))
+    tun_e = isx.tuning(*best["encode"]) if best else None
+    tun_d = isx.tuning(*best["decode"]) if best else None
+    enc = isx.Encoder(descs, tune=tun_e)
     enc.run(d_pix)
     torch.cuda.synchronize()
     streams = enc.streams()
@@ -345,7 +478,7 @@ def bench_batch(args):
         j.out_offset, j.out_row_stride_bytes, j.target_level = out_off, d.width * 3, 0
         jobs.append(j)
         out_off += d.width * d.height * 3
-    dec = isx.Decoder(jobs, out_off, tune=isx.tuning(*best["decode"]))
+    dec = isx.Decoder(jobs, out_off, tune=tun_d)
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -365,20 +498,20 @@ def bench_batch(args):
         log("[batch] oracle parity ok on the sample")
     enc.capture(d_pix)
     dec.capture(enc.out)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         enc.replay()
         dec.replay()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     a.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         enc.replay()
         dec.replay()
     b.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    ms = (t1 - t0) * 1e3 / steps
     if enc.streams() != streams or int(dec.status.abs().sum().item()) != 0:
         raise SystemExit("graph replays changed the output")
     host = dec.out.cpu().numpy()
@@ -389,6 +522,7 @@ def bench_batch(args):
             raise SystemExit(f"lossless tile {i} did not round-trip")
         o += n
     sbytes = sum(len(s) for s in streams)
+    stages = {}
     # one stage-by-stage pass with events, for the per-stage breakdown
     for kind, obj, src, names in (("enc", enc, d_pix, isx.stage_names(0)), ("dec", dec, enc.out, isx.stage_names(1))):
         evs = []
@@ -404,16 +538,138 @@ def bench_batch(args):
         for st in range(len(names)):
             t = evs[st].elapsed_time(evs[st + 1])
             if t > 0.02:
+                stages[f"{kind}:{names[st]}"] = round(t, 3)
                 log(f"[stage] {kind} {names[st]:>20s} {t * 1e3:9.1f} us")
+    return {"workload": f"{len(tiles)} uneven RGB uint8 tiles (512/256/128 + 15% ragged), levels 3-5, "
+                        f"half lossless / half step 4, one graph replay each for encode and decode",
+            "mpx_s": round(px / 1e6 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4), "steps": steps,
+            "pixels": px, "stream_bytes": sbytes,
+            "event_ms_per_step": round(a.elapsed_time(b) / steps, 4),
+            "tuning": best or "default", "stage_ms": stages, "cpu_oracle": cpu}
+
+
+def leg_served(args):
+    """The served slide at full size (default 192x160 tiles of 512x512 RGB =
+    98304x81920): HBM-resident encoded tiles, viewer-trace requests re-timed
+    as Poisson arrivals at one rate, continuous batching; the alone / in-mix
+    / oracle checks of bench_serve on a sample first."""
+    import torch
+    from paper_2005_08713_amd import serve
+    tx, ty = (int(v) for v in args.serve_slide.split("x"))
+    log(f"[c5] building {tx}x{ty}-tile slide")
+    slide = serve.Slide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log)
+    enc_bytes = int(slide.sizes.sum())
+    log(f"[c5] slide encoded: {slide.raw_bytes / 1e9:.2f} GB raw -> {enc_bytes / 1e9:.3f} GB in HBM "
+        f"({slide.encode_s:.1f} s incl. generation)")
+    n = args.serve_requests
+    trace = serve.viewer_trace(slide, n_viewers=32, steps=max(400, n // 100 + 200), zmax=6, seed=502)
+    if len(trace) < n:
+        raise SystemExit(f"viewer trace has only {len(trace)} requests")
+    srv = serve.Server(slide, slots=3, ws_bytes=512 << 20, max_reqs=64)
+    cpu = None if args.no_cpu else _tiles_checks(slide, srv, trace)
+    reqs = [serve.Request(i, z, X, Y) for i, (z, X, Y) in enumerate(trace[:n])]
+    for r, t in zip(reqs, serve.poisson_arrivals(n, args.serve_rate, seed=502)):
+        r.arrival = float(t)
+    st = srv.run(reqs)
+    log(f"[c5] lambda={args.serve_rate:.0f}/s: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms, "
+        f"{st['decoded_mpx_s']:.0f} MP/s decoded, {st['batches']} batches")
+    res = {"workload": f"served {tx * 512}x{ty * 512} RGB slide of 512x512 tiles (6 levels), 32 viewers, "
+                       f"zoom 0-6, 512x512 views, Poisson arrivals",
+           "slide_raw_bytes": slide.raw_bytes, "slide_encoded_bytes": enc_bytes,
+           "lambda": args.serve_rate, "requests": n,
+           "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+           "decoded_mpx_s": round(st["decoded_mpx_s"], 1), "served_rps": round(st["served_rps"], 1),
+           "latency_clock": "device events at batch completion",
+           "cpu_oracle": cpu}
+    del srv, slide
+    return res
+
+
+def _tiles_checks(slide, srv, trace):
+    """A sample of served requests: equal alone and in a mixed batch, and
+    equal to the oracle's stitched decodes (timed: the CPU figure)."""
+    import oracle
+    from paper_2005_08713_amd import serve
+    sample = trace[:24]
+    reqs = [serve.Request(i, z, X, Y) for i, (z, X, Y) in enumerate(sample)]
+    for r in reqs:
+        r.arrival = 0.0
+    got = {}
+
+    def check(slot, rs):
+        host = slot.out.cpu().numpy()
+        for r in rs:
+            got[r.rid] = host[r.out_off:r.out_off + srv.req_bytes].copy()
+    srv.run(reqs, check=check)
+    t0 = time.perf_counter()
+    spx = 0
+    for r in reqs[:8]:
+        sub = 512 >> r.z
+        exp = np.zeros((512, 512, 3), np.uint8)
+        for tid, i, j in slide.sources(r.z, r.X, r.Y):
+            o, n = int(slide.offsets[tid]), int(slide.sizes[tid])
+            blob = slide.arena[o:o + n].cpu().numpy().tobytes()
+            exp[j * sub:(j + 1) * sub, i * sub:(i + 1) * sub] = oracle.decode_tile(blob, r.z)
+            spx += sub * sub
+        if not np.array_equal(exp.reshape(-1), got[r.rid]):
+            raise SystemExit(f"served request {r} differs from the oracle")
+        alone = srv.decode_alone(serve.Request(r.rid, r.z, r.X, r.Y))
+        if not np.array_equal(alone, got[r.rid]):
+            raise SystemExit(f"served request {r} differs alone vs in the mix")
+    t1 = time.perf_counter()
+    log("[serve] oracle parity ok")
+    return {"value": round(8 / (t1 - t0), 3), "unit": "requests/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle decode of 8 served requests ({spx / 1e6:.2f} Mpx output, single thread)"}
+
+
+def calibrate_copy():
+    """Plain device-to-device copies of 256 MiB (5 dispatches), so the HBM
+    counters of a kernel of known traffic can scale FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    n = 256 << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": n, "bytes_written": n, "dispatches": 5}))
+
+
+def bench_batch(args):
+    """4096 uneven RGB tiles (85% square 512/256/128, 15% ragged edge tiles),
+    levels 3-5, half lossless / half step 4: the autotuner picks the launch
+    parameters, then one graph replay encodes the whole batch, one decodes it
+    at full resolution."""
+    from paper_2005_08713_amd import synth
+    log(f"[batch] generating {args.tiles} tiles")
+    tiles = synth.tile_batch(args.tiles, seed=401, content_seed_base=401000, workers=host_threads())
+    import torch
+    from paper_2005_08713_amd import autotune, isx
+    torch.cuda.set_device(0)
+    descs, chunks, off = [], [], 0
+    for t in tiles:
+        a = t["pixels"]
+        h, w, c = a.shape
+        descs.append(isx.tile_desc(w, h, c, 1, 8, t["levels"], qstep=t["qstep"], pixel_offset=off))
+        chunks.append(a.reshape(-1))
+        off += a.size
+        pad = (-off) % 16
+        chunks.append(np.zeros(pad, np.uint8))
+        off += pad
+    d_pix = torch.from_numpy(np.concatenate(chunks)).cuda()
+    del chunks
+    log(f"[batch] {len(descs)} tiles; autotuning")
+    best = autotune.tune(descs, d_pix, reps=2, log=log)
+    log(f"[batch] tuned: {best}")
+    del d_pix
+    res = _batch_run(tiles, best, args, steps=args.steps, warmup=args.warmup)
     out = {"metric": "bit-exact encode+decode megapixels/s per GPU (batched, graph-captured)",
-           "value": round(px / 1e6 / (ms * 1e-3), 2), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-           "config": {"workload": f"{len(tiles)} uneven RGB uint8 tiles (512/256/128 + 15% ragged), levels 3-5, "
-                                  f"half lossless / half step 4, one graph replay each for encode and decode",
-                      "pixels": px, "stream_bytes": sbytes, "tuning": best,
-                      "event_ms_per_step": round(a.elapsed_time(b) / args.steps, 4)},
-           "cpu_baseline": cpu}
+           "value": res["mpx_s"], "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {k: v for k, v in res.items() if k not in ("mpx_s", "ms_per_step", "steps", "cpu_oracle")},
+           "cpu_baseline": res["cpu_oracle"]}
     print(json.dumps(out), flush=True)
 
 
@@ -426,6 +682,8 @@ def bench_serve(args):
     torch.cuda.set_device(0)
     tx, ty = (int(v) for v in args.slide.split("x"))
     pyr = args.layout == "pyramid"
+    if pyr and max(tx, ty) * 512 > 65535:
+        raise SystemExit("a pyramid slide is one stream: at most 65535 px per side (--slide 127x127 or less)")
     log(f"[serve] building {tx}x{ty}-tile slide ({args.layout})")
     if pyr:
         slide = serve.PyramidSlide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log)
@@ -435,45 +693,15 @@ def bench_serve(args):
         enc_bytes = int(slide.sizes.sum())
     log(f"[serve] slide encoded: {slide.raw_bytes / 1e9:.2f} GB raw -> {enc_bytes / 1e9:.3f} GB in HBM "
         f"({slide.encode_s:.1f} s incl. generation)")
-    trace = serve.viewer_trace(slide, n_viewers=32, steps=400, zmax=6, seed=502)
+    trace = serve.viewer_trace(slide, n_viewers=32, steps=max(400, args.requests // 100 + 200), zmax=6,
+                               seed=502)
     srv = serve.Server(slide, slots=3, ws_bytes=512 << 20, max_reqs=64)
     # correctness: a sample of requests alone vs in a mixed batch, and vs the oracle
     cpu = None
     if pyr:
         cpu = _pyramid_checks(args, slide, srv, trace)
     elif not args.no_cpu:
-        import oracle
-        enc = None
-        sample = trace[:24]
-        reqs = [serve.Request(i, z, X, Y) for i, (z, X, Y) in enumerate(sample)]
-        for r in reqs:
-            r.arrival = 0.0
-        got = {}
-
-        def check(slot, rs):
-            host = slot.out.cpu().numpy()
-            for r in rs:
-                got[r.rid] = host[r.out_off:r.out_off + srv.req_bytes].copy()
-        srv.run(reqs, check=check)
-        t0 = time.perf_counter()
-        spx = 0
-        for r in reqs[:8]:
-            sub = 512 >> r.z
-            exp = np.zeros((512, 512, 3), np.uint8)
-            for tid, i, j in slide.sources(r.z, r.X, r.Y):
-                o, n = int(slide.offsets[tid]), int(slide.sizes[tid])
-                blob = slide.arena[o:o + n].cpu().numpy().tobytes()
-                exp[j * sub:(j + 1) * sub, i * sub:(i + 1) * sub] = oracle.decode_tile(blob, r.z)
-                spx += sub * sub
-            if not np.array_equal(exp.reshape(-1), got[r.rid]):
-                raise SystemExit(f"served request {r} differs from the oracle")
-            alone = srv.decode_alone(serve.Request(r.rid, r.z, r.X, r.Y))
-            if not np.array_equal(alone, got[r.rid]):
-                raise SystemExit(f"served request {r} differs alone vs in the mix")
-        t1 = time.perf_counter()
-        cpu = {"value": round(8 / (t1 - t0), 3), "unit": "requests/s", "cores": 1, "kind": "oracle",
-               "sample": f"oracle decode of 8 served requests ({spx / 1e6:.2f} Mpx output, single thread)"}
-        log("[serve] oracle parity ok")
+        cpu = _tiles_checks(slide, srv, trace)
     rows = []
     for lam in [float(x) for x in args.rates.split(",")]:
         n = min(args.requests, len(trace))
@@ -569,32 +797,6 @@ def _pyramid_checks(args, slide, srv, trace):
     log("[serve] oracle parity ok on views at zoom >= 4")
     return {"value": round(len(deep) / (t1 - t0), 3), "unit": "requests/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle: {len(deep)} views at zoom >= 4, each the crop of its whole level-z decode"}
-
-
-def stream_symbol_count(blob: bytes) -> int:
-    """Number of area symbols (one byte each) in the kept planes of every block
-    of a tile stream, read from the block headers (d and masks)."""
-    import struct
-    nb = struct.unpack_from("<I", blob, 20)[0]
-    w, h = struct.unpack_from("<II", blob, 12)
-    ch, lv = blob[6], blob[9]
-    from tests.format_reader import block_geometry
-    geo = block_geometry(w, h, ch, lv)
-    sizes = struct.unpack_from("<%dI" % nb, blob, 24)
-    pos = 24 + 4 * nb
-    total = 0
-    for (lvl, c, bx, by, p, wb, hb, ext), sz in zip(geo, sizes):
-        bits = int.from_bytes(blob[pos:pos + 16].ljust(16, b"\0"), "big")
-        d = bits >> 123
-        n = wb * hb // 8
-        masks = []
-        for t in range(p):
-            masks.append((bits >> (123 - d * (t + 1))) & ((1 << d) - 1))
-        for b in range(d):
-            kept = sum(1 for m in masks if not (m >> b) & 1)
-            total += kept * n
-        pos += sz
-    return total
 
 
 if __name__ == "__main__":
