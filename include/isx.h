@@ -15,12 +15,14 @@
  *  - Calls are asynchronous and stream ordered: they validate their host
  *    arguments, enqueue kernels (and, for the convenience entry points, one
  *    small host-to-device copy of the plan) on `stream` and return without
- *    synchronising.  The library never allocates or frees device memory.
+ *    synchronising.  The library never allocates or frees device memory (the
+ *    fixed workspace of isx_decode_run_noalloc is part of its code object).
  *  - The return value is ISX_OK or a negative status for errors detected on
  *    the host before anything was enqueued.  Errors only the device can see
  *    (corrupt streams, full output buffer) are written per tile or per job
  *    into d_status, readable after the stream has been synchronised.
- *  - Entry points are thread safe; the library keeps no mutable global state.
+ *  - Entry points are thread safe.  The only mutable global state is the
+ *    per-device address table of isx_decode_run_noalloc's fixed workspace.
  */
 #ifndef ISX_H
 #define ISX_H
@@ -180,6 +182,33 @@ int32_t isx_decode_plan_build(const isx_decode_job *h_jobs, int32_t n_jobs, void
 int32_t isx_decode_run(const void *h_plan, const void *d_plan, const void *d_encoded,
                        void *d_pixels_out, int32_t *d_status, void *d_workspace,
                        uint64_t workspace_bytes, void *stream);
+
+/* ---- decode without any allocation ------------------------------------------
+ * For callers that cannot allocate memory of any kind during the call: code
+ * recorded under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  isx_decode_run_noalloc is isx_decode_run with its
+ * workspace taken from a fixed array of ISX_NOALLOC_SCRATCH_BYTES in the
+ * library's own device memory instead of a d_workspace argument: it calls no
+ * hipMalloc, hipFree, host allocator or other allocating routine (the
+ * address of the array is looked up once per device, on the first call with
+ * that device current).  The caller still passes the plan (h_plan and its
+ * device copy d_plan, from isx_decode_plan_build or isx_region_plan_build),
+ * the encoded arena, the output arena and d_status, exactly as for
+ * isx_decode_run; the output is identical to isx_decode_run's.
+ * Returns ISX_E_WORKSPACE if the plan needs more than
+ * ISX_NOALLOC_SCRATCH_BYTES of workspace (isx_decode_workspace_bytes of its
+ * jobs: 64 MiB covers one 1024x1024 RGB tile at any level count, one
+ * 2048x2048 single-channel 16-bit tile, or eleven 512x512 RGB tiles of 6
+ * levels), ISX_E_INVALID_ARG for a null pointer or a plan
+ * that is not a decode plan, ISX_E_HIP if the runtime fails.
+ * Every call on one GPU uses that GPU's one array, which keeps the contents
+ * of the last call (every counter and queue the kernels need is cleared by
+ * the kernels themselves): calls that overlap on one GPU (on different
+ * streams, or from different threads without ordering) race and produce
+ * undefined output.  Calls ordered on one stream are safe. */
+#define ISX_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int32_t isx_decode_run_noalloc(const void *h_plan, const void *d_plan, const void *d_encoded,
+                               void *d_pixels_out, int32_t *d_status, void *stream);
 
 /* Launch parameters of a plan.  They change speed only: the encoded bytes and
  * decoded pixels are identical for every setting.

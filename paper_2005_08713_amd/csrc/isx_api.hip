@@ -2,6 +2,7 @@
 // (geometry, workspace layout, work lists) and the C ABI of include/isx.h.
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "isx.h"
@@ -474,6 +475,32 @@ int upload_plan(Plan &P, uint8_t *d_ws, hipStream_t stream, uint8_t **d_plan)
     return ISX_OK;
 }
 
+// Workspace of isx_decode_run_noalloc: a fixed array in the library's device
+// memory (each GPU that loads the library holds its own copy until the
+// process ends).  Host code never passes `scratch` itself to a kernel: in host
+// code the name is a stand-in, not a device address; the address is looked up
+// per device with hipGetSymbolAddress and kept in g_scratch.
+static __device__ __align__(256) uint8_t scratch[ISX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current); nullptr on a HIP error.
+uint8_t *scratch_ptr()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch[dev] = (uint8_t *)p;
+    }
+    return g_scratch[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -633,6 +660,23 @@ int32_t isx_decode_run(const void *h_plan, const void *d_plan, const void *d_enc
     if (workspace_bytes < H.ws_bytes) return ISX_E_WORKSPACE;
     hipError_t e = launch_decode(H, (const uint8_t *)d_plan, (const uint8_t *)d_encoded, (uint8_t *)d_pixels_out,
                                  d_status, (uint8_t *)d_workspace, (hipStream_t)stream, 0, DEC_NSTAGES - 1);
+    return e == hipSuccess ? ISX_OK : ISX_E_HIP;
+}
+
+int32_t isx_decode_run_noalloc(const void *h_plan, const void *d_plan, const void *d_encoded, void *d_pixels_out,
+                               int32_t *d_status, void *stream)
+{
+    int rc = check_plan(h_plan, MODE_DECODE);
+    if (rc) return rc;
+    const PlanHdr &H = *(const PlanHdr *)h_plan;
+    if (!d_plan || !d_encoded || !d_pixels_out || !d_status) return ISX_E_INVALID_ARG;
+    if (H.ws_bytes > ISX_NOALLOC_SCRATCH_BYTES) return ISX_E_WORKSPACE;
+    uint8_t *ws = scratch_ptr();
+    if (!ws) return ISX_E_HIP;
+    // the stages clear every counter and queue they use with kernels; no
+    // other state of a previous call is read
+    hipError_t e = launch_decode(H, (const uint8_t *)d_plan, (const uint8_t *)d_encoded, (uint8_t *)d_pixels_out,
+                                 d_status, ws, (hipStream_t)stream, 0, DEC_NSTAGES - 1);
     return e == hipSuccess ? ISX_OK : ISX_E_HIP;
 }
 

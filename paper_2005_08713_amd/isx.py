@@ -99,6 +99,7 @@ def lib():
             "isx_region_plan_build": (i32, [P, i32, P, P, u64]),
             "isx_decode_regions": (i32, [P, P, i32, P, P, P, u64, P]),
             "isx_read_tile_header": (i32, [P, u64, P]),
+            "isx_decode_run_noalloc": (i32, [P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -115,7 +116,10 @@ EXPORTS = ["isx_max_encoded_bytes", "isx_encode_workspace_bytes", "isx_decode_wo
            "isx_debug_huffman", "isx_stage_count", "isx_stage_name", "isx_encode_run_stages",
            "isx_decode_run_stages", "isx_encode_plan_build_tuned", "isx_decode_plan_build_tuned",
            "isx_stream_block_offsets", "isx_region_workspace_bytes", "isx_region_plan_bytes",
-           "isx_region_plan_build", "isx_decode_regions", "isx_read_tile_header"]
+           "isx_region_plan_build", "isx_decode_regions", "isx_read_tile_header",
+           "isx_decode_run_noalloc"]
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # ISX_NOALLOC_SCRATCH_BYTES
 
 
 def status_string(code: int) -> str:
@@ -270,6 +274,12 @@ class Decoder:
                                   _ptr(self.status), _ptr(self.ws), self.ws_bytes,
                                   _stream_ptr(stream))
         _check(rc, "isx_decode_run")
+
+    def run_noalloc(self, d_encoded, stream=None):
+        """The same decode through isx_decode_run_noalloc: the library's fixed
+        device workspace instead of self.ws (returns the library's status)."""
+        return int(lib().isx_decode_run_noalloc(self.h_plan, _ptr(self.d_plan), _ptr(d_encoded),
+                                                _ptr(self.out), _ptr(self.status), _stream_ptr(stream)))
 
     def run_stages(self, d_encoded, first, count, stream=None):
         rc = lib().isx_decode_run_stages(self.h_plan, _ptr(self.d_plan), _ptr(d_encoded),

@@ -161,3 +161,26 @@ def test_read_tile_header_matches_oracle_and_rejects_bad_heads():
     assert rc(blob[:6] + b"\x00" + blob[7:24]) == isx.E_CORRUPT            # zero channels
     assert out.width == 777
     assert L.isx_read_tile_header(None, 24, ctypes.byref(out)) == isx.E_INVALID_ARG
+
+
+def test_noalloc_decode_validates_on_the_host():
+    """isx_decode_run_noalloc refuses null pointers, a non-decode plan and a
+    plan beyond its fixed workspace before touching the device."""
+    L = isx.lib()
+    d = isx.tile_desc(2048, 2048, 3, 1, 8, 5)
+    j = isx.DecodeJob()
+    j.tile, j.in_bytes, j.out_row_stride_bytes = d, 1 << 20, 2048 * 3
+    arr = (isx.DecodeJob * 1)(j)
+    pb = L.isx_decode_plan_bytes(arr, 1)
+    plan = (ctypes.c_uint8 * pb)()
+    assert L.isx_decode_plan_build(arr, 1, plan, pb) == isx.OK
+    assert L.isx_decode_workspace_bytes(arr, 1) > isx.NOALLOC_SCRATCH_BYTES
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every check here is on the host
+    assert L.isx_decode_run_noalloc(plan, fake, fake, fake, fake, None) == isx.E_WORKSPACE
+    assert L.isx_decode_run_noalloc(plan, None, fake, fake, fake, None) == isx.E_INVALID_ARG
+    assert L.isx_decode_run_noalloc(None, fake, fake, fake, fake, None) == isx.E_INVALID_ARG
+    e = isx.tile_desc(64, 64, 3, 1, 8, 3)
+    eb = L.isx_encode_plan_bytes(ctypes.byref(e), 1)
+    eplan = (ctypes.c_uint8 * eb)()
+    assert L.isx_encode_plan_build(ctypes.byref(e), 1, eplan, eb) == isx.OK
+    assert L.isx_decode_run_noalloc(eplan, fake, fake, fake, fake, None) == isx.E_INVALID_ARG
