@@ -478,6 +478,7 @@ def _batch_run(tiles, best, args, steps, warmup):
         j.out_offset, j.out_row_stride_bytes, j.target_level = out_off, d.width * 3, 0
         jobs.append(j)
         out_off += d.width * d.height * 3
+        out_off += (-out_off) % 256  # every output image starts 256-byte aligned
     dec = isx.Decoder(jobs, out_off, tune=tun_d)
     cpu = None
     if not args.no_cpu:
@@ -515,12 +516,10 @@ def _batch_run(tiles, best, args, steps, warmup):
     if enc.streams() != streams or int(dec.status.abs().sum().item()) != 0:
         raise SystemExit("graph replays changed the output")
     host = dec.out.cpu().numpy()
-    o = 0
-    for i, t in enumerate(tiles):
-        n = t["pixels"].size
+    for i, (t, j) in enumerate(zip(tiles, jobs)):
+        o, n = j.out_offset, t["pixels"].size
         if t["qstep"] == 1 and not np.array_equal(host[o:o + n], t["pixels"].reshape(-1)):
             raise SystemExit(f"lossless tile {i} did not round-trip")
-        o += n
     sbytes = sum(len(s) for s in streams)
     stages = {}
     # one stage-by-stage pass with events, for the per-stage breakdown

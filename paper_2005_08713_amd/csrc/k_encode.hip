@@ -940,9 +940,20 @@ __global__ void __launch_bounds__(256) k_enc_tile_finish(PlanHdr H, const uint8_
 }
 
 // ---------------------------------------------------------------- pack
-constexpr int kStageWords = 4160;  // > (2^17 + 64) / 32
-constexpr uint32_t kPackNT = 512;  // packer workgroup
-constexpr uint32_t kPackPT = 12;   // symbols per thread: 512 x 12 >= 6144
+// One wave per item (a block header, or one segment).  A segment is packed
+// in rounds of 512 symbols, 8 per lane: the lanes' token bits are counted,
+// scanned across the wave, written into a staging area in LDS, and the
+// round's complete words are stored to the stream; the last, partial word
+// is carried into the next round.  No workgroup barriers, no block scans:
+// the per-item cost of small segments is one wave's.
+constexpr uint32_t kPackK = 8;                    // symbols per lane and round
+constexpr uint32_t kPackRound = 64 * kPackK;      // symbols per round
+// Staging words of one round.  Per symbol at most one literal token (a code
+// of at most 32 bits plus a counter of at most 13 bits, wz <= 13); a zero run
+// is emitted at its end, at most 45 bits per two of its symbols, except the
+// run that began in an earlier round (at most 8 digit tokens for runs of at
+// most 6144 zeros); plus the carried partial word and the put's second word.
+constexpr uint32_t kPackStage = (kPackRound * 45 + 8 * 45 + 31) / 32 + 3;
 
 __device__ inline void put_bits(uint32_t *st, uint32_t pos, uint32_t val, uint32_t nb)
 {
@@ -955,66 +966,83 @@ __device__ inline void put_bits(uint32_t *st, uint32_t pos, uint32_t val, uint32
     if (lo) atomicOr(&st[wi + 1], lo);
 }
 
-__device__ inline void flush_bits(const uint32_t *st, uint64_t abs_bit, uint32_t nbits, uint32_t *outw)
+// Store staging words [0, n) at stream word w0 (big-endian).  The item's
+// first word (when `first_shared`) and the word `last_shared` (when <= n-1)
+// are shared with the neighbouring region and ORed in; every other word
+// belongs to this item alone.
+__device__ inline void store_words(const uint32_t *st, uint32_t n, uint64_t w0, bool first_shared,
+                                   uint32_t last_shared, uint32_t *outw)
 {
-    uint32_t o = (uint32_t)(abs_bit & 31u);
-    uint64_t w0 = abs_bit >> 5;
-    uint32_t nw = (o + nbits + 31) >> 5;
-    for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
-        uint32_t v = st[i];
-        bool partial = (i == 0 && o != 0) || (i == nw - 1 && ((o + nbits) & 31u) != 0);
-        if (partial) { if (v) atomicOr(&outw[w0 + i], __builtin_bswap32(v)); }
-        else outw[w0 + i] = __builtin_bswap32(v);
+    for (uint32_t i = threadIdx.x; i < n; i += 64) {
+        const uint32_t v = st[i];
+        if ((i == 0 && first_shared) || i == last_shared) {
+            if (v) atomicOr(&outw[w0 + i], __builtin_bswap32(v));
+        } else {
+            outw[w0 + i] = __builtin_bswap32(v);
+        }
     }
 }
 
+__device__ inline uint32_t wave_excl_sum(uint32_t v, uint32_t &total)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if ((int)lane >= o) x += y;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+__device__ inline int32_t wave_excl_max(int32_t v, int32_t &total)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    int32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if ((int)lane >= o) x = max(x, y);
+    }
+    total = __shfl(x, 63, 64);
+    const int32_t ex = __shfl_up(x, 1, 64);
+    return lane == 0 ? INT32_MIN : ex;
+}
+
 struct PackShared {
-    uint32_t st[kStageWords];
-    uint32_t s_code[256];
-    uint8_t s_len[256];
-    uint64_t sh[kPackNT / 64];
-    int32_t shi[kPackNT / 64];
+    uint32_t st[kPackStage];
+    uint32_t code[256];
+    uint8_t len[256];
 };
 
-// Pack one item: y = 0 the block header, y = 1.. segment y-1.
-__device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__restrict__ ws,
-                                          uint8_t *__restrict__ out, PackShared &S, uint32_t blk,
-                                          uint32_t y)
+// Item y of block blk: y = 0 the block header, y = 1.. segment y-1.  The
+// longest items (the last segments: low, dense planes) come first in the
+// grid, the headers last.
+__global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__restrict__ ws,
+                                                 uint8_t *__restrict__ out)
 {
-    uint32_t *st = S.st, *s_code = S.s_code;
-    uint8_t *s_len = S.s_len;
-    uint64_t *sh = S.sh;
-    int32_t *shi = S.shi;
-    const uint32_t tid = threadIdx.x;
+    __shared__ PackShared S;
+    const uint32_t blk = blockIdx.x, y = gridDim.y - 1u - blockIdx.y;
+    const uint32_t lane = threadIdx.x;
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
-    // the plan fields a segment needs are loaded together, before the checks
-    // that depend on them, so that they cost one round trip to memory
-    const uint32_t s = y ? y - 1 : 0;
-    const uint32_t lane = tid & 63u;
-    const uint32_t tile = B.tile;
-    const uint64_t sym_off = B.sym_off;
-    const uint32_t nseg = P.nseg, hdr_bits = P.hdr_bits, czr = P.czr, wz = P.wz, pp = P.p, pn = P.n;
-    const uint32_t seg_lane = P.seg_bits[lane & 31u];
-    const uint32_t nbits_s = P.seg_bits[s], M = P.seg_M[s], plane = P.seg_plane[s];
-    const uint64_t byte_off = P.byte_off;
-    const uint32_t code_t = P.code[tid & 255u], len_t = P.len[tid & 255u];
-    if (y > nseg) return;  // no such segment: leave before the tile's status is read
-    const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[tile];
-    const uint32_t status = O.status;
-    const uint64_t toff = O.offset;
-    if (status != ISX_STATUS_OK) return;
+    const uint32_t nseg = __builtin_amdgcn_readfirstlane(P.nseg);
+    if (y > nseg) return;
+    const TileOut &O = ((const TileOut *)(ws + H.ws_tileout))[B.tile];
+    if (__builtin_amdgcn_readfirstlane(O.status) != ISX_STATUS_OK) return;
+    uint32_t *st = S.st;
     uint32_t *outw = (uint32_t *)out;
-    const uint64_t bit0 = (toff + byte_off) * 8;
+    const uint64_t bit0 = (O.offset + P.byte_off) * 8;
+    const uint32_t hdr_bits = P.hdr_bits;
     if (y == 0) {
         // header: d | masks | C_zr | wz | tree | seek table (Fig. 3)
-        const uint32_t nbits = P.hdr_bits;
         const uint32_t o = (uint32_t)(bit0 & 31u);
-        const uint32_t nw = (o + nbits + 31) >> 5;
-        for (uint32_t i = tid; i < nw + 1; i += blockDim.x) st[i] = 0;
+        const uint32_t nw = (o + hdr_bits + 31) >> 5;
+        for (uint32_t i = lane; i < nw + 1; i += 64) st[i] = 0;
         __syncthreads();
         const uint32_t d = P.d, p = P.p;
-        if (tid == 0) {
+        if (lane == 0) {
             put_bits(st, o, d, 5);
             for (uint32_t t = 0; t < p; t++) put_bits(st, o + 5 + t * d, P.masks[t], d);
             if (nseg) {
@@ -1023,74 +1051,69 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
             }
         }
         if (nseg) {
+            // pre-order tree: leaf j (canonical order) is preceded by zj
+            // internal-node zeros; lane takes leaves 4 lane .. 4 lane + 3
             const uint32_t tree0 = o + 17 + p * d;
             const uint32_t m = P.m;
-            uint32_t zj = 0, sym = 0;
-            if (tid < m) {
-                sym = P.order[tid];
-                uint32_t lj = P.len[sym];
-                if (tid == 0) zj = lj;
-                else {
-                    uint32_t ps = P.order[tid - 1];
-                    uint32_t lp = P.len[ps], cp = P.code[ps];
-                    zj = lj - lp + (uint32_t)__builtin_ctz(~cp);  // trailing ones of the previous code
+            uint32_t z[4], sy[4], sum = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++) {
+                const uint32_t j = 4 * lane + k;
+                z[k] = 0; sy[k] = 0;
+                if (j < m) {
+                    const uint32_t sym = P.order[j], lj = P.len[sym];
+                    if (j == 0) z[k] = lj;
+                    else {
+                        const uint32_t ps = P.order[j - 1];
+                        z[k] = lj - P.len[ps] + (uint32_t)__builtin_ctz(~P.code[ps]);  // trailing ones
+                    }
+                    sy[k] = sym;
+                    sum += z[k] + 9;
                 }
             }
-            uint64_t ex = block_excl_sum_u64<kPackNT>(tid < m ? (uint64_t)(zj + 9) : 0ull, sh, nullptr);
-            if (tid < m) put_bits(st, tree0 + (uint32_t)ex + zj, 0x100u | sym, 9);
+            uint32_t tot;
+            uint32_t ex = wave_excl_sum(sum, tot);
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++) {
+                if (4 * lane + k < m) {
+                    put_bits(st, tree0 + ex + z[k], 0x100u | sy[k], 9);
+                    ex += z[k] + 9;
+                }
+            }
             const uint32_t seek0 = tree0 + 10 * m - 1;
-            if (tid < nseg) put_bits(st, seek0 + tid * P.tbits, P.seg_bits[tid], P.tbits);
+            if (lane < nseg) put_bits(st, seek0 + lane * P.tbits, P.seg_bits[lane], P.tbits);
         }
         __syncthreads();
-        flush_bits(st, bit0, nbits, outw);
+        const uint32_t tail = ((o + hdr_bits) & 31u) ? nw - 1 : ~0u;
+        store_words(st, nw, bit0 >> 5, o != 0, tail, outw);
         return;
     }
-    // segment s = y-1: tokens of the plane's symbols; its start = header +
-    // the lengths of the segments before it (a wave sum in every wave)
+    // segment s = y-1: it starts after the header and segments 0 .. s-1
+    const uint32_t s = y - 1;
+    const uint32_t czr = P.czr, wz = P.wz;
+    const uint32_t M = P.seg_M[s];
     uint32_t start;
     {
-        uint32_t v = lane < s ? seg_lane : 0u;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        start = hdr_bits + v;
+        uint32_t t;
+        (void)wave_excl_sum(lane < s ? P.seg_bits[lane & 31u] : 0u, t);
+        start = hdr_bits + t;
     }
-    const uint32_t nbits = nbits_s;
     const uint64_t abit = bit0 + start;
     const uint32_t o = (uint32_t)(abit & 31u);
-    const uint32_t nw = (o + nbits + 31) >> 5;
-    for (uint32_t i = tid; i < nw + 1; i += blockDim.x) st[i] = 0;
-    if (tid < 256) {
-        s_code[tid] = code_t;
-        s_len[tid] = (uint8_t)len_t;
+    const uint64_t w0 = abit >> 5;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k++) {
+        S.code[lane + 64 * k] = P.code[lane + 64 * k];
+        S.len[lane + 64 * k] = P.len[lane + 64 * k];
     }
-    const uint8_t *syms = ws + sym_off + (uint64_t)plane * plane_stride(pp * pn);
+    for (uint32_t i = lane; i < kPackStage; i += 64) st[i] = 0;
+    const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride(P.p * P.n);
     __syncthreads();
     const uint32_t Bb = (1u << wz) - 1u;
-    const uint32_t lz = s_len[czr];
-    // a multiple of 4 symbols per thread, <= kPackPT for M <= 6144: the
-    // thread's symbols are whole aligned words of the plane (its stride is
-    // padded to 16 bytes, so the last word stays inside it)
-    const uint32_t chunk = (((M + kPackNT - 1) / kPackNT) + 3u) & ~3u;
-    const uint32_t lo = tid * chunk;
-    uint32_t hi = lo + chunk;
-    if (hi > M) hi = M;
-    uint32_t lw[kPackPT / 4];  // the thread's symbols, 4 per register
-    int32_t lastnz = -1;
-#pragma unroll
-    for (uint32_t k = 0; k < kPackPT / 4; k++) {
-        const uint32_t ps = lo + 4 * k;
-        uint32_t w = (4 * k < chunk && ps < hi) ? *(const uint32_t *)(syms + ps) : 0u;
-        if (ps + 4 > hi) w &= ps < hi ? (1u << (8 * (hi - ps))) - 1u : 0u;  // hi - ps <= 3 here
-        lw[k] = w;
-        if (w) lastnz = (int32_t)(ps + (31u - (uint32_t)__builtin_clz(w)) / 8u);
-    }
-#define LOC(i) ((lw[(i) / 4] >> (8 * ((i) % 4))) & 0xffu)
-    int32_t prev = block_excl_max_i32<kPackNT>(lastnz, shi);
-    // token bits, branch-free: a symbol that ends a zero run (non-zero, or
-    // the segment's last) emits the run (one zero literal for length 1, else
-    // nd(L) digit tokens) and then itself when non-zero
+    const uint32_t lz = S.len[czr];
     const uint32_t tokz = lz + wz;
-    const uint32_t lit0 = s_len[0] + (czr == 0 ? wz : 0u);
+    const uint32_t lit0 = S.len[0] + (czr == 0 ? wz : 0u);
+    const uint32_t code0 = S.code[0], codez = S.code[czr];
     // nd(L) = 1 + #{k >= 1 : B + B^2 + ... + B^k < L}; 8 digits cover L <= 6144
     uint32_t thr[7];
     {
@@ -1102,89 +1125,104 @@ __device__ __forceinline__ void pack_item(const PlanHdr &H, const uint8_t *__res
             t += pw;
         }
     }
-    uint32_t bits = 0;
-    {
-        int32_t cur = prev;
-#pragma unroll
-        for (uint32_t i = 0; i < kPackPT; i++) {
-            const uint32_t v = LOC(i);
-            const int32_t ps = (int32_t)(lo + i);
-            const bool valid = (uint32_t)ps < hi;
-            const bool term = valid && (v != 0 || (uint32_t)ps == M - 1);
-            const int32_t L = v ? (ps - cur - 1) : (ps - cur);
-            uint32_t nd = 1;
-#pragma unroll
-            for (int k = 0; k < 7; k++) nd += thr[k] < (uint32_t)L;
-            const uint32_t runb = (L == 1) ? lit0 : (L >= 2 ? nd * tokz : 0u);
-            const uint32_t litb = v ? s_len[v] + (v == czr ? wz : 0u) : 0u;
-            bits += term ? runb + litb : 0u;
-            cur = (valid && v) ? ps : cur;
+    int32_t cur = -1;     // position of the last non-zero symbol before the round
+    uint32_t bp = o;      // bit position of the round's first token in the staging
+    uint64_t wdone = 0;   // stream words stored so far (staging word 0 = stream word w0 + wdone)
+    for (uint32_t r0 = 0; r0 < M; r0 += kPackRound) {
+        const uint32_t lo = r0 + kPackK * lane;
+        const uint32_t hi = min(lo + kPackK, M);
+        // 8 symbols of the lane (the plane stride is a multiple of 16 bytes,
+        // so the 8-byte load stays in the plane); symbols >= hi read as 0
+        uint2 q = make_uint2(0, 0);
+        if (lo < M) q = *(const uint2 *)(syms + lo);
+        if (hi - lo < 8 && lo < M) {
+            const uint32_t nb = hi - lo;  // 1..7
+            if (nb < 4) { q.x &= (1u << (8 * nb)) - 1u; q.y = 0; }
+            else if (nb > 4) q.y &= (1u << (8 * (nb - 4))) - 1u;
+            else q.y = 0;
         }
-    }
-    uint64_t off = block_excl_sum_u64<kPackNT>(bits, sh, nullptr);
-    // pass 2: write
-    {
-        uint32_t bp = o + (uint32_t)off;
-        int32_t cur = prev;
+        int32_t lastnz = -1;
+        if (q.y) lastnz = (int32_t)(lo + 4 + (31u - (uint32_t)__builtin_clz(q.y)) / 8u);
+        else if (q.x) lastnz = (int32_t)(lo + (31u - (uint32_t)__builtin_clz(q.x)) / 8u);
+        int32_t mx;
+        const int32_t prev = max(cur, wave_excl_max(lastnz, mx));
+#define LOC(i) ((((i) < 4 ? q.x : q.y) >> (8 * ((i) & 3))) & 0xffu)
+        // token bits, branch-free: a symbol that ends a zero run (non-zero,
+        // or the segment's last) emits the run (one zero literal for length
+        // 1, else nd(L) digit tokens) and then itself when non-zero
+        uint32_t bits = 0;
+        {
+            int32_t c = prev;
 #pragma unroll
-        for (uint32_t i = 0; i < kPackPT; i++) {
-            const uint32_t v = LOC(i);
-            const int32_t ps = (int32_t)(lo + i);
-            const bool valid = (uint32_t)ps < hi;
-            const bool term = valid && (v != 0 || (uint32_t)ps == M - 1);
-            const int32_t L = v ? (ps - cur - 1) : (ps - cur);
-            cur = (valid && v) ? ps : cur;
-            if (!term) continue;
-            if (L == 1) {
-                put_bits(st, bp, s_code[0], s_len[0]);  // literal zero (counter 0 when it is C_zr)
-                bp += lit0;
-            } else if (L >= 2) {
-                // bijective base-(2^wz - 1) digits, most significant first
-                uint32_t dg[8], nd = 0, x = (uint32_t)L;
-                while (x > 0 && nd < 8) { uint32_t q = (x - 1) / Bb; dg[nd++] = x - q * Bb; x = q; }
-                for (int k = (int)nd - 1; k >= 0; k--) {
-                    put_bits(st, bp, s_code[czr], lz);
-                    put_bits(st, bp + lz, dg[k], wz);
-                    bp += tokz;
+            for (uint32_t i = 0; i < kPackK; i++) {
+                const uint32_t v = LOC(i);
+                const int32_t ps = (int32_t)(lo + i);
+                const bool valid = (uint32_t)ps < hi;
+                const bool term = valid && (v != 0 || (uint32_t)ps == M - 1);
+                const int32_t L = v ? (ps - c - 1) : (ps - c);
+                uint32_t nd = 1;
+#pragma unroll
+                for (int k = 0; k < 7; k++) nd += thr[k] < (uint32_t)L;
+                const uint32_t runb = (L == 1) ? lit0 : (L >= 2 ? nd * tokz : 0u);
+                const uint32_t litb = v ? S.len[v] + (v == czr ? wz : 0u) : 0u;
+                bits += term ? runb + litb : 0u;
+                c = (valid && v) ? ps : c;
+            }
+        }
+        uint32_t rbits;
+        const uint32_t off = wave_excl_sum(bits, rbits);
+        {
+            uint32_t b = bp + off;
+            int32_t c = prev;
+#pragma unroll
+            for (uint32_t i = 0; i < kPackK; i++) {
+                const uint32_t v = LOC(i);
+                const int32_t ps = (int32_t)(lo + i);
+                const bool valid = (uint32_t)ps < hi;
+                const bool term = valid && (v != 0 || (uint32_t)ps == M - 1);
+                const int32_t L = v ? (ps - c - 1) : (ps - c);
+                c = (valid && v) ? ps : c;
+                if (!term) continue;
+                if (L == 1) {
+                    put_bits(st, b, code0, S.len[0]);  // literal zero (counter 0 when it is C_zr)
+                    b += lit0;
+                } else if (L >= 2) {
+                    // bijective base-(2^wz - 1) digits, most significant first
+                    uint32_t dg[8], nd = 0, x = (uint32_t)L;
+                    while (x > 0 && nd < 8) { uint32_t qq = (x - 1) / Bb; dg[nd++] = x - qq * Bb; x = qq; }
+                    for (int k = (int)nd - 1; k >= 0; k--) {
+                        put_bits(st, b, codez, lz);
+                        put_bits(st, b + lz, dg[k], wz);
+                        b += tokz;
+                    }
+                }
+                if (v) {
+                    const uint32_t lv = S.len[v];
+                    put_bits(st, b, S.code[v], lv);
+                    b += lv + (v == czr ? wz : 0u);
                 }
             }
-            if (v) {
-                const uint32_t lv = s_len[v];
-                put_bits(st, bp, s_code[v], lv);
-                bp += lv + (v == czr ? wz : 0u);
-            }
         }
-    }
 #undef LOC
-    __syncthreads();
-    flush_bits(st, abit, nbits, outw);
-}
-
-__global__ void __launch_bounds__(kPackNT) k_enc_pack(PlanHdr H, const uint8_t *__restrict__ ws,
-                                                  uint8_t *__restrict__ out)
-{
-    __shared__ PackShared S;
-    // the last segments (the low, dense planes) are the longest items: they
-    // are dispatched first, the headers last
-    pack_item(H, ws, out, S, blockIdx.x, gridDim.y - 1u - blockIdx.y);
-}
-
-// Persistent variant: segment-major items over a fixed grid.
-__global__ void __launch_bounds__(kPackNT) k_enc_pack_pers(PlanHdr H, const uint8_t *__restrict__ ws,
-                                                       uint8_t *__restrict__ out)
-{
-    __shared__ PackShared S;
-    const uint64_t nitems = (uint64_t)H.total_blocks * (H.max_dmax + 1);
-    for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-        const uint32_t blk = (uint32_t)(item % H.total_blocks), y = (uint32_t)(item / H.total_blocks);
-        const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
-        if (y > P.nseg) continue;
         __syncthreads();
-        pack_item(H, ws, out, S, blk, y);
+        // the round's complete words go out; the partial one is carried
+        const uint32_t end = bp + rbits;
+        const uint32_t nfull = end >> 5;
+        store_words(st, nfull, w0 + wdone, wdone == 0 && o != 0, ~0u, outw);
+        __syncthreads();
+        const uint32_t carry = st[nfull];
+        const uint32_t used = (end + 63) >> 5;  // words the round may have touched
+        for (uint32_t i = lane; i < used; i += 64) st[i] = 0;
+        __syncthreads();
+        if (lane == 0) st[0] = carry;
+        __syncthreads();
+        bp = end & 31u;
+        wdone += nfull;
+        cur = max(cur, mx);
     }
+    // the segment's last, partial word is shared with what follows it
+    if (bp && lane == 0 && st[0]) atomicOr(&outw[w0 + wdone], __builtin_bswap32(st[0]));
 }
-
-
 
 // ---------------------------------------------------------------- launch
 hipError_t launch_forward_level(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
@@ -1233,15 +1271,10 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             hipLaunchKernelGGL(k_enc_tile_finish, dim3(H.n_tiles + (H.total_blocks + 3) / 4), dim3(256), 0, stream, H,
                                d_plan, d_ws, d_out);
         } else if (st == ENC_PACK) {
+            // item y = 0 is the header, y = 1 .. nseg the segments; nseg <= d <= the tile's plane bound
             if (H.total_blocks)
-            {
-                if (H.blocks_per_cu)
-                    hipLaunchKernelGGL(k_enc_pack_pers, dim3(H.blk_grid), dim3(kPackNT), 0, stream, H, d_ws, d_out);
-                else
-                    // item y = 0 is the header, y = 1 .. nseg the segments; nseg <= d <= the tile's plane bound
-                    hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, H.max_dmax + 1), dim3(kPackNT), 0, stream, H,
-                                       d_ws, d_out);
-            }
+                hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, H.max_dmax + 1), dim3(64), 0, stream, H, d_ws,
+                                   d_out);
         }
     }
     return hipGetLastError();
