@@ -54,8 +54,10 @@ def parse():
                     help="single: one 4096x4096 image (default); batch: 4096 uneven tiles; "
                          "serve: tile-decode requests against an HBM-resident slide")
     ap.add_argument("--slide", type=str, default="192x160",
-                    help="serve: slide size in 512-px tiles (default 98304x81920; a pyramid is one "
-                         "stream, at most 65535 px per side)")
+                    help="serve: slide size in 512-px tiles (default 98304x81920)")
+    ap.add_argument("--sub", type=str, default="48x40",
+                    help="serve, pyramid layout: tiles per sub-pyramid stream when the slide exceeds "
+                         "65535 px a side (default 24576x20480 px)")
     ap.add_argument("--layout", choices=["tiles", "pyramid"], default="tiles",
                     help="serve: the slide as independent 512-px tiles, or as one pyramid (region decode)")
     ap.add_argument("--rates", type=str, default="2000,5000,10000,20000", help="serve: requests/s")
@@ -521,6 +523,7 @@ def _batch_run(tiles, best, args, steps, warmup):
         if t["qstep"] == 1 and not np.array_equal(host[o:o + n], t["pixels"].reshape(-1)):
             raise SystemExit(f"lossless tile {i} did not round-trip")
     sbytes = sum(len(s) for s in streams)
+    plain = _plain_per_tile(descs, d_pix, streams, jobs)
     stages = {}
     # one stage-by-stage pass with events, for the per-stage breakdown
     for kind, obj, src, names in (("enc", enc, d_pix, isx.stage_names(0)), ("dec", dec, enc.out, isx.stage_names(1))):
@@ -544,7 +547,43 @@ def _batch_run(tiles, best, args, steps, warmup):
             "mpx_s": round(px / 1e6 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4), "steps": steps,
             "pixels": px, "stream_bytes": sbytes,
             "event_ms_per_step": round(a.elapsed_time(b) / steps, 4),
-            "tuning": best or "default", "stage_ms": stages, "cpu_oracle": cpu}
+            "tuning": best or "default", "stage_ms": stages, "plain_per_tile": plain, "cpu_oracle": cpu}
+
+
+def _plain_per_tile(descs, d_pix, streams, jobs, n=256):
+    """The plain per-image path on tiles of the same batch: each sampled tile
+    encoded and decoded by its own plan and launch sequence (one tile per
+    call), outputs checked against the batched run's; MP/s over the sample."""
+    import torch
+    from paper_2005_08713_amd import isx
+    rng = np.random.default_rng(7)
+    idx = sorted(rng.choice(len(descs), size=min(n, len(descs)), replace=False).tolist())
+    pairs = []
+    for i in idx:
+        enc = isx.Encoder([descs[i]])
+        j = isx.DecodeJob()
+        j.tile = descs[i]
+        j.in_offset, j.in_bytes = 0, enc.capacity
+        j.out_offset, j.out_row_stride_bytes, j.target_level = 0, descs[i].width * 3, 0
+        pairs.append((i, enc, isx.Decoder([j], descs[i].width * descs[i].height * 3)))
+    for _, enc, dec in pairs:  # warm-up, and the outputs
+        enc.run(d_pix)
+        dec.run(enc.out)
+    torch.cuda.synchronize()
+    for i, enc, dec in pairs:
+        if enc.streams()[0] != streams[i]:
+            raise SystemExit(f"plain per-tile stream {i} differs from the batched one")
+    t0 = time.perf_counter()
+    for _, enc, dec in pairs:
+        enc.run(d_pix)
+        dec.run(enc.out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    px = sum(descs[i].width * descs[i].height for i in idx)
+    del pairs
+    return {"mpx_s": round(px / 1e6 / dt, 1), "tiles": len(idx), "pixels": px,
+            "what": "each sampled tile encoded and decoded by its own plan (one tile per call), "
+                    "streams equal to the batched run's"}
 
 
 def leg_served(args):
@@ -681,11 +720,11 @@ def bench_serve(args):
     torch.cuda.set_device(0)
     tx, ty = (int(v) for v in args.slide.split("x"))
     pyr = args.layout == "pyramid"
-    if pyr and max(tx, ty) * 512 > 65535:
-        raise SystemExit("a pyramid slide is one stream: at most 65535 px per side (--slide 127x127 or less)")
-    log(f"[serve] building {tx}x{ty}-tile slide ({args.layout})")
+    # a stream is at most 65535 px a side: larger slides are a grid of pyramids
+    sub = tuple(int(v) for v in args.sub.split("x")) if max(tx, ty) * 512 > 65535 else None
+    log(f"[serve] building {tx}x{ty}-tile slide ({args.layout}{f', sub-pyramids of {sub} tiles' if pyr and sub else ''})")
     if pyr:
-        slide = serve.PyramidSlide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log)
+        slide = serve.PyramidSlide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log, sub=sub)
         enc_bytes = slide.size
     else:
         slide = serve.Slide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log)
@@ -713,7 +752,8 @@ def bench_serve(args):
         log(f"[serve] lambda={lam:.0f}/s: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms, "
             f"{st['decoded_mpx_s']:.0f} MP/s decoded, {st['batches']} batches")
     best = max(rows, key=lambda r: r["decoded_mpx_s"])
-    layout = (f"one {tx * 512}x{ty * 512} RGB pyramid (6 levels), region decode" if pyr else
+    layout = ((f"{tx * 512}x{ty * 512} RGB slide as {len(slide.descs)} pyramid stream(s) of up to "
+               f"{slide.sx * 512}x{slide.sy * 512} (6 levels), region decode") if pyr else
               f"{tx}x{ty} slide of 512x512 RGB tiles (6 levels)")
     out = {"metric": "p99 tile-decode ms (served slide, continuous batching)",
            "value": round(rows[-1]["p99_ms"], 3), "unit": "ms", "n_gpus": 1, "steps": len(rows),
@@ -729,11 +769,12 @@ def bench_serve(args):
 
 
 def _pyramid_checks(args, slide, srv, trace):
-    """Served views of the one-pyramid slide: equal to the same view decoded
-    alone; at zoom 0 equal to the slide's pixels; at zoom z >= 1 equal to
-    the crop of the GPU's whole-slide level-z decode (region decode equals
-    that crop at any size); and, for views at zoom >= 4, equal to the
-    oracle's crop of its own level-z decode (timed: the CPU baseline)."""
+    """Served views of the pyramid slide: equal to the same view decoded
+    alone; equal to the stitched crops of the GPU's whole-stream level-z
+    decodes of the sub-pyramids they touch (region decode equals that crop at
+    any size); at zoom 0 of a one-stream slide equal to the slide's pixels;
+    and, for views at zoom >= 4, equal to the crops of the oracle's own
+    level-z decodes (timed: the CPU baseline)."""
     import torch
     from paper_2005_08713_amd import isx, serve
     sample = trace[:24] + [t for t in trace if t[0] >= 4][:4]
@@ -749,53 +790,65 @@ def _pyramid_checks(args, slide, srv, trace):
     srv.run(reqs, check=check)
     T = slide.tile
 
-    def expect(r, full):
-        x0, y0, w, h = slide.region(r.z, r.X, r.Y)
+    def expect(r, fetch):
         e = np.zeros((T, T, 3), np.uint8)
-        e[:h, :w] = full[y0:y0 + h, x0:x0 + w]
+        for (k, x0, y0, w, h, dx, dy) in slide.parts(r.z, r.X, r.Y):
+            e[dy:dy + h, dx:dx + w] = fetch(k, r.z)[y0:y0 + h, x0:x0 + w]
         return e.reshape(-1)
 
-    fulls = {}
+    gpu_full = {}
+
+    def gpu_level(k, z):
+        if (k, z) not in gpu_full:
+            d = slide.descs[k]
+            ow, oh = isx.out_size(d.width, d.height, z)
+            j = isx.DecodeJob()
+            j.tile, j.in_offset, j.in_bytes = d, slide.offs[k], slide.sizes[k]
+            j.out_offset, j.out_row_stride_bytes, j.target_level = 0, ow * 3, z
+            dec = isx.Decoder([j], ow * oh * 3)
+            dec.run(slide.arena)
+            torch.cuda.synchronize()
+            if int(dec.status[0]) != 0:
+                raise SystemExit("whole-stream decode failed")
+            gpu_full[(k, z)] = dec.out.cpu().numpy().reshape(oh, ow, 3)
+            del dec
+            torch.cuda.empty_cache()
+        return gpu_full[(k, z)]
+
     for r in reqs[:12]:
-        if r.z == 0:
-            full = slide.image
+        exp = expect(r, gpu_level)
+        if not np.array_equal(exp, got[r.rid]):
+            raise SystemExit(f"served pyramid view {r} differs from the whole-stream decodes")
+        if r.z == 0 and slide.image is not None:
             x0, y0, w, h = slide.region(0, r.X, r.Y)
             e = np.zeros((T, T, 3), np.uint8)
-            e[:h, :w] = full[y0:y0 + h, x0:x0 + w].cpu().numpy()
-            exp = e.reshape(-1)
-        else:
-            if r.z not in fulls:
-                ow, oh = isx.out_size(slide.W, slide.H, r.z)
-                j = isx.DecodeJob()
-                j.tile, j.in_offset, j.in_bytes = slide.desc, 0, slide.size
-                j.out_offset, j.out_row_stride_bytes, j.target_level = 0, ow * 3, r.z
-                dec = isx.Decoder([j], ow * oh * 3)
-                dec.run(slide.arena)
-                torch.cuda.synchronize()
-                if int(dec.status[0]) != 0:
-                    raise SystemExit("whole-slide decode failed")
-                fulls[r.z] = dec.out.cpu().numpy().reshape(oh, ow, 3)
-                del dec
-            exp = expect(r, fulls[r.z])
-        if not np.array_equal(exp, got[r.rid]):
-            raise SystemExit(f"served pyramid view {r} differs from the whole-slide decode")
+            e[:h, :w] = slide.image[y0:y0 + h, x0:x0 + w].cpu().numpy()
+            if not np.array_equal(e.reshape(-1), got[r.rid]):
+                raise SystemExit(f"served pyramid view {r} differs from the slide's pixels")
         alone = srv.decode_alone(serve.Request(r.rid, r.z, r.X, r.Y))
         if not np.array_equal(alone, got[r.rid]):
             raise SystemExit(f"served pyramid view {r} differs alone vs in the mix")
-    log("[serve] pyramid views equal the whole-slide decode and their lone decodes")
+    gpu_full.clear()
+    log("[serve] pyramid views equal the whole-stream decodes and their lone decodes")
     if args.no_cpu:
         return None
     import oracle
-    blob = slide.arena.cpu().numpy().tobytes()
+    ora = {}
+
+    def oracle_level(k, z):
+        if (k, z) not in ora:
+            o, n = slide.offs[k], slide.sizes[k]
+            ora[(k, z)] = oracle.decode_tile(slide.arena[o:o + n].cpu().numpy().tobytes(), z)
+        return ora[(k, z)]
     deep = [r for r in reqs if r.z >= 4][:4]
     t0 = time.perf_counter()
     for r in deep:
-        if not np.array_equal(expect(r, oracle.decode_tile(blob, r.z)), got[r.rid]):
+        if not np.array_equal(expect(r, oracle_level), got[r.rid]):
             raise SystemExit(f"served pyramid view {r} differs from the oracle")
     t1 = time.perf_counter()
     log("[serve] oracle parity ok on views at zoom >= 4")
     return {"value": round(len(deep) / (t1 - t0), 3), "unit": "requests/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle: {len(deep)} views at zoom >= 4, each the crop of its whole level-z decode"}
+            "sample": f"oracle: {len(deep)} views at zoom >= 4, each from its streams' level-z decodes"}
 
 
 if __name__ == "__main__":

@@ -210,6 +210,15 @@ int32_t isx_decode_run(const void *h_plan, const void *d_plan, const void *d_enc
 int32_t isx_decode_run_noalloc(const void *h_plan, const void *d_plan, const void *d_encoded,
                                void *d_pixels_out, int32_t *d_status, void *stream);
 
+/* Sizes recorded in a plan built by any isx_*_plan_build call (host
+ * memory): the plan's length in bytes and the workspace its runs need (the
+ * same figures as isx_*_plan_bytes and isx_*_workspace_bytes for its tiles
+ * or jobs, without planning them again).  A caller may build into a buffer
+ * of a known capacity and read the sizes back here.  Returns ISX_OK, or
+ * ISX_E_INVALID_ARG for null pointers or bytes that are not a plan of this
+ * library. */
+int32_t isx_plan_info(const void *h_plan, uint64_t *plan_bytes, uint64_t *workspace_bytes);
+
 /* Launch parameters of a plan.  They change speed only: the encoded bytes and
  * decoded pixels are identical for every setting.
  *  transform_tile: quads per side of a lifting tile staged in LDS, 16 or 32

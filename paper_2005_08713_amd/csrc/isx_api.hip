@@ -76,6 +76,10 @@ int tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb, const
 {
     TileGeo &T = tb.g;
     memset(&T, 0, sizeof(T));
+    tb.arena_elems = 0; tb.tmp_elems[0] = tb.tmp_elems[1] = 0; tb.sym_bytes = 0;
+    tb.sel.clear();
+    memset(tb.kx0, 0, sizeof(tb.kx0)); memset(tb.kx1, 0, sizeof(tb.kx1));
+    memset(tb.ky0, 0, sizeof(tb.ky0)); memset(tb.ky1, 0, sizeof(tb.ky1));
     T.pix_offset = d.pixel_offset;
     T.pix_stride = d.row_stride_bytes;
     T.width = d.width; T.height = d.height;
@@ -217,9 +221,14 @@ int tile_geometry(const isx_tile_desc &d, int target_level, TileBuild &tb, const
     return ISX_OK;
 }
 
+// A plan: the header, and the plan bytes in `bytes`, or written straight
+// into a caller's buffer (dst, cap), or not at all (sizes only).
 struct Plan {
     std::vector<uint8_t> bytes;
     PlanHdr H;
+    uint8_t *dst = nullptr;
+    uint64_t cap = 0;
+    bool sizes_only = false;
 };
 
 int device_cus()
@@ -236,7 +245,13 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     if (mode == MODE_DECODE && !jobs && !regions) return ISX_E_INVALID_ARG;
     auto job_at = [&](int32_t i) -> const isx_decode_job & { return regions ? regions[i].job : jobs[i]; };
     if (n < 1) return ISX_E_INVALID_ARG;
-    std::vector<TileBuild> tb((size_t)n);
+    // per-thread scratch kept between calls: planning large batches often
+    // (a serving loop) then touches no fresh pages
+    static thread_local std::vector<TileBuild> tls_tb;
+    static thread_local std::vector<WorkItem> tls_items;
+    static thread_local std::vector<uint32_t> tls_big, tls_small;
+    if (tls_tb.size() < (size_t)n) tls_tb.resize((size_t)n);
+    TileBuild *tb = tls_tb.data();
     PlanHdr &H = P.H;
     memset(&H, 0, sizeof(H));
     H.magic = kPlanMagic;
@@ -280,8 +295,21 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
             rgp = &rg;
             ow = R.width;  // output row width
         }
-        rc = tile_geometry(d, z, tb[i], rgp);
-        if (rc) return rc;
+        // consecutive tiles of one shape (a served batch, a slide) share
+        // their geometry: computed once, copied after
+        const isx_tile_desc *dp = i ? &(mode == MODE_ENCODE ? descs[i - 1] : job_at(i - 1).tile) : nullptr;
+        const bool same = dp && !regions && dp->width == d.width && dp->height == d.height &&
+                          dp->row_stride_bytes == d.row_stride_bytes && dp->channels == d.channels &&
+                          dp->bytes_per_sample == d.bytes_per_sample && dp->bits == d.bits &&
+                          dp->levels == d.levels && dp->colour_transform == d.colour_transform &&
+                          dp->qstep == d.qstep && tb[i - 1].g.target_level == (uint8_t)z;
+        if (same) {
+            tb[i] = tb[i - 1];
+            tb[i].g.pix_offset = d.pixel_offset;
+        } else {
+            rc = tile_geometry(d, z, tb[i], rgp);
+            if (rc) return rc;
+        }
         TileGeo &T = tb[i].g;
         if (mode == MODE_DECODE) {
             const isx_decode_job &j = job_at(i);
@@ -340,7 +368,8 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     }
     H.ws_bytes = o;
     // work lists
-    std::vector<WorkItem> items;
+    std::vector<WorkItem> &items = tls_items;
+    items.clear();
     auto add_level = [&](int lvl, bool inverse) {
         H.lvl_first[lvl] = (uint32_t)items.size();
         uint32_t wg = 0;
@@ -396,7 +425,9 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         H.fin_wgs = wg;
     }
     // block lists by size class (symbol kernel launch shape)
-    std::vector<uint32_t> big, small;
+    std::vector<uint32_t> &big = tls_big, &small = tls_small;
+    big.clear();
+    small.clear();
     for (int32_t i = 0; i < n; i++) {
         const TileGeo &T = tb[i].g;
         for (uint32_t b = 0; b < T.nblocks; b++) {
@@ -424,16 +455,25 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         uint64_t extra = al(H.plan_bytes);
         H.ws_bytes += extra;
     }
-    P.bytes.assign(H.plan_bytes, 0);
-    memcpy(P.bytes.data(), &H, sizeof(H));
-    for (int32_t i = 0; i < n; i++) memcpy(P.bytes.data() + H.tiles_off + (uint64_t)i * sizeof(TileGeo), &tb[i].g, sizeof(TileGeo));
-    if (!items.empty()) memcpy(P.bytes.data() + H.work_off, items.data(), items.size() * sizeof(WorkItem));
-    if (!big.empty()) memcpy(P.bytes.data() + H.list_off, big.data(), big.size() * sizeof(uint32_t));
+    if (P.sizes_only) return ISX_OK;
+    uint8_t *out;
+    if (P.dst) {
+        if (P.cap < H.plan_bytes) return ISX_E_INVALID_ARG;
+        out = P.dst;
+        memset(out, 0, H.plan_bytes);
+    } else {
+        P.bytes.assign(H.plan_bytes, 0);
+        out = P.bytes.data();
+    }
+    memcpy(out, &H, sizeof(H));
+    for (int32_t i = 0; i < n; i++) memcpy(out + H.tiles_off + (uint64_t)i * sizeof(TileGeo), &tb[i].g, sizeof(TileGeo));
+    if (!items.empty()) memcpy(out + H.work_off, items.data(), items.size() * sizeof(WorkItem));
+    if (!big.empty()) memcpy(out + H.list_off, big.data(), big.size() * sizeof(uint32_t));
     if (!small.empty())
-        memcpy(P.bytes.data() + H.list_off + big.size() * sizeof(uint32_t), small.data(), small.size() * sizeof(uint32_t));
+        memcpy(out + H.list_off + big.size() * sizeof(uint32_t), small.data(), small.size() * sizeof(uint32_t));
     for (int32_t i = 0; i < n; i++)
         if (!tb[i].sel.empty())
-            memcpy(P.bytes.data() + tb[i].g.sel_off, tb[i].sel.data(), tb[i].sel.size() * sizeof(SelBlock));
+            memcpy(out + tb[i].g.sel_off, tb[i].sel.data(), tb[i].sel.size() * sizeof(SelBlock));
     return ISX_OK;
 }
 
@@ -555,6 +595,7 @@ uint64_t isx_max_encoded_bytes(const isx_tile_desc *h_descs, int32_t n_tiles)
 uint64_t isx_encode_workspace_bytes(const isx_tile_desc *h_descs, int32_t n_tiles)
 {
     Plan P;
+    P.sizes_only = true;
     if (!h_descs || build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P)) return 0;
     return P.H.ws_bytes;
 }
@@ -562,6 +603,7 @@ uint64_t isx_encode_workspace_bytes(const isx_tile_desc *h_descs, int32_t n_tile
 uint64_t isx_decode_workspace_bytes(const isx_decode_job *h_jobs, int32_t n_jobs)
 {
     Plan P;
+    P.sizes_only = true;
     if (!h_jobs || build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P)) return 0;
     return P.H.ws_bytes;
 }
@@ -569,6 +611,7 @@ uint64_t isx_decode_workspace_bytes(const isx_decode_job *h_jobs, int32_t n_jobs
 uint64_t isx_encode_plan_bytes(const isx_tile_desc *h_descs, int32_t n_tiles)
 {
     Plan P;
+    P.sizes_only = true;
     if (!h_descs || build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P)) return 0;
     return P.H.plan_bytes;
 }
@@ -577,10 +620,10 @@ int32_t isx_encode_plan_build(const isx_tile_desc *h_descs, int32_t n_tiles, voi
 {
     Plan P;
     if (!h_descs || !h_plan) return ISX_E_INVALID_ARG;
+    P.dst = (uint8_t *)h_plan;
+    P.cap = plan_bytes;
     int rc = build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P);
     if (rc) return rc;
-    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
-    memcpy(h_plan, P.bytes.data(), P.bytes.size());
     return ISX_OK;
 }
 
@@ -589,10 +632,10 @@ int32_t isx_encode_plan_build_tuned(const isx_tile_desc *h_descs, int32_t n_tile
 {
     Plan P;
     if (!h_descs || !h_plan) return ISX_E_INVALID_ARG;
+    P.dst = (uint8_t *)h_plan;
+    P.cap = plan_bytes;
     int rc = build_plan(MODE_ENCODE, h_descs, nullptr, n_tiles, P, tuning);
     if (rc) return rc;
-    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
-    memcpy(h_plan, P.bytes.data(), P.bytes.size());
     return ISX_OK;
 }
 
@@ -601,16 +644,17 @@ int32_t isx_decode_plan_build_tuned(const isx_decode_job *h_jobs, int32_t n_jobs
 {
     Plan P;
     if (!h_jobs || !h_plan) return ISX_E_INVALID_ARG;
+    P.dst = (uint8_t *)h_plan;
+    P.cap = plan_bytes;
     int rc = build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P, tuning);
     if (rc) return rc;
-    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
-    memcpy(h_plan, P.bytes.data(), P.bytes.size());
     return ISX_OK;
 }
 
 uint64_t isx_decode_plan_bytes(const isx_decode_job *h_jobs, int32_t n_jobs)
 {
     Plan P;
+    P.sizes_only = true;
     if (!h_jobs || build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P)) return 0;
     return P.H.plan_bytes;
 }
@@ -619,10 +663,10 @@ int32_t isx_decode_plan_build(const isx_decode_job *h_jobs, int32_t n_jobs, void
 {
     Plan P;
     if (!h_jobs || !h_plan) return ISX_E_INVALID_ARG;
+    P.dst = (uint8_t *)h_plan;
+    P.cap = plan_bytes;
     int rc = build_plan(MODE_DECODE, nullptr, h_jobs, n_jobs, P);
     if (rc) return rc;
-    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
-    memcpy(h_plan, P.bytes.data(), P.bytes.size());
     return ISX_OK;
 }
 
@@ -631,6 +675,16 @@ static int check_plan(const void *h_plan, int mode)
     if (!h_plan) return ISX_E_INVALID_ARG;
     const PlanHdr *H = (const PlanHdr *)h_plan;
     if (H->magic != kPlanMagic || H->mode != (uint32_t)mode) return ISX_E_INVALID_ARG;
+    return ISX_OK;
+}
+
+int32_t isx_plan_info(const void *h_plan, uint64_t *plan_bytes, uint64_t *workspace_bytes)
+{
+    if (!h_plan || !plan_bytes || !workspace_bytes) return ISX_E_INVALID_ARG;
+    const PlanHdr *H = (const PlanHdr *)h_plan;
+    if (H->magic != kPlanMagic || (H->mode != MODE_ENCODE && H->mode != MODE_DECODE)) return ISX_E_INVALID_ARG;
+    *plan_bytes = H->plan_bytes;
+    *workspace_bytes = H->ws_bytes;
     return ISX_OK;
 }
 
@@ -838,6 +892,7 @@ int32_t isx_stream_block_offsets(const void *h_head, uint64_t head_bytes, uint64
 uint64_t isx_region_workspace_bytes(const isx_region_job *h_jobs, int32_t n_jobs)
 {
     Plan P;
+    P.sizes_only = true;
     if (!h_jobs || build_plan(MODE_DECODE, nullptr, nullptr, n_jobs, P, nullptr, h_jobs)) return 0;
     return P.H.ws_bytes;
 }
@@ -845,6 +900,7 @@ uint64_t isx_region_workspace_bytes(const isx_region_job *h_jobs, int32_t n_jobs
 uint64_t isx_region_plan_bytes(const isx_region_job *h_jobs, int32_t n_jobs)
 {
     Plan P;
+    P.sizes_only = true;
     if (!h_jobs || build_plan(MODE_DECODE, nullptr, nullptr, n_jobs, P, nullptr, h_jobs)) return 0;
     return P.H.plan_bytes;
 }
@@ -854,10 +910,10 @@ int32_t isx_region_plan_build(const isx_region_job *h_jobs, int32_t n_jobs, cons
 {
     Plan P;
     if (!h_jobs || !h_plan) return ISX_E_INVALID_ARG;
+    P.dst = (uint8_t *)h_plan;
+    P.cap = plan_bytes;
     int rc = build_plan(MODE_DECODE, nullptr, nullptr, n_jobs, P, tuning, h_jobs);
     if (rc) return rc;
-    if (plan_bytes < P.bytes.size()) return ISX_E_INVALID_ARG;
-    memcpy(h_plan, P.bytes.data(), P.bytes.size());
     return ISX_OK;
 }
 

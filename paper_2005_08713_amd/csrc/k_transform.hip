@@ -687,11 +687,19 @@ __device__ inline int32_t rgb_channel(uint32_t R, uint32_t G, uint32_t B)
     return CH == 0 ? t + (cg >> 1) : (CH == 1 ? co : cg);
 }
 
-// Window of an interior tile at level 1 from interleaved RGB u8 pixels: each
-// task loads 12 bytes (4 pixels) of a window row; the window starts at pixel
+// Window of a tile at level 1 from interleaved RGB u8 pixels: each task
+// loads 12 bytes (4 pixels) of a window row; the window starts at pixel
 // 2 qx0 - 2 and the loads at 2 qx0 - 4, so every load is dword aligned.
+//
+// Any tile, including the image borders: the window's rows come through the
+// reflected row map, and a group of 4 window columns whose pixels all lie
+// inside the image is loaded as 12 bytes; the groups at the left and right
+// borders gather their 4 pixels through the reflected column map, byte by
+// byte, into the same 3-dword form.  `tb` is the tile's first pixel row and
+// dword aligned, as is the stride.
 template <int CT, int CH>
-__device__ inline void stage_rgb8(const uint8_t *base, uint32_t stride, int32_t *win)
+__device__ inline void stage_rgb8(const uint8_t *tb, uint32_t stride, const int32_t *rmap, const int32_t *cmap,
+                                  int qx0, int w, int32_t *win)
 {
     constexpr int NG = 18, NT = WN * NG, NK = (NT + 255) / 256;
     uint32_t d[NK][3];
@@ -700,8 +708,26 @@ __device__ inline void stage_rgb8(const uint8_t *base, uint32_t stride, int32_t 
         const int t = (int)threadIdx.x + 256 * k;
         if (t < NT) {
             const int lr = t / NG, g = t - lr * NG;
-            const uint32_t *p = (const uint32_t *)(base + (uint64_t)lr * stride + 12 * g);
-            d[k][0] = p[0]; d[k][1] = p[1]; d[k][2] = p[2];
+            const uint8_t *row = tb + (uint64_t)rmap[lr] * stride;
+            const int p0 = 2 * qx0 - 4 + 4 * g;
+            if (p0 >= 0 && p0 + 3 < w) {
+                const uint32_t *p = (const uint32_t *)(row + 3 * p0);
+                d[k][0] = p[0]; d[k][1] = p[1]; d[k][2] = p[2];
+            } else {
+                uint32_t q[3] = {0, 0, 0};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    int lc = 4 * g - 2 + e;
+                    lc = lc < 0 ? 0 : (lc > WN - 1 ? WN - 1 : lc);  // outside the window: never stored
+                    const uint8_t *px = row + 3 * cmap[lc];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        const int b = 3 * e + c;
+                        q[b >> 2] |= (uint32_t)px[c] << (8 * (b & 3));
+                    }
+                }
+                d[k][0] = q[0]; d[k][1] = q[1]; d[k][2] = q[2];
+            }
         }
     }
 #pragma unroll
@@ -757,18 +783,16 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
     if (level == 1) {
         const uint32_t C = T.channels, bps = T.bps;
         const uint8_t *tb = pix + T.pix_offset;
-        const bool fast = bps == 1 && C == 3 && T.ct != 0 && qx0 >= 2 && 2 * qx0 + 68 <= w && qy0 >= 1 &&
-                          2 * qy0 + 66 <= h && ((((uintptr_t)tb) | T.pix_stride) & 3u) == 0;
+        const bool fast = bps == 1 && C == 3 && T.ct != 0 && ((((uintptr_t)tb) | T.pix_stride) & 3u) == 0;
         if (fast) {
-            const uint8_t *base = tb + (uint64_t)(2 * qy0 - 2) * T.pix_stride + (uint32_t)(6 * qx0 - 12);
             if (T.ct == 1) {
-                if (c == 0) stage_rgb8<1, 0>(base, T.pix_stride, win);
-                else if (c == 1) stage_rgb8<1, 1>(base, T.pix_stride, win);
-                else stage_rgb8<1, 2>(base, T.pix_stride, win);
+                if (c == 0) stage_rgb8<1, 0>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else if (c == 1) stage_rgb8<1, 1>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else stage_rgb8<1, 2>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
             } else {
-                if (c == 0) stage_rgb8<2, 0>(base, T.pix_stride, win);
-                else if (c == 1) stage_rgb8<2, 1>(base, T.pix_stride, win);
-                else stage_rgb8<2, 2>(base, T.pix_stride, win);
+                if (c == 0) stage_rgb8<2, 0>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else if (c == 1) stage_rgb8<2, 1>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else stage_rgb8<2, 2>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
             }
         } else {
             // any format, or a tile at the image border: element by element,

@@ -100,6 +100,7 @@ def lib():
             "isx_decode_regions": (i32, [P, P, i32, P, P, P, u64, P]),
             "isx_read_tile_header": (i32, [P, u64, P]),
             "isx_decode_run_noalloc": (i32, [P, P, P, P, P, P]),
+            "isx_plan_info": (i32, [P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -117,7 +118,7 @@ EXPORTS = ["isx_max_encoded_bytes", "isx_encode_workspace_bytes", "isx_decode_wo
            "isx_decode_run_stages", "isx_encode_plan_build_tuned", "isx_decode_plan_build_tuned",
            "isx_stream_block_offsets", "isx_region_workspace_bytes", "isx_region_plan_bytes",
            "isx_region_plan_build", "isx_decode_regions", "isx_read_tile_header",
-           "isx_decode_run_noalloc"]
+           "isx_decode_run_noalloc", "isx_plan_info"]
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # ISX_NOALLOC_SCRATCH_BYTES
 

@@ -8,7 +8,8 @@ Two layouts of the same slide:
   source tiles (X 2^z + i, Y 2^z + j), each to level z (only its coarser
   blocks), straight into its place in the request's output buffer.
 * ``PyramidSlide``: the whole slide as ONE stream, one non-redundant wavelet
-  pyramid.  The same request is one region job: the 512x512 window
+  pyramid (or, beyond 65535 pixels a side, a grid of such streams).  The same
+  request is one region job per stream it touches: the 512x512 window
   [512 X, 512 X + 512) x [512 Y, 512 Y + 512) of the level-z image, decoded
   from the blocks under its halo at levels z+1 .. L only.
 
@@ -116,59 +117,124 @@ class Slide:
 
 class PyramidSlide:
     """The slide of ``Slide`` (same generator, seed and tile batches, so the
-    same pixels) assembled in HBM and encoded as one tile: one pyramid, one
-    stream.  Host index: the byte offset of every block (from the stream's
-    size table)."""
+    same pixels) encoded as non-redundant wavelet pyramids: one stream for the
+    whole slide, or a grid of streams of `sub` = (sx, sy) tiles each when the
+    slide is larger than one stream allows (65535 pixels a side).  The level-z
+    slide image is the sub-pyramids' level-z images side by side (every
+    sub-pyramid but the last of a row or column spans a multiple of 2^levels
+    pixels).  Host index per stream: the byte offset of every block (from
+    its size table)."""
 
-    def __init__(self, tiles_x, tiles_y, tile=512, levels=6, seed=501, batch=256, device="cuda", log=None):
+    def __init__(self, tiles_x, tiles_y, tile=512, levels=6, seed=501, batch=256, device="cuda", log=None,
+                 sub=None, keep_image=None):
         import torch
         from .synth import SlideGen
         self.tx, self.ty, self.tile, self.levels = tiles_x, tiles_y, tile, levels
         self.n = tiles_x * tiles_y
         W, H = tiles_x * tile, tiles_y * tile
         self.W, self.H = W, H
+        sx, sy = sub if sub else (tiles_x, tiles_y)
+        if (sx * tile) % (1 << levels) or (sy * tile) % (1 << levels):
+            raise ValueError("sub-pyramid sides must be multiples of 2^levels")
+        self.sx, self.sy = sx, sy
+        self.gx, self.gy = -(-tiles_x // sx), -(-tiles_y // sy)
+        if keep_image is None:
+            keep_image = self.gx * self.gy == 1
         gen = SlideGen(tiles_x, tiles_y, tile, seed, device)
         self.gen = gen
         t0 = time.perf_counter()
-        img = torch.empty((H, W, 3), dtype=torch.uint8, device=device)
+        imgs = []
+        for j in range(self.gy):
+            for i in range(self.gx):
+                w = (min(tiles_x, (i + 1) * sx) - i * sx) * tile
+                h = (min(tiles_y, (j + 1) * sy) - j * sy) * tile
+                imgs.append(torch.empty((h, w, 3), dtype=torch.uint8, device=device))
         for b0 in range(0, self.n, batch):
             ids = list(range(b0, min(self.n, b0 + batch)))
             px = gen.tiles(ids, b0 // batch)
             for k, t in enumerate(ids):
                 X, Y = t % tiles_x, t // tiles_x
-                img[Y * tile:(Y + 1) * tile, X * tile:(X + 1) * tile] = px[k]
+                im = imgs[(Y // sy) * self.gx + X // sx]
+                x, y = (X % sx) * tile, (Y % sy) * tile
+                im[y:y + tile, x:x + tile] = px[k]
         torch.cuda.synchronize()
-        self.desc = isx.tile_desc(W, H, 3, 1, 8, levels)
-        enc = isx.Encoder([self.desc], device)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        enc.run(img.reshape(-1))
-        torch.cuda.synchronize()
-        self.encode_only_s = time.perf_counter() - t1
-        if int(enc.status[0]) != 0:
-            raise RuntimeError("pyramid encode failed")
-        size = int(enc.sizes[0])
-        self.arena = enc.out[int(enc.offsets[0]):int(enc.offsets[0]) + size].clone()
-        self.size = size
-        del enc
-        self.image = img
-        nb = int.from_bytes(self.arena[20:24].cpu().numpy().tobytes(), "little")
-        self.offsets = isx.stream_block_offsets(self.arena[:24 + 4 * nb].cpu().numpy().tobytes())
+        self.descs, self.offs, self.sizes, self.block_offsets = [], [], [], []
+        parts, total = [], 0
+        self.encode_only_s = 0.0
+        for k, im in enumerate(imgs):
+            h, w = im.shape[:2]
+            d = isx.tile_desc(w, h, 3, 1, 8, levels)
+            enc = isx.Encoder([d], device)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            enc.run(im.reshape(-1))
+            torch.cuda.synchronize()
+            self.encode_only_s += time.perf_counter() - t1
+            if int(enc.status[0]) != 0:
+                raise RuntimeError("pyramid encode failed")
+            size = int(enc.sizes[0])
+            blob = enc.out[int(enc.offsets[0]):int(enc.offsets[0]) + size].clone()
+            del enc
+            nb = int.from_bytes(blob[20:24].cpu().numpy().tobytes(), "little")
+            self.block_offsets.append(isx.stream_block_offsets(blob[:24 + 4 * nb].cpu().numpy().tobytes()))
+            self.descs.append(d)
+            self.offs.append(total)
+            self.sizes.append(size)
+            parts.append(blob)
+            pad = (-size) % 256
+            if pad:
+                parts.append(torch.zeros(pad, dtype=torch.uint8, device=device))
+            total += size + pad
+            if not keep_image:
+                imgs[k] = None
+                del im
+        self.arena = torch.cat(parts)
+        del parts
+        self.size = int(sum(self.sizes))
+        self.image = imgs[0] if keep_image and len(imgs) == 1 else None
+        # single-stream names kept for callers of a one-stream slide
+        self.desc = self.descs[0]
+        self.offsets = self.block_offsets[0]
         self.encode_s = time.perf_counter() - t0
         self.raw_bytes = W * H * 3
         if log:
-            log(f"[pyramid] {W}x{H} slide encoded as one stream: {size / 1e9:.3f} GB, {nb} blocks, "
-                f"encode {self.encode_only_s * 1e3:.1f} ms")
+            log(f"[pyramid] {W}x{H} slide encoded as {len(self.descs)} stream(s) of up to "
+                f"{sx * tile}x{sy * tile}: {self.size / 1e9:.3f} GB, "
+                f"{sum(len(o) - 1 for o in self.block_offsets)} blocks, encode {self.encode_only_s * 1e3:.1f} ms")
 
     def grid(self, z):
         s = 1 << z
         return -(-self.tx // s), -(-self.ty // s)
 
     def region(self, z, X, Y):
-        """(x0, y0, w, h) of view (z, X, Y) in the level-z image."""
-        ow, oh = isx.out_size(self.W, self.H, z)
+        """(x0, y0, w, h) of view (z, X, Y) in the level-z slide image."""
+        ow, oh = self.level_size(z)
         x0, y0 = X * self.tile, Y * self.tile
         return x0, y0, min(self.tile, ow - x0), min(self.tile, oh - y0)
+
+    def level_size(self, z):
+        ow = sum(isx.out_size(self.descs[i].width, 1, z)[0] for i in range(self.gx))
+        oh = sum(isx.out_size(1, self.descs[j * self.gx].height, z)[1] for j in range(self.gy))
+        return ow, oh
+
+    def parts(self, z, X, Y):
+        """The sub-pyramid regions of view (z, X, Y): (stream k, x0, y0, w, h
+        in that stream's level-z image, dx, dy in the view)."""
+        vx0, vy0, vw, vh = self.region(z, X, Y)
+        if vw <= 0 or vh <= 0:
+            return []
+        sw, sh = (self.sx * self.tile) >> z, (self.sy * self.tile) >> z
+        out = []
+        for j in range(vy0 // sh, min(self.gy, (vy0 + vh - 1) // sh + 1)):
+            for i in range(vx0 // sw, min(self.gx, (vx0 + vw - 1) // sw + 1)):
+                k = j * self.gx + i
+                kw, kh = isx.out_size(self.descs[k].width, self.descs[k].height, z)
+                ax0, ay0 = i * sw, j * sh
+                x0, y0 = max(vx0, ax0), max(vy0, ay0)
+                x1, y1 = min(vx0 + vw, ax0 + kw), min(vy0 + vh, ay0 + kh)
+                if x1 > x0 and y1 > y0:
+                    out.append((k, x0 - ax0, y0 - ay0, x1 - x0, y1 - y0, x0 - vx0, y0 - vy0))
+        return out
 
 
 def viewer_trace(slide, n_viewers=32, steps=200, zmax=6, vw=4, vh=3, seed=502):
@@ -264,13 +330,25 @@ class Server:
                                                                               hp, pb)
         self.t = slide.tile
         self.req_bytes = self.t * self.t * 3
+        if self.pyr:  # per-stream fields of the region jobs
+            self._sub_w = np.array([d.width for d in slide.descs], dtype=np.int64)
+            self._sub_h = np.array([d.height for d in slide.descs], dtype=np.int64)
+            self._sub_off = np.array(slide.offs, dtype=np.int64)
+            self._sub_size = np.array(slide.sizes, dtype=np.int64)
+            self._sub_bofs = np.array([o.ctypes.data for o in slide.block_offsets], dtype=np.uint64)
         self.max_reqs = max_reqs
         self.max_jobs = 16384  # decode jobs (source tiles) per batch
         self.tune = tune if tune is not None else isx.tuning()
         # plan bytes upper bound for max_jobs jobs
-        if self.pyr:  # a region job lists at most ~ (4 + 2 * levels) x 4 blocks x channels per level
-            probe = self._jobs([Request(0, 0, 0, 0)] * max_reqs)
-            pb = int(self._plan_bytes(probe.ctypes.data, len(probe))) * 4
+        if self.pyr:  # the widest batch: views that cross sub-pyramid edges, at every zoom
+            pb = 0
+            for z in range(slide.levels + 1):
+                gx, gy = slide.grid(z)
+                for X, Y in ((0, 0), (min(1, gx - 1), min(1, gy - 1)), (gx // 2, gy // 2)):
+                    probe = self._jobs([Request(0, z, X, Y)] * max_reqs)
+                    if len(probe):
+                        pb = max(pb, int(self._plan_bytes(probe.ctypes.data, len(probe))))
+            pb *= 4
         else:
             probe = self._jobs([Request(0, 0, 0, 0)], dummy=self.max_jobs)
             pb = int(self._plan_bytes(probe.ctypes.data, len(probe)))
@@ -285,16 +363,24 @@ class Server:
         isx_region_job for a pyramid) for requests."""
         d = self.slide.desc
         if self.pyr:
-            a = np.zeros(len(reqs), dtype=REGION_DTYPE)
-            _fill_tile(a["job"], d)
-            a["job"]["in_bytes"] = self.slide.size
-            a["job"]["out_stride"] = self.t * 3
-            a["offsets"] = self.slide.offsets.ctypes.data
-            if len(reqs):
-                g = np.array([self.slide.region(r.z, r.X, r.Y) for r in reqs], dtype=np.int64)
-                a["x0"], a["y0"], a["w"], a["h"] = g[:, 0], g[:, 1], g[:, 2], g[:, 3]
-                a["job"]["out_offset"] = [r.out_off for r in reqs]
-                a["job"]["target"] = [r.z for r in reqs]
+            sl = self.slide
+            rows = [(r, p) for r in reqs for p in sl.parts(r.z, r.X, r.Y)]
+            a = np.zeros(len(rows), dtype=REGION_DTYPE)
+            job = a["job"]
+            _fill_tile(job, d)  # shared fields; the sizes per stream below
+            if rows:
+                P = np.array([p for _, p in rows], dtype=np.int64)
+                k = P[:, 0]
+                job["width"] = self._sub_w[k]
+                job["height"] = self._sub_h[k]
+                job["row_stride"] = self._sub_w[k] * 3
+                job["in_offset"] = self._sub_off[k]
+                job["in_bytes"] = self._sub_size[k]
+                job["out_offset"] = np.array([r.out_off for r, _ in rows], dtype=np.int64) + (P[:, 6] * self.t + P[:, 5]) * 3
+                job["target"] = [r.z for r, _ in rows]
+                a["offsets"] = self._sub_bofs[k]
+                a["x0"], a["y0"], a["w"], a["h"] = P[:, 1], P[:, 2], P[:, 3], P[:, 4]
+            job["out_stride"] = self.t * 3
             return a
         if dummy:
             a = np.zeros(dummy, dtype=JOB_DTYPE)
@@ -323,7 +409,7 @@ class Server:
             # interior view (the widest halo cover of a pyramid region)
             gx, gy = self.slide.grid(z)
             est = 0
-            for X, Y in ((0, 0), (gx // 2, gy // 2)):
+            for X, Y in ((0, 0), (min(1, gx - 1), min(1, gy - 1)), (gx // 2, gy // 2), (gx - 1, gy - 1)):
                 jobs = self._jobs([Request(0, z, X, Y)])
                 est = max(est, int(self._ws_bytes(jobs.ctypes.data, len(jobs))))
             self.ws_est[z] = est
@@ -332,14 +418,12 @@ class Server:
     def covered(self, r) -> bool:
         """Does the view lie wholly inside the slide?"""
         if self.pyr:
-            _, _, w, h = self.slide.region(r.z, r.X, r.Y)
-            return w == self.t and h == self.t
+            return sum(p[3] * p[4] for p in self.slide.parts(r.z, r.X, r.Y)) == self.t * self.t
         return self.slide.source_count(r.z, r.X, r.Y) == (1 << (2 * r.z))
 
     def view_pixels(self, r) -> int:
         if self.pyr:
-            _, _, w, h = self.slide.region(r.z, r.X, r.Y)
-            return w * h
+            return sum(p[3] * p[4] for p in self.slide.parts(r.z, r.X, r.Y))
         return (self.t >> r.z) ** 2 * self.slide.source_count(r.z, r.X, r.Y)
 
     def launch(self, slot: _Slot, reqs):
@@ -350,16 +434,18 @@ class Server:
         jobs = self._jobs(reqs)
         n = len(jobs)
         jp = jobs.ctypes.data
-        need = int(self._ws_bytes(jp, n))
-        if need > self.ws_cap:
-            raise RuntimeError("batch exceeds the slot workspace")
-        pb = int(self._plan_bytes(jp, n))
-        if pb > self.plan_cap:
-            raise RuntimeError("batch plan exceeds the slot's plan buffer")
-        hp = (ctypes.c_uint8 * pb).from_address(slot.h_plan.data_ptr())
-        rc = self._build(jp, n, hp, pb)
+        # one planning pass: build into the slot's buffer, read the sizes back
+        hp = (ctypes.c_uint8 * self.plan_cap).from_address(slot.h_plan.data_ptr())
+        rc = self._build(jp, n, hp, self.plan_cap)
         if rc:
-            raise isx.IsxError(rc, "serve plan")
+            raise isx.IsxError(rc, "serve plan (or plan beyond the slot's buffer)")
+        pbv, need = ctypes.c_uint64(), ctypes.c_uint64()
+        rc = L.isx_plan_info(hp, ctypes.byref(pbv), ctypes.byref(need))
+        if rc:
+            raise isx.IsxError(rc, "serve plan info")
+        pb = int(pbv.value)
+        if int(need.value) > self.ws_cap:
+            raise RuntimeError("batch exceeds the slot workspace")
         with torch.cuda.stream(slot.stream):
             for r in reqs:  # views that run off the slide: clear the part no source covers
                 if not self.covered(r):
@@ -417,7 +503,7 @@ class Server:
                 batch, ws, nj = [], 0, 0
                 while ready and len(batch) < self.max_reqs:
                     need = self.req_ws(ready[0].z)
-                    jobs = 1 if self.pyr else 1 << (2 * ready[0].z)
+                    jobs = 4 if self.pyr else 1 << (2 * ready[0].z)
                     if batch and (ws + need > self.ws_cap * 0.9 or nj + jobs > self.max_jobs):
                         break
                     ws += need
