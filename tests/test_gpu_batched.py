@@ -199,3 +199,60 @@ def test_pyramid_serving_regions_match_the_oracle():
             assert np.array_equal(exp[:h, :w], img[y0:y0 + h, x0:x0 + w])
     for r in reqs[1::9]:
         assert np.array_equal(srv.decode_alone(serve.Request(r.rid, r.z, r.X, r.Y)), got[r.rid]), r
+
+
+def test_pyramid_grid_serving_regions_match_the_oracle():
+    """A slide as a grid of pyramid streams (2 x 2 sub-pyramids, the last
+    column narrower): served views, which cross the streams' edges at every
+    zoom, equal the stitched crops of the oracle's level-z decodes of the
+    streams they touch, and the same view decoded alone; at zoom 0 every view
+    equals the generator's tile pixels."""
+    from paper_2005_08713_amd import serve
+    pyr = serve.PyramidSlide(6, 4, tile=128, levels=4, seed=11, batch=8, sub=(4, 2))
+    assert (pyr.gx, pyr.gy) == (2, 2) and pyr.image is None
+    srv = serve.Server(pyr, slots=3, ws_bytes=96 << 20, max_reqs=16)
+    trace = serve.viewer_trace(pyr, n_viewers=6, steps=8, zmax=4, seed=13)
+    extra = [(z, X, Y) for z in range(5) for X in range(pyr.grid(z)[0]) for Y in range(pyr.grid(z)[1])]
+    sample = trace[:40] + extra
+    reqs = [serve.Request(i, z, X, Y) for i, (z, X, Y) in enumerate(sample)]
+    times = serve.poisson_arrivals(len(reqs), 4000.0, seed=5)
+    for r, t in zip(reqs, times):
+        r.arrival = float(t)
+    got = {}
+
+    def check(slot, rs):
+        host = slot.out.cpu().numpy()
+        for r in rs:
+            got[r.rid] = host[r.out_off:r.out_off + srv.req_bytes].copy()
+
+    print("pyramid grid serve", len(reqs), "requests", flush=True)
+    srv.run(reqs, check=check)
+    assert len(got) == len(reqs)
+    arena = pyr.arena.cpu().numpy()
+    full = {}
+
+    def level(k, z):
+        if (k, z) not in full:
+            o, n = pyr.offs[k], pyr.sizes[k]
+            full[(k, z)] = oracle.decode_tile(arena[o:o + n].tobytes(), z)
+        return full[(k, z)]
+
+    T = pyr.tile
+    # the tile pixels, generated again batch by batch as the slide was
+    tiles = {}
+    for b0 in range(0, pyr.n, 8):
+        ids = list(range(b0, min(pyr.n, b0 + 8)))
+        px = pyr.gen.tiles(ids, b0 // 8).cpu().numpy()
+        for k, t in enumerate(ids):
+            tiles[t] = px[k]
+    for r in reqs:
+        exp = np.zeros((T, T, 3), np.uint8)
+        parts = pyr.parts(r.z, r.X, r.Y)
+        assert parts, r
+        for (k, x0, y0, w, h, dx, dy) in parts:
+            exp[dy:dy + h, dx:dx + w] = level(k, r.z)[y0:y0 + h, x0:x0 + w]
+        assert np.array_equal(got[r.rid].reshape(T, T, 3), exp), r
+        if r.z == 0:
+            assert np.array_equal(exp, tiles[r.Y * pyr.tx + r.X]), r
+    for r in reqs[1::7]:
+        assert np.array_equal(srv.decode_alone(serve.Request(r.rid, r.z, r.X, r.Y)), got[r.rid]), r
