@@ -41,11 +41,15 @@ def parse():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--levels", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle check and CPU baseline")
+    ap.add_argument("--no-progressive", action="store_true",
+                    help="single: skip the quality-progressive decode measurement (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
                     help="single: skip the high-bit-depth, batched and served legs")
     ap.add_argument("--serve-slide", type=str, default="192x160",
                     help="single: served leg's slide in 512-px tiles (default: 98304x81920)")
     ap.add_argument("--serve-rate", type=float, default=10000.0, help="single: served leg's requests/s")
+    ap.add_argument("--serve-layout", choices=["tiles", "pyramid"], default="pyramid",
+                    help="single: served leg's slide layout (512-px tiles, or pyramid streams)")
     ap.add_argument("--serve-requests", type=int, default=100000, help="single: served leg's requests")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="JSON record of measured HBM bytes per launch of the dominant kernel "
@@ -221,7 +225,7 @@ def main():
     # quality-progressive decode of the lossless stream: r magnitude planes
     # left out of every block (decode only, full resolution)
     prog = {}
-    for r in (0, 2, 4, 6):
+    for r in (() if args.no_progressive else (0, 2, 4, 6)):
         job = isx.DecodeJob()
         job.tile = isx.tile_desc(W, H, C, 1, 8, L, qstep=1)
         job.in_offset, job.in_bytes = offs[0], stream_bytes[1]
@@ -588,15 +592,24 @@ def _plain_per_tile(descs, d_pix, streams, jobs, n=256):
 
 def leg_served(args):
     """The served slide at full size (default 192x160 tiles of 512x512 RGB =
-    98304x81920): HBM-resident encoded tiles, viewer-trace requests re-timed
-    as Poisson arrivals at one rate, continuous batching; the alone / in-mix
-    / oracle checks of bench_serve on a sample first."""
-    import torch
+    98304x81920): HBM-resident, as a grid of pyramid streams (default) or as
+    independent 512-px tiles; viewer-trace requests re-timed as Poisson
+    arrivals at one rate, continuous batching; the alone / in-mix / oracle
+    checks of bench_serve on a sample first."""
     from paper_2005_08713_amd import serve
     tx, ty = (int(v) for v in args.serve_slide.split("x"))
-    log(f"[c5] building {tx}x{ty}-tile slide")
-    slide = serve.Slide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log)
-    enc_bytes = int(slide.sizes.sum())
+    pyr = args.serve_layout == "pyramid"
+    sub = tuple(int(v) for v in args.sub.split("x")) if max(tx, ty) * 512 > 65535 else None
+    log(f"[c5] building {tx}x{ty}-tile slide ({args.serve_layout})")
+    if pyr:
+        slide = serve.PyramidSlide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log, sub=sub)
+        enc_bytes = slide.size
+        layout = (f"{len(slide.descs)} pyramid streams of up to {slide.sx * 512}x{slide.sy * 512}, "
+                  f"region decode")
+    else:
+        slide = serve.Slide(tx, ty, tile=512, levels=6, seed=501, batch=256, log=log)
+        enc_bytes = int(slide.sizes.sum())
+        layout = "512x512 tiles"
     log(f"[c5] slide encoded: {slide.raw_bytes / 1e9:.2f} GB raw -> {enc_bytes / 1e9:.3f} GB in HBM "
         f"({slide.encode_s:.1f} s incl. generation)")
     n = args.serve_requests
@@ -604,14 +617,18 @@ def leg_served(args):
     if len(trace) < n:
         raise SystemExit(f"viewer trace has only {len(trace)} requests")
     srv = serve.Server(slide, slots=3, ws_bytes=512 << 20, max_reqs=64)
-    cpu = None if args.no_cpu else _tiles_checks(slide, srv, trace)
+    cpu = None
+    if pyr:
+        cpu = _pyramid_checks(args, slide, srv, trace)
+    elif not args.no_cpu:
+        cpu = _tiles_checks(slide, srv, trace)
     reqs = [serve.Request(i, z, X, Y) for i, (z, X, Y) in enumerate(trace[:n])]
     for r, t in zip(reqs, serve.poisson_arrivals(n, args.serve_rate, seed=502)):
         r.arrival = float(t)
     st = srv.run(reqs)
     log(f"[c5] lambda={args.serve_rate:.0f}/s: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms, "
         f"{st['decoded_mpx_s']:.0f} MP/s decoded, {st['batches']} batches")
-    res = {"workload": f"served {tx * 512}x{ty * 512} RGB slide of 512x512 tiles (6 levels), 32 viewers, "
+    res = {"workload": f"served {tx * 512}x{ty * 512} RGB slide as {layout} (6 levels), 32 viewers, "
                        f"zoom 0-6, 512x512 views, Poisson arrivals",
            "slide_raw_bytes": slide.raw_bytes, "slide_encoded_bytes": enc_bytes,
            "lambda": args.serve_rate, "requests": n,

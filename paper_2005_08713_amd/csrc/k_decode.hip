@@ -477,7 +477,10 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         P.seg_bitpos[lane] = s_pos[lane];
     }
     // prefix table: entry e belongs to the last leaf whose left-aligned code
-    // is <= e << (32 - K): sym | len << 8, or kLutLong for codes longer than K
+    // is <= e << (32 - K): sym | len << 8; for codes longer than K, kLutLong |
+    // the first candidate leaf | the number of candidates << 8 (the leaves
+    // whose codes start with e; 0 = 64 or more), so that a long code is found
+    // by a search over those leaves only
     uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
     {
         constexpr uint32_t per = (1u << kLutK) / 64;
@@ -487,14 +490,18 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
             const uint32_t mid = (lo + hi) >> 1;
             if (s_acode[mid] <= (e0 << (32 - kLutK))) lo = mid; else hi = mid;
         }
-        uint32_t j = lo;
+        uint32_t j = lo, jh = lo;
         uint32_t packed[per / 2];
 #pragma unroll
         for (uint32_t k = 0; k < per; k++) {
             const uint32_t key = (e0 + k) << (32 - kLutK);
+            const uint32_t keyhi = key | ((1u << (32 - kLutK)) - 1u);
             while (j + 1 < m && s_acode[j + 1] <= key) j++;
-            const uint32_t L = s_len[j];
-            const uint32_t e = (L <= (uint32_t)kLutK) ? (s_sym[j] | (L << 8)) : kLutLong;
+            if (jh < j) jh = j;
+            while (jh + 1 < m && s_acode[jh + 1] <= keyhi) jh++;
+            const uint32_t L = s_len[j], cnt = jh - j + 1;
+            const uint32_t e = (L <= (uint32_t)kLutK) ? (s_sym[j] | (L << 8))
+                                                      : (kLutLong | j | ((cnt < 64 ? cnt : 0u) << 8));
             if (k & 1) packed[k / 2] |= e << 16; else packed[k / 2] = e;
         }
         uint4 *dst = (uint4 *)(tab + (uint64_t)e0 * 2);
@@ -597,7 +604,9 @@ __device__ inline uint32_t dec_token(const Src &S, const DecTab &T, uint32_t r, 
         L = (e >> 8) & 0x3fu;
         cw = w << L;
     } else {
-        uint32_t lo = 0, hi = T.m;
+        // the leaves whose codes start with this prefix
+        const uint32_t n = (e >> 8) & 0x3fu;
+        uint32_t lo = e & 0xffu, hi = n ? lo + n : T.m;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
             if (T.acode[mid] <= w) lo = mid; else hi = mid;
