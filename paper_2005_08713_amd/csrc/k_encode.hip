@@ -1112,7 +1112,8 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
     const uint32_t Bb = (1u << wz) - 1u;
     const uint32_t lz = S.len[czr];
     const uint32_t tokz = lz + wz;
-    const uint32_t lit0 = S.len[0] + (czr == 0 ? wz : 0u);
+    const uint32_t len0 = S.len[0];
+    const uint32_t lit0 = len0 + (czr == 0 ? wz : 0u);
     const uint32_t code0 = S.code[0], codez = S.code[czr];
     // nd(L) = 1 + #{k >= 1 : B + B^2 + ... + B^k < L}; 8 digits cover L <= 6144
     uint32_t thr[7];
@@ -1147,9 +1148,11 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
         int32_t mx;
         const int32_t prev = max(cur, wave_excl_max(lastnz, mx));
 #define LOC(i) ((((i) < 4 ? q.x : q.y) >> (8 * ((i) & 3))) & 0xffu)
-        // token bits, branch-free: a symbol that ends a zero run (non-zero,
-        // or the segment's last) emits the run (one zero literal for length
-        // 1, else nd(L) digit tokens) and then itself when non-zero
+        // token bits: a symbol that ends a zero run (non-zero, or the
+        // segment's last) emits the run (one zero literal for length 1, else
+        // nd(L) digit tokens) and then itself when non-zero.  Symbols past
+        // the segment read as 0 and end nothing.  nd(L) is 1 up to L = B
+        // (most runs); the longer ones count their thresholds.
         uint32_t bits = 0;
         {
             int32_t c = prev;
@@ -1157,16 +1160,19 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
             for (uint32_t i = 0; i < kPackK; i++) {
                 const uint32_t v = LOC(i);
                 const int32_t ps = (int32_t)(lo + i);
-                const bool valid = (uint32_t)ps < hi;
-                const bool term = valid && (v != 0 || (uint32_t)ps == M - 1);
-                const int32_t L = v ? (ps - c - 1) : (ps - c);
-                uint32_t nd = 1;
+                const bool nz = v != 0;
+                const int32_t L = nz ? (ps - c - 1) : ((uint32_t)ps == M - 1 ? ps - c : 0);
+                if (L > 0) {
+                    uint32_t nd = 1;
+                    if ((uint32_t)L > thr[0]) {
+                        nd = 2;
 #pragma unroll
-                for (int k = 0; k < 7; k++) nd += thr[k] < (uint32_t)L;
-                const uint32_t runb = (L == 1) ? lit0 : (L >= 2 ? nd * tokz : 0u);
-                const uint32_t litb = v ? S.len[v] + (v == czr ? wz : 0u) : 0u;
-                bits += term ? runb + litb : 0u;
-                c = (valid && v) ? ps : c;
+                        for (int k = 1; k < 7; k++) nd += thr[k] < (uint32_t)L;
+                    }
+                    bits += L == 1 ? lit0 : nd * tokz;
+                }
+                if (nz) bits += S.len[v] + (v == czr ? wz : 0u);
+                c = nz ? ps : c;
             }
         }
         uint32_t rbits;
@@ -1178,13 +1184,11 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
             for (uint32_t i = 0; i < kPackK; i++) {
                 const uint32_t v = LOC(i);
                 const int32_t ps = (int32_t)(lo + i);
-                const bool valid = (uint32_t)ps < hi;
-                const bool term = valid && (v != 0 || (uint32_t)ps == M - 1);
-                const int32_t L = v ? (ps - c - 1) : (ps - c);
-                c = (valid && v) ? ps : c;
-                if (!term) continue;
+                const bool nz = v != 0;
+                const int32_t L = nz ? (ps - c - 1) : ((uint32_t)ps == M - 1 ? ps - c : 0);
+                c = nz ? ps : c;
                 if (L == 1) {
-                    put_bits(st, b, code0, S.len[0]);  // literal zero (counter 0 when it is C_zr)
+                    put_bits(st, b, code0, len0);  // literal zero (counter 0 when it is C_zr)
                     b += lit0;
                 } else if (L >= 2) {
                     // bijective base-(2^wz - 1) digits, most significant first
@@ -1196,7 +1200,7 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
                         b += tokz;
                     }
                 }
-                if (v) {
+                if (nz) {
                     const uint32_t lv = S.len[v];
                     put_bits(st, b, S.code[v], lv);
                     b += lv + (v == czr ? wz : 0u);
