@@ -516,8 +516,31 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         llen[j] = j < m ? s_len[j] : 0;
         lsym[j] = j < m ? s_sym[j] : 0;
     }
-    // work items: large segments first in the decode order
+    // work items: large segments first in the decode order.  A small block
+    // (at most 1536 symbols per plane: 64x64-coefficient types, or smaller)
+    // whose kept segments are all short and fit the LDS staging together is
+    // one item (segment field kWholeBlock): one wave decodes its segments
+    // one after the other with the tables and bits loaded once.  Large
+    // blocks keep one item per segment, decoded side by side.
     uint32_t *ctr = (uint32_t *)(ws + H.ws_items);
+    {
+        const uint32_t bl = lane < nkeep ? s_bits[lane] : 0u;
+        uint32_t mx = bl, sum = bl;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+            sum += __shfl_xor(sum, o, 64);
+        }
+        const bool small_block = p * n <= 1536u && mx < kSmallSegBits;
+        if (nkeep >= 2 && small_block && sum + 64 <= (kSegWords - 2) * 32u) {
+            if (lane == 0) {
+                const uint32_t sb1 = atomicAdd(&ctr[kQSmall], 1u);
+                uint32_t *list = (uint32_t *)(ws + H.ws_items + kItemsHdr);
+                list[H.total_blocks * 32ull + sb1] = (blk << 5) | kWholeBlock;
+            }
+            return;
+        }
+    }
     const bool big = lane < nkeep && s_bits[lane] >= kBigSegBits;
     const uint64_t bm = __ballot(big);
     const uint32_t nbig = __popcll(bm), nsmall = nkeep - nbig;
@@ -864,19 +887,28 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
         const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
         const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
         if (__builtin_amdgcn_readfirstlane(status[B.tile]) != D_OK) continue;
-        const uint32_t M = P.seg_M[s];
-        const uint64_t S0 = P.seg_bitpos[s];
-        const uint32_t N = P.seg_bits[s];
-        uint4 *gout = (uint4 *)(ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride((uint32_t)B.p * B.wb * B.hb / 8));
-        if (M > kMaxSeg) {  // not reachable for 128-grid blocks
+        // segments [s0, s1) of the block: one, or all kept ones of a block item
+        const bool whole = s == kWholeBlock;
+        const uint32_t s0 = whole ? 0u : s;
+        const uint32_t s1 = whole ? __builtin_amdgcn_readfirstlane(P.nseg) : s + 1;
+        const uint64_t S0 = P.seg_bitpos[s0];
+        const uint64_t Send = P.seg_bitpos[s1 - 1] + P.seg_bits[s1 - 1];
+        const uint32_t Nall = (uint32_t)(Send - S0);
+        const uint32_t pstride = plane_stride((uint32_t)B.p * B.wb * B.hb / 8);
+        bool toolong = false;
+        for (uint32_t k = s0; k < s1; k++) toolong |= P.seg_M[k] > kMaxSeg;
+        if (toolong) {  // not reachable for 128-grid blocks
             if (lane == 0) atomicMin(&status[B.tile], D_CORRUPT);
             continue;
         }
         const uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
-        // the plane starts as zeros (16-byte aligned, its stride padded to 16
-        // bytes); the decode writes only non-zero symbols over them
-        const uint32_t M16 = (M + 15) / 16;
-        for (uint32_t i = lane; i < M16; i += 64) gout[i] = make_uint4(0, 0, 0, 0);
+        // the planes start as zeros (16-byte aligned, their stride padded to
+        // 16 bytes); the decode writes only non-zero symbols over them
+        for (uint32_t k = s0; k < s1; k++) {
+            uint4 *gz = (uint4 *)(ws + B.sym_off + (uint64_t)P.seg_plane[k] * pstride);
+            const uint32_t M16 = (P.seg_M[k] + 15) / 16;
+            for (uint32_t i = lane; i < M16; i += 64) gz[i] = make_uint4(0, 0, 0, 0);
+        }
         __syncthreads();  // the previous item is done with S
         {
             // code tables (352 x 16 bytes): all loads of a lane first
@@ -892,8 +924,7 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
         }
         const uint64_t lo = B.byte_off, hi = B.byte_off + B.byte_len;
         const uint64_t w0 = S0 >> 5;
-        const uint32_t off = (uint32_t)(S0 & 31);
-        const uint32_t nw = N ? (uint32_t)(((S0 + N - 1) >> 5) + 2 - w0) : 0u;
+        const uint32_t nw = Nall ? (uint32_t)(((S0 + Nall - 1) >> 5) + 2 - w0) : 0u;
         const bool staged = nw <= kSegWords;
         if (staged) {
             // words w0 .. w0+nw-1 from 16-byte loads (4 per lane in flight);
@@ -940,20 +971,27 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
         DecTab T;
         T.lut = S.lut; T.acode = S.acode; T.llen = S.llen; T.lsym = S.lsym;
         T.m = P.m; T.czr = P.czr; T.wz = P.wz;
-        uint8_t *out = (uint8_t *)gout;
         int32_t err = 0;
-        if (T.m == 1 && S.lsym[0] != T.czr) {
-            // zero-length codewords: the segment is M copies of the leaf
-            if (N != 0) err = D_CORRUPT;
-            else if (S.lsym[0]) for (uint32_t i = lane; i < M; i += 64) out[i] = S.lsym[0];
-        } else if (staged) {
-            SrcLds src;
-            src.w = S.bits; src.off = off; src.nw = nw;
-            err = decode_segment(src, T, N, M, out);
-        } else {
-            SrcGlb src;
-            src.enc = enc; src.lo = lo; src.hi = hi; src.w0 = w0; src.off = off;
-            err = decode_segment(src, T, N, M, out);
+        for (uint32_t k = s0; k < s1; k++) {
+            const uint32_t M = P.seg_M[k], N = P.seg_bits[k];
+            const uint64_t Sk = P.seg_bitpos[k];
+            uint8_t *out = ws + B.sym_off + (uint64_t)P.seg_plane[k] * pstride;
+            int32_t e = 0;
+            if (T.m == 1 && S.lsym[0] != T.czr) {
+                // zero-length codewords: the segment is M copies of the leaf
+                if (N != 0) e = D_CORRUPT;
+                else if (S.lsym[0]) for (uint32_t i = lane; i < M; i += 64) out[i] = S.lsym[0];
+            } else if (staged) {
+                const uint32_t wk = (uint32_t)((Sk >> 5) - w0);
+                SrcLds src;
+                src.w = S.bits + wk; src.off = (uint32_t)(Sk & 31); src.nw = nw - wk;
+                e = decode_segment(src, T, N, M, out);
+            } else {
+                SrcGlb src;
+                src.enc = enc; src.lo = lo; src.hi = hi; src.w0 = Sk >> 5; src.off = (uint32_t)(Sk & 31);
+                e = decode_segment(src, T, N, M, out);
+            }
+            err = e ? e : err;
         }
         if (err) atomicMin(&status[B.tile], err);
     }
@@ -978,16 +1016,22 @@ __device__ inline void transpose16(uint32_t (&r)[16])
     }
 }
 
-__global__ void __launch_bounds__(1024) k_dec_reasm(PlanHdr H, const uint8_t *__restrict__ plan,
-                                                    uint8_t *__restrict__ ws,
-                                                    const int32_t *__restrict__ status)
+// Blocks of the plan's list [list0, list0 + nlist): NT = 1024 threads for the
+// blocks of more than 768 cells, 256 for the others.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_dec_reasm(PlanHdr H, const uint8_t *__restrict__ plan,
+                                                  uint8_t *__restrict__ ws,
+                                                  const int32_t *__restrict__ status, uint32_t list0,
+                                                  uint32_t nlist)
 {
     // per plane b of the block and type t: the byte offset of the type's
     // symbols in the plane (~0: not decoded for the type), so that the cell
     // loop issues only independent symbol loads
     __shared__ uint32_t s_off[32][3];
     const uint32_t tid = threadIdx.x;
-    for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
+    const uint32_t *list = (const uint32_t *)(plan + H.list_off) + list0;
+    for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
+    const uint32_t blk = list[li];
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
     if (status[B.tile] != D_OK) continue;
@@ -1098,8 +1142,17 @@ hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
                 hipLaunchKernelGGL(k_dec_segments, dim3(g), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
             }
         } else if (st == DEC_REASM) {
-            if (H.total_blocks)
-                hipLaunchKernelGGL(k_dec_reasm, dim3(H.blk_grid), dim3(1024), 0, stream, H, d_plan, d_ws, d_status);
+            if (H.n_big) {
+                const uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(H.n_big, H.num_cus * H.blocks_per_cu) : H.n_big;
+                hipLaunchKernelGGL(k_dec_reasm<1024>, dim3(g), dim3(1024), 0, stream, H, d_plan, d_ws, d_status, 0u,
+                                   H.n_big);
+            }
+            if (H.n_small) {
+                const uint32_t g =
+                    H.blocks_per_cu ? std::min<uint32_t>(H.n_small, H.num_cus * H.blocks_per_cu * 4) : H.n_small;
+                hipLaunchKernelGGL(k_dec_reasm<256>, dim3(g), dim3(256), 0, stream, H, d_plan, d_ws, d_status, H.n_big,
+                                   H.n_small);
+            }
         } else if (st >= DEC_INV15 && st <= DEC_FINAL) {
             int level = DEC_FINAL - st;  // 15..1, then 0 = final stage
             hipError_t e = launch_inverse_level(H, d_plan, d_ws, d_pixels_out, d_status, level, stream);
