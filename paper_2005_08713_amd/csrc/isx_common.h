@@ -159,7 +159,7 @@ struct BlkPlan {
 
 // decode code tables, per block: prefix table of 2^kLutK uint16 entries, then
 // the left-aligned codes (uint32[256]), lengths and symbols (uint8[256] each)
-constexpr int kLutK = 11;
+constexpr int kLutK = 10;
 constexpr uint32_t kLutBytes16 = (1u << kLutK) * 2;
 constexpr uint32_t kLutStride = kLutBytes16 + 1024 + 256 + 256;
 constexpr uint32_t kMaxSeg = 3 * 128 * 128 / 8;  // symbols in the largest segment
@@ -167,7 +167,7 @@ constexpr uint32_t kSegWords = 2048;             // segment bits staged in LDS (
 constexpr uint32_t kBigSegBits = 16384;          // queue class of a segment
 constexpr uint32_t kSmallSegBits = 4096;         // a block of only such segments is one decode item
 constexpr uint32_t kWholeBlock = 31;             // segment field of such an item (segments are 0..30)
-constexpr uint32_t kSegWavesPerCu = 11;  // one-wave workgroups of 13.8 KB LDS each
+constexpr uint32_t kSegWavesPerCu = 13;  // one-wave workgroups of 11.8 KB LDS each
 // Segment work queue header: the large-list length, the small-list length
 // and the take counter, each in a 128-byte line of its own (atomics of
 // thousands of waves on one shared line contend); the lists follow.

@@ -911,16 +911,21 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
         }
         __syncthreads();  // the previous item is done with S
         {
-            // code tables (352 x 16 bytes): all loads of a lane first
-            static_assert(kLutStride / 16 > 320 && kLutStride / 16 <= 384, "table copy layout");
+            // code tables (kLutStride / 16 pieces of 16 bytes, in the order of
+            // SegShared): all loads of a lane first
+            static_assert(kLutStride % 16 == 0, "table copy layout");
+            constexpr uint32_t NQ = kLutStride / 16, NR = (NQ + 63) / 64;
             const uint4 *src = (const uint4 *)tab;
             uint4 *dst = (uint4 *)S.lut;
-            const uint4 a0 = src[lane], a1 = src[lane + 64], a2 = src[lane + 128], a3 = src[lane + 192],
-                        a4 = src[lane + 256];
-            const bool l5 = lane + 320 < kLutStride / 16;
-            const uint4 a5 = l5 ? src[lane + 320] : make_uint4(0, 0, 0, 0);
-            dst[lane] = a0; dst[lane + 64] = a1; dst[lane + 128] = a2; dst[lane + 192] = a3; dst[lane + 256] = a4;
-            if (l5) dst[lane + 320] = a5;
+            uint4 a[NR];
+#pragma unroll
+            for (uint32_t r = 0; r < NR; r++) {
+                const uint32_t i = lane + 64 * r;
+                a[r] = i < NQ ? src[i] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (uint32_t r = 0; r < NR; r++)
+                if (lane + 64 * r < NQ) dst[lane + 64 * r] = a[r];
         }
         const uint64_t lo = B.byte_off, hi = B.byte_off + B.byte_len;
         const uint64_t w0 = S0 >> 5;
