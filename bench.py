@@ -277,6 +277,7 @@ def main():
     del enc, dec, d_pix
     torch.cuda.empty_cache()
     if not args.no_extras:
+        out["small_tile"] = leg_small_tile(args)
         out["high_bit_depth"] = leg_high_bit_depth(args)
         torch.cuda.empty_cache()
         out["batched"] = leg_batched(args)
@@ -376,6 +377,56 @@ def cpu_baseline_threads(img, levels, lossless_stream, one):
             "single_thread": {"value": round(single, 3), "unit": "MP/s", "cores": 1,
                               "sample": f"one lossless encode+decode of the {W}x{H} RGB image "
                                         f"({one[0]:.1f} s + {one[1]:.1f} s)"}}
+
+
+def leg_small_tile(args):
+    """One 256x256 RGB uint8 tile, 3 levels, lossless (seeds 101-103: the
+    streams equal the oracle's and decode to the input), encode + decode per
+    step as one captured HIP graph each: the latency of a single small image."""
+    import torch
+    from paper_2005_08713_amd import isx, synth
+    W = H = 256
+    res = {"workload": "256x256 RGB uint8 H&E-like tile, 3 levels, lossless, encode+decode per step "
+                       "(one graph replay each)"}
+    imgs = [synth.he_like(W, H, sd) for sd in (101, 102, 103)]
+    desc = isx.tile_desc(W, H, 3, 1, 8, 3)
+    for k, img in enumerate(imgs):
+        d_pix = torch.from_numpy(img.reshape(-1).copy()).cuda()
+        enc = isx.Encoder([desc])
+        enc.run(d_pix)
+        torch.cuda.synchronize()
+        blob = enc.streams()[0]
+        j = isx.DecodeJob()
+        j.tile, j.in_offset, j.in_bytes = desc, 0, len(blob)
+        j.out_offset, j.out_row_stride_bytes, j.target_level = 0, W * 3, 0
+        dec = isx.Decoder([j], W * H * 3)
+        dec.run(enc.out)
+        torch.cuda.synchronize()
+        if not np.array_equal(dec.out.cpu().numpy().reshape(H, W, 3), img):
+            raise SystemExit("small tile lossless round trip failed")
+        if not args.no_cpu:
+            import oracle
+            if oracle.encode_tile(img, 3) != blob:
+                raise SystemExit(f"small tile (seed {101 + k}) differs from the oracle")
+    enc.capture(d_pix)
+    dec.capture(enc.out)
+    for _ in range(20):
+        enc.replay()
+        dec.replay()
+    torch.cuda.synchronize()
+    steps = 200
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        enc.replay()
+        dec.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    if enc.streams()[0] != blob:
+        raise SystemExit("small tile stream changed between replays")
+    res.update({"mpx_s": round(W * H / 1e6 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4), "steps": steps,
+                "stream_bytes": len(blob), "oracle_parity": not args.no_cpu})
+    log(f"[c1] {res['mpx_s']} MP/s, {ms:.3f} ms per step")
+    return res
 
 
 def leg_high_bit_depth(args):
