@@ -225,11 +225,15 @@ int32_t isx_plan_info(const void *h_plan, uint64_t *plan_bytes, uint64_t *worksp
  *                  (0 = 32); 32 stages 68x68-sample windows, 16 stages 36x36.
  *  blocks_per_cu:  0 = one workgroup per coefficient block for the per-block
  *                  kernels; k > 0 = a persistent grid of k workgroups per
- *                  compute unit that loops over the blocks (1..64). */
+ *                  compute unit that loops over the blocks (1..64).
+ *  seg_waves_per_cu: decode only: persistent one-wave workgroups per compute
+ *                  unit of the segment decoder (0 = 13, the most its LDS
+ *                  allows; 1..13). */
 typedef struct {
     int32_t transform_tile;
     int32_t blocks_per_cu;
-    int32_t reserved[6];
+    int32_t seg_waves_per_cu;
+    int32_t reserved[5];
 } isx_tuning;
 
 /* As isx_*_plan_build, with explicit launch parameters (NULL = defaults).

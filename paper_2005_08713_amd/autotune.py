@@ -1,7 +1,8 @@
 """Autotuner for the batched encode/decode launches.
 
 Searches the launch parameters of a plan (isx_tuning: LDS transform-tile
-shape and persistent workgroups per CU for the per-block kernels) by timing
+shape, persistent workgroups per CU for the per-block kernels, persistent
+waves per CU of the segment decoder) by timing
 real runs of the caller's batch with HIP events, checks that every candidate
 produces byte-identical streams and identical pixels, and caches the winner
 in a JSON file keyed by the GPU architecture and a summary of the batch.
@@ -15,7 +16,9 @@ import numpy as np
 
 from . import isx
 
-CANDIDATES = [(32, 0), (16, 0), (32, 2), (32, 4), (32, 8), (16, 4), (16, 8)]
+# (transform tile, blocks per CU, segment-decoder waves per CU; 0 = default)
+CANDIDATES = [(32, 0, 0), (16, 0, 0), (32, 2, 0), (32, 4, 0), (32, 8, 0), (16, 4, 0), (16, 8, 0),
+              (32, 0, 10), (32, 0, 8)]
 
 
 def cache_path() -> str:
@@ -66,7 +69,7 @@ def _time(fn, reps):
 
 
 def tune(descs, d_pixels, reps: int = 3, candidates=CANDIDATES, use_cache: bool = True, log=None):
-    """Returns {'encode': (tq, bpc), 'decode': (tq, bpc), 'timings': {...}}."""
+    """Returns {'encode': (tq, bpc, swpc), 'decode': (tq, bpc, swpc), 'timings': {...}}."""
     import torch
     key = batch_key(descs)
     cache = _load() if use_cache else {}
@@ -74,8 +77,10 @@ def tune(descs, d_pixels, reps: int = 3, candidates=CANDIDATES, use_cache: bool 
         return cache[key]
     ref_streams, ref_pixels = None, None
     enc_t, dec_t = {}, {}
-    for tq, bpc in candidates:
-        t = isx.tuning(tq, bpc)
+    for cand in candidates:
+        cand = tuple(cand) + (0,) * (3 - len(cand))
+        tq, bpc, swpc = cand
+        t = isx.tuning(tq, bpc, swpc)
         enc = isx.Encoder(descs, tune=t)
         enc.run(d_pixels)
         torch.cuda.synchronize()
@@ -83,7 +88,7 @@ def tune(descs, d_pixels, reps: int = 3, candidates=CANDIDATES, use_cache: bool 
         if ref_streams is None:
             ref_streams = streams
         elif streams != ref_streams:
-            raise RuntimeError(f"tuning {tq, bpc} changed the encoded bytes")
+            raise RuntimeError(f"tuning {cand} changed the encoded bytes")
         jobs, out_off = [], 0
         offs = enc.offsets.cpu().numpy()
         for i, d in enumerate(descs):
@@ -104,16 +109,16 @@ def tune(descs, d_pixels, reps: int = 3, candidates=CANDIDATES, use_cache: bool 
         if ref_pixels is None:
             ref_pixels = px
         elif not torch.equal(px, ref_pixels):
-            raise RuntimeError(f"tuning {tq, bpc} changed the decoded pixels")
-        enc_t[(tq, bpc)] = _time(lambda: enc.run(d_pixels), reps)
-        dec_t[(tq, bpc)] = _time(lambda: dec.run(enc.out), reps)
+            raise RuntimeError(f"tuning {cand} changed the decoded pixels")
+        enc_t[cand] = _time(lambda: enc.run(d_pixels), reps)
+        dec_t[cand] = _time(lambda: dec.run(enc.out), reps)
         if log:
-            log(f"[tune] tq={tq} bpc={bpc} encode {enc_t[(tq, bpc)]:.3f} ms decode {dec_t[(tq, bpc)]:.3f} ms")
+            log(f"[tune] tq={tq} bpc={bpc} swpc={swpc} encode {enc_t[cand]:.3f} ms decode {dec_t[cand]:.3f} ms")
         del enc, dec
     best_e = min(enc_t, key=enc_t.get)
     best_d = min(dec_t, key=dec_t.get)
     res = {"encode": list(best_e), "decode": list(best_d),
-           "timings_ms": {f"{k[0]}/{k[1]}": [round(enc_t[k], 4), round(dec_t[k], 4)] for k in enc_t}}
+           "timings_ms": {"/".join(str(x) for x in k): [round(enc_t[k], 4), round(dec_t[k], 4)] for k in enc_t}}
     if use_cache:
         cache[key] = res
         _store(cache)

@@ -259,10 +259,13 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     H.n_tiles = (uint32_t)n;
     H.tq = 32;
     H.blocks_per_cu = 0;
+    H.seg_waves_per_cu = kSegWavesPerCu;
     if (tune) {
         if (tune->transform_tile != 0 && tune->transform_tile != 16 && tune->transform_tile != 32)
             return ISX_E_INVALID_ARG;
         if (tune->blocks_per_cu < 0 || tune->blocks_per_cu > 64) return ISX_E_INVALID_ARG;
+        if (tune->seg_waves_per_cu < 0 || tune->seg_waves_per_cu > (int32_t)kSegWavesPerCu) return ISX_E_INVALID_ARG;
+        if (tune->seg_waves_per_cu) H.seg_waves_per_cu = (uint32_t)tune->seg_waves_per_cu;
         if (tune->transform_tile) H.tq = (uint32_t)tune->transform_tile;
         H.blocks_per_cu = (uint32_t)tune->blocks_per_cu;
     }

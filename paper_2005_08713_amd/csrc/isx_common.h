@@ -98,6 +98,8 @@ struct PlanHdr {
     uint32_t tq;        // transform tile: quads per side (16 or 32)
     uint32_t blk_grid;  // workgroups of the per-block kernels (== total_blocks unless persistent)
     uint32_t num_cus, blocks_per_cu;
+    uint32_t seg_waves_per_cu;  // segment decoder: persistent waves per CU
+    uint32_t pad_swpc;
     uint64_t list_off;      // plan offset of the block list (u32): large blocks, then small ones
     uint32_t n_big, n_small;  // blocks with > 768 4x4 cells / with <= 768
 };
@@ -163,11 +165,11 @@ constexpr int kLutK = 10;
 constexpr uint32_t kLutBytes16 = (1u << kLutK) * 2;
 constexpr uint32_t kLutStride = kLutBytes16 + 1024 + 256 + 256;
 constexpr uint32_t kMaxSeg = 3 * 128 * 128 / 8;  // symbols in the largest segment
-constexpr uint32_t kSegWords = 1792;             // segment bits staged in LDS (larger: read from HBM)
+constexpr uint32_t kSegWords = 2048;             // segment bits staged in LDS (larger: read from HBM)
 constexpr uint32_t kBigSegBits = 16384;          // queue class of a segment
 constexpr uint32_t kSmallSegBits = 4096;         // a block of only such segments is one decode item
 constexpr uint32_t kWholeBlock = 31;             // segment field of such an item (segments are 0..30)
-constexpr uint32_t kSegWavesPerCu = 14;  // one-wave workgroups of 10.8 KB LDS each
+constexpr uint32_t kSegWavesPerCu = 13;  // one-wave workgroups of 11.8 KB LDS each
 // Segment work queue header: the large-list length, the small-list length
 // and the take counter, each in a 128-byte line of its own (atomics of
 // thousands of waves on one shared line contend); the lists follow.

@@ -1061,15 +1061,17 @@ __global__ void __launch_bounds__(NT) k_dec_reasm(PlanHdr H, const uint8_t *__re
     for (uint32_t cell = tid; cell < p * cpt; cell += blockDim.x) {
         const uint32_t t = cell / cpt, ci = cell % cpt;
         // the 16 low magnitude planes and the sign plane (d - 1) in flight
-        // together (a plane the type skips reads plane 0 and counts as 0),
-        // then one 16x16 bit-matrix transpose turns plane words into the
-        // cell's magnitudes
+        // together (a plane the type skips, or above the block's depth, is
+        // not read and counts as 0: the condition is the same for a wave's
+        // cells of one type), then one 16x16 bit-matrix transpose turns plane
+        // words into the cell's magnitudes
         uint32_t mag[16];
 #pragma unroll
         for (int b = 0; b < 16; b++) {
             const uint32_t o = (uint32_t)b + 1 < d ? s_off[b][t] : ~0u;
-            const uint32_t v = *(const uint16_t *)(sym + (o != ~0u ? o : 0u) + 2 * ci);
-            mag[b] = o != ~0u ? v : 0u;
+            uint32_t v = 0;
+            if (o != ~0u) v = *(const uint16_t *)(sym + o + 2 * ci);
+            mag[b] = v;
         }
         uint32_t sgn;
         {
@@ -1143,7 +1145,7 @@ hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             if (H.total_blocks) {
                 // no more waves than the plan can queue segments (a block
                 // queues at most one per plane, at most its tile's plane bound)
-                const uint32_t g = std::min<uint32_t>(H.num_cus * kSegWavesPerCu, std::max<uint32_t>(H.total_slots, 1u));
+                const uint32_t g = std::min<uint32_t>(H.num_cus * H.seg_waves_per_cu, std::max<uint32_t>(H.total_slots, 1u));
                 hipLaunchKernelGGL(k_dec_segments, dim3(g), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
             }
         } else if (st == DEC_REASM) {

@@ -44,12 +44,13 @@ class RegionJob(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("transform_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("seg_waves_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
-def tuning(transform_tile=0, blocks_per_cu=0) -> Tuning:
+def tuning(transform_tile=0, blocks_per_cu=0, seg_waves_per_cu=0) -> Tuning:
     t = Tuning()
     t.transform_tile, t.blocks_per_cu = int(transform_tile), int(blocks_per_cu)
+    t.seg_waves_per_cu = int(seg_waves_per_cu)
     return t
 
 
@@ -296,12 +297,19 @@ class Decoder:
         self.graph.replay()
 
 
+_capture_stream = None
+
+
 def _capture(fn):
     """Record the kernels `fn` enqueues into a torch CUDA(HIP) graph.  The
     library enqueues kernels only (no copies, no memsets) on the current
-    stream, which torch points at its capture stream."""
+    stream, which torch points at its capture stream (one side stream for
+    every capture of the process)."""
+    global _capture_stream
     torch = _torch()
-    s = torch.cuda.Stream()
+    if _capture_stream is None:
+        _capture_stream = torch.cuda.Stream()
+    s = _capture_stream
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         fn()  # warm-up outside the graph

@@ -184,3 +184,15 @@ def test_noalloc_decode_validates_on_the_host():
     eplan = (ctypes.c_uint8 * eb)()
     assert L.isx_encode_plan_build(ctypes.byref(e), 1, eplan, eb) == isx.OK
     assert L.isx_decode_run_noalloc(eplan, fake, fake, fake, fake, None) == isx.E_INVALID_ARG
+
+
+def test_tuning_ranges_are_checked_on_the_host():
+    L = isx.lib()
+    d = isx.tile_desc(64, 64, 3, 1, 8, 3)
+    pb = L.isx_encode_plan_bytes(ctypes.byref(d), 1)
+    buf = (ctypes.c_uint8 * pb)()
+    for t, ok in [((32, 0, 0), True), ((32, 0, 13), True), ((16, 64, 1), True), ((32, 0, 14), False),
+                  ((32, 0, -1), False), ((24, 0, 0), False), ((32, 65, 0), False)]:
+        tu = isx.tuning(*t)
+        rc = L.isx_encode_plan_build_tuned(ctypes.byref(d), 1, ctypes.byref(tu), buf, pb)
+        assert (rc == isx.OK) == ok, t

@@ -55,9 +55,9 @@ def test_tunings_give_identical_bytes_and_pixels():
     tiles = _batch()
     descs, d_pix = _upload(tiles)
     ref = None
-    for tq, bpc in [(32, 0), (16, 0), (32, 1), (16, 3), (32, 8)]:
-        print("tuning", tq, bpc, flush=True)
-        enc = isx.Encoder(descs, tune=isx.tuning(tq, bpc))
+    for tq, bpc, swpc in [(32, 0, 0), (16, 0, 0), (32, 1, 0), (16, 3, 0), (32, 8, 0), (32, 0, 1), (32, 0, 7)]:
+        print("tuning", tq, bpc, swpc, flush=True)
+        enc = isx.Encoder(descs, tune=isx.tuning(tq, bpc, swpc))
         enc.run(d_pix)
         torch.cuda.synchronize()
         streams = enc.streams()
@@ -68,14 +68,14 @@ def test_tunings_give_identical_bytes_and_pixels():
         assert streams == ref
         zs = [i % (t["levels"] + 1) for i, t in enumerate(tiles)]
         jobs, nbytes, outs = _jobs(descs, enc, streams, zs)
-        dec = isx.Decoder(jobs, nbytes, tune=isx.tuning(tq, bpc))
+        dec = isx.Decoder(jobs, nbytes, tune=isx.tuning(tq, bpc, swpc))
         dec.run(enc.out)
         torch.cuda.synchronize()
         assert int(dec.status.abs().sum().item()) == 0
         host = dec.out.cpu().numpy()
         for i, (o, oh, ow, c) in enumerate(outs):
             got = host[o:o + oh * ow * c].reshape(oh, ow, c)
-            assert np.array_equal(got, oracle.decode_tile(ref[i], zs[i])), (tq, bpc, i)
+            assert np.array_equal(got, oracle.decode_tile(ref[i], zs[i])), (tq, bpc, swpc, i)
 
 
 def test_graph_replay_matches_eager_every_time():
@@ -114,8 +114,9 @@ def test_autotuner_picks_a_valid_setting(tmp_path, monkeypatch):
     monkeypatch.setenv("ISX_TUNE_CACHE", str(tmp_path / "tune.json"))
     tiles = _batch(16, seed=13)
     descs, d_pix = _upload(tiles)
-    res = autotune.tune(descs, d_pix, reps=1, candidates=[(32, 0), (16, 0), (32, 4)])
-    assert tuple(res["encode"]) in [(32, 0), (16, 0), (32, 4)]
+    res = autotune.tune(descs, d_pix, reps=1, candidates=[(32, 0), (16, 0), (32, 4), (32, 0, 8)])
+    assert tuple(res["encode"]) in [(32, 0, 0), (16, 0, 0), (32, 4, 0), (32, 0, 8)]
+    assert tuple(res["decode"]) in [(32, 0, 0), (16, 0, 0), (32, 4, 0), (32, 0, 8)]
     assert os.path.exists(tmp_path / "tune.json")
     again = autotune.tune(descs, d_pix, reps=1)
     assert again == res
