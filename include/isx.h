@@ -227,8 +227,8 @@ int32_t isx_plan_info(const void *h_plan, uint64_t *plan_bytes, uint64_t *worksp
  *                  kernels; k > 0 = a persistent grid of k workgroups per
  *                  compute unit that loops over the blocks (1..64).
  *  seg_waves_per_cu: decode only: persistent one-wave workgroups per compute
- *                  unit of the segment decoder (0 = 13, the most its LDS
- *                  allows; 1..13). */
+ *                  unit of the segment decoder (0 = 11, the most its LDS
+ *                  allows; 1..11). */
 typedef struct {
     int32_t transform_tile;
     int32_t blocks_per_cu;

@@ -18,7 +18,7 @@ from . import isx
 
 # (transform tile, blocks per CU, segment-decoder waves per CU; 0 = default)
 CANDIDATES = [(32, 0, 0), (16, 0, 0), (32, 2, 0), (32, 4, 0), (32, 8, 0), (16, 4, 0), (16, 8, 0),
-              (32, 0, 10), (32, 0, 8)]
+              (32, 0, 8), (32, 0, 6)]
 
 
 def cache_path() -> str:

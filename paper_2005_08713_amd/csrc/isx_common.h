@@ -165,11 +165,11 @@ constexpr int kLutK = 10;
 constexpr uint32_t kLutBytes16 = (1u << kLutK) * 2;
 constexpr uint32_t kLutStride = kLutBytes16 + 1024 + 256 + 256;
 constexpr uint32_t kMaxSeg = 3 * 128 * 128 / 8;  // symbols in the largest segment
-constexpr uint32_t kSegWords = 2048;             // segment bits staged in LDS (larger: read from HBM)
+constexpr uint32_t kSegWords = 1662;             // segment bits staged in LDS, 53 Kbit (larger: read from HBM)
 constexpr uint32_t kBigSegBits = 16384;          // queue class of a segment
 constexpr uint32_t kSmallSegBits = 4096;         // a block of only such segments is one decode item
 constexpr uint32_t kWholeBlock = 31;             // segment field of such an item (segments are 0..30)
-constexpr uint32_t kSegWavesPerCu = 13;  // one-wave workgroups of 11.8 KB LDS each
+constexpr uint32_t kSegWavesPerCu = 11;  // one-wave workgroups of 14.5 KB LDS each
 // Segment work queue header: the large-list length, the small-list length
 // and the take counter, each in a 128-byte line of its own (atomics of
 // thousands of waves on one shared line contend); the lists follow.

@@ -561,26 +561,23 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
 }
 
 // ------------------------------------------------------------------ segments
-// Bit sources of one segment.  Positions are relative to the segment start;
-// win(r) = the 32 stream bits from r on (MSB first).
-struct SrcLds {
-    const uint32_t *w;  // staged words, from the word holding the first bit
+// Bit cursors over one segment; positions are relative to the segment start
+// and only move forward between seeks.  A cursor holds three consecutive
+// stream words (MSB first): bit r lies in the first, a, at an offset k < 32;
+// the third, n, is fetched when the window moves on, so that its latency
+// overlaps the next token's table lookup instead of adding to it.
+struct CurLds {
+    const uint32_t *w;  // staged words, from the word holding the first bit (w[nw], w[nw + 1] are zero)
     uint32_t off;       // bit offset of the segment start in w[0]
-    uint32_t nw;        // staged words (w[nw], w[nw + 1] are zero)
-    __device__ inline uint32_t win(uint32_t r) const
+    uint32_t nw;        // staged words
+    uint32_t wi, a, b, n;
+    __device__ inline uint32_t ld(uint32_t i) const { return w[i <= nw + 1 ? i : nw + 1]; }
+    __device__ inline void seek(uint32_t r)
     {
-        const uint32_t b = r + off, i = b >> 5;
-        const uint64_t x = ((uint64_t)w[i] << 32) | w[i + 1];
-        return (uint32_t)(x >> (32 - (b & 31)));
+        wi = (r + off) >> 5;
+        a = ld(wi); b = ld(wi + 1); n = ld(wi + 2);
     }
-    __device__ inline uint32_t win_safe(uint32_t r) const
-    {
-        const uint32_t b = r + off;
-        uint32_t i = b >> 5;
-        i = i < nw ? i : nw;
-        const uint64_t x = ((uint64_t)w[i] << 32) | w[i + 1];
-        return (uint32_t)(x >> (32 - (b & 31)));
-    }
+    __device__ inline void step() { a = b; b = n; wi++; n = ld(wi + 2); }
 };
 
 // big-endian word `wi` of the stream, bytes outside [lo, hi) read as 0
@@ -593,19 +590,38 @@ __device__ inline uint32_t stream_word(const uint8_t *enc, uint64_t lo, uint64_t
     return x;
 }
 
-struct SrcGlb {
+struct CurGlb {
     const uint8_t *enc;
     uint64_t lo, hi, w0;  // readable bytes; word of the first bit
     uint32_t off;
-    __device__ inline uint32_t win(uint32_t r) const
+    uint32_t wi, a, b, n;
+    __device__ inline uint32_t ld(uint32_t i) const { return stream_word(enc, lo, hi, w0 + i); }
+    __device__ inline void seek(uint32_t r)
     {
-        const uint32_t b = r + off;
-        const uint64_t i = w0 + (b >> 5);
-        const uint64_t x = ((uint64_t)stream_word(enc, lo, hi, i) << 32) | stream_word(enc, lo, hi, i + 1);
-        return (uint32_t)(x >> (32 - (b & 31)));
+        wi = (r + off) >> 5;
+        a = ld(wi); b = ld(wi + 1); n = ld(wi + 2);
     }
-    __device__ inline uint32_t win_safe(uint32_t r) const { return win(r); }
+    __device__ inline void step() { a = b; b = n; wi++; n = ld(wi + 2); }
 };
+
+// moves the window to bit r; returns r's offset in a
+template <class Cur>
+__device__ inline uint32_t cur_at(Cur &C, uint32_t r)
+{
+    uint32_t k = r + C.off - (C.wi << 5);
+    while (k >= 32) {
+        C.step();
+        k -= 32;
+    }
+    return k;
+}
+// the 32 bits from offset k < 64 of the window
+template <class Cur>
+__device__ inline uint32_t cur_win(const Cur &C, uint32_t k)
+{
+    const uint64_t x = k < 32 ? (((uint64_t)C.a << 32) | C.b) : (((uint64_t)C.b << 32) | C.n);
+    return (uint32_t)((x << (k & 31)) >> 32);
+}
 
 struct DecTab {
     const uint16_t *lut;
@@ -616,10 +632,11 @@ struct DecTab {
 
 // One token at r: returns the symbol; c = counter of a C_zr symbol (else 0),
 // adv = bits taken.
-template <class Src>
-__device__ inline uint32_t dec_token(const Src &S, const DecTab &T, uint32_t r, uint32_t &c, uint32_t &adv)
+template <class Cur>
+__device__ inline uint32_t dec_token(Cur &C, const DecTab &T, uint32_t r, uint32_t &c, uint32_t &adv)
 {
-    const uint32_t w = S.win(r);
+    const uint32_t k = cur_at(C, r);
+    const uint32_t w = (uint32_t)(((((uint64_t)C.a << 32) | C.b) << k) >> 32);
     const uint32_t e = T.lut[w >> (32 - kLutK)];
     uint32_t v, L, cw;
     if (!(e & kLutLong)) {
@@ -636,7 +653,7 @@ __device__ inline uint32_t dec_token(const Src &S, const DecTab &T, uint32_t r, 
         }
         v = T.lsym[lo];
         L = T.llen[lo];
-        cw = S.win_safe(r + L);
+        cw = cur_win(C, k + L);
     }
     const bool z = (v == T.czr);
     c = z ? (cw >> (32 - T.wz)) : 0u;
@@ -703,20 +720,20 @@ __device__ inline void xf_push(RunXf &f, bool dig, uint32_t c, uint32_t wz)
 // Tokens from r up to the first token start at or after lim, appended to f.
 // Once f holds a literal only mid and V1 change (a digit extends the pending
 // run, a symbol closes it), so the rest of the range takes a shorter update.
-template <class Src>
-__device__ inline uint32_t run_tokens(const Src &S, const DecTab &T, uint32_t r, uint32_t lim, RunXf &f)
+template <class Cur>
+__device__ inline uint32_t run_tokens(Cur &C, const DecTab &T, uint32_t r, uint32_t lim, RunXf &f)
 {
     const uint32_t czr = T.czr, wz = T.wz;
     while (r < lim && !f.lit) {
         uint32_t c, adv;
-        const uint32_t v = dec_token(S, T, r, c, adv);
+        const uint32_t v = dec_token(C, T, r, c, adv);
         r += adv;
         xf_push(f, v == czr && c, c, wz);
     }
     uint32_t mid = f.mid, V1 = f.V1;
     while (r < lim) {
         uint32_t c, adv;
-        const uint32_t v = dec_token(S, T, r, c, adv);
+        const uint32_t v = dec_token(C, T, r, c, adv);
         r += adv;
         const bool dig = v == czr && c;
         mid = dig ? mid : min(mid + V1 + 1u, kSat);
@@ -741,9 +758,31 @@ constexpr uint32_t kSyncWin = 128, kSyncWin2 = 384;
 // resynchronise), else it decodes the whole chunk; repeated until no lane
 // changes.  A wave scan of the run maps gives each lane its output position
 // and pending run; phase 3 decodes again and writes the non-zero symbols
-// (the plane was zeroed, so runs write nothing).
-template <class Src>
-__device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uint32_t M, uint8_t *out)
+// into a zeroed copy of the plane in LDS (runs write nothing), which the wave
+// then stores to the plane with whole-line 16-byte stores.
+// The segment decoder runs one-wave workgroups, and the LDS operations of a
+// wave take effect in program order: ordering the accesses in the compiled
+// code is all a hand-over between lanes needs (no wait for memory).
+__device__ inline void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// Stores the M symbols staged in LDS to the plane (both 16-byte aligned, the
+// plane's stride padded to 16 bytes) with the whole wave.
+__device__ inline void store_plane(const uint8_t *pl, uint8_t *out, uint32_t M)
+{
+    const uint4 *src = (const uint4 *)pl;
+    uint4 *dst = (uint4 *)out;
+    const uint32_t M16 = (M + 15) / 16;
+    for (uint32_t i = threadIdx.x & 63; i < M16; i += 64) dst[i] = src[i];
+}
+__device__ inline void zero_lds_plane(uint8_t *pl, uint32_t M)
+{
+    uint4 *d = (uint4 *)pl;
+    const uint32_t M16 = (M + 15) / 16;
+    for (uint32_t i = threadIdx.x & 63; i < M16; i += 64) d[i] = make_uint4(0, 0, 0, 0);
+}
+
+template <class Cur>
+__device__ int32_t decode_segment(Cur C, const DecTab &T, uint32_t N, uint32_t M, uint8_t *pl, uint8_t *out)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wz = T.wz, czr = T.czr;
@@ -756,10 +795,11 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
     // phase 1
     RunXf fpre = xf_id(), G1 = xf_id(), G2 = xf_id();
     const uint32_t l1 = (cs + kSyncWin < ce) ? cs + kSyncWin : ce;
-    const uint32_t sw1 = run_tokens(S, T, cs, l1, fpre);
+    C.seek(cs);
+    const uint32_t sw1 = run_tokens(C, T, cs, l1, fpre);
     const uint32_t l2 = (cs + kSyncWin2 < ce) ? cs + kSyncWin2 : ce;
-    const uint32_t sw2 = run_tokens(S, T, sw1, l2, G1);
-    const uint32_t exit1 = run_tokens(S, T, sw2, ce, G2);
+    const uint32_t sw2 = run_tokens(C, T, sw1, l2, G1);
+    const uint32_t exit1 = run_tokens(C, T, sw2, ce, G2);
     const RunXf G12 = xf_combine(G1, G2);
     RunXf f = xf_combine(fpre, G12);
     uint32_t start = cs, exitc = exit1;
@@ -771,18 +811,19 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
         if (!__any(chg)) break;
         if (chg) {
             start = want;
+            C.seek(want);
             RunXf Pm = xf_id();
-            uint32_t q = run_tokens(S, T, want, min(sw1, ce), Pm);
+            uint32_t q = run_tokens(C, T, want, min(sw1, ce), Pm);
             if (q == sw1) {
                 f = xf_combine(Pm, G12);
                 exitc = exit1;
             } else {
-                q = run_tokens(S, T, q, min(sw2, ce), Pm);
+                q = run_tokens(C, T, q, min(sw2, ce), Pm);
                 if (q == sw2) {
                     f = xf_combine(Pm, G2);
                     exitc = exit1;
                 } else {
-                    q = run_tokens(S, T, q, ce, Pm);
+                    q = run_tokens(C, T, q, ce, Pm);
                     f = Pm;
                     exitc = q;
                 }
@@ -805,43 +846,26 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
     uint32_t op, run;
     if (ex.lit) { op = sadd(ex.V0, ex.mid); run = ex.V1; }
     else { op = 0; run = ex.V0; }
-    // phase 3: write.  A lane's output positions only grow, so its non-zero
-    // symbols are gathered into 32-bit words of the (zeroed, 4-byte aligned)
-    // plane: a word left behind lies inside the lane's range and is stored
-    // whole; the first word written and the last may be shared with the
-    // neighbouring lanes and are ORed in.
+    zero_lds_plane(pl, M);
+    wave_sync();
+    // phase 3: write the non-zero symbols into the LDS plane
     int32_t err = 0;
     const bool last = active && (lane == 63 || cs + chunk >= N);
     if (active) {
-        uint32_t *outw = (uint32_t *)out;
-        uint32_t wcur = ~0u, wacc = 0;
-        bool wfirst = true;
         uint32_t q = start;
         bool bad = false;
+        C.seek(start);
         while (q < ce) {
             uint32_t c, adv;
-            const uint32_t v = dec_token(S, T, q, c, adv);
+            const uint32_t v = dec_token(C, T, q, c, adv);
             q += adv;
             const bool dig = (v == czr) && c;
             const uint32_t opr = sadd(op, run);
             bad |= !dig && (run == 1 || opr >= M);
-            if (!dig && v && opr < M) {
-                const uint32_t wi = opr >> 2;
-                if (wi != wcur) {
-                    if (wacc) {
-                        if (wfirst) atomicOr(&outw[wcur], wacc);
-                        else outw[wcur] = wacc;
-                    }
-                    wfirst = wcur == ~0u;
-                    wcur = wi;
-                    wacc = 0;
-                }
-                wacc |= v << (8 * (opr & 3u));
-            }
+            if (!dig && v && opr < M) pl[opr] = (uint8_t)v;
             op = dig ? op : opr + 1;
             run = dig ? run_push(run, c, wz) : 0u;
         }
-        if (wacc) atomicOr(&outw[wcur], wacc);
         if (last) {
             if (run) {
                 bad |= run < 2;
@@ -851,21 +875,22 @@ __device__ int32_t decode_segment(const Src &S, const DecTab &T, uint32_t N, uin
         }
         if (bad) err = D_CORRUPT;
     }
+    wave_sync();
+    store_plane(pl, out, M);
     if (N == 0 && lane == 0 && M != 0) err = D_CORRUPT;
     return err;
 }
 
 struct SegShared {
     uint16_t lut[1 << kLutK];
-    uint32_t acode[256];
-    uint8_t llen[256], lsym[256];
+    alignas(16) uint8_t plane[kMaxSeg];  // one segment's symbols
     uint32_t bits[kSegWords + 2];
 };
 
 // Persistent waves taking (block, segment) items from the two lists (large
-// segments first); per item: the symbol plane zeroed in place, code tables
-// and the segment's bits to LDS, then the non-zero symbols written straight
-// to the plane (13.8 KB of LDS per wave: eleven waves per CU).
+// segments first); per item: the prefix table and the segment's bits to LDS,
+// then per segment the three phases, the symbols gathered in LDS and stored
+// to the plane in whole lines (14.5 KB of LDS per wave: eleven waves per CU).
 __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
                                                      uint8_t *__restrict__ ws,
                                                      int32_t *__restrict__ status)
@@ -902,30 +927,20 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
             continue;
         }
         const uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
-        // the planes start as zeros (16-byte aligned, their stride padded to
-        // 16 bytes); the decode writes only non-zero symbols over them
-        for (uint32_t k = s0; k < s1; k++) {
-            uint4 *gz = (uint4 *)(ws + B.sym_off + (uint64_t)P.seg_plane[k] * pstride);
-            const uint32_t M16 = (P.seg_M[k] + 15) / 16;
-            for (uint32_t i = lane; i < M16; i += 64) gz[i] = make_uint4(0, 0, 0, 0);
-        }
-        __syncthreads();  // the previous item is done with S
+        wave_sync();  // the previous item is done with S
         {
-            // code tables (kLutStride / 16 pieces of 16 bytes, in the order of
-            // SegShared): all loads of a lane first
-            static_assert(kLutStride % 16 == 0, "table copy layout");
-            constexpr uint32_t NQ = kLutStride / 16, NR = (NQ + 63) / 64;
+            // prefix table (kLutBytes16 / 16 pieces of 16 bytes): all loads
+            // of a lane first.  The leaf tables that resolve the long codes
+            // stay in global memory (read through the L1 cache).
+            static_assert(kLutBytes16 % (16 * 64) == 0, "table copy layout");
+            constexpr uint32_t NR = kLutBytes16 / (16 * 64);
             const uint4 *src = (const uint4 *)tab;
             uint4 *dst = (uint4 *)S.lut;
             uint4 a[NR];
 #pragma unroll
-            for (uint32_t r = 0; r < NR; r++) {
-                const uint32_t i = lane + 64 * r;
-                a[r] = i < NQ ? src[i] : make_uint4(0, 0, 0, 0);
-            }
+            for (uint32_t r = 0; r < NR; r++) a[r] = src[lane + 64 * r];
 #pragma unroll
-            for (uint32_t r = 0; r < NR; r++)
-                if (lane + 64 * r < NQ) dst[lane + 64 * r] = a[r];
+            for (uint32_t r = 0; r < NR; r++) dst[lane + 64 * r] = a[r];
         }
         const uint64_t lo = B.byte_off, hi = B.byte_off + B.byte_len;
         const uint64_t w0 = S0 >> 5;
@@ -971,10 +986,12 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
             }
             if (lane < 2) S.bits[nw + lane] = 0u;
         }
-        __threadfence_block();  // the zero stores are complete before any symbol store
-        __syncthreads();
+        wave_sync();
         DecTab T;
-        T.lut = S.lut; T.acode = S.acode; T.llen = S.llen; T.lsym = S.lsym;
+        T.lut = S.lut;
+        T.acode = (const uint32_t *)(tab + kLutBytes16);
+        T.llen = tab + kLutBytes16 + 1024;
+        T.lsym = T.llen + 256;
         T.m = P.m; T.czr = P.czr; T.wz = P.wz;
         int32_t err = 0;
         for (uint32_t k = s0; k < s1; k++) {
@@ -982,19 +999,26 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
             const uint64_t Sk = P.seg_bitpos[k];
             uint8_t *out = ws + B.sym_off + (uint64_t)P.seg_plane[k] * pstride;
             int32_t e = 0;
-            if (T.m == 1 && S.lsym[0] != T.czr) {
+            if (T.m == 1 && T.lsym[0] != T.czr) {
                 // zero-length codewords: the segment is M copies of the leaf
                 if (N != 0) e = D_CORRUPT;
-                else if (S.lsym[0]) for (uint32_t i = lane; i < M; i += 64) out[i] = S.lsym[0];
+                const uint32_t fill = T.lsym[0] * 0x01010101u;
+                uint32_t *pw = (uint32_t *)S.plane;
+                for (uint32_t i = lane; i < (M + 15) / 16 * 4; i += 64) {
+                    const uint32_t b = 4 * i;
+                    pw[i] = b + 4 <= M ? fill : (b < M ? fill & ((1u << (8 * (M - b))) - 1u) : 0u);
+                }
+                wave_sync();
+                store_plane(S.plane, out, M);
             } else if (staged) {
                 const uint32_t wk = (uint32_t)((Sk >> 5) - w0);
-                SrcLds src;
+                CurLds src;
                 src.w = S.bits + wk; src.off = (uint32_t)(Sk & 31); src.nw = nw - wk;
-                e = decode_segment(src, T, N, M, out);
+                e = decode_segment(src, T, N, M, S.plane, out);
             } else {
-                SrcGlb src;
+                CurGlb src;
                 src.enc = enc; src.lo = lo; src.hi = hi; src.w0 = Sk >> 5; src.off = (uint32_t)(Sk & 31);
-                e = decode_segment(src, T, N, M, out);
+                e = decode_segment(src, T, N, M, S.plane, out);
             }
             err = e ? e : err;
         }

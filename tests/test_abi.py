@@ -191,7 +191,7 @@ def test_tuning_ranges_are_checked_on_the_host():
     d = isx.tile_desc(64, 64, 3, 1, 8, 3)
     pb = L.isx_encode_plan_bytes(ctypes.byref(d), 1)
     buf = (ctypes.c_uint8 * pb)()
-    for t, ok in [((32, 0, 0), True), ((32, 0, 13), True), ((16, 64, 1), True), ((32, 0, 14), False),
+    for t, ok in [((32, 0, 0), True), ((32, 0, 11), True), ((16, 64, 1), True), ((32, 0, 12), False),
                   ((32, 0, -1), False), ((24, 0, 0), False), ((32, 65, 0), False)]:
         tu = isx.tuning(*t)
         rc = L.isx_encode_plan_build_tuned(ctypes.byref(d), 1, ctypes.byref(tu), buf, pb)
