@@ -229,6 +229,7 @@ struct Plan {
     uint8_t *dst = nullptr;
     uint64_t cap = 0;
     bool sizes_only = false;
+    bool wide_coeffs = false;  // keep every band int32 (coefficient dumps)
 };
 
 int device_cus()
@@ -360,6 +361,17 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     H.ws_tileout = o; o = al(o + (uint64_t)n * sizeof(TileOut));
     for (int32_t i = 0; i < n; i++) {
         TileGeo &T = tb[i].g;
+        // The level-1 LH, HL and HH bands (three quarters of the coefficients)
+        // are held as int16 by the strip kernels when every value fits: an
+        // encode's quantised level-1 outputs are at most 4 (2^bits - 1) + 2 in
+        // magnitude (the high-pass step of the bit-depth bound), and a decode's
+        // dequantised ones at most (2^(dmax-1) - 1) step + step/2, since the
+        // decoder rejects a block deeper than dmax planes.
+        T.coef16 = 0;
+        if (H.tq == 32 && !P.wide_coeffs) {
+            if (mode == MODE_ENCODE) T.coef16 = T.bits <= 13;
+            else T.coef16 = ((1ull << (T.dmax - 1)) - 1) * T.qstep + T.qstep / 2 <= 32767u;
+        }
         uint64_t base = o / 4;  // int32 elements
         T.ll_off += base;
         for (uint32_t l = 1; l <= T.levels; l++)
@@ -941,6 +953,7 @@ int32_t isx_debug_forward(const isx_tile_desc *h_desc, const void *d_pixels, int
 {
     if (!h_desc || !d_pixels || !d_coeffs || !d_workspace) return ISX_E_INVALID_ARG;
     Plan P;
+    P.wide_coeffs = true;
     int rc = build_plan(MODE_ENCODE, h_desc, nullptr, 1, P);
     if (rc) return rc;
     if (workspace_bytes < P.H.ws_bytes) return ISX_E_WORKSPACE;

@@ -40,6 +40,8 @@ struct TileGeo {
     uint32_t width, height;
     uint8_t channels, bps, bits, levels;
     uint8_t ct, target_level, dmax, first_level;  // first_level: lowest level reconstructed
+    uint8_t coef16;        // level-1 LH, HL, HH held as int16 in their (int32-sized) arena regions
+    uint8_t pad8[3];
     uint32_t qstep;
     uint32_t qmul, qsh;    // n / qstep = (t + ((n - t) >> 1)) >> qsh, t = mulhi(qmul, n), for qstep > 1
     uint64_t enc_offset;   // decode: encoded tile offset in d_encoded
@@ -111,7 +113,8 @@ struct BlockDesc {
     uint16_t bx, by;
     uint16_t wb, hb;       // padded block size (multiples of 4, <= 128)
     uint8_t tw[3], th[3];  // extent of each type inside the cell (<= 128)
-    uint16_t pad1;
+    uint8_t c16;           // coefficients held as int16: off[] counts int16 elements
+    uint8_t pad1;
     uint32_t pitch[3];
     uint64_t off[3];       // int32-element offset of each type's cell origin (ws)
     uint64_t sym_off;      // byte offset of the block's symbols (ws)
@@ -200,6 +203,7 @@ __host__ __device__ inline void block_geometry(const TileGeo &T, uint32_t local,
 {
     uint32_t nll = T.ll_gx * T.ll_gy;
     B.local = local;
+    B.c16 = 0;
     if (local < nll * T.channels) {
         uint32_t c = local / nll, r = local % nll;
         uint32_t by = r / T.ll_gx, bx = r % T.ll_gx;
@@ -239,9 +243,11 @@ __host__ __device__ inline void block_geometry(const TileGeo &T, uint32_t local,
         B.tw[t] = (uint8_t)(tw[t] >= 128 ? 128 : tw[t]);
         B.th[t] = (uint8_t)(th[t] >= 128 ? 128 : th[t]);
         B.pitch[t] = G.pitch[t];
-        B.off[t] = G.off[t] + (uint64_t)c * T.chan_elems + (uint64_t)(by * kBlock - G.wy0) * G.pitch[t] +
-                   (bx * kBlock - G.wx0);
+        const uint64_t band = G.off[t] + (uint64_t)c * T.chan_elems;  // int32 elements
+        const uint64_t org = (uint64_t)(by * kBlock - G.wy0) * G.pitch[t] + (bx * kBlock - G.wx0);
+        B.off[t] = (l == 1 && T.coef16) ? 2 * band + org : band + org;
     }
+    B.c16 = (l == 1 && T.coef16) ? 1 : 0;
 }
 
 // The 8 XCDs of the chip receive a launch's workgroups round-robin, and each

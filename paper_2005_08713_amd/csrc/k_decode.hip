@@ -1068,6 +1068,7 @@ __global__ void __launch_bounds__(NT) k_dec_reasm(PlanHdr H, const uint8_t *__re
     const uint32_t p = B.p, wb = B.wb, hb = B.hb, n = wb * hb / 8, cpt = n / 2, wq = wb / 4;
     const uint32_t d = P.d, nseg = P.nseg;
     const uint32_t step = (B.level == 0) ? 1u : T.qstep;
+    const bool c16 = B.c16 != 0;
     int32_t *wsi = (int32_t *)ws;
     const uint8_t *sym = ws + B.sym_off;
     const uint32_t pstr = plane_stride(p * n);
@@ -1133,6 +1134,13 @@ __global__ void __launch_bounds__(NT) k_dec_reasm(PlanHdr H, const uint8_t *__re
                 int32_t q = (int32_t)mag[i];
                 if (step > 1 && q) q = q * (int32_t)step + (int32_t)(step / 2);
                 o[cc] = ((sgn >> i) & 1u) ? -q : q;
+            }
+            if (c16) {  // coefficients held as int16 (their bound fits)
+                int16_t *dst = (int16_t *)ws + toff + (uint64_t)row * tpitch + c0;
+                if (c0 + 3 < tw) *(short4 *)dst = make_short4((short)o[0], (short)o[1], (short)o[2], (short)o[3]);
+                else
+                    for (int cc = 0; cc < 4 && c0 + cc < tw; cc++) dst[cc] = (int16_t)o[cc];
+                continue;
             }
             int32_t *dst = wsi + toff + (uint64_t)row * tpitch + c0;
             if (c0 + 3 < tw) *(int4 *)dst = make_int4(o[0], o[1], o[2], o[3]);

@@ -186,6 +186,7 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
     const uint32_t pstr = plane_stride(p * n);
     uint8_t *symb = ws + B.sym_off;
     const BlockDesc &Bg = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+    const bool c16 = Bg.c16 != 0;  // coefficients held as int16
 #pragma unroll 1
     for (int k = 0; k < kCellsPT; k++) {
         const uint32_t cell = (uint32_t)k * kSymNT + tid;
@@ -203,7 +204,16 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
         for (int rr = 0; rr < 4; rr++) {
             const uint32_t row = r0 + rr;
             int32_t v[4] = {0, 0, 0, 0};
-            if (row < th && c0 < tw) {
+            if (row < th && c0 < tw && c16) {
+                const int16_t *src = (const int16_t *)ws + toff + (uint64_t)row * tpitch + c0;
+                if (c0 + 3 < tw) {
+                    const short4 q = *(const short4 *)src;
+                    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < 4; cc++) v[cc] = (c0 + cc < tw) ? src[cc] : 0;
+                }
+            } else if (row < th && c0 < tw) {
                 const int32_t *src = wsi + toff + (uint64_t)row * tpitch + c0;
                 if (c0 + 3 < tw) {
                     const int4 q = *(const int4 *)src;

@@ -926,6 +926,7 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
                                   wsi + G.off[2] + (uint64_t)c * T.chan_elems};
         const uint32_t bpitch[4] = {llpitch, G.pitch[1], G.pitch[0], G.pitch[2]};
         const int bw[4] = {llw, hw, llw, hw}, bh[4] = {llh, llh, hh, hh};
+        const bool b16 = level == 1 && T.coef16;  // the H bands of level 1 as int16
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const int b = k;  // band of this pass: thread t stores row t >> 3, piece t & 7
@@ -933,6 +934,14 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
             const int qy = qy0 + row, qxs = qx0 + 4 * part;
             if (qy >= bh[b] || qxs >= bw[b]) continue;
             const int32_t *src = win + b * BS + row * BP + 4 * part;
+            if (b16 && b > 0) {
+                int16_t *dst = (int16_t *)bptr[b] + (uint64_t)qy * bpitch[b] + qxs;
+                if (qxs + 3 < bw[b])
+                    *(short4 *)dst = make_short4((short)src[0], (short)src[1], (short)src[2], (short)src[3]);
+                else
+                    for (int e = 0; e < 4 && qxs + e < bw[b]; e++) dst[e] = (int16_t)src[e];
+                continue;
+            }
             int32_t *dst = bptr[b] + (uint64_t)qy * bpitch[b] + qxs;
             if (qxs + 3 < bw[b]) *(int4 *)dst = *(const int4 *)src;
             else
@@ -989,8 +998,21 @@ struct InvLoad {
     int hdst;
 };
 
+// b16: the LH, HL and HH bands are held as int16 (level 1 of a tile whose
+// level-1 values fit); LL is int32.
+__device__ inline int32_t band_at(const int32_t *base, bool is16, uint64_t i)
+{
+    // one 32-bit load either way (lanes of one instruction may read bands
+    // of both kinds): an int16 element comes with its 4-byte-aligned
+    // neighbour, which lies inside the row's padded pitch
+    const uint8_t *b = (const uint8_t *)base;
+    const int32_t w = *(const int32_t *)(b + (is16 ? 2 * (i & ~1ull) : 4 * i));
+    const uint32_t sh = is16 ? 16u - 16u * (uint32_t)(i & 1) : 0u;
+    return is16 ? (int32_t)((uint32_t)w << sh) >> 16 : w;
+}
+
 __device__ inline void inv_strips_load(const TileGeo &T, int level, int ch, const int32_t *rmap, const int32_t *cmap,
-                                       const int32_t *wsi, int lane, int wv, InvLoad &L)
+                                       const int32_t *wsi, int lane, int wv, bool b16, InvLoad &L)
 {
     using namespace strips;
     const LevelGeo &G = T.lv[level];
@@ -1015,21 +1037,21 @@ __device__ inline void inv_strips_load(const TileGeo &T, int level, int ch, cons
         const int gy = rmap[lr], gx = cmap[lc];
         const int32_t *src = (gy & 1) ? ((gx & 1) ? hh : lh) : ((gx & 1) ? hl : ll);
         const uint32_t pitch = (gy & 1) ? G.pitch[(gx & 1) ? 2 : 0] : ((gx & 1) ? G.pitch[1] : llp);
-        L.hv = src[(uint64_t)(gy >> 1) * pitch + (gx >> 1)];
+        L.hv = band_at(src, b16 && ((gy | gx) & 1), (uint64_t)(gy >> 1) * pitch + (gx >> 1));
         L.hdst = lr * WP + lc;
     }
     // window column 2 + lane: even rows LL | HL, odd rows LH | HH
     const int gx = cmap[2 + lane];
     const bool xo = (gx & 1) != 0;
-    const int32_t *pe = (xo ? hl : ll) + (gx >> 1);
-    const int32_t *po = (xo ? hh : lh) + (gx >> 1);
+    const int32_t *pe = xo ? hl : ll;
+    const int32_t *po = xo ? hh : lh;
     const uint32_t pitch_e = xo ? G.pitch[1] : llp, pitch_o = G.pitch[xo ? 2 : 0];
+    const bool e16 = b16 && xo;
 #pragma unroll
     for (int j = 0; j < 19; j++) {
         const int gy = __builtin_amdgcn_readfirstlane(rmap[1 + 16 * wv + j]);
-        const int32_t *p = (gy & 1) ? po : pe;
-        const uint32_t pitch = (gy & 1) ? pitch_o : pitch_e;
-        L.x[j] = p[(uint64_t)(gy >> 1) * pitch];
+        if (gy & 1) L.x[j] = band_at(po, b16, (uint64_t)(gy >> 1) * pitch_o + (gx >> 1));
+        else L.x[j] = band_at(pe, e16, (uint64_t)(gy >> 1) * pitch_e + (gx >> 1));
     }
 }
 
@@ -1098,7 +1120,7 @@ __global__ void __launch_bounds__(256) k_inv_level_strips(PlanHdr H, const uint8
     int32_t o[16];
     {
         InvLoad L;
-        inv_strips_load(T, level, c, rmap, cmap, wsi, lane, wv, L);
+        inv_strips_load(T, level, c, rmap, cmap, wsi, lane, wv, false, L);
         inv_strips_cols(L, win, lane, wv, G.h > 1);
     }
     __syncthreads();
@@ -1185,7 +1207,8 @@ __global__ void __launch_bounds__(256) k_inv_final_strips(PlanHdr H, const uint8
     const int xs = 2 * qx0 + 16 * wv;  // its first output column
     int32_t v[3][16];
     InvLoad L;  // the coefficients of the channel the window takes next
-    if (fused) inv_strips_load(T, z + 1, c0, rmap, cmap, wsi, lane, wv, L);
+    const bool b16 = z == 0 && T.coef16;
+    if (fused) inv_strips_load(T, z + 1, c0, rmap, cmap, wsi, lane, wv, b16, L);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         if (k >= nc) {
@@ -1197,7 +1220,7 @@ __global__ void __launch_bounds__(256) k_inv_final_strips(PlanHdr H, const uint8
             if (k) __syncthreads();  // the previous row pass has read the window
             inv_strips_cols(L, win, lane, wv, oh > 1);
             // the next channel's loads are in flight during this row pass
-            if (k + 1 < nc) inv_strips_load(T, z + 1, c0 + k + 1, rmap, cmap, wsi, lane, wv, L);
+            if (k + 1 < nc) inv_strips_load(T, z + 1, c0 + k + 1, rmap, cmap, wsi, lane, wv, b16, L);
             __syncthreads();
             inv_strips_rows(win, lane, wv, oh > 1, ow > 1, v[k]);
         } else {
