@@ -187,6 +187,11 @@ struct TileOut {
 // ---------------------------------------------------------------- helpers
 __host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline uint32_t round4(uint32_t a) { return (a + 3u) & ~3u; }
+// Hand-over between the lanes of a one-wave workgroup through LDS: the LDS
+// operations of a wave take effect in program order, so keeping the compiled
+// accesses in order is all it needs (no wait for memory, no barrier).
+__device__ inline void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
 __host__ __device__ inline uint32_t bitlen32(uint32_t v) { return v ? 32u - (uint32_t)__builtin_clz(v) : 0u; }
 // Bytes between the bitplanes of a block's symbol area (p*n symbols per
 // plane, padded to 16 bytes so each plane is written with 16-byte stores).

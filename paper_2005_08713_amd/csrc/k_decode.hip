@@ -760,11 +760,6 @@ constexpr uint32_t kSyncWin = 128, kSyncWin2 = 384;
 // and pending run; phase 3 decodes again and writes the non-zero symbols
 // into a zeroed copy of the plane in LDS (runs write nothing), which the wave
 // then stores to the plane with whole-line 16-byte stores.
-// The segment decoder runs one-wave workgroups, and the LDS operations of a
-// wave take effect in program order: ordering the accesses in the compiled
-// code is all a hand-over between lanes needs (no wait for memory).
-__device__ inline void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
-
 // Stores the M symbols staged in LDS to the plane (both 16-byte aligned, the
 // plane's stride padded to 16 bytes) with the whole wave.
 __device__ inline void store_plane(const uint8_t *pl, uint8_t *out, uint32_t M)

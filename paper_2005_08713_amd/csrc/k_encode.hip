@@ -440,44 +440,86 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
 // ---------------------------------------------------------------- Huffman
 // Code lengths of the per-block Huffman code (Sec. 3 / Sec. 4): leaves with
 // f > 0 sorted by (f, symbol); two-queue merge taking the leaf on equal
-// weight; length = depth.
+// weight; length = depth.  One wave per block, no workgroup barriers: lane l
+// holds the symbols l, l + 64, l + 128 and l + 192; lanes hand values over
+// through LDS with wave_sync.
 //
-// The merge runs in rounds over the whole workgroup.  With s the sum of the
-// two smallest candidates (the next internal weight), every candidate of
-// weight <= s precedes every internal node created from now on (leaves win
-// ties, older internal nodes precede newer ones), so the sequential merge
-// pairs these candidates two by two in their merged order before it looks
-// at a new node: one round makes all floor(T/2) of those merges at once
-// (T = candidates <= s).  This gives the same tree as the one-at-a-time
-// merge; blocks take about ten rounds.
-struct HuffScratch {
-    uint32_t w[512];
+// The merge runs in rounds.  With s the sum of the two smallest candidates
+// (the next internal weight), every candidate of weight <= s precedes every
+// internal node created from now on (leaves win ties, older internal nodes
+// precede newer ones), so the sequential merge pairs these candidates two by
+// two in their merged order before it looks at a new node: one round makes
+// all floor(T/2) of those merges at once (T = candidates <= s).  This gives
+// the same tree as the one-at-a-time merge; blocks take about ten rounds.
+// A node is merged only in a round after the one that made it, so depths
+// follow top-down, a round at a time from the last (whose one node is the
+// root).
+
+struct HuffW {
+    uint32_t w[512];       // sorted leaf weights, then internal nodes in creation order
     uint16_t par[512];
-    uint16_t srt[256];
-    uint16_t ord[512];
-    __attribute__((aligned(16))) uint32_t key[256];
-    uint32_t cnt[8];
-    uint32_t m;
+    uint16_t srt[256];     // symbol of sorted leaf r
+    uint16_t ord[512];     // a round's candidates in merged order
+    uint16_t rfirst[256];  // first internal node of each round
+    uint8_t dep[512];
 };
 
-// Number of keys in k[0..256) below x (k is in LDS, read 4 at a time).
-__device__ inline uint32_t count_below(const uint32_t *k, uint32_t x)
+// Ascending bitonic sort of 256 keys held as a[j] = element j * 64 + lane.
+__device__ inline void wave_sort256(uint32_t (&a)[4])
 {
-    const uint4 *k4 = (const uint4 *)k;
-    uint32_t r = 0;
-#pragma unroll 16
-    for (uint32_t u = 0; u < 64; u++) {
-        const uint4 q = k4[u];
-        r += (q.x < x) + (q.y < x) + (q.z < x) + (q.w < x);
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (uint32_t k = 2; k <= 256; k <<= 1) {
+#pragma unroll
+        for (uint32_t d = k >> 1; d > 0; d >>= 1) {
+            uint32_t o[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                o[j] = d >= 64 ? a[j ^ (int)(d >> 6)] : (uint32_t)__shfl_xor((int)a[j], (int)d, 64);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t i = (uint32_t)j * 64 + lane;
+                const bool keep_min = ((i & d) == 0) == ((i & k) == 0);
+                a[j] = keep_min ? min(a[j], o[j]) : max(a[j], o[j]);
+            }
+        }
     }
-    return r;
 }
 
-__device__ void huff_merge_rounds(HuffScratch &S, uint32_t m)
+// The leaves with f > 0 in (f, symbol) order: S.srt, S.w.  Returns m.
+__device__ inline uint32_t sort_leaves(const uint32_t *f, HuffW &S)
 {
-    const uint32_t v = threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t a[4], m = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t s = (uint32_t)j * 64 + lane, fv = f[s];
+        a[j] = fv ? (fv << 8) | s : 0xffffffffu;  // f < 2^24
+        m += (uint32_t)__popcll(__ballot(fv > 0));
+    }
+    if (m <= 1) return m;
+    wave_sort256(a);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t i = (uint32_t)j * 64 + lane;
+        if (i < m) {
+            S.srt[i] = (uint16_t)(a[j] & 0xffu);
+            S.w[i] = a[j] >> 8;
+        }
+    }
+    wave_sync();
+    return m;
+}
+
+__device__ void huff_lengths(const uint32_t *f, uint8_t *len, HuffW &S)
+{
+    const uint32_t lane = threadIdx.x & 63;
     constexpr uint32_t INF = 0xffffffffu;
-    uint32_t qa = 0, qb = 0, ne = 0;  // leaf head, internal head, internal count
+#pragma unroll
+    for (int j = 0; j < 4; j++) len[j * 64 + lane] = 0;
+    const uint32_t m = sort_leaves(f, S);
+    if (m <= 1) { wave_sync(); return; }
+    uint32_t qa = 0, qb = 0, ne = 0, nr = 0;  // leaf head, internal head, internal count, rounds
     while (ne + 1 < m) {
         // the two smallest candidates (leaf first on ties)
         const uint32_t x0 = qa < m ? S.w[qa] : INF, x1 = qa + 1 < m ? S.w[qa + 1] : INF;
@@ -485,112 +527,97 @@ __device__ void huff_merge_rounds(HuffScratch &S, uint32_t m)
         uint32_t sum;
         if (x0 <= y0) sum = x0 + (x1 <= y0 ? x1 : y0);
         else sum = y0 + (x0 <= y1 ? x0 : y1);
-        // candidates <= sum in each queue (both sorted): per-wave ballots,
-        // one barrier for both counts (4 waves)
-        const uint64_t bl = __ballot(qa + v < m && S.w[qa + v] <= sum);
-        const uint64_t bi = __ballot(qb + v < ne && S.w[m + qb + v] <= sum);
-        uint32_t *cs = S.cnt;
-        if ((v & 63) == 0) {
-            cs[v >> 6] = (uint32_t)__popcll(bl);
-            cs[4 + (v >> 6)] = (uint32_t)__popcll(bi);
-        }
-        __syncthreads();
+        // candidates <= sum in each queue (both sorted)
         uint32_t cl = 0, ci = 0;
 #pragma unroll
-        for (int k = 0; k < 4; k++) { cl += cs[k]; ci += cs[4 + k]; }
+        for (int c = 0; c < 4; c++) {
+            const uint32_t t = lane + 64u * c;
+            cl += (uint32_t)__popcll(__ballot(qa + t < m && S.w[qa + t] <= sum));
+            ci += (uint32_t)__popcll(__ballot(qb + t < ne && S.w[m + qb + t] <= sum));
+        }
         const uint32_t T = cl + ci, P = T / 2;
         // merged order: a leaf goes before internal nodes of equal weight
-        if (v < cl) {
-            const uint32_t x = S.w[qa + v];
-            uint32_t lo = 0, hi = ci;  // internal nodes < x
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (S.w[m + qb + mid] < x) lo = mid + 1; else hi = mid;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const uint32_t t = lane + 64u * c;
+            if (t < cl) {
+                const uint32_t x = S.w[qa + t];
+                uint32_t lo = 0, hi = ci;  // internal nodes < x
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (S.w[m + qb + mid] < x) lo = mid + 1; else hi = mid;
+                }
+                S.ord[t + lo] = (uint16_t)(qa + t);
             }
-            S.ord[v + lo] = (uint16_t)(qa + v);
-        }
-        if (v < ci) {
-            const uint32_t y = S.w[m + qb + v];
-            uint32_t lo = 0, hi = cl;  // leaves <= y
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (S.w[qa + mid] <= y) lo = mid + 1; else hi = mid;
+            if (t < ci) {
+                const uint32_t y = S.w[m + qb + t];
+                uint32_t lo = 0, hi = cl;  // leaves <= y
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (S.w[qa + mid] <= y) lo = mid + 1; else hi = mid;
+                }
+                S.ord[t + lo] = (uint16_t)(m + qb + t);
             }
-            S.ord[v + lo] = (uint16_t)(m + qb + v);
         }
-        __syncthreads();
-        if (v < P) {
-            const uint32_t a = S.ord[2 * v], b = S.ord[2 * v + 1];
-            const uint32_t id = m + ne + v;
-            S.w[id] = S.w[a] + S.w[b];
-            S.par[a] = (uint16_t)id;
-            S.par[b] = (uint16_t)id;
+        wave_sync();
+        if (lane == 0) S.rfirst[nr] = (uint16_t)(m + ne);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {  // P <= 128
+            const uint32_t t = lane + 64u * c;
+            if (t < P) {
+                const uint32_t a = S.ord[2 * t], b = S.ord[2 * t + 1];
+                const uint32_t id = m + ne + t;
+                S.w[id] = S.w[a] + S.w[b];
+                S.par[a] = (uint16_t)id;
+                S.par[b] = (uint16_t)id;
+            }
         }
         // leaves among the consumed 2P candidates
         const uint32_t lastleaf = (T & 1u) ? (S.ord[T - 1] < m ? 1u : 0u) : 0u;
+        wave_sync();
         const uint32_t nl = cl - lastleaf;
-        __syncthreads();
         qa += nl;
         qb += 2 * P - nl;
         ne += P;
+        nr++;
     }
-    if (v == 0) S.par[m + ne - 1] = 0xffff;
-    __syncthreads();
-}
-
-__device__ void huff_lengths(const uint32_t *f, uint8_t *len, HuffScratch &S)
-{
-    const uint32_t v = threadIdx.x;
-    uint32_t fv = f[v];
-    uint32_t m = __syncthreads_count(fv > 0);
-    len[v] = 0;
-    if (m <= 1) { __syncthreads(); return; }
-    // rank by (f, symbol): key f << 8 | symbol (f < 2^24), absent = max
-    const uint32_t kv = fv > 0 ? (fv << 8) | v : 0xffffffffu;
-    S.key[v] = kv;
-    __syncthreads();
-    if (fv > 0) {
-        const uint32_t r = count_below(S.key, kv);
-        S.srt[r] = (uint16_t)v;
-        S.w[r] = fv;
+    // depths: the root (the last round's one node) at 0, then each earlier
+    // round's nodes one below their parents
+    if (lane == 0) S.dep[m + ne - 1] = 0;
+    wave_sync();
+    for (int r = (int)nr - 2; r >= 0; r--) {
+        const uint32_t a = S.rfirst[r], b = S.rfirst[r + 1];
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            const uint32_t id = a + lane + 64u * c;
+            if (id < b) S.dep[id] = (uint8_t)(S.dep[S.par[id]] + 1);
+        }
+        wave_sync();
     }
-    __syncthreads();
-    huff_merge_rounds(S, m);
-    if (v < m) {
-        uint32_t dpt = 0, x = v;
-        while (S.par[x] != 0xffff) { x = S.par[x]; dpt++; }
-        len[S.srt[v]] = (uint8_t)dpt;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t i = (uint32_t)j * 64 + lane;
+        if (i < m) len[S.srt[i]] = (uint8_t)(S.dep[S.par[i]] + 1);
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // Length-limited optimal code by package-merge (fallback when a seek-table
-// entry of t bits cannot hold a segment length).  Thread 0 runs it; lengths
+// entry of t bits cannot hold a segment length).  Lane 0 runs it; lengths
 // are added level by level while backtracking the chosen items.
 struct PMScratch {
     uint32_t wa[512], wb[512];
     uint32_t flag[16][16];  // per level: bit i = item i is a package
 };
 
-__device__ void package_merge_lengths(const uint32_t *f, int limit, uint8_t *len, HuffScratch &S,
-                                      PMScratch &Q)
+__device__ void package_merge_lengths(const uint32_t *f, int limit, uint8_t *len, HuffW &S, PMScratch &Q)
 {
-    const uint32_t v = threadIdx.x;
-    uint32_t fv = f[v];
-    uint32_t m = __syncthreads_count(fv > 0);
-    len[v] = 0;
-    if (m <= 1) { __syncthreads(); return; }
-    if (fv > 0) {
-        uint32_t r = 0;
-        for (uint32_t u = 0; u < 256; u++) {
-            uint32_t fu = f[u];
-            r += (fu > 0) && (fu < fv || (fu == fv && u < v));
-        }
-        S.srt[r] = (uint16_t)v;
-        S.w[r] = fv;
-    }
-    __syncthreads();
-    if (v == 0) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < 4; j++) len[j * 64 + lane] = 0;
+    const uint32_t m = sort_leaves(f, S);
+    if (m <= 1) { wave_sync(); return; }
+    if (lane == 0) {
         uint32_t *prev = Q.wa, *cur = Q.wb;
         for (uint32_t i = 0; i < m; i++) prev[i] = S.w[i];
         uint32_t nprev = m;
@@ -624,92 +651,95 @@ __device__ void package_merge_lengths(const uint32_t *f, int limit, uint8_t *len
             if (!take) break;
         }
     }
-    __syncthreads();
+    wave_sync();
 }
 
-// Canonical codes (sort by (length, symbol), count up) and the leaf order:
-// the position of a symbol in (length, symbol) order is its count of smaller
-// keys, its index within its length that position minus the symbols of
-// shorter codes.
-__device__ void canonical(const uint8_t *len, uint32_t *code, uint8_t *order, uint32_t *s_cnt,
-                          uint32_t *s_first, uint32_t *s_below, uint32_t *s_key)
+// Canonical codes (RFC 1951 Sec. 3.2.2: by length, then symbol, counting
+// up) and the leaf order, a length at a time: a symbol's rank among the
+// symbols of its length is the count of those with a smaller index (ballots).
+__device__ void canonical(const uint8_t *len, uint32_t *code, uint8_t *order)
 {
-    const uint32_t v = threadIdx.x;
-    if (v < 40) s_cnt[v] = 0;
-    __syncthreads();
-    const uint32_t lv = len[v];
-    const uint32_t kv = lv ? (lv << 8) | v : 0xffffffffu;
-    s_key[v] = kv;
-    if (lv) atomicAdd(&s_cnt[lv], 1u);
-    __syncthreads();
-    if (v == 0) {
-        uint32_t c = 0, below = 0;
-        s_first[0] = 0;
-        s_below[0] = 0;
-        for (int b = 1; b < 40; b++) {
-            c = (c + (b >= 2 ? s_cnt[b - 1] : 0)) << 1;
-            s_first[b] = c;
-            s_below[b] = below;
-            below += s_cnt[b];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint32_t l[4], cd[4] = {0, 0, 0, 0}, mx = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        l[j] = len[j * 64 + lane];
+        mx = max(mx, l[j]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    uint32_t first = 0, below = 0, prev = 0;
+    for (uint32_t L = 1; L <= mx; L++) {
+        first = (first + prev) << 1;  // first code of length L (0 for L = 1)
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint64_t b = __ballot(l[j] == L);
+            if (l[j] == L) {
+                const uint32_t r = acc + (uint32_t)__popcll(b & lt);
+                cd[j] = first + r;
+                order[below + r] = (uint8_t)(j * 64 + lane);
+            }
+            acc += (uint32_t)__popcll(b);
         }
+        below += acc;
+        prev = acc;
     }
-    __syncthreads();
-    if (lv) {
-        const uint32_t pos = count_below(s_key, kv);
-        code[v] = s_first[lv] + (pos - s_below[lv]);
-        order[pos] = (uint8_t)v;
-    } else {
-        code[v] = 0;
-    }
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; j++) code[j * 64 + lane] = cd[j];
 }
 
 struct CodeShared {
-    uint16_t sh_hist[kMaxPlanes][256];
     uint32_t f[256];
     uint8_t len[256];
-    uint32_t code[256];
-    uint8_t order[256];
     uint32_t segbits[32];
-    uint32_t cnt[40], first[40], below[40];
-    uint32_t scal[16];
-    uint64_t red[4];
     uint32_t plane[32];             // kept planes, segment order
     uint32_t zir[32];               // per segment: zeros inside runs
     uint16_t dig[32][kNumWz];       // per segment: run digits per counter width (< 8 * 3073)
-    HuffScratch hs;
+    HuffW hs;
 };
 
 // Bits of every segment under the current code: symbol counts times code
 // lengths, C_zr counted once per run digit plus once per literal C_zr.
-__device__ void seg_lengths(CodeShared &C, uint32_t nseg, uint32_t czr, uint32_t wz)
+__device__ void seg_lengths(CodeShared &C, const uint16_t *seghist, uint32_t slot, uint32_t nseg, uint32_t czr,
+                            uint32_t wz)
 {
-    const uint32_t v = threadIdx.x;
-    if (v < 32) C.segbits[v] = 0;
-    __syncthreads();
-    const uint32_t cost = C.len[v] + (v == czr ? wz : 0u);
-    for (uint32_t s = 0; s < nseg; s++) {
-        uint32_t cnt = C.sh_hist[s][v];
-        if (v == 0) cnt -= C.zir[s];
-        uint32_t add = cnt * cost;
-        if (v == 0) add += C.dig[s][wz - 2] * (C.len[czr] + wz);
-        for (int o = 32; o >= 1; o >>= 1) add += __shfl_xor(add, o, 64);
-        if ((v & 63) == 0 && add) atomicAdd(&C.segbits[s], add);
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t cost[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t s = (uint32_t)j * 64 + lane;
+        cost[j] = C.len[s] + (s == czr ? wz : 0u);
     }
-    __syncthreads();
+    const uint32_t zcost = C.len[czr] + wz;
+    for (uint32_t sg = 0; sg < nseg; sg++) {
+        const uint16_t *h = seghist + (uint64_t)(slot + C.plane[sg]) * 256;
+        uint32_t add = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t s = (uint32_t)j * 64 + lane;
+            uint32_t cnt = h[s];
+            if (s == 0) cnt -= C.zir[sg];
+            add += cnt * cost[j];
+        }
+        if (lane == 0) add += C.dig[sg][wz - 2] * zcost;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) add += __shfl_xor(add, o, 64);
+        if (lane == 0) C.segbits[sg] = add;
+    }
+    wave_sync();
 }
 
-// five workgroups per CU (at most 96 VGPRs and 31.25 KB of LDS, as LDS is
-// allocated in 1280-byte units): a batch of two 4096x4096 RGB images has
-// 2052 blocks, which then take two rounds of the 256 CUs instead of three
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_enc_code(PlanHdr H,
-                                                                                         uint8_t *__restrict__ ws)
+// One wave per block (12 per CU: 13.2 KB of LDS each), looping over the
+// blocks of the grid.
+__global__ void __launch_bounds__(64) k_enc_code(PlanHdr H, uint8_t *__restrict__ ws)
 {
     __shared__ CodeShared C;
     __shared__ PMScratch Q;
+    const uint32_t lane = threadIdx.x;
     for (uint32_t blk = blockIdx.x; blk < H.total_blocks; blk += gridDim.x) {
-    __syncthreads();
-    const uint32_t v = threadIdx.x;
+    wave_sync();
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     BlkPlan &P = ((BlkPlan *)(ws + H.ws_blkplan))[blk];
     const BlkStat &S = ((const BlkStat *)(ws + H.ws_blkstat))[blk];
@@ -718,45 +748,50 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
     const uint32_t nseg = P.nseg, d = P.d, p = P.p, n = P.n;
     const uint32_t tb = bitlen32(p * n) - 1 + 5;  // t = floor(log2(p w h / 8)) + 5
     if (nseg == 0) {
-        if (v == 0) {
+        if (lane == 0) {
             P.czr = 0; P.wz = 0; P.m = 0; P.tbits = tb; P.limited = 0;
             P.hdr_bits = 5 + p * d;
             P.bytes = (P.hdr_bits + 7) / 8;
         }
         continue;
     }
-    // segment statistics to LDS (independent loads, all threads)
+    // segment statistics to LDS
     const uint32_t slot = B.slot;
-    if (v < nseg) C.plane[v] = P.seg_plane[v];
-    __syncthreads();
-    for (uint32_t i = v; i < nseg * (kNumWz + 1); i += blockDim.x) {
+    if (lane < nseg) C.plane[lane] = P.seg_plane[lane];
+    wave_sync();
+    for (uint32_t i = lane; i < nseg * (kNumWz + 1); i += 64) {
         const uint32_t sg = i / (kNumWz + 1), k = i % (kNumWz + 1);
         const SegStat &st = segstat[slot + C.plane[sg]];
         if (k == kNumWz) C.zir[sg] = st.zir;
         else C.dig[sg][k] = (uint16_t)st.dig[k];
     }
-    // per-segment histograms into LDS, block histogram
-    uint32_t h = 0;
-#pragma unroll 4
+    // block histogram
+    uint32_t h[4] = {0, 0, 0, 0};
     for (uint32_t sg = 0; sg < nseg; sg++) {
-        const uint16_t x = seghist[(uint64_t)(slot + C.plane[sg]) * 256 + v];
-        C.sh_hist[sg][v] = x;
-        h += x;
+        const uint16_t *hs = seghist + (uint64_t)(slot + C.plane[sg]) * 256;
+#pragma unroll
+        for (int j = 0; j < 4; j++) h[j] += hs[j * 64 + lane];
     }
-    __syncthreads();
+    wave_sync();
     uint32_t Z = 0;
     for (uint32_t sg = 0; sg < nseg; sg++) Z += C.zir[sg];
     // C_zr: least frequent symbol, smallest value on ties (Sec. 4)
-    uint64_t key = ((uint64_t)h << 8) | v;
+    uint64_t key = ~0ull;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint64_t kj = ((uint64_t)h[j] << 8) | (uint32_t)(j * 64 + lane);
+        key = kj < key ? kj : key;
+    }
     for (int o = 32; o >= 1; o >>= 1) { uint64_t y = __shfl_xor(key, o, 64); key = y < key ? y : key; }
-    if ((v & 63) == 0) C.red[v >> 6] = key;
-    __syncthreads();
-    uint64_t kmin = C.red[0];
-    for (int i = 1; i < 4; i++) kmin = C.red[i] < kmin ? C.red[i] : kmin;
-    const uint32_t czr = (uint32_t)(kmin & 0xff);
-    uint32_t lit = h - (v == 0 ? Z : 0u);
-    C.f[v] = lit + (v == czr ? S.nruns : 0u);
-    __syncthreads();
+    const uint32_t czr = (uint32_t)(key & 0xff);
+    uint32_t lit[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t s = (uint32_t)j * 64 + lane;
+        lit[j] = h[j] - (s == 0 ? Z : 0u);
+        C.f[s] = lit[j] + (s == czr ? S.nruns : 0u);
+    }
+    wave_sync();
     // provisional code (each run one C_zr token) -> l
     huff_lengths(C.f, C.len, C.hs);
     const uint32_t l = C.len[czr];
@@ -764,48 +799,48 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
     // w - 2 prices width w, smallest width on ties
     const uint32_t beta = bitlen32(p * n - 1);
     const uint32_t wzhi = beta > 2 ? beta : 2;
-    if (v < 64) {
-        const uint32_t w = v + 2;
+    uint32_t wz, D = 0;
+    {
+        const uint32_t w = lane + 2;
         uint64_t key2 = ~0ull;
         if (w <= wzhi) {
             uint64_t cost = 0;
             for (uint32_t i = 1; i < 16; i++) cost += (uint64_t)S.F[i] * ((i + w - 1) / w) * (w + l);
-            key2 = (cost << 6) | v;  // cost < 2^56: counts < 2^24, factors < 2^6 each
+            key2 = (cost << 6) | lane;  // cost < 2^56: counts < 2^24, factors < 2^6 each
         }
         for (int o = 32; o >= 1; o >>= 1) { uint64_t y = __shfl_xor(key2, o, 64); key2 = y < key2 ? y : key2; }
-        if (v == 0) {
-            const uint32_t bw = (uint32_t)(key2 & 63u) + 2;
-            uint32_t D = 0;
-            for (uint32_t sg = 0; sg < nseg; sg++) D += C.dig[sg][bw - 2];
-            C.scal[1] = bw;
-            C.scal[2] = D;
-        }
+        wz = (uint32_t)(key2 & 63u) + 2;
+        for (uint32_t sg = 0; sg < nseg; sg++) D += C.dig[sg][wz - 2];
     }
-    __syncthreads();
-    const uint32_t wz = C.scal[1];
-    C.f[v] = lit + (v == czr ? C.scal[2] : 0u);
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t s = (uint32_t)j * 64 + lane;
+        C.f[s] = lit[j] + (s == czr ? D : 0u);
+    }
+    wave_sync();
     huff_lengths(C.f, C.len, C.hs);
-    seg_lengths(C, nseg, czr, wz);
+    seg_lengths(C, seghist, slot, nseg, czr, wz);
     // seek-table overflow -> length-limited fallback
     uint32_t limited = 0;
-    {
-        uint32_t ov = (v < nseg) && (C.segbits[v] >= (1u << tb));
-        if (__syncthreads_or(ov)) {
-            package_merge_lengths(C.f, 14, C.len, C.hs, Q);
-            seg_lengths(C, nseg, czr, wz);
-            limited = 1;
-        }
+    if (__any(lane < nseg && C.segbits[lane] >= (1u << tb))) {
+        package_merge_lengths(C.f, 14, C.len, C.hs, Q);
+        seg_lengths(C, seghist, slot, nseg, czr, wz);
+        limited = 1;
     }
-    canonical(C.len, C.code, C.order, C.cnt, C.first, C.below, C.hs.key);
-    uint32_t m = __syncthreads_count(C.f[v] > 0);
-    if (m == 1 && C.f[v] > 0) C.order[0] = (uint8_t)v;  // single leaf: code length 0
-    __syncthreads();
-    P.code[v] = C.code[v];
-    P.len[v] = C.len[v];
-    P.order[v] = C.order[v];
-    if (v < nseg) P.seg_bits[v] = C.segbits[v];
-    if (v == 0) {
+    canonical(C.len, P.code, P.order);
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t s = (uint32_t)j * 64 + lane;
+        const bool has = C.f[s] > 0;
+        m += (uint32_t)__popcll(__ballot(has));
+        P.len[s] = C.len[s];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++)  // single leaf: code length 0
+        if (m == 1 && C.f[j * 64 + lane] > 0) P.order[0] = (uint8_t)(j * 64 + lane);
+    if (lane < nseg) P.seg_bits[lane] = C.segbits[lane];
+    if (lane == 0) {
         uint32_t over = 0, sum = 0;
         for (uint32_t sg = 0; sg < nseg; sg++) { sum += C.segbits[sg]; over |= C.segbits[sg] >= (1u << tb); }
         P.czr = czr; P.wz = wz; P.m = m; P.tbits = tb; P.limited = limited;
@@ -1275,7 +1310,7 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
                 hipLaunchKernelGGL(k_enc_symbols<256>, dim3(g), dim3(256), 0, stream, H, d_plan, d_ws, H.n_big, H.n_small);
             }
         } else if (st == ENC_CODE) {
-            if (H.total_blocks) hipLaunchKernelGGL(k_enc_code, dim3(H.blk_grid), dim3(256), 0, stream, H, d_ws);
+            if (H.total_blocks) hipLaunchKernelGGL(k_enc_code, dim3(H.blk_grid), dim3(64), 0, stream, H, d_ws);
         } else if (st == ENC_BOFF) {
             hipLaunchKernelGGL(k_enc_block_offsets, dim3(H.n_tiles), dim3(256), 0, stream, H, d_plan, d_ws);
         } else if (st == ENC_TOFF) {
@@ -1295,22 +1330,22 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
 }
 
 // Debug: Huffman lengths of one frequency table, as the block coder builds them.
-__global__ void __launch_bounds__(256) k_debug_huffman(const uint32_t *freq, int limit, uint8_t *out)
+__global__ void __launch_bounds__(64) k_debug_huffman(const uint32_t *freq, int limit, uint8_t *out)
 {
     __shared__ uint32_t f[256];
     __shared__ uint8_t len[256];
-    __shared__ HuffScratch hs;
+    __shared__ HuffW hs;
     __shared__ PMScratch q;
-    f[threadIdx.x] = freq[threadIdx.x];
-    __syncthreads();
+    for (int j = 0; j < 4; j++) f[j * 64 + threadIdx.x] = freq[j * 64 + threadIdx.x];
+    wave_sync();
     if (limit <= 0) huff_lengths(f, len, hs);
     else package_merge_lengths(f, limit, len, hs, q);
-    out[threadIdx.x] = len[threadIdx.x];
+    for (int j = 0; j < 4; j++) out[j * 64 + threadIdx.x] = len[j * 64 + threadIdx.x];
 }
 
 hipError_t launch_debug_huffman(const uint32_t *d_freq, int limit, uint8_t *d_len, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_debug_huffman, dim3(1), dim3(256), 0, stream, d_freq, limit, d_len);
+    hipLaunchKernelGGL(k_debug_huffman, dim3(1), dim3(64), 0, stream, d_freq, limit, d_len);
     return hipGetLastError();
 }
 
