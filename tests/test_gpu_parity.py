@@ -319,3 +319,30 @@ def _check_everything(case):
     prog = isx.decode_streams([blob], drop=r)[0]
     assert np.array_equal(prog, oracle.decode_tile(blob, 0, drop=r))
 
+
+
+@pytest.mark.parametrize("case", [
+    # encode side: level-1 bands are held as int16 up to 13 significant bits
+    (96, 80, 3, 13, 2, 1, "checker"), (96, 80, 1, 13, 3, 1, "max"), (96, 80, 3, 14, 2, 1, "checker"),
+    (70, 66, 1, 14, 3, 1, "max"),
+    # decode side: 8-bit, 5 levels (plane bound 13): int16 up to step 8, int32 from step 9
+    (160, 144, 3, 8, 5, 7, "checker"), (160, 144, 3, 8, 5, 8, "checker"), (160, 144, 3, 8, 5, 9, "checker"),
+    (150, 130, 3, 8, 5, 8, "uniform"),
+], ids=lambda c: "x".join(map(str, c)))
+def test_int16_band_bounds_match_oracle(case):
+    """Both sides of the int16 level-1 band rule: images with the largest
+    level-1 coefficients the bit depth allows (checkerboards, alternating
+    extremes) and steps on both sides of the decoder's dequantisation bound,
+    encoded and decoded at every level against the oracle."""
+    w, h, c, bits, lv, q, kind = case
+    img = _img(case, 3)
+    print("int16 bound", case, flush=True)
+    got = isx.encode_image(img, lv, bits=bits, ct=_ct(c), qstep=q)
+    ref = oracle.encode_tile(img, lv, bits=bits, ct=_ct(c), qstep=q)
+    assert got == ref
+    levels = list(range(lv + 1))
+    dec = isx.decode_streams([ref] * len(levels), levels=levels)
+    for z, g in zip(levels, dec):
+        assert np.array_equal(g, oracle.decode_tile(ref, z)), z
+    if q == 1:
+        assert np.array_equal(dec[0], img.reshape(dec[0].shape))
