@@ -1040,6 +1040,88 @@ __device__ inline void transpose16(uint32_t (&r)[16])
     }
 }
 
+// Reassembly of NC (1 or 2) consecutive cells ci .. ci + NC - 1 of type t
+// (4x4 coefficients each): the 16 low magnitude planes and the sign plane
+// (d - 1) in flight together (a plane the type skips, or above the block's
+// depth, is not read and counts as 0: the condition is the same for a wave's
+// cells of one type), then one 16x16 bit-matrix transpose per cell turns
+// plane words into magnitudes; dequantised, signed and stored.
+template <int NC>
+__device__ inline void reasm_cells(const BlockDesc &B, uint8_t *ws, const uint8_t *sym,
+                                   const uint32_t (*s_off)[3], uint32_t t, uint32_t ci, uint32_t d,
+                                   uint32_t wq, uint32_t step, bool c16)
+{
+    auto ld = [&](uint32_t o) -> uint32_t {
+        return NC == 2 ? *(const uint32_t *)(sym + o + 2 * ci) : (uint32_t)*(const uint16_t *)(sym + o + 2 * ci);
+    };
+    uint32_t mag[NC][16], sgn[NC];
+#pragma unroll
+    for (int b = 0; b < 16; b++) {
+        const uint32_t o = (uint32_t)b + 1 < d ? s_off[b][t] : ~0u;
+        uint32_t v = 0;
+        if (o != ~0u) v = ld(o);
+#pragma unroll
+        for (int k = 0; k < NC; k++) mag[k][b] = (v >> (16 * k)) & 0xffffu;
+    }
+    {
+        const uint32_t o = d ? s_off[d - 1][t] : ~0u;
+        const uint32_t v = ld(o != ~0u ? o : 0u);
+#pragma unroll
+        for (int k = 0; k < NC; k++) sgn[k] = o != ~0u ? (v >> (16 * k)) & 0xffffu : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < NC; k++) transpose16(mag[k]);
+    // magnitude planes 16 .. d-2 (samples deeper than 16 bits)
+    for (uint32_t b = 16; b + 1 < d; b++) {
+        const uint32_t o = s_off[b][t];
+        if (o == ~0u) continue;
+        const uint32_t v = ld(o);
+#pragma unroll
+        for (int k = 0; k < NC; k++)
+#pragma unroll
+            for (int i = 0; i < 16; i++) mag[k][i] |= ((v >> (16 * k + i)) & 1u) << b;
+    }
+    if (B.drop) {  // midpoint of the dropped magnitude bits
+        const uint32_t half = 1u << (B.drop - 1);
+#pragma unroll
+        for (int k = 0; k < NC; k++)
+#pragma unroll
+            for (int i = 0; i < 16; i++) mag[k][i] += mag[k][i] ? half : 0u;
+    }
+    const uint32_t tw = B.tw[t], th = B.th[t];
+    const uint64_t toff = B.off[t];
+    const uint32_t tpitch = B.pitch[t];
+#pragma unroll
+    for (int k = 0; k < NC; k++) {
+        const uint32_t band = (ci + k) / wq, cg = (ci + k) % wq;
+        const uint32_t r0 = 4 * band, c0 = 4 * cg;
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            const uint32_t row = r0 + rr;
+            if (row >= th || c0 >= tw) continue;
+            int32_t o[4];
+#pragma unroll
+            for (int cc = 0; cc < 4; cc++) {
+                const int i = rr * 4 + cc;
+                int32_t q = (int32_t)mag[k][i];
+                if (step > 1 && q) q = q * (int32_t)step + (int32_t)(step / 2);
+                o[cc] = ((sgn[k] >> i) & 1u) ? -q : q;
+            }
+            if (c16) {  // coefficients held as int16 (their bound fits)
+                int16_t *dst = (int16_t *)ws + toff + (uint64_t)row * tpitch + c0;
+                if (c0 + 3 < tw) *(short4 *)dst = make_short4((short)o[0], (short)o[1], (short)o[2], (short)o[3]);
+                else
+                    for (int cc = 0; cc < 4 && c0 + cc < tw; cc++) dst[cc] = (int16_t)o[cc];
+                continue;
+            }
+            int32_t *dst = (int32_t *)ws + toff + (uint64_t)row * tpitch + c0;
+            if (c0 + 3 < tw) *(int4 *)dst = make_int4(o[0], o[1], o[2], o[3]);
+            else
+                for (int cc = 0; cc < 4 && c0 + cc < tw; cc++) dst[cc] = o[cc];
+        }
+    }
+}
+
 // Blocks of the plan's list [list0, list0 + nlist): NT = 1024 threads for the
 // blocks of more than 768 cells, 256 for the others.
 template <int NT>
@@ -1064,7 +1146,6 @@ __global__ void __launch_bounds__(NT) k_dec_reasm(PlanHdr H, const uint8_t *__re
     const uint32_t d = P.d, nseg = P.nseg;
     const uint32_t step = (B.level == 0) ? 1u : T.qstep;
     const bool c16 = B.c16 != 0;
-    int32_t *wsi = (int32_t *)ws;
     const uint8_t *sym = ws + B.sym_off;
     const uint32_t pstr = plane_stride(p * n);
     __syncthreads();  // the previous block's table has been read
@@ -1078,70 +1159,16 @@ __global__ void __launch_bounds__(NT) k_dec_reasm(PlanHdr H, const uint8_t *__re
             s_off[b][u] = ((pm >> u) & 1u) ? b * pstr + (uint32_t)__popc(pm & ((1u << u) - 1u)) * n : ~0u;
     }
     __syncthreads();
-    for (uint32_t cell = tid; cell < p * cpt; cell += blockDim.x) {
-        const uint32_t t = cell / cpt, ci = cell % cpt;
-        // the 16 low magnitude planes and the sign plane (d - 1) in flight
-        // together (a plane the type skips, or above the block's depth, is
-        // not read and counts as 0: the condition is the same for a wave's
-        // cells of one type), then one 16x16 bit-matrix transpose turns plane
-        // words into the cell's magnitudes
-        uint32_t mag[16];
-#pragma unroll
-        for (int b = 0; b < 16; b++) {
-            const uint32_t o = (uint32_t)b + 1 < d ? s_off[b][t] : ~0u;
-            uint32_t v = 0;
-            if (o != ~0u) v = *(const uint16_t *)(sym + o + 2 * ci);
-            mag[b] = v;
+    if ((cpt & 1u) == 0 && (n & 3u) == 0) {
+        // two horizontally consecutive cells per thread: their symbols are
+        // adjacent in every plane, one 32-bit load per plane
+        for (uint32_t pr = tid; pr < p * cpt / 2; pr += blockDim.x) {
+            const uint32_t cell = 2 * pr, t = cell / cpt;
+            reasm_cells<2>(B, ws, sym, s_off, t, cell % cpt, d, wq, step, c16);
         }
-        uint32_t sgn;
-        {
-            const uint32_t o = d ? s_off[d - 1][t] : ~0u;
-            const uint32_t v = *(const uint16_t *)(sym + (o != ~0u ? o : 0u) + 2 * ci);
-            sgn = o != ~0u ? v : 0u;
-        }
-        transpose16(mag);
-        // magnitude planes 16 .. d-2 (samples deeper than 16 bits)
-        for (uint32_t b = 16; b + 1 < d; b++) {
-            const uint32_t o = s_off[b][t];
-            if (o == ~0u) continue;
-            const uint32_t v = *(const uint16_t *)(sym + o + 2 * ci);
-#pragma unroll
-            for (int i = 0; i < 16; i++) mag[i] |= ((v >> i) & 1u) << b;
-        }
-        if (B.drop) {  // midpoint of the dropped magnitude bits
-            const uint32_t half = 1u << (B.drop - 1);
-#pragma unroll
-            for (int i = 0; i < 16; i++) mag[i] += mag[i] ? half : 0u;
-        }
-        const uint32_t band = ci / wq, cg = ci % wq;
-        const uint32_t r0 = 4 * band, c0 = 4 * cg;
-        const uint32_t tw = B.tw[t], th = B.th[t];
-        const uint64_t toff = B.off[t];
-        const uint32_t tpitch = B.pitch[t];
-#pragma unroll
-        for (int rr = 0; rr < 4; rr++) {
-            const uint32_t row = r0 + rr;
-            if (row >= th || c0 >= tw) continue;
-            int32_t o[4];
-#pragma unroll
-            for (int cc = 0; cc < 4; cc++) {
-                const int i = rr * 4 + cc;
-                int32_t q = (int32_t)mag[i];
-                if (step > 1 && q) q = q * (int32_t)step + (int32_t)(step / 2);
-                o[cc] = ((sgn >> i) & 1u) ? -q : q;
-            }
-            if (c16) {  // coefficients held as int16 (their bound fits)
-                int16_t *dst = (int16_t *)ws + toff + (uint64_t)row * tpitch + c0;
-                if (c0 + 3 < tw) *(short4 *)dst = make_short4((short)o[0], (short)o[1], (short)o[2], (short)o[3]);
-                else
-                    for (int cc = 0; cc < 4 && c0 + cc < tw; cc++) dst[cc] = (int16_t)o[cc];
-                continue;
-            }
-            int32_t *dst = wsi + toff + (uint64_t)row * tpitch + c0;
-            if (c0 + 3 < tw) *(int4 *)dst = make_int4(o[0], o[1], o[2], o[3]);
-            else
-                for (int cc = 0; cc < 4 && c0 + cc < tw; cc++) dst[cc] = o[cc];
-        }
+    } else {
+        for (uint32_t cell = tid; cell < p * cpt; cell += blockDim.x)
+            reasm_cells<1>(B, ws, sym, s_off, cell / cpt, cell % cpt, d, wq, step, c16);
     }
     }
 }
