@@ -1091,6 +1091,28 @@ __device__ inline void reasm_cells(const BlockDesc &B, uint8_t *ws, const uint8_
     const uint32_t tw = B.tw[t], th = B.th[t];
     const uint64_t toff = B.off[t];
     const uint32_t tpitch = B.pitch[t];
+    auto coef = [&](int k, int i) -> int32_t {
+        int32_t q = (int32_t)mag[k][i];
+        if (step > 1 && q) q = q * (int32_t)step + (int32_t)(step / 2);
+        return ((sgn[k] >> i) & 1u) ? -q : q;
+    };
+    if (NC == 2 && c16 && ((toff | tpitch) & 7u) == 0 && (ci % wq) + 1 < wq && 4 * ((ci % wq) + 1) + 3 < tw) {
+        // both cells in one band row, whole: each row's 8 coefficients in
+        // one 16-byte store (8 int16 elements, aligned)
+        const uint32_t r0 = 4 * (ci / wq), c0 = 4 * (ci % wq);
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            const uint32_t row = r0 + rr;
+            if (row >= th) continue;
+            int16_t *dst = (int16_t *)ws + toff + (uint64_t)row * tpitch + c0;
+            const uint32_t w0 = (uint16_t)coef(0, rr * 4) | ((uint32_t)(uint16_t)coef(0, rr * 4 + 1) << 16);
+            const uint32_t w1 = (uint16_t)coef(0, rr * 4 + 2) | ((uint32_t)(uint16_t)coef(0, rr * 4 + 3) << 16);
+            const uint32_t w2 = (uint16_t)coef(NC - 1, rr * 4) | ((uint32_t)(uint16_t)coef(NC - 1, rr * 4 + 1) << 16);
+            const uint32_t w3 = (uint16_t)coef(NC - 1, rr * 4 + 2) | ((uint32_t)(uint16_t)coef(NC - 1, rr * 4 + 3) << 16);
+            *(uint4 *)dst = make_uint4(w0, w1, w2, w3);
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < NC; k++) {
         const uint32_t band = (ci + k) / wq, cg = (ci + k) % wq;
@@ -1101,12 +1123,7 @@ __device__ inline void reasm_cells(const BlockDesc &B, uint8_t *ws, const uint8_
             if (row >= th || c0 >= tw) continue;
             int32_t o[4];
 #pragma unroll
-            for (int cc = 0; cc < 4; cc++) {
-                const int i = rr * 4 + cc;
-                int32_t q = (int32_t)mag[k][i];
-                if (step > 1 && q) q = q * (int32_t)step + (int32_t)(step / 2);
-                o[cc] = ((sgn[k] >> i) & 1u) ? -q : q;
-            }
+            for (int cc = 0; cc < 4; cc++) o[cc] = coef(k, rr * 4 + cc);
             if (c16) {  // coefficients held as int16 (their bound fits)
                 int16_t *dst = (int16_t *)ws + toff + (uint64_t)row * tpitch + c0;
                 if (c0 + 3 < tw) *(short4 *)dst = make_short4((short)o[0], (short)o[1], (short)o[2], (short)o[3]);
