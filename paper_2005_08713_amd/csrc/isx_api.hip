@@ -339,6 +339,13 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     if (mode == MODE_DECODE && total_blocks >= (1ull << 27)) return ISX_E_UNSUPPORTED;  // segment item = block << 5 | segment
     H.total_blocks = (uint32_t)total_blocks;
     H.total_slots = (uint32_t)total_slots;
+    // A decode with few segments (a served view, one small tile) spreads
+    // each over two or four waves, so that the lone segments finish sooner;
+    // a large one keeps one wave per segment (more segments per CU, less
+    // work per token).  total_slots bounds the segment count.
+    H.seg_nw = 1;
+    if (mode == MODE_DECODE && total_slots <= 4ull * H.num_cus) H.seg_nw = 4;
+    else if (mode == MODE_DECODE && total_slots <= 8ull * H.num_cus) H.seg_nw = 2;
     H.blk_grid = H.total_blocks;
     if (H.blocks_per_cu) {
         uint64_t g = (uint64_t)H.num_cus * H.blocks_per_cu;

@@ -101,7 +101,7 @@ struct PlanHdr {
     uint32_t blk_grid;  // workgroups of the per-block kernels (== total_blocks unless persistent)
     uint32_t num_cus, blocks_per_cu;
     uint32_t seg_waves_per_cu;  // segment decoder: persistent waves per CU
-    uint32_t pad_swpc;
+    uint32_t seg_nw;            // segment decoder: waves per segment (1, or 2 / 4 for small plans)
     uint64_t list_off;      // plan offset of the block list (u32): large blocks, then small ones
     uint32_t n_big, n_small;  // blocks with > 768 4x4 cells / with <= 768
 };

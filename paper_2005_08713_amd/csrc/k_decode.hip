@@ -532,7 +532,9 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
             sum += __shfl_xor(sum, o, 64);
         }
         const bool small_block = p * n <= 1536u && mx < kSmallSegBits;
-        if (nkeep >= 2 && small_block && sum + 64 <= (kSegWords - 2) * 32u) {
+        // (a plan decoded with several waves per segment keeps one item per
+        // segment: there the segments of a block run side by side)
+        if (H.seg_nw == 1 && nkeep >= 2 && small_block && sum + 64 <= (kSegWords - 2) * 32u) {
             if (lane == 0) {
                 const uint32_t sb1 = atomicAdd(&ctr[kQSmall], 1u);
                 uint32_t *list = (uint32_t *)(ws + H.ws_items + kItemsHdr);
@@ -747,44 +749,67 @@ __device__ inline uint32_t run_tokens(Cur &C, const DecTab &T, uint32_t r, uint3
 // Phase-1 bits before the first and the second resynchronisation point.
 constexpr uint32_t kSyncWin = 128, kSyncWin2 = 384;
 
-// Decode of one segment by one wave: the segment's N bits are split into 64
-// chunks.  Phase 1: every lane decodes its chunk from the chunk start
-// (speculatively, for lanes > 0), keeping the run maps of the tokens before
-// the first token start sw1 at or after kSyncWin bits, from sw1 to the first
-// token start sw2 at or after kSyncWin2 bits, and from sw2 on, and its exit
-// (first token start at or after the chunk end).  Phase 2: a lane whose
-// start differs from its left neighbour's exit decodes again from that exit;
-// on reaching sw1, or else sw2, the rest of phase 1 stands (Huffman codes
-// resynchronise), else it decodes the whole chunk; repeated until no lane
-// changes.  A wave scan of the run maps gives each lane its output position
-// and pending run; phase 3 decodes again and writes the non-zero symbols
-// into a zeroed copy of the plane in LDS (runs write nothing), which the wave
-// then stores to the plane with whole-line 16-byte stores.
+// Decode of one segment by a workgroup of NW waves (G = 64 NW lanes): the
+// segment's N bits are split into G chunks.  Phase 1: every lane decodes its
+// chunk from the chunk start (speculatively, for lanes > 0), keeping the run
+// maps of the tokens before the first token start sw1 at or after kSyncWin
+// bits, from sw1 to the first token start sw2 at or after kSyncWin2 bits,
+// and from sw2 on, and its exit (first token start at or after the chunk
+// end).  Phase 2: a lane whose start differs from its left neighbour's exit
+// decodes again from that exit; on reaching sw1, or else sw2, the rest of
+// phase 1 stands (Huffman codes resynchronise), else it decodes the whole
+// chunk; repeated until no lane changes.  A scan of the run maps over the
+// lanes gives each lane its output position and pending run; phase 3 decodes
+// again and writes the non-zero symbols into a zeroed copy of the plane in
+// LDS (runs write nothing), which the workgroup then stores to the plane
+// with whole-line 16-byte stores.  One wave (NW = 1) is the throughput form;
+// more waves per segment shorten a lone segment's decode (the latency form):
+// the lanes' chunks halve, and the waves exchange their edge values through
+// LDS at barriers.
+
+// workgroup-wide hand-over between lanes: a wave's own LDS order, or a barrier
+template <int NW>
+__device__ inline void wg_sync()
+{
+    if (NW == 1) wave_sync();
+    else __syncthreads();
+}
+
 // Stores the M symbols staged in LDS to the plane (both 16-byte aligned, the
-// plane's stride padded to 16 bytes) with the whole wave.
+// plane's stride padded to 16 bytes) with the whole workgroup.
+template <int NW>
 __device__ inline void store_plane(const uint8_t *pl, uint8_t *out, uint32_t M)
 {
     const uint4 *src = (const uint4 *)pl;
     uint4 *dst = (uint4 *)out;
     const uint32_t M16 = (M + 15) / 16;
-    for (uint32_t i = threadIdx.x & 63; i < M16; i += 64) dst[i] = src[i];
+    for (uint32_t i = threadIdx.x; i < M16; i += 64 * NW) dst[i] = src[i];
 }
+template <int NW>
 __device__ inline void zero_lds_plane(uint8_t *pl, uint32_t M)
 {
     uint4 *d = (uint4 *)pl;
     const uint32_t M16 = (M + 15) / 16;
-    for (uint32_t i = threadIdx.x & 63; i < M16; i += 64) d[i] = make_uint4(0, 0, 0, 0);
+    for (uint32_t i = threadIdx.x; i < M16; i += 64 * NW) d[i] = make_uint4(0, 0, 0, 0);
 }
 
-template <class Cur>
-__device__ int32_t decode_segment(Cur C, const DecTab &T, uint32_t N, uint32_t M, uint8_t *pl, uint8_t *out)
+// values the waves of a workgroup exchange
+struct WaveX {
+    uint32_t exit[4], any[4];
+    uint32_t tot[4][5];  // each wave's run-map total (lit, P0, V0, mid, V1)
+};
+
+template <int NW, class Cur>
+__device__ int32_t decode_segment(Cur C, const DecTab &T, uint32_t N, uint32_t M, uint8_t *pl, uint8_t *out,
+                                  WaveX &X)
 {
-    const uint32_t lane = threadIdx.x & 63;
+    constexpr uint32_t G = 64 * NW;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = threadIdx.x;
     const uint32_t wz = T.wz, czr = T.czr;
-    uint32_t chunk = (N + 63) / 64;
+    uint32_t chunk = (N + G - 1) / G;
     chunk = (chunk + 31) & ~31u;
     if (chunk < 32) chunk = 32;
-    const uint32_t cs = lane * chunk;
+    const uint32_t cs = g * chunk;
     const bool active = cs < N;
     const uint32_t ce = active ? (cs + chunk < N ? cs + chunk : N) : cs;
     // phase 1
@@ -799,11 +824,25 @@ __device__ int32_t decode_segment(Cur C, const DecTab &T, uint32_t N, uint32_t M
     RunXf f = xf_combine(fpre, G12);
     uint32_t start = cs, exitc = exit1;
     // phase 2
-    for (int it = 0; it < 64; it++) {
-        const uint32_t left = __shfl_up(exitc, 1, 64);
-        const uint32_t want = (lane == 0) ? 0u : left;
+    for (uint32_t it = 0; it < G; it++) {
+        uint32_t left = __shfl_up(exitc, 1, 64);
+        if (NW > 1) {
+            if (lane == 63) X.exit[wave] = exitc;
+            __syncthreads();
+            if (lane == 0 && wave > 0) left = X.exit[wave - 1];
+        }
+        const uint32_t want = (g == 0) ? 0u : left;
         const bool chg = active && want != start;
-        if (!__any(chg)) break;
+        bool anyc = __any(chg);
+        if (NW > 1) {
+            if (lane == 0) X.any[wave] = anyc ? 1u : 0u;
+            __syncthreads();
+            anyc = false;
+#pragma unroll
+            for (int w = 0; w < NW; w++) anyc |= X.any[w] != 0;
+            __syncthreads();  // every wave has read X before it is written again
+        }
+        if (!anyc) break;
         if (chg) {
             start = want;
             C.seek(want);
@@ -826,7 +865,7 @@ __device__ int32_t decode_segment(Cur C, const DecTab &T, uint32_t N, uint32_t M
         }
     }
     if (!active) f = xf_id();
-    // exclusive scan of the run maps
+    // exclusive scan of the run maps: within each wave, then across the waves
     RunXf x = f;
     for (int o = 1; o < 64; o <<= 1) {
         RunXf y;
@@ -834,18 +873,32 @@ __device__ int32_t decode_segment(Cur C, const DecTab &T, uint32_t N, uint32_t M
         y.mid = __shfl_up(x.mid, o, 64); y.V1 = __shfl_up(x.V1, o, 64);
         if ((int)lane >= o) x = xf_combine(y, x);
     }
+    RunXf wpre = xf_id();  // the waves before this one
+    if (NW > 1) {
+        if (lane == 63) {
+            X.tot[wave][0] = x.lit; X.tot[wave][1] = x.P0; X.tot[wave][2] = x.V0;
+            X.tot[wave][3] = x.mid; X.tot[wave][4] = x.V1;
+        }
+        __syncthreads();
+        for (uint32_t w = 0; w < wave; w++) {
+            RunXf t;
+            t.lit = X.tot[w][0]; t.P0 = X.tot[w][1]; t.V0 = X.tot[w][2]; t.mid = X.tot[w][3]; t.V1 = X.tot[w][4];
+            wpre = xf_combine(wpre, t);
+        }
+        x = xf_combine(wpre, x);
+    }
     RunXf ex;
     ex.lit = __shfl_up(x.lit, 1, 64); ex.P0 = __shfl_up(x.P0, 1, 64); ex.V0 = __shfl_up(x.V0, 1, 64);
     ex.mid = __shfl_up(x.mid, 1, 64); ex.V1 = __shfl_up(x.V1, 1, 64);
-    if (lane == 0) ex = xf_id();
+    if (lane == 0) ex = wpre;
     uint32_t op, run;
     if (ex.lit) { op = sadd(ex.V0, ex.mid); run = ex.V1; }
     else { op = 0; run = ex.V0; }
-    zero_lds_plane(pl, M);
-    wave_sync();
+    zero_lds_plane<NW>(pl, M);
+    wg_sync<NW>();
     // phase 3: write the non-zero symbols into the LDS plane
     int32_t err = 0;
-    const bool last = active && (lane == 63 || cs + chunk >= N);
+    const bool last = active && (g == G - 1 || cs + chunk >= N);
     if (active) {
         uint32_t q = start;
         bool bad = false;
@@ -870,9 +923,9 @@ __device__ int32_t decode_segment(Cur C, const DecTab &T, uint32_t N, uint32_t M
         }
         if (bad) err = D_CORRUPT;
     }
-    wave_sync();
-    store_plane(pl, out, M);
-    if (N == 0 && lane == 0 && M != 0) err = D_CORRUPT;
+    wg_sync<NW>();
+    store_plane<NW>(pl, out, M);
+    if (N == 0 && g == 0 && M != 0) err = D_CORRUPT;
     return err;
 }
 
@@ -882,23 +935,35 @@ struct SegShared {
     uint32_t bits[kSegWords + 2];
 };
 
-// Persistent waves taking (block, segment) items from the two lists (large
-// segments first); per item: the prefix table and the segment's bits to LDS,
-// then per segment the three phases, the symbols gathered in LDS and stored
-// to the plane in whole lines (14.5 KB of LDS per wave: eleven waves per CU).
-__global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
-                                                     uint8_t *__restrict__ ws,
-                                                     int32_t *__restrict__ status)
+// Persistent workgroups of NW waves taking (block, segment) items from the
+// two lists (large segments first); per item: the prefix table and the
+// segment's bits to LDS, then per segment the three phases, the symbols
+// gathered in LDS and stored to the plane in whole lines (14.5 KB of LDS per
+// workgroup: eleven one-wave workgroups per CU in the throughput form).
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
+                                                          uint8_t *__restrict__ ws,
+                                                          int32_t *__restrict__ status)
 {
+    constexpr uint32_t NT = 64 * NW;
     __shared__ SegShared S;
-    const uint32_t lane = threadIdx.x;
+    __shared__ WaveX X;
+    __shared__ uint32_t s_item;
+    __shared__ int32_t s_status;
+    const uint32_t tid = threadIdx.x;
     uint32_t *ctr = (uint32_t *)(ws + H.ws_items);
     const uint32_t nbig = __builtin_amdgcn_readfirstlane(ctr[kQBig]);
     const uint32_t ntot = nbig + __builtin_amdgcn_readfirstlane(ctr[kQSmall]);
     const uint32_t *list = (const uint32_t *)(ws + H.ws_items + kItemsHdr);
     for (;;) {
         uint32_t idx = 0;
-        if (lane == 0) idx = atomicAdd(&ctr[kQTake], 1u);
+        if (tid == 0) idx = atomicAdd(&ctr[kQTake], 1u);
+        if (NW > 1) {
+            __syncthreads();  // the previous item is done with S and s_item
+            if (tid == 0) s_item = idx;
+            __syncthreads();
+            idx = s_item;
+        }
         idx = __builtin_amdgcn_readfirstlane(idx);
         if (idx >= ntot) break;
         const uint32_t item =
@@ -906,7 +971,17 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
         const uint32_t blk = item >> 5, s = item & 31;
         const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
         const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
-        if (__builtin_amdgcn_readfirstlane(status[B.tile]) != D_OK) continue;
+        // the tile's status, as one thread read it (other workgroups may set
+        // it meanwhile, and every wave must take the same branch)
+        int32_t st;
+        if (NW > 1) {
+            if (tid == 0) s_status = status[B.tile];
+            __syncthreads();
+            st = s_status;
+        } else {
+            st = status[B.tile];
+        }
+        if (__builtin_amdgcn_readfirstlane(st) != D_OK) continue;
         // segments [s0, s1) of the block: one, or all kept ones of a block item
         const bool whole = s == kWholeBlock;
         const uint32_t s0 = whole ? 0u : s;
@@ -918,40 +993,46 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
         bool toolong = false;
         for (uint32_t k = s0; k < s1; k++) toolong |= P.seg_M[k] > kMaxSeg;
         if (toolong) {  // not reachable for 128-grid blocks
-            if (lane == 0) atomicMin(&status[B.tile], D_CORRUPT);
+            if (tid == 0) atomicMin(&status[B.tile], D_CORRUPT);
             continue;
         }
         const uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
-        wave_sync();  // the previous item is done with S
+        wg_sync<NW>();  // the previous item is done with S
         {
             // prefix table (kLutBytes16 / 16 pieces of 16 bytes): all loads
-            // of a lane first.  The leaf tables that resolve the long codes
+            // of a thread first.  The leaf tables that resolve the long codes
             // stay in global memory (read through the L1 cache).
-            static_assert(kLutBytes16 % (16 * 64) == 0, "table copy layout");
-            constexpr uint32_t NR = kLutBytes16 / (16 * 64);
+            constexpr uint32_t NQ = kLutBytes16 / 16;
+            static_assert(kLutBytes16 % 16 == 0, "table copy layout");
             const uint4 *src = (const uint4 *)tab;
             uint4 *dst = (uint4 *)S.lut;
-            uint4 a[NR];
+            if constexpr (NQ % NT == 0) {
+                constexpr uint32_t NR = NQ / NT;
+                uint4 a[NR];
 #pragma unroll
-            for (uint32_t r = 0; r < NR; r++) a[r] = src[lane + 64 * r];
+                for (uint32_t r = 0; r < NR; r++) a[r] = src[tid + NT * r];
 #pragma unroll
-            for (uint32_t r = 0; r < NR; r++) dst[lane + 64 * r] = a[r];
+                for (uint32_t r = 0; r < NR; r++) dst[tid + NT * r] = a[r];
+            } else {
+                static_assert(NT > NQ, "table copy layout");
+                if (tid < NQ) dst[tid] = src[tid];
+            }
         }
         const uint64_t lo = B.byte_off, hi = B.byte_off + B.byte_len;
         const uint64_t w0 = S0 >> 5;
         const uint32_t nw = Nall ? (uint32_t)(((S0 + Nall - 1) >> 5) + 2 - w0) : 0u;
         const bool staged = nw <= kSegWords;
         if (staged) {
-            // words w0 .. w0+nw-1 from 16-byte loads (4 per lane in flight);
-            // a chunk not wholly inside the block falls back to bytes
+            // words w0 .. w0+nw-1 from 16-byte loads (4 per thread in
+            // flight); a chunk not wholly inside the block falls back to bytes
             const bool al16 = (((uintptr_t)enc) & 15u) == 0;
             const uint64_t c0 = (w0 * 4) & ~15ull, c1 = (w0 + nw) * 4;
             const uint32_t nch = (uint32_t)((c1 - c0 + 15) / 16);
-            for (uint32_t base = 0; base < nch; base += 256) {
+            for (uint32_t base = 0; base < nch; base += 4 * NT) {
                 uint4 q[4];
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
-                    const uint32_t ci = base + lane + 64 * k;
+                    const uint32_t ci = base + tid + NT * k;
                     const uint64_t cb = c0 + 16ull * ci;
                     if (ci < nch && al16 && cb >= lo && cb + 16 <= hi) q[k] = *(const uint4 *)(enc + cb);
                     else if (ci < nch) {
@@ -963,7 +1044,7 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
                 }
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
-                    const uint32_t ci = base + lane + 64 * k;
+                    const uint32_t ci = base + tid + NT * k;
                     if (ci >= nch) continue;
                     const int64_t r0 = (int64_t)((c0 / 4) + 4ull * ci) - (int64_t)w0;  // staged index of q[k].x
                     if (r0 >= 0 && r0 + 3 < (int64_t)nw) {
@@ -979,9 +1060,9 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
                     }
                 }
             }
-            if (lane < 2) S.bits[nw + lane] = 0u;
+            if (tid < 2) S.bits[nw + tid] = 0u;
         }
-        wave_sync();
+        wg_sync<NW>();
         DecTab T;
         T.lut = S.lut;
         T.acode = (const uint32_t *)(tab + kLutBytes16);
@@ -999,21 +1080,24 @@ __global__ void __launch_bounds__(64) k_dec_segments(PlanHdr H, const uint8_t *_
                 if (N != 0) e = D_CORRUPT;
                 const uint32_t fill = T.lsym[0] * 0x01010101u;
                 uint32_t *pw = (uint32_t *)S.plane;
-                for (uint32_t i = lane; i < (M + 15) / 16 * 4; i += 64) {
+                wg_sync<NW>();  // the previous segment's plane has been stored
+                for (uint32_t i = tid; i < (M + 15) / 16 * 4; i += NT) {
                     const uint32_t b = 4 * i;
                     pw[i] = b + 4 <= M ? fill : (b < M ? fill & ((1u << (8 * (M - b))) - 1u) : 0u);
                 }
-                wave_sync();
-                store_plane(S.plane, out, M);
+                wg_sync<NW>();
+                store_plane<NW>(S.plane, out, M);
             } else if (staged) {
                 const uint32_t wk = (uint32_t)((Sk >> 5) - w0);
                 CurLds src;
                 src.w = S.bits + wk; src.off = (uint32_t)(Sk & 31); src.nw = nw - wk;
-                e = decode_segment(src, T, N, M, S.plane, out);
+                wg_sync<NW>();  // the previous segment's plane has been stored
+                e = decode_segment<NW>(src, T, N, M, S.plane, out, X);
             } else {
                 CurGlb src;
                 src.enc = enc; src.lo = lo; src.hi = hi; src.w0 = Sk >> 5; src.off = (uint32_t)(Sk & 31);
-                e = decode_segment(src, T, N, M, S.plane, out);
+                wg_sync<NW>();
+                e = decode_segment<NW>(src, T, N, M, S.plane, out, X);
             }
             err = e ? e : err;
         }
@@ -1216,8 +1300,16 @@ hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             if (H.total_blocks) {
                 // no more waves than the plan can queue segments (a block
                 // queues at most one per plane, at most its tile's plane bound)
-                const uint32_t g = std::min<uint32_t>(H.num_cus * H.seg_waves_per_cu, std::max<uint32_t>(H.total_slots, 1u));
-                hipLaunchKernelGGL(k_dec_segments, dim3(g), dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
+                const uint32_t slots = std::max<uint32_t>(H.total_slots, 1u);
+                if (H.seg_nw == 4)  // four workgroups of four waves per CU (registers)
+                    hipLaunchKernelGGL(k_dec_segments<4>, dim3(std::min<uint32_t>(H.num_cus * 4, slots)), dim3(256), 0,
+                                       stream, H, d_encoded, d_ws, d_status);
+                else if (H.seg_nw == 2)
+                    hipLaunchKernelGGL(k_dec_segments<2>, dim3(std::min<uint32_t>(H.num_cus * 8, slots)), dim3(128), 0,
+                                       stream, H, d_encoded, d_ws, d_status);
+                else
+                    hipLaunchKernelGGL(k_dec_segments<1>, dim3(std::min<uint32_t>(H.num_cus * H.seg_waves_per_cu, slots)),
+                                       dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
             }
         } else if (st == DEC_REASM) {
             if (H.n_big) {
