@@ -228,12 +228,20 @@ int32_t isx_plan_info(const void *h_plan, uint64_t *plan_bytes, uint64_t *worksp
  *                  compute unit that loops over the blocks (1..64).
  *  seg_waves_per_cu: decode only: persistent one-wave workgroups per compute
  *                  unit of the segment decoder (0 = 11, the most its LDS
- *                  allows; 1..11). */
+ *                  allows; 1..11); used with seg_wave_group 1.
+ *  seg_wave_group: decode only: waves per segment-decoder workgroup, 1, 2 or
+ *                  4 (0 = 4 for plans of at most 4 segment slots per compute
+ *                  unit, else 2).  1: each wave decodes its own segments.
+ *                  2: both waves decode a large segment together, each
+ *                  decodes small ones alone; 8 workgroups per compute unit.
+ *                  4: all four decode every segment together; 4 workgroups
+ *                  per compute unit. */
 typedef struct {
     int32_t transform_tile;
     int32_t blocks_per_cu;
     int32_t seg_waves_per_cu;
-    int32_t reserved[5];
+    int32_t seg_wave_group;
+    int32_t reserved[4];
 } isx_tuning;
 
 /* As isx_*_plan_build, with explicit launch parameters (NULL = defaults).

@@ -1,8 +1,8 @@
 """Autotuner for the batched encode/decode launches.
 
 Searches the launch parameters of a plan (isx_tuning: LDS transform-tile
-shape, persistent workgroups per CU for the per-block kernels, persistent
-waves per CU of the segment decoder) by timing
+shape, persistent workgroups per CU for the per-block kernels, the segment
+decoder's waves per workgroup and, in its one-wave form, waves per CU) by timing
 real runs of the caller's batch with HIP events, checks that every candidate
 produces byte-identical streams and identical pixels, and caches the winner
 in a JSON file keyed by the GPU architecture and a summary of the batch.
@@ -16,9 +16,10 @@ import numpy as np
 
 from . import isx
 
-# (transform tile, blocks per CU, segment-decoder waves per CU; 0 = default)
-CANDIDATES = [(32, 0, 0), (16, 0, 0), (32, 2, 0), (32, 4, 0), (32, 8, 0), (16, 4, 0), (16, 8, 0),
-              (32, 0, 8), (32, 0, 6)]
+# (transform tile, blocks per CU, segment-decoder waves per CU, segment-decoder
+# waves per workgroup; 0 = default)
+CANDIDATES = [(32, 0, 0, 0), (16, 0, 0, 0), (32, 2, 0, 0), (32, 4, 0, 0), (32, 8, 0, 0), (16, 4, 0, 0),
+              (16, 8, 0, 0), (32, 0, 0, 1), (32, 0, 8, 1), (32, 0, 0, 4)]
 
 
 def cache_path() -> str:
@@ -69,7 +70,7 @@ def _time(fn, reps):
 
 
 def tune(descs, d_pixels, reps: int = 3, candidates=CANDIDATES, use_cache: bool = True, log=None):
-    """Returns {'encode': (tq, bpc, swpc), 'decode': (tq, bpc, swpc), 'timings': {...}}."""
+    """Returns {'encode': (tq, bpc, swpc, swg), 'decode': (tq, bpc, swpc, swg), 'timings': {...}}."""
     import torch
     key = batch_key(descs)
     cache = _load() if use_cache else {}
@@ -78,9 +79,9 @@ def tune(descs, d_pixels, reps: int = 3, candidates=CANDIDATES, use_cache: bool 
     ref_streams, ref_pixels = None, None
     enc_t, dec_t = {}, {}
     for cand in candidates:
-        cand = tuple(cand) + (0,) * (3 - len(cand))
-        tq, bpc, swpc = cand
-        t = isx.tuning(tq, bpc, swpc)
+        cand = tuple(cand) + (0,) * (4 - len(cand))
+        tq, bpc, swpc, swg = cand
+        t = isx.tuning(tq, bpc, swpc, swg)
         enc = isx.Encoder(descs, tune=t)
         enc.run(d_pixels)
         torch.cuda.synchronize()
@@ -113,7 +114,7 @@ def tune(descs, d_pixels, reps: int = 3, candidates=CANDIDATES, use_cache: bool 
         enc_t[cand] = _time(lambda: enc.run(d_pixels), reps)
         dec_t[cand] = _time(lambda: dec.run(enc.out), reps)
         if log:
-            log(f"[tune] tq={tq} bpc={bpc} swpc={swpc} encode {enc_t[cand]:.3f} ms decode {dec_t[cand]:.3f} ms")
+            log(f"[tune] tq={tq} bpc={bpc} swpc={swpc} swg={swg} encode {enc_t[cand]:.3f} ms decode {dec_t[cand]:.3f} ms")
         del enc, dec
     best_e = min(enc_t, key=enc_t.get)
     best_d = min(dec_t, key=dec_t.get)

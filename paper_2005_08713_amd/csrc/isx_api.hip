@@ -267,6 +267,9 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         if (tune->blocks_per_cu < 0 || tune->blocks_per_cu > 64) return ISX_E_INVALID_ARG;
         if (tune->seg_waves_per_cu < 0 || tune->seg_waves_per_cu > (int32_t)kSegWavesPerCu) return ISX_E_INVALID_ARG;
         if (tune->seg_waves_per_cu) H.seg_waves_per_cu = (uint32_t)tune->seg_waves_per_cu;
+        if (tune->seg_wave_group != 0 && tune->seg_wave_group != 1 && tune->seg_wave_group != 2 &&
+            tune->seg_wave_group != 4)
+            return ISX_E_INVALID_ARG;
         if (tune->transform_tile) H.tq = (uint32_t)tune->transform_tile;
         H.blocks_per_cu = (uint32_t)tune->blocks_per_cu;
     }
@@ -339,13 +342,20 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     if (mode == MODE_DECODE && total_blocks >= (1ull << 27)) return ISX_E_UNSUPPORTED;  // segment item = block << 5 | segment
     H.total_blocks = (uint32_t)total_blocks;
     H.total_slots = (uint32_t)total_slots;
-    // A decode with few segments (a served view, one small tile) spreads
-    // each over two or four waves, so that the lone segments finish sooner;
-    // a large one keeps one wave per segment (more segments per CU, less
-    // work per token).  total_slots bounds the segment count.
-    H.seg_nw = 1;
-    if (mode == MODE_DECODE && total_slots <= 4ull * H.num_cus) H.seg_nw = 4;
-    else if (mode == MODE_DECODE && total_slots <= 8ull * H.num_cus) H.seg_nw = 2;
+    // Segment decoder workgroups: two waves (large segments decoded by both,
+    // small ones by each wave alone: sixteen waves per CU where one-wave
+    // workgroups fit eleven); four waves for a decode with few segments (a
+    // served view, one small tile), so that the lone segments finish sooner.
+    // total_slots bounds the segment count.
+    H.seg_nw = mode == MODE_DECODE && total_slots <= 4ull * H.num_cus ? 4u : 2u;
+    if (tune && tune->seg_wave_group) H.seg_nw = (uint32_t)tune->seg_wave_group;
+    // Large segments are queued first.  With two waves per workgroup they
+    // are the ones that a lone wave's half of the LDS could not stage (the
+    // small ones are decoded a wave each); a whole-block item must fit the
+    // staging of the wave that takes it.
+    const bool latency_form = total_slots <= 8ull * H.num_cus;
+    H.seg_big_bits = H.seg_nw == 2 ? (kHalfWords - 3) * 32u : kBigSegBits;
+    H.seg_whole_words = H.seg_nw == 1 ? kSegWords : (H.seg_nw == 2 && !latency_form ? kHalfWords : 0u);
     H.blk_grid = H.total_blocks;
     if (H.blocks_per_cu) {
         uint64_t g = (uint64_t)H.num_cus * H.blocks_per_cu;

@@ -101,7 +101,10 @@ struct PlanHdr {
     uint32_t blk_grid;  // workgroups of the per-block kernels (== total_blocks unless persistent)
     uint32_t num_cus, blocks_per_cu;
     uint32_t seg_waves_per_cu;  // segment decoder: persistent waves per CU
-    uint32_t seg_nw;            // segment decoder: waves per segment (1, or 2 / 4 for small plans)
+    uint32_t seg_nw;            // segment decoder: waves per workgroup (1, 2 or 4)
+    uint32_t seg_big_bits;      // segment decoder: a segment of at least this many bits is a large item
+    uint32_t seg_whole_words;   // segment decoder: staging words of a whole-block item (0 = none)
+    uint32_t pad3;
     uint64_t list_off;      // plan offset of the block list (u32): large blocks, then small ones
     uint32_t n_big, n_small;  // blocks with > 768 4x4 cells / with <= 768
 };
@@ -169,6 +172,7 @@ constexpr uint32_t kLutBytes16 = (1u << kLutK) * 2;
 constexpr uint32_t kLutStride = kLutBytes16 + 1024 + 256 + 256;
 constexpr uint32_t kMaxSeg = 3 * 128 * 128 / 8;  // symbols in the largest segment
 constexpr uint32_t kSegWords = 1662;             // segment bits staged in LDS, 53 Kbit (larger: read from HBM)
+constexpr uint32_t kHalfWords = 480;             // the same, per wave, where two waves split a workgroup's LDS
 constexpr uint32_t kBigSegBits = 16384;          // queue class of a segment
 constexpr uint32_t kSmallSegBits = 4096;         // a block of only such segments is one decode item
 constexpr uint32_t kWholeBlock = 31;             // segment field of such an item (segments are 0..30)

@@ -516,7 +516,8 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
         llen[j] = j < m ? s_len[j] : 0;
         lsym[j] = j < m ? s_sym[j] : 0;
     }
-    // work items: large segments first in the decode order.  A small block
+    // work items: large segments (at least seg_big_bits) first in the
+    // decode order.  A small block
     // (at most 1536 symbols per plane: 64x64-coefficient types, or smaller)
     // whose kept segments are all short and fit the LDS staging together is
     // one item (segment field kWholeBlock): one wave decodes its segments
@@ -532,9 +533,10 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
             sum += __shfl_xor(sum, o, 64);
         }
         const bool small_block = p * n <= 1536u && mx < kSmallSegBits;
-        // (a plan decoded with several waves per segment keeps one item per
-        // segment: there the segments of a block run side by side)
-        if (H.seg_nw == 1 && nkeep >= 2 && small_block && sum + 64 <= (kSegWords - 2) * 32u) {
+        // (seg_whole_words: the staging of the wave that takes such an
+        // item; 0 in the latency form, where the segments of a block run
+        // side by side)
+        if (H.seg_whole_words && nkeep >= 2 && small_block && sum + 64 <= (H.seg_whole_words - 2) * 32u) {
             if (lane == 0) {
                 const uint32_t sb1 = atomicAdd(&ctr[kQSmall], 1u);
                 uint32_t *list = (uint32_t *)(ws + H.ws_items + kItemsHdr);
@@ -543,7 +545,7 @@ __global__ void __launch_bounds__(64) k_dec_header(PlanHdr H, const uint8_t *__r
             return;
         }
     }
-    const bool big = lane < nkeep && s_bits[lane] >= kBigSegBits;
+    const bool big = lane < nkeep && s_bits[lane] >= H.seg_big_bits;
     const uint64_t bm = __ballot(big);
     const uint32_t nbig = __popcll(bm), nsmall = nkeep - nbig;
     uint32_t bb = 0, sb = 0;
@@ -783,14 +785,14 @@ __device__ inline void store_plane(const uint8_t *pl, uint8_t *out, uint32_t M)
     const uint4 *src = (const uint4 *)pl;
     uint4 *dst = (uint4 *)out;
     const uint32_t M16 = (M + 15) / 16;
-    for (uint32_t i = threadIdx.x; i < M16; i += 64 * NW) dst[i] = src[i];
+    for (uint32_t i = NW == 1 ? (threadIdx.x & 63) : threadIdx.x; i < M16; i += 64 * NW) dst[i] = src[i];
 }
 template <int NW>
 __device__ inline void zero_lds_plane(uint8_t *pl, uint32_t M)
 {
     uint4 *d = (uint4 *)pl;
     const uint32_t M16 = (M + 15) / 16;
-    for (uint32_t i = threadIdx.x; i < M16; i += 64 * NW) d[i] = make_uint4(0, 0, 0, 0);
+    for (uint32_t i = NW == 1 ? (threadIdx.x & 63) : threadIdx.x; i < M16; i += 64 * NW) d[i] = make_uint4(0, 0, 0, 0);
 }
 
 // values the waves of a workgroup exchange
@@ -804,7 +806,9 @@ __device__ int32_t decode_segment(Cur C, const DecTab &T, uint32_t N, uint32_t M
                                   WaveX &X)
 {
     constexpr uint32_t G = 64 * NW;
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = threadIdx.x;
+    // g: the thread's index in the group (one wave of a two-wave workgroup
+    // may decode alone)
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = NW == 1 ? lane : threadIdx.x;
     const uint32_t wz = T.wz, czr = T.czr;
     uint32_t chunk = (N + G - 1) / G;
     chunk = (chunk + 31) & ~31u;
@@ -934,19 +938,168 @@ struct SegShared {
     alignas(16) uint8_t plane[kMaxSeg];  // one segment's symbols
     uint32_t bits[kSegWords + 2];
 };
+// one wave's part where the two waves of a workgroup decode on their own
+struct SegHalf {
+    uint16_t lut[1 << kLutK];
+    alignas(16) uint8_t plane[kMaxSeg];
+    uint32_t bits[kHalfWords + 2];
+};
+template <int NW>
+union SegLds {
+    SegShared all;
+    SegHalf half[NW == 2 ? 2 : 1];
+};
+
+// One queue item (a segment, or all kept segments of a small block) with the
+// NW waves of the group: the prefix table and the bits (up to CAP words) to
+// LDS, then per segment the three phases and the plane store.  t is the
+// thread's index in the group.
+template <int NW, uint32_t CAP>
+__device__ void dec_item(const PlanHdr &H, const uint8_t *__restrict__ enc, uint8_t *__restrict__ ws,
+                         int32_t *__restrict__ status, uint32_t item, uint16_t *lut, uint8_t *plane,
+                         uint32_t *bits, WaveX &X)
+{
+    constexpr uint32_t NT = 64 * NW;
+    const uint32_t t = NW == 1 ? (threadIdx.x & 63) : threadIdx.x;
+    const uint32_t blk = item >> 5, s = item & 31;
+    const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
+    const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
+    // segments [s0, s1) of the block: one, or all kept ones of a block item
+    const bool whole = s == kWholeBlock;
+    const uint32_t s0 = whole ? 0u : s;
+    const uint32_t s1 = whole ? __builtin_amdgcn_readfirstlane(P.nseg) : s + 1;
+    const uint64_t S0 = P.seg_bitpos[s0];
+    const uint64_t Send = P.seg_bitpos[s1 - 1] + P.seg_bits[s1 - 1];
+    const uint32_t Nall = (uint32_t)(Send - S0);
+    const uint32_t pstride = plane_stride((uint32_t)B.p * B.wb * B.hb / 8);
+    bool toolong = false;
+    for (uint32_t k = s0; k < s1; k++) toolong |= P.seg_M[k] > kMaxSeg;
+    if (toolong) {  // not reachable for 128-grid blocks
+        if (t == 0) atomicMin(&status[B.tile], D_CORRUPT);
+        return;
+    }
+    const uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
+    wg_sync<NW>();  // the group's previous item is done with the LDS
+    {
+        // prefix table (kLutBytes16 / 16 pieces of 16 bytes): all loads
+        // of a thread first.  The leaf tables that resolve the long codes
+        // stay in global memory (read through the L1 cache).
+        constexpr uint32_t NQ = kLutBytes16 / 16;
+        static_assert(kLutBytes16 % 16 == 0, "table copy layout");
+        const uint4 *src = (const uint4 *)tab;
+        uint4 *dst = (uint4 *)lut;
+        if constexpr (NQ % NT == 0) {
+            constexpr uint32_t NR = NQ / NT;
+            uint4 a[NR];
+#pragma unroll
+            for (uint32_t r = 0; r < NR; r++) a[r] = src[t + NT * r];
+#pragma unroll
+            for (uint32_t r = 0; r < NR; r++) dst[t + NT * r] = a[r];
+        } else {
+            static_assert(NT > NQ, "table copy layout");
+            if (t < NQ) dst[t] = src[t];
+        }
+    }
+    const uint64_t lo = B.byte_off, hi = B.byte_off + B.byte_len;
+    const uint64_t w0 = S0 >> 5;
+    const uint32_t nw = Nall ? (uint32_t)(((S0 + Nall - 1) >> 5) + 2 - w0) : 0u;
+    const bool staged = nw <= CAP;
+    if (staged) {
+        // words w0 .. w0+nw-1 from 16-byte loads (4 per thread in
+        // flight); a chunk not wholly inside the block falls back to bytes
+        const bool al16 = (((uintptr_t)enc) & 15u) == 0;
+        const uint64_t c0 = (w0 * 4) & ~15ull, c1 = (w0 + nw) * 4;
+        const uint32_t nch = (uint32_t)((c1 - c0 + 15) / 16);
+        for (uint32_t base = 0; base < nch; base += 4 * NT) {
+            uint4 q[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t ci = base + t + NT * k;
+                const uint64_t cb = c0 + 16ull * ci;
+                if (ci < nch && al16 && cb >= lo && cb + 16 <= hi) q[k] = *(const uint4 *)(enc + cb);
+                else if (ci < nch) {
+                    q[k].x = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4));
+                    q[k].y = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4 + 1));
+                    q[k].z = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4 + 2));
+                    q[k].w = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4 + 3));
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t ci = base + t + NT * k;
+                if (ci >= nch) continue;
+                const int64_t r0 = (int64_t)((c0 / 4) + 4ull * ci) - (int64_t)w0;  // staged index of q[k].x
+                if (r0 >= 0 && r0 + 3 < (int64_t)nw) {
+                    bits[r0] = __builtin_bswap32(q[k].x);
+                    bits[r0 + 1] = __builtin_bswap32(q[k].y);
+                    bits[r0 + 2] = __builtin_bswap32(q[k].z);
+                    bits[r0 + 3] = __builtin_bswap32(q[k].w);
+                } else {
+                    if (r0 >= 0 && r0 < (int64_t)nw) bits[r0] = __builtin_bswap32(q[k].x);
+                    if (r0 + 1 >= 0 && r0 + 1 < (int64_t)nw) bits[r0 + 1] = __builtin_bswap32(q[k].y);
+                    if (r0 + 2 >= 0 && r0 + 2 < (int64_t)nw) bits[r0 + 2] = __builtin_bswap32(q[k].z);
+                    if (r0 + 3 >= 0 && r0 + 3 < (int64_t)nw) bits[r0 + 3] = __builtin_bswap32(q[k].w);
+                }
+            }
+        }
+        if (t < 2) bits[nw + t] = 0u;
+    }
+    wg_sync<NW>();
+    DecTab T;
+    T.lut = lut;
+    T.acode = (const uint32_t *)(tab + kLutBytes16);
+    T.llen = tab + kLutBytes16 + 1024;
+    T.lsym = T.llen + 256;
+    T.m = P.m; T.czr = P.czr; T.wz = P.wz;
+    int32_t err = 0;
+    for (uint32_t k = s0; k < s1; k++) {
+        const uint32_t M = P.seg_M[k], N = P.seg_bits[k];
+        const uint64_t Sk = P.seg_bitpos[k];
+        uint8_t *out = ws + B.sym_off + (uint64_t)P.seg_plane[k] * pstride;
+        int32_t e = 0;
+        if (T.m == 1 && T.lsym[0] != T.czr) {
+            // zero-length codewords: the segment is M copies of the leaf
+            if (N != 0) e = D_CORRUPT;
+            const uint32_t fill = T.lsym[0] * 0x01010101u;
+            uint32_t *pw = (uint32_t *)plane;
+            wg_sync<NW>();  // the previous segment's plane has been stored
+            for (uint32_t i = t; i < (M + 15) / 16 * 4; i += NT) {
+                const uint32_t b = 4 * i;
+                pw[i] = b + 4 <= M ? fill : (b < M ? fill & ((1u << (8 * (M - b))) - 1u) : 0u);
+            }
+            wg_sync<NW>();
+            store_plane<NW>(plane, out, M);
+        } else if (staged) {
+            const uint32_t wk = (uint32_t)((Sk >> 5) - w0);
+            CurLds src;
+            src.w = bits + wk; src.off = (uint32_t)(Sk & 31); src.nw = nw - wk;
+            wg_sync<NW>();  // the previous segment's plane has been stored
+            e = decode_segment<NW>(src, T, N, M, plane, out, X);
+        } else {
+            CurGlb src;
+            src.enc = enc; src.lo = lo; src.hi = hi; src.w0 = Sk >> 5; src.off = (uint32_t)(Sk & 31);
+            wg_sync<NW>();
+            e = decode_segment<NW>(src, T, N, M, plane, out, X);
+        }
+        err = e ? e : err;
+    }
+    if (err) atomicMin(&status[B.tile], err);
+}
 
 // Persistent workgroups of NW waves taking (block, segment) items from the
-// two lists (large segments first); per item: the prefix table and the
-// segment's bits to LDS, then per segment the three phases, the symbols
-// gathered in LDS and stored to the plane in whole lines (14.5 KB of LDS per
-// workgroup: eleven one-wave workgroups per CU in the throughput form).
+// two lists (large segments first).  One wave (NW = 1) is the throughput form
+// for plans of many small segments: 14.5 KB of LDS per wave, eleven waves per
+// CU.  Two waves share 14.5 KB for a large segment and decode it together;
+// once the large list is drained each of them takes small items on its own
+// in half of the workgroup's LDS (20 KB per workgroup: eight per CU, sixteen
+// waves, as many as their registers allow).  Four waves decode every item
+// together (the latency form for plans of few segments).
 template <int NW>
-__global__ void __launch_bounds__(64 * NW) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
+__global__ void __launch_bounds__(64 * NW, NW == 2 ? 4 : 1) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
                                                           uint8_t *__restrict__ ws,
                                                           int32_t *__restrict__ status)
 {
-    constexpr uint32_t NT = 64 * NW;
-    __shared__ SegShared S;
+    __shared__ SegLds<NW> S;
     __shared__ WaveX X;
     __shared__ uint32_t s_item;
     __shared__ int32_t s_status;
@@ -955,6 +1108,7 @@ __global__ void __launch_bounds__(64 * NW) k_dec_segments(PlanHdr H, const uint8
     const uint32_t nbig = __builtin_amdgcn_readfirstlane(ctr[kQBig]);
     const uint32_t ntot = nbig + __builtin_amdgcn_readfirstlane(ctr[kQSmall]);
     const uint32_t *list = (const uint32_t *)(ws + H.ws_items + kItemsHdr);
+    const uint32_t *small = list + H.total_blocks * 32ull;
     for (;;) {
         uint32_t idx = 0;
         if (tid == 0) idx = atomicAdd(&ctr[kQTake], 1u);
@@ -966,11 +1120,34 @@ __global__ void __launch_bounds__(64 * NW) k_dec_segments(PlanHdr H, const uint8
         }
         idx = __builtin_amdgcn_readfirstlane(idx);
         if (idx >= ntot) break;
-        const uint32_t item =
-            __builtin_amdgcn_readfirstlane(idx < nbig ? list[idx] : list[H.total_blocks * 32ull + (idx - nbig)]);
-        const uint32_t blk = item >> 5, s = item & 31;
-        const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
-        const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
+        if constexpr (NW == 2) {
+            if (idx >= nbig) {
+                // the large list is drained (the take counter only grows):
+                // from here on each wave takes small items alone, wave 0
+                // starting with this one.  No barrier follows; the
+                // barriers above saw both waves done with S.all.
+                const uint32_t w = tid >> 6;
+                SegHalf &Hf = S.half[w];
+                uint32_t id = idx;
+                if (w != 0) {
+                    id = 0;
+                    if ((tid & 63) == 0) id = atomicAdd(&ctr[kQTake], 1u);
+                    id = __builtin_amdgcn_readfirstlane(id);
+                }
+                while (id < ntot) {
+                    const uint32_t item = __builtin_amdgcn_readfirstlane(small[id - nbig]);
+                    const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[item >> 5];
+                    if (__builtin_amdgcn_readfirstlane(status[B.tile]) == D_OK)
+                        dec_item<1, kHalfWords>(H, enc, ws, status, item, Hf.lut, Hf.plane, Hf.bits, X);
+                    id = 0;
+                    if ((tid & 63) == 0) id = atomicAdd(&ctr[kQTake], 1u);
+                    id = __builtin_amdgcn_readfirstlane(id);
+                }
+                return;
+            }
+        }
+        const uint32_t item = __builtin_amdgcn_readfirstlane(idx < nbig ? list[idx] : small[idx - nbig]);
+        const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[item >> 5];
         // the tile's status, as one thread read it (other workgroups may set
         // it meanwhile, and every wave must take the same branch)
         int32_t st;
@@ -982,126 +1159,7 @@ __global__ void __launch_bounds__(64 * NW) k_dec_segments(PlanHdr H, const uint8
             st = status[B.tile];
         }
         if (__builtin_amdgcn_readfirstlane(st) != D_OK) continue;
-        // segments [s0, s1) of the block: one, or all kept ones of a block item
-        const bool whole = s == kWholeBlock;
-        const uint32_t s0 = whole ? 0u : s;
-        const uint32_t s1 = whole ? __builtin_amdgcn_readfirstlane(P.nseg) : s + 1;
-        const uint64_t S0 = P.seg_bitpos[s0];
-        const uint64_t Send = P.seg_bitpos[s1 - 1] + P.seg_bits[s1 - 1];
-        const uint32_t Nall = (uint32_t)(Send - S0);
-        const uint32_t pstride = plane_stride((uint32_t)B.p * B.wb * B.hb / 8);
-        bool toolong = false;
-        for (uint32_t k = s0; k < s1; k++) toolong |= P.seg_M[k] > kMaxSeg;
-        if (toolong) {  // not reachable for 128-grid blocks
-            if (tid == 0) atomicMin(&status[B.tile], D_CORRUPT);
-            continue;
-        }
-        const uint8_t *tab = ws + H.ws_lut + (uint64_t)blk * kLutStride;
-        wg_sync<NW>();  // the previous item is done with S
-        {
-            // prefix table (kLutBytes16 / 16 pieces of 16 bytes): all loads
-            // of a thread first.  The leaf tables that resolve the long codes
-            // stay in global memory (read through the L1 cache).
-            constexpr uint32_t NQ = kLutBytes16 / 16;
-            static_assert(kLutBytes16 % 16 == 0, "table copy layout");
-            const uint4 *src = (const uint4 *)tab;
-            uint4 *dst = (uint4 *)S.lut;
-            if constexpr (NQ % NT == 0) {
-                constexpr uint32_t NR = NQ / NT;
-                uint4 a[NR];
-#pragma unroll
-                for (uint32_t r = 0; r < NR; r++) a[r] = src[tid + NT * r];
-#pragma unroll
-                for (uint32_t r = 0; r < NR; r++) dst[tid + NT * r] = a[r];
-            } else {
-                static_assert(NT > NQ, "table copy layout");
-                if (tid < NQ) dst[tid] = src[tid];
-            }
-        }
-        const uint64_t lo = B.byte_off, hi = B.byte_off + B.byte_len;
-        const uint64_t w0 = S0 >> 5;
-        const uint32_t nw = Nall ? (uint32_t)(((S0 + Nall - 1) >> 5) + 2 - w0) : 0u;
-        const bool staged = nw <= kSegWords;
-        if (staged) {
-            // words w0 .. w0+nw-1 from 16-byte loads (4 per thread in
-            // flight); a chunk not wholly inside the block falls back to bytes
-            const bool al16 = (((uintptr_t)enc) & 15u) == 0;
-            const uint64_t c0 = (w0 * 4) & ~15ull, c1 = (w0 + nw) * 4;
-            const uint32_t nch = (uint32_t)((c1 - c0 + 15) / 16);
-            for (uint32_t base = 0; base < nch; base += 4 * NT) {
-                uint4 q[4];
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const uint32_t ci = base + tid + NT * k;
-                    const uint64_t cb = c0 + 16ull * ci;
-                    if (ci < nch && al16 && cb >= lo && cb + 16 <= hi) q[k] = *(const uint4 *)(enc + cb);
-                    else if (ci < nch) {
-                        q[k].x = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4));
-                        q[k].y = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4 + 1));
-                        q[k].z = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4 + 2));
-                        q[k].w = __builtin_bswap32(stream_word(enc, lo, hi, cb / 4 + 3));
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const uint32_t ci = base + tid + NT * k;
-                    if (ci >= nch) continue;
-                    const int64_t r0 = (int64_t)((c0 / 4) + 4ull * ci) - (int64_t)w0;  // staged index of q[k].x
-                    if (r0 >= 0 && r0 + 3 < (int64_t)nw) {
-                        S.bits[r0] = __builtin_bswap32(q[k].x);
-                        S.bits[r0 + 1] = __builtin_bswap32(q[k].y);
-                        S.bits[r0 + 2] = __builtin_bswap32(q[k].z);
-                        S.bits[r0 + 3] = __builtin_bswap32(q[k].w);
-                    } else {
-                        if (r0 >= 0 && r0 < (int64_t)nw) S.bits[r0] = __builtin_bswap32(q[k].x);
-                        if (r0 + 1 >= 0 && r0 + 1 < (int64_t)nw) S.bits[r0 + 1] = __builtin_bswap32(q[k].y);
-                        if (r0 + 2 >= 0 && r0 + 2 < (int64_t)nw) S.bits[r0 + 2] = __builtin_bswap32(q[k].z);
-                        if (r0 + 3 >= 0 && r0 + 3 < (int64_t)nw) S.bits[r0 + 3] = __builtin_bswap32(q[k].w);
-                    }
-                }
-            }
-            if (tid < 2) S.bits[nw + tid] = 0u;
-        }
-        wg_sync<NW>();
-        DecTab T;
-        T.lut = S.lut;
-        T.acode = (const uint32_t *)(tab + kLutBytes16);
-        T.llen = tab + kLutBytes16 + 1024;
-        T.lsym = T.llen + 256;
-        T.m = P.m; T.czr = P.czr; T.wz = P.wz;
-        int32_t err = 0;
-        for (uint32_t k = s0; k < s1; k++) {
-            const uint32_t M = P.seg_M[k], N = P.seg_bits[k];
-            const uint64_t Sk = P.seg_bitpos[k];
-            uint8_t *out = ws + B.sym_off + (uint64_t)P.seg_plane[k] * pstride;
-            int32_t e = 0;
-            if (T.m == 1 && T.lsym[0] != T.czr) {
-                // zero-length codewords: the segment is M copies of the leaf
-                if (N != 0) e = D_CORRUPT;
-                const uint32_t fill = T.lsym[0] * 0x01010101u;
-                uint32_t *pw = (uint32_t *)S.plane;
-                wg_sync<NW>();  // the previous segment's plane has been stored
-                for (uint32_t i = tid; i < (M + 15) / 16 * 4; i += NT) {
-                    const uint32_t b = 4 * i;
-                    pw[i] = b + 4 <= M ? fill : (b < M ? fill & ((1u << (8 * (M - b))) - 1u) : 0u);
-                }
-                wg_sync<NW>();
-                store_plane<NW>(S.plane, out, M);
-            } else if (staged) {
-                const uint32_t wk = (uint32_t)((Sk >> 5) - w0);
-                CurLds src;
-                src.w = S.bits + wk; src.off = (uint32_t)(Sk & 31); src.nw = nw - wk;
-                wg_sync<NW>();  // the previous segment's plane has been stored
-                e = decode_segment<NW>(src, T, N, M, S.plane, out, X);
-            } else {
-                CurGlb src;
-                src.enc = enc; src.lo = lo; src.hi = hi; src.w0 = Sk >> 5; src.off = (uint32_t)(Sk & 31);
-                wg_sync<NW>();
-                e = decode_segment<NW>(src, T, N, M, S.plane, out, X);
-            }
-            err = e ? e : err;
-        }
-        if (err) atomicMin(&status[B.tile], err);
+        dec_item<NW, kSegWords>(H, enc, ws, status, item, S.all.lut, S.all.plane, S.all.bits, X);
     }
 }
 

@@ -44,13 +44,14 @@ class RegionJob(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("transform_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("seg_waves_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("seg_waves_per_cu", ctypes.c_int32), ("seg_wave_group", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
-def tuning(transform_tile=0, blocks_per_cu=0, seg_waves_per_cu=0) -> Tuning:
+def tuning(transform_tile=0, blocks_per_cu=0, seg_waves_per_cu=0, seg_wave_group=0) -> Tuning:
     t = Tuning()
     t.transform_tile, t.blocks_per_cu = int(transform_tile), int(blocks_per_cu)
-    t.seg_waves_per_cu = int(seg_waves_per_cu)
+    t.seg_waves_per_cu, t.seg_wave_group = int(seg_waves_per_cu), int(seg_wave_group)
     return t
 
 

@@ -192,7 +192,9 @@ def test_tuning_ranges_are_checked_on_the_host():
     pb = L.isx_encode_plan_bytes(ctypes.byref(d), 1)
     buf = (ctypes.c_uint8 * pb)()
     for t, ok in [((32, 0, 0), True), ((32, 0, 11), True), ((16, 64, 1), True), ((32, 0, 12), False),
-                  ((32, 0, -1), False), ((24, 0, 0), False), ((32, 65, 0), False)]:
+                  ((32, 0, -1), False), ((24, 0, 0), False), ((32, 65, 0), False), ((32, 0, 0, 1), True),
+                  ((32, 0, 0, 2), True), ((32, 0, 0, 4), True), ((32, 0, 0, 3), False), ((32, 0, 0, 8), False),
+                  ((32, 0, 0, -1), False)]:
         tu = isx.tuning(*t)
         rc = L.isx_encode_plan_build_tuned(ctypes.byref(d), 1, ctypes.byref(tu), buf, pb)
         assert (rc == isx.OK) == ok, t

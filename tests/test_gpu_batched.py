@@ -55,9 +55,12 @@ def test_tunings_give_identical_bytes_and_pixels():
     tiles = _batch()
     descs, d_pix = _upload(tiles)
     ref = None
-    for tq, bpc, swpc in [(32, 0, 0), (16, 0, 0), (32, 1, 0), (16, 3, 0), (32, 8, 0), (32, 0, 1), (32, 0, 7)]:
-        print("tuning", tq, bpc, swpc, flush=True)
-        enc = isx.Encoder(descs, tune=isx.tuning(tq, bpc, swpc))
+    # the last four force the segment decoder's waves per segment (the
+    # default picks four for a batch this small)
+    for tun in [(32, 0, 0), (16, 0, 0), (32, 1, 0), (16, 3, 0), (32, 8, 0), (32, 0, 1, 1), (32, 0, 7, 1),
+                (32, 0, 0, 1), (32, 0, 3, 1), (16, 3, 0, 2), (32, 0, 0, 4)]:
+        print("tuning", tun, flush=True)
+        enc = isx.Encoder(descs, tune=isx.tuning(*tun))
         enc.run(d_pix)
         torch.cuda.synchronize()
         streams = enc.streams()
@@ -68,14 +71,14 @@ def test_tunings_give_identical_bytes_and_pixels():
         assert streams == ref
         zs = [i % (t["levels"] + 1) for i, t in enumerate(tiles)]
         jobs, nbytes, outs = _jobs(descs, enc, streams, zs)
-        dec = isx.Decoder(jobs, nbytes, tune=isx.tuning(tq, bpc, swpc))
+        dec = isx.Decoder(jobs, nbytes, tune=isx.tuning(*tun))
         dec.run(enc.out)
         torch.cuda.synchronize()
         assert int(dec.status.abs().sum().item()) == 0
         host = dec.out.cpu().numpy()
         for i, (o, oh, ow, c) in enumerate(outs):
             got = host[o:o + oh * ow * c].reshape(oh, ow, c)
-            assert np.array_equal(got, oracle.decode_tile(ref[i], zs[i])), (tq, bpc, swpc, i)
+            assert np.array_equal(got, oracle.decode_tile(ref[i], zs[i])), (tun, i)
 
 
 def test_graph_replay_matches_eager_every_time():
@@ -114,9 +117,10 @@ def test_autotuner_picks_a_valid_setting(tmp_path, monkeypatch):
     monkeypatch.setenv("ISX_TUNE_CACHE", str(tmp_path / "tune.json"))
     tiles = _batch(16, seed=13)
     descs, d_pix = _upload(tiles)
-    res = autotune.tune(descs, d_pix, reps=1, candidates=[(32, 0), (16, 0), (32, 4), (32, 0, 8)])
-    assert tuple(res["encode"]) in [(32, 0, 0), (16, 0, 0), (32, 4, 0), (32, 0, 8)]
-    assert tuple(res["decode"]) in [(32, 0, 0), (16, 0, 0), (32, 4, 0), (32, 0, 8)]
+    res = autotune.tune(descs, d_pix, reps=1, candidates=[(32, 0), (16, 0), (32, 4), (32, 0, 8, 1)])
+    ok = [(32, 0, 0, 0), (16, 0, 0, 0), (32, 4, 0, 0), (32, 0, 8, 1)]
+    assert tuple(res["encode"]) in ok
+    assert tuple(res["decode"]) in ok
     assert os.path.exists(tmp_path / "tune.json")
     again = autotune.tune(descs, d_pix, reps=1)
     assert again == res
