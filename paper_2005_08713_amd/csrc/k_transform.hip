@@ -1011,6 +1011,24 @@ __device__ inline int32_t band_at(const int32_t *base, bool is16, uint64_t i)
     return is16 ? (int32_t)((uint32_t)w << sh) >> 16 : w;
 }
 
+// The 32-bit words of 19 consecutive window rows of one column: even rows
+// from pE, odd rows from pO (row strides sE, sO bytes); P0 = parity of the
+// first row.
+template <int P0>
+__device__ inline void load_rows19(const uint8_t *pE, const uint8_t *pO, uint64_t sE, uint64_t sO, int32_t (&x)[19])
+{
+#pragma unroll
+    for (int j = 0; j < 19; j++) {
+        if (((j + P0) & 1) == 0) {
+            x[j] = *(const int32_t *)pE;
+            pE += sE;
+        } else {
+            x[j] = *(const int32_t *)pO;
+            pO += sO;
+        }
+    }
+}
+
 __device__ inline void inv_strips_load(const TileGeo &T, int level, int ch, const int32_t *rmap, const int32_t *cmap,
                                        const int32_t *wsi, int lane, int wv, bool b16, InvLoad &L)
 {
@@ -1047,6 +1065,35 @@ __device__ inline void inv_strips_load(const TileGeo &T, int level, int ch, cons
     const int32_t *po = xo ? hh : lh;
     const uint32_t pitch_e = xo ? G.pitch[1] : llp, pitch_o = G.pitch[xo ? 2 : 0];
     const bool e16 = b16 && xo;
+    const int a = 1 + 16 * wv;
+    const int gy0 = __builtin_amdgcn_readfirstlane(rmap[a]);
+    if (__all(lane >= 19 || rmap[a + lane] == gy0 + lane)) {
+        // the strip's 19 rows are consecutive (no reflection): each lane
+        // walks one pointer through the even rows and one through the odd
+        // rows of its column instead of computing every address (pitches
+        // are multiples of 4, so an int16 element keeps its half of the
+        // 32-bit word in every row)
+        const int p0 = gy0 & 1;
+        const uint32_t xe = (uint32_t)(gx >> 1);
+        const uint64_t ie = (uint64_t)((gy0 + p0) >> 1) * pitch_e + xe;
+        const uint64_t io = (uint64_t)((gy0 + 1 - p0) >> 1) * pitch_o + xe;
+        const uint8_t *pE = (const uint8_t *)pe + (e16 ? 2 * (ie & ~1ull) : 4 * ie);
+        const uint8_t *pO = (const uint8_t *)po + (b16 ? 2 * (io & ~1ull) : 4 * io);
+        const uint64_t sE = (uint64_t)pitch_e * (e16 ? 2u : 4u), sO = (uint64_t)pitch_o * (b16 ? 2u : 4u);
+        if (p0) load_rows19<1>(pE, pO, sE, sO, L.x);
+        else load_rows19<0>(pE, pO, sE, sO, L.x);
+        if (b16) {
+            // int16 elements: the low half of the word for even ones
+            const uint32_t lE = e16 ? 16u - 16u * (xe & 1u) : 0u, rE = e16 ? 16u : 0u;
+            const uint32_t lO = 16u - 16u * (xe & 1u);
+#pragma unroll
+            for (int j = 0; j < 19; j++) {
+                if (((j + p0) & 1) == 0) L.x[j] = (int32_t)((uint32_t)L.x[j] << lE) >> rE;
+                else L.x[j] = (int32_t)((uint32_t)L.x[j] << lO) >> 16;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < 19; j++) {
         const int gy = __builtin_amdgcn_readfirstlane(rmap[1 + 16 * wv + j]);
