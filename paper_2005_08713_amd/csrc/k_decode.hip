@@ -955,7 +955,7 @@ union SegLds {
 // LDS, then per segment the three phases and the plane store.  t is the
 // thread's index in the group.
 template <int NW, uint32_t CAP>
-__device__ void dec_item(const PlanHdr &H, const uint8_t *__restrict__ enc, uint8_t *__restrict__ ws,
+__device__ __forceinline__ void dec_item(const PlanHdr &H, const uint8_t *__restrict__ enc, uint8_t *__restrict__ ws,
                          int32_t *__restrict__ status, uint32_t item, uint16_t *lut, uint8_t *plane,
                          uint32_t *bits, WaveX &X)
 {
@@ -1188,59 +1188,145 @@ __device__ inline void transpose16(uint32_t (&r)[16])
 // depth, is not read and counts as 0: the condition is the same for a wave's
 // cells of one type), then one 16x16 bit-matrix transpose per cell turns
 // plane words into magnitudes; dequantised, signed and stored.
+// The same transpose for two cells at once: each word holds a plane word of
+// the first cell in its low half and of the second in its high half (the
+// masks keep every exchange inside its half).
+__device__ inline void transpose16x2(uint32_t (&r)[16])
+{
+#pragma unroll
+    for (int s = 8, k = 0; s >= 1; s >>= 1, k++) {
+        const uint32_t m = k == 0 ? 0x00ff00ffu : (k == 1 ? 0x0f0f0f0fu : (k == 2 ? 0x33333333u : 0x55555555u));
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            if (i & s) continue;
+            const uint32_t x = ((r[i] >> s) ^ r[i + s]) & m;
+            r[i + s] ^= x;
+            r[i] ^= x << s;
+        }
+    }
+}
+
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
 template <int NC>
-__device__ inline void reasm_cells(const BlockDesc &B, uint8_t *ws, const uint8_t *sym,
+__device__ __forceinline__ void reasm_cells(const BlockDesc &B, uint8_t *ws, const uint8_t *sym,
                                    const uint32_t (*s_off)[3], uint32_t t, uint32_t ci, uint32_t d,
                                    uint32_t wq, uint32_t step, bool c16)
 {
     auto ld = [&](uint32_t o) -> uint32_t {
         return NC == 2 ? *(const uint32_t *)(sym + o + 2 * ci) : (uint32_t)*(const uint16_t *)(sym + o + 2 * ci);
     };
-    uint32_t mag[NC][16], sgn[NC];
-#pragma unroll
-    for (int b = 0; b < 16; b++) {
-        const uint32_t o = (uint32_t)b + 1 < d ? s_off[b][t] : ~0u;
-        uint32_t v = 0;
-        if (o != ~0u) v = ld(o);
-#pragma unroll
-        for (int k = 0; k < NC; k++) mag[k][b] = (v >> (16 * k)) & 0xffffu;
-    }
-    {
-        const uint32_t o = d ? s_off[d - 1][t] : ~0u;
-        const uint32_t v = ld(o != ~0u ? o : 0u);
-#pragma unroll
-        for (int k = 0; k < NC; k++) sgn[k] = o != ~0u ? (v >> (16 * k)) & 0xffffu : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < NC; k++) transpose16(mag[k]);
-    // magnitude planes 16 .. d-2 (samples deeper than 16 bits)
-    for (uint32_t b = 16; b + 1 < d; b++) {
-        const uint32_t o = s_off[b][t];
-        if (o == ~0u) continue;
-        const uint32_t v = ld(o);
-#pragma unroll
-        for (int k = 0; k < NC; k++)
-#pragma unroll
-            for (int i = 0; i < 16; i++) mag[k][i] |= ((v >> (16 * k + i)) & 1u) << b;
-    }
-    if (B.drop) {  // midpoint of the dropped magnitude bits
-        const uint32_t half = 1u << (B.drop - 1);
-#pragma unroll
-        for (int k = 0; k < NC; k++)
-#pragma unroll
-            for (int i = 0; i < 16; i++) mag[k][i] += mag[k][i] ? half : 0u;
-    }
     const uint32_t tw = B.tw[t], th = B.th[t];
     const uint64_t toff = B.off[t];
     const uint32_t tpitch = B.pitch[t];
+    // both cells in one band row, whole, int16: each row's 8 coefficients
+    // in one 16-byte store (8 int16 elements, aligned)
+    const bool row16 =
+        NC == 2 && c16 && ((toff | tpitch) & 7u) == 0 && (ci % wq) + 1 < wq && 4 * ((ci % wq) + 1) + 3 < tw;
+    uint32_t mag[NC][16], sgn[NC];
+    bool split = true;
+    if constexpr (NC == 2) {
+        if (d <= 17) {
+            // magnitudes of at most 16 bits: the two cells' plane words
+            // stay packed in one register through the transpose
+            uint32_t pw[16];
+#pragma unroll
+            for (int b = 0; b < 16; b++) {
+                const uint32_t o = (uint32_t)b + 1 < d ? s_off[b][t] : ~0u;
+                pw[b] = o != ~0u ? ld(o) : 0u;
+            }
+            uint32_t sg;
+            {
+                const uint32_t o = d ? s_off[d - 1][t] : ~0u;
+                const uint32_t v = ld(o != ~0u ? o : 0u);
+                sg = o != ~0u ? v : 0u;
+            }
+            transpose16x2(pw);
+            if (B.drop) {  // midpoint of the dropped magnitude bits (no carry out of a half)
+                const uint32_t half = 1u << (B.drop - 1);
+#pragma unroll
+                for (int i = 0; i < 16; i++)
+                    pw[i] += ((pw[i] & 0xffffu) ? half : 0u) + ((pw[i] >> 16) ? half << 16 : 0u);
+            }
+            if (row16) {
+                // dequantised and signed as 16-bit pairs: (q*step + step/2
+                // for q != 0), then two's complement where the sign bit is set
+                const u16x2 stp = (u16x2)(uint16_t)step, hlf = (u16x2)(uint16_t)(step / 2), one = (u16x2)1;
+                uint32_t v[16];
+#pragma unroll
+                for (int i = 0; i < 16; i++) {
+                    u16x2 q = __builtin_bit_cast(u16x2, pw[i]);
+                    if (step > 1) q = q * stp + __builtin_elementwise_min(q, one) * hlf;
+                    const uint32_t s1 = (sg >> i) & 0x00010001u;  // sign bits, one per half
+                    const u16x2 m = __builtin_bit_cast(u16x2, __builtin_bit_cast(uint32_t, q) ^ (s1 * 0xffffu));
+                    v[i] = __builtin_bit_cast(uint32_t, m + __builtin_bit_cast(u16x2, s1));
+                }
+                const uint32_t r0 = 4 * (ci / wq), c0 = 4 * (ci % wq);
+#pragma unroll
+                for (int rr = 0; rr < 4; rr++) {
+                    const uint32_t row = r0 + rr;
+                    if (row >= th) continue;
+                    int16_t *dst = (int16_t *)ws + toff + (uint64_t)row * tpitch + c0;
+                    const uint32_t *q = v + 4 * rr;
+                    // low halves: the first cell's row, high halves: the second's
+                    *(uint4 *)dst = make_uint4(__builtin_amdgcn_perm(q[1], q[0], 0x05040100u),
+                                               __builtin_amdgcn_perm(q[3], q[2], 0x05040100u),
+                                               __builtin_amdgcn_perm(q[1], q[0], 0x07060302u),
+                                               __builtin_amdgcn_perm(q[3], q[2], 0x07060302u));
+                }
+                return;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                mag[0][i] = pw[i] & 0xffffu;
+                mag[NC - 1][i] = pw[i] >> 16;
+            }
+            sgn[0] = sg & 0xffffu;
+            sgn[NC - 1] = sg >> 16;
+            split = false;
+        }
+    }
+    if (split) {
+#pragma unroll
+        for (int b = 0; b < 16; b++) {
+            const uint32_t o = (uint32_t)b + 1 < d ? s_off[b][t] : ~0u;
+            uint32_t v = 0;
+            if (o != ~0u) v = ld(o);
+#pragma unroll
+            for (int k = 0; k < NC; k++) mag[k][b] = (v >> (16 * k)) & 0xffffu;
+        }
+        {
+            const uint32_t o = d ? s_off[d - 1][t] : ~0u;
+            const uint32_t v = ld(o != ~0u ? o : 0u);
+#pragma unroll
+            for (int k = 0; k < NC; k++) sgn[k] = o != ~0u ? (v >> (16 * k)) & 0xffffu : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < NC; k++) transpose16(mag[k]);
+        // magnitude planes 16 .. d-2 (samples deeper than 16 bits)
+        for (uint32_t b = 16; b + 1 < d; b++) {
+            const uint32_t o = s_off[b][t];
+            if (o == ~0u) continue;
+            const uint32_t v = ld(o);
+#pragma unroll
+            for (int k = 0; k < NC; k++)
+#pragma unroll
+                for (int i = 0; i < 16; i++) mag[k][i] |= ((v >> (16 * k + i)) & 1u) << b;
+        }
+        if (B.drop) {  // midpoint of the dropped magnitude bits
+            const uint32_t half = 1u << (B.drop - 1);
+#pragma unroll
+            for (int k = 0; k < NC; k++)
+#pragma unroll
+                for (int i = 0; i < 16; i++) mag[k][i] += mag[k][i] ? half : 0u;
+        }
+    }
     auto coef = [&](int k, int i) -> int32_t {
         int32_t q = (int32_t)mag[k][i];
         if (step > 1 && q) q = q * (int32_t)step + (int32_t)(step / 2);
         return ((sgn[k] >> i) & 1u) ? -q : q;
     };
-    if (NC == 2 && c16 && ((toff | tpitch) & 7u) == 0 && (ci % wq) + 1 < wq && 4 * ((ci % wq) + 1) + 3 < tw) {
-        // both cells in one band row, whole: each row's 8 coefficients in
-        // one 16-byte store (8 int16 elements, aligned)
+    if (row16) {
         const uint32_t r0 = 4 * (ci / wq), c0 = 4 * (ci % wq);
 #pragma unroll
         for (int rr = 0; rr < 4; rr++) {
