@@ -697,7 +697,9 @@ __device__ inline int32_t rgb_channel(uint32_t R, uint32_t G, uint32_t B)
 // borders gather their 4 pixels through the reflected column map, byte by
 // byte, into the same 3-dword form.  `tb` is the tile's first pixel row and
 // dword aligned, as is the stride.
-template <int CT, int CH>
+// AL: every row starts 4-byte aligned; else a group's 12 bytes come from the
+// four aligned words around them, shifted into place
+template <int CT, int CH, bool AL>
 __device__ inline void stage_rgb8(const uint8_t *tb, uint32_t stride, const int32_t *rmap, const int32_t *cmap,
                                   int qx0, int w, int32_t *win)
 {
@@ -711,8 +713,22 @@ __device__ inline void stage_rgb8(const uint8_t *tb, uint32_t stride, const int3
             const uint8_t *row = tb + (uint64_t)rmap[lr] * stride;
             const int p0 = 2 * qx0 - 4 + 4 * g;
             if (p0 >= 0 && p0 + 3 < w) {
-                const uint32_t *p = (const uint32_t *)(row + 3 * p0);
-                d[k][0] = p[0]; d[k][1] = p[1]; d[k][2] = p[2];
+                if (AL) {
+                    const uint32_t *p = (const uint32_t *)(row + 3 * p0);
+                    d[k][0] = p[0]; d[k][1] = p[1]; d[k][2] = p[2];
+                } else {
+                    // the aligned words holding bytes 3 p0 .. 3 p0 + 11 (the
+                    // fourth only when they straddle it: it holds the last
+                    // byte, so it lies in the same page)
+                    const uint8_t *pb = row + 3 * p0;
+                    const uint32_t m = (uint32_t)(uintptr_t)pb & 3u;
+                    const uint32_t *p = (const uint32_t *)(pb - m);
+                    const uint32_t a0 = p[0], a1 = p[1], a2 = p[2];
+                    const uint32_t a3 = m ? p[3] : 0u;
+                    d[k][0] = __builtin_amdgcn_alignbyte(a1, a0, m);
+                    d[k][1] = __builtin_amdgcn_alignbyte(a2, a1, m);
+                    d[k][2] = __builtin_amdgcn_alignbyte(a3, a2, m);
+                }
             } else {
                 uint32_t q[3] = {0, 0, 0};
 #pragma unroll
@@ -783,16 +799,27 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
     if (level == 1) {
         const uint32_t C = T.channels, bps = T.bps;
         const uint8_t *tb = pix + T.pix_offset;
-        const bool fast = bps == 1 && C == 3 && T.ct != 0 && ((((uintptr_t)tb) | T.pix_stride) & 3u) == 0;
-        if (fast) {
+        const bool fast = bps == 1 && C == 3 && T.ct != 0;
+        const bool al = ((((uintptr_t)tb) | T.pix_stride) & 3u) == 0;
+        if (fast && al) {
             if (T.ct == 1) {
-                if (c == 0) stage_rgb8<1, 0>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
-                else if (c == 1) stage_rgb8<1, 1>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
-                else stage_rgb8<1, 2>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                if (c == 0) stage_rgb8<1, 0, true>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else if (c == 1) stage_rgb8<1, 1, true>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else stage_rgb8<1, 2, true>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
             } else {
-                if (c == 0) stage_rgb8<2, 0>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
-                else if (c == 1) stage_rgb8<2, 1>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
-                else stage_rgb8<2, 2>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                if (c == 0) stage_rgb8<2, 0, true>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else if (c == 1) stage_rgb8<2, 1, true>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else stage_rgb8<2, 2, true>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+            }
+        } else if (fast) {
+            if (T.ct == 1) {
+                if (c == 0) stage_rgb8<1, 0, false>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else if (c == 1) stage_rgb8<1, 1, false>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else stage_rgb8<1, 2, false>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+            } else {
+                if (c == 0) stage_rgb8<2, 0, false>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else if (c == 1) stage_rgb8<2, 1, false>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
+                else stage_rgb8<2, 2, false>(tb, T.pix_stride, rmap, cmap, qx0, w, win);
             }
         } else {
             // any format, or a tile at the image border: element by element,
@@ -1290,8 +1317,10 @@ __global__ void __launch_bounds__(256) k_inv_final_strips(PlanHdr H, const uint8
     }
     const uint32_t C = T.channels, bps = T.bps, sb = C * bps;
     const uint64_t rowbase0 = T.pix_offset + (uint64_t)(2 * qx0 - rx0) * sb;
-    const bool staged = nc == (int)C && sb <= 4 && 2 * qx0 >= rx0 &&
-                        ((rowbase0 | T.pix_stride | (uint64_t)(uintptr_t)pix) & 3u) == 0;
+    // rows that do not start 4-byte aligned (odd widths of 1- and 3-byte
+    // pixels) are stored as aligned words assembled from the staged bytes
+    const bool al4 = ((rowbase0 | T.pix_stride | (uint64_t)(uintptr_t)pix) & 3u) == 0;
+    const bool staged = nc == (int)C && (al4 ? sb <= 4 : sb <= 3) && 2 * qx0 >= rx0;
     if (staged) {
         __syncthreads();  // every row pass has read the window
         uint8_t *ob = (uint8_t *)win;  // 64 rows x 64 * sb bytes
@@ -1325,9 +1354,41 @@ __global__ void __launch_bounds__(256) k_inv_final_strips(PlanHdr H, const uint8
                 }
         }
         __syncthreads();
+        const int nbytes = min(64, rx1 - 2 * qx0) * (int)sb;
+        if (!al4) {
+            // a row's bytes [0, nbytes) start at an address m bytes past a
+            // word boundary; aligned word i of the destination holds bytes
+            // 4i - m .. 4i - m + 3, the top m bytes of staged word i - 1 and
+            // the low 4 - m of word i.  16 lanes per row, four words each
+            // (RB <= 192 bytes: at most 49 words).
+            const int k = lane & 15;
+            const int nst = RB / 4;
+#pragma unroll
+            for (int mm = 0; mm < 4; mm++) {
+                const int ly = 4 * (wv + 4 * mm) + (lane >> 4);
+                const int yy = 2 * qy0 + ly;
+                if (yy < ry0 || yy >= ry1) continue;
+                uint8_t *rdst = pix + rowbase0 + (uint64_t)(yy - ry0) * T.pix_stride;
+                const uint32_t m = (uint32_t)(uintptr_t)rdst & 3u;
+                uint32_t *wdst = (uint32_t *)(rdst - m);
+                const uint32_t *ls = (const uint32_t *)(ob + ly * RB);
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int i = 4 * k + e;
+                    const int b0 = 4 * i - (int)m;  // row byte of the word's first byte
+                    if (b0 >= nbytes) break;
+                    const uint32_t lo = i > 0 ? ls[i - 1] : 0u, hi = i < nst ? ls[i] : 0u;
+                    const uint32_t v = m ? __builtin_amdgcn_alignbyte(hi, lo, 4u - m) : hi;
+                    if (b0 >= 0 && b0 + 4 <= nbytes) wdst[i] = v;
+                    else
+                        for (int q = 0; q < 4; q++)
+                            if (b0 + q >= 0 && b0 + q < nbytes) rdst[b0 + q] = (uint8_t)(v >> (8 * q));
+                }
+            }
+            return;
+        }
         // 16-byte pieces: 16 lanes per row, four rows per wave and pass
         const int nq = RB / 16;
-        const int nbytes = min(64, rx1 - 2 * qx0) * (int)sb;
         const bool a16 = ((rowbase0 | T.pix_stride | (uint64_t)(uintptr_t)pix) & 15u) == 0;
         const int k = lane & 15;
 #pragma unroll
