@@ -698,9 +698,11 @@ __device__ inline int32_t rgb_channel(uint32_t R, uint32_t G, uint32_t B)
 // byte, into the same 3-dword form.  `tb` is the tile's first pixel row and
 // dword aligned, as is the stride.
 // AL: every row starts 4-byte aligned; else a group's 12 bytes come from the
-// four aligned words around them, shifted into place
+// four aligned words around them, shifted into place.  Kept out of line: the
+// twelve variants inlined into the kernel make it several times larger and
+// slower (instruction cache).
 template <int CT, int CH, bool AL>
-__device__ inline void stage_rgb8(const uint8_t *tb, uint32_t stride, const int32_t *rmap, const int32_t *cmap,
+__device__ __noinline__ void stage_rgb8(const uint8_t *tb, uint32_t stride, const int32_t *rmap, const int32_t *cmap,
                                   int qx0, int w, int32_t *win)
 {
     constexpr int NG = 18, NT = WN * NG, NK = (NT + 255) / 256;
@@ -915,7 +917,9 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
     const int qx = qx0 + (lane >> 1);
     const bool xin = qx < (odd ? hw : llw);
     const uint32_t step = T.qstep, qmul = T.qmul, qsh = T.qsh;
-    uint32_t or_e = 0, or_o = 0, negs = 0;
+    // OR of the magnitudes per row parity; the OR of the values themselves
+    // has its sign bit set iff one of them is negative
+    uint32_t or_e = 0, or_o = 0, sg_e = 0, sg_o = 0;
     const int qyb = qy0 + 8 * wv;
 #pragma unroll
     for (int j = 0; j < 16; j++) {
@@ -925,17 +929,18 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
             if (step > 1) v = quantise(v, qmul, qsh);
             if (xin && qy < hh) {
                 or_o |= v < 0 ? 0u - (uint32_t)v : (uint32_t)v;
-                negs |= v < 0 ? 2u : 0u;
+                sg_o |= (uint32_t)v;
             }
         } else {
             if (step > 1 && odd) v = quantise(v, qmul, qsh);
             if (xin && qy < llh) {
                 or_e |= v < 0 ? 0u - (uint32_t)v : (uint32_t)v;
-                negs |= v < 0 ? 1u : 0u;
+                sg_e |= (uint32_t)v;
             }
         }
         o[j] = v;
     }
+    uint32_t negs = (sg_e >> 31) | ((sg_o >> 31) << 1);
     // the four 32x32 bands of the tile go through LDS (the window is free
     // once every column pass has read it) and out in 16-byte pieces: a wave
     // stores eight whole band rows per instruction
