@@ -141,6 +141,24 @@ __device__ inline void transpose16(uint32_t (&r)[16])
     }
 }
 
+// The same for two cells at once: each word holds a row of the first cell in
+// its low half and of the second in its high half (the masks keep every
+// exchange inside its half).
+__device__ inline void transpose16x2(uint32_t (&r)[16])
+{
+#pragma unroll
+    for (int s = 8, k = 0; s >= 1; s >>= 1, k++) {
+        const uint32_t m = k == 0 ? 0x00ff00ffu : (k == 1 ? 0x0f0f0f0fu : (k == 2 ? 0x33333333u : 0x55555555u));
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            if (i & s) continue;
+            const uint32_t x = ((r[i] >> s) ^ r[i + s]) & m;
+            r[i + s] ^= x;
+            r[i] ^= x << s;
+        }
+    }
+}
+
 template <int kSymNT>
 __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint8_t *__restrict__ plan,
                                                         uint8_t *__restrict__ ws, uint32_t list0,
@@ -187,8 +205,63 @@ __global__ void __launch_bounds__(kSymNT, 8) k_enc_symbols(PlanHdr H, const uint
     uint8_t *symb = ws + B.sym_off;
     const BlockDesc &Bg = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const bool c16 = Bg.c16 != 0;  // coefficients held as int16
+    // two horizontally adjacent cells per thread where their symbols are
+    // adjacent, 4-byte aligned, in every plane and magnitudes fit 16 bits:
+    // both cells' magnitudes go packed (first cell in the low halves)
+    // through one 16x16 bit transpose and each plane gets one 32-bit store
+    // (int16 blocks only: the int32 rows' loads would not fit the registers)
+    const bool pairs = c16 && (cpt & 1u) == 0 && (wq & 1u) == 0 && (n & 3u) == 0 && d <= 17;
 #pragma unroll 1
-    for (int k = 0; k < kCellsPT; k++) {
+    for (int k = 0; pairs && k < (kCellsPT + 1) / 2; k++) {
+        const uint32_t pr = (uint32_t)k * kSymNT + tid;
+        if (2 * pr >= ncell) break;
+        const uint32_t cell = 2 * pr, t = cell / cpt, ci = cell % cpt;
+        const uint32_t band = ci / wq, cg = ci % wq;
+        const uint32_t r0 = 4 * band, c0 = 4 * cg;
+        const uint32_t tw = Bg.tw[t], th = Bg.th[t];
+        const uint64_t toff = Bg.off[t];
+        const uint32_t tpitch = Bg.pitch[t];
+        uint32_t pw[16], sg = 0;
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            const uint32_t row = r0 + rr;
+            int32_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (row < th && c0 < tw) {
+                const int16_t *src = (const int16_t *)ws + toff + (uint64_t)row * tpitch + c0;
+                if (c0 + 7 < tw && ((toff + (uint64_t)row * tpitch + c0) & 7u) == 0) {
+                    const uint4 q = *(const uint4 *)src;
+                    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        v[2 * e] = (int32_t)(w[e] << 16) >> 16;
+                        v[2 * e + 1] = (int32_t)w[e] >> 16;
+                    }
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < 8; cc++) v[cc] = (c0 + cc < tw) ? src[cc] : 0;
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < 4; cc++) {
+                const int32_t a = v[cc], b = v[4 + cc];
+                pw[rr * 4 + cc] = (uint32_t)(a < 0 ? -a : a) | ((uint32_t)(b < 0 ? -b : b) << 16);
+                sg |= ((a < 0 ? 1u : 0u) | (b < 0 ? 0x10000u : 0u)) << (rr * 4 + cc);
+            }
+        }
+        auto put2 = [&](int b, uint32_t v) {
+            const uint32_t pm = ((pres[0] >> b) & 1u) | (((pres[1] >> b) & 1u) << 1) | (((pres[2] >> b) & 1u) << 2);
+            if (!((pm >> t) & 1u)) return;
+            const uint32_t rank = __popc(pm & ((1u << t) - 1u));
+            *(uint32_t *)(symb + (uint64_t)b * pstr + rank * n + 2 * ci) = v;
+        };
+        put2((int)d - 1, sg);
+        transpose16x2(pw);
+#pragma unroll
+        for (int b = 0; b < 16; b++)
+            if (b + 1 < (int)d) put2(b, pw[b]);
+    }
+#pragma unroll 1
+    for (int k = 0; !pairs && k < kCellsPT; k++) {
         const uint32_t cell = (uint32_t)k * kSymNT + tid;
         if (cell >= ncell) break;
         const uint32_t t = cell / cpt, ci = cell % cpt;
