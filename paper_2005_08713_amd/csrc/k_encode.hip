@@ -1132,6 +1132,7 @@ struct PackShared {
     uint32_t st[kPackStage];
     uint32_t code[256];
     uint8_t len[256];
+    uint8_t cost[256];  // bits of a literal: its code, plus the counter for C_zr
 };
 
 // Item y of block blk: y = 0 the block header, y = 1.. segment y-1.  The
@@ -1221,8 +1222,10 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
     const uint64_t w0 = abit >> 5;
 #pragma unroll
     for (uint32_t k = 0; k < 4; k++) {
-        S.code[lane + 64 * k] = P.code[lane + 64 * k];
-        S.len[lane + 64 * k] = P.len[lane + 64 * k];
+        const uint32_t sy = lane + 64 * k, lv = P.len[sy];
+        S.code[sy] = P.code[sy];
+        S.len[sy] = (uint8_t)lv;
+        S.cost[sy] = (uint8_t)(lv + (sy == czr ? wz : 0u));
     }
     for (uint32_t i = lane; i < kPackStage; i += 64) st[i] = 0;
     const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride(P.p * P.n);
@@ -1289,7 +1292,7 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
                     }
                     bits += L == 1 ? lit0 : nd * tokz;
                 }
-                if (nz) bits += S.len[v] + (v == czr ? wz : 0u);
+                if (nz) bits += S.cost[v];
                 c = nz ? ps : c;
             }
         }
