@@ -349,6 +349,8 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     // total_slots bounds the segment count.
     H.seg_nw = mode == MODE_DECODE && total_slots <= 4ull * H.num_cus ? 4u : 2u;
     if (tune && tune->seg_wave_group) H.seg_nw = (uint32_t)tune->seg_wave_group;
+    // the packer likewise: four waves per segment when there are few
+    H.pack_nw = mode == MODE_ENCODE && total_slots <= 4ull * H.num_cus ? 4u : 1u;
     // Large segments are queued first.  With two waves per workgroup they
     // are the ones that a lone wave's half of the LDS could not stage (the
     // small ones are decoded a wave each); a whole-block item must fit the

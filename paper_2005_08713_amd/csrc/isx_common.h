@@ -104,7 +104,7 @@ struct PlanHdr {
     uint32_t seg_nw;            // segment decoder: waves per workgroup (1, 2 or 4)
     uint32_t seg_big_bits;      // segment decoder: a segment of at least this many bits is a large item
     uint32_t seg_whole_words;   // segment decoder: staging words of a whole-block item (0 = none)
-    uint32_t pad3;
+    uint32_t pack_nw;           // packer: waves per item (1, or 4 for plans of few segments)
     uint64_t list_off;      // plan offset of the block list (u32): large blocks, then small ones
     uint32_t n_big, n_small;  // blocks with > 768 4x4 cells / with <= 768
 };

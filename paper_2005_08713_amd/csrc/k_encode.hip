@@ -1058,12 +1058,15 @@ __global__ void __launch_bounds__(256) k_enc_tile_finish(PlanHdr H, const uint8_
 }
 
 // ---------------------------------------------------------------- pack
-// One wave per item (a block header, or one segment).  A segment is packed
-// in rounds of 512 symbols, 8 per lane: the lanes' token bits are counted,
-// scanned across the wave, written into a staging area in LDS, and the
+// One workgroup per item (a block header, or one segment).  A segment is
+// packed in rounds of 8 symbols per lane: the lanes' token bits are counted,
+// scanned across the lanes, written into a staging area in LDS, and the
 // round's complete words are stored to the stream; the last, partial word
-// is carried into the next round.  No workgroup barriers, no block scans:
-// the per-item cost of small segments is one wave's.
+// is carried into the next round.  The throughput form is one wave per item
+// (rounds of 512 symbols, scans within the wave: the per-item cost of small
+// segments is one wave's); a plan of few segments (one small tile) packs
+// each with four waves (rounds of 2048 symbols, the waves' totals combined
+// through LDS), so that its longest segment takes a quarter of the rounds.
 constexpr uint32_t kPackK = 8;                    // symbols per lane and round
 constexpr uint32_t kPackRound = 64 * kPackK;      // symbols per round
 // Staging words of one round.  Per symbol at most one literal token (a code
@@ -1071,7 +1074,8 @@ constexpr uint32_t kPackRound = 64 * kPackK;      // symbols per round
 // is emitted at its end, at most 45 bits per two of its symbols, except the
 // run that began in an earlier round (at most 8 digit tokens for runs of at
 // most 6144 zeros); plus the carried partial word and the put's second word.
-constexpr uint32_t kPackStage = (kPackRound * 45 + 8 * 45 + 31) / 32 + 3;
+// Rounds of nw waves take nw times the symbols.
+constexpr uint32_t pack_stage(int nw) { return (kPackRound * (uint32_t)nw * 45 + 8 * 45 + 31) / 32 + 3; }
 
 __device__ inline void put_bits(uint32_t *st, uint32_t pos, uint32_t val, uint32_t nb)
 {
@@ -1089,9 +1093,9 @@ __device__ inline void put_bits(uint32_t *st, uint32_t pos, uint32_t val, uint32
 // are shared with the neighbouring region and ORed in; every other word
 // belongs to this item alone.
 __device__ inline void store_words(const uint32_t *st, uint32_t n, uint64_t w0, bool first_shared,
-                                   uint32_t last_shared, uint32_t *outw)
+                                   uint32_t last_shared, uint32_t *outw, uint32_t nt = 64)
 {
-    for (uint32_t i = threadIdx.x; i < n; i += 64) {
+    for (uint32_t i = threadIdx.x; i < n; i += nt) {
         const uint32_t v = st[i];
         if ((i == 0 && first_shared) || i == last_shared) {
             if (v) atomicOr(&outw[w0 + i], __builtin_bswap32(v));
@@ -1128,22 +1132,74 @@ __device__ inline int32_t wave_excl_max(int32_t v, int32_t &total)
     return lane == 0 ? INT32_MIN : ex;
 }
 
+template <int NW>
 struct PackShared {
-    uint32_t st[kPackStage];
+    uint32_t st[pack_stage(NW)];
     uint32_t code[256];
     uint8_t len[256];
     uint8_t cost[256];  // bits of a literal: its code, plus the counter for C_zr
+    int32_t wmax[NW];   // per wave: its last non-zero position (NW > 1)
+    uint32_t wsum[NW];  // per wave: its token bits (NW > 1)
 };
+
+// Exclusive max / sum over the NW waves' lanes in thread order, and the
+// total; for NW > 1 through LDS at a barrier that every thread reaches.
+template <int NW>
+__device__ inline int32_t group_excl_max(int32_t v, int32_t &total, int32_t *sh)
+{
+    int32_t wt;
+    const int32_t ex = wave_excl_max(v, wt);
+    if (NW == 1) {
+        total = wt;
+        return ex;
+    }
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = wt;
+    __syncthreads();
+    int32_t before = INT32_MIN, all = INT32_MIN;
+#pragma unroll
+    for (int w = 0; w < NW; w++) {
+        const int32_t x = sh[w];
+        if ((uint32_t)w < wave) before = max(before, x);
+        all = max(all, x);
+    }
+    total = all;
+    return max(before, ex);
+}
+template <int NW>
+__device__ inline uint32_t group_excl_sum(uint32_t v, uint32_t &total, uint32_t *sh)
+{
+    uint32_t wt;
+    const uint32_t ex = wave_excl_sum(v, wt);
+    if (NW == 1) {
+        total = wt;
+        return ex;
+    }
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = wt;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) {
+        const uint32_t x = sh[w];
+        if ((uint32_t)w < wave) before += x;
+        all += x;
+    }
+    total = all;
+    return before + ex;
+}
 
 // Item y of block blk: y = 0 the block header, y = 1.. segment y-1.  The
 // longest items (the last segments: low, dense planes) come first in the
 // grid, the headers last.
-__global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__restrict__ ws,
-                                                 uint8_t *__restrict__ out)
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_enc_pack(PlanHdr H, const uint8_t *__restrict__ ws,
+                                                      uint8_t *__restrict__ out)
 {
-    __shared__ PackShared S;
+    constexpr uint32_t NT = 64 * NW;
+    __shared__ PackShared<NW> S;
     const uint32_t blk = blockIdx.x, y = gridDim.y - 1u - blockIdx.y;
-    const uint32_t lane = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const BlockDesc &B = ((const BlockDesc *)(ws + H.ws_blockdesc))[blk];
     const BlkPlan &P = ((const BlkPlan *)(ws + H.ws_blkplan))[blk];
     const uint32_t nseg = __builtin_amdgcn_readfirstlane(P.nseg);
@@ -1158,10 +1214,10 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
         // header: d | masks | C_zr | wz | tree | seek table (Fig. 3)
         const uint32_t o = (uint32_t)(bit0 & 31u);
         const uint32_t nw = (o + hdr_bits + 31) >> 5;
-        for (uint32_t i = lane; i < nw + 1; i += 64) st[i] = 0;
+        for (uint32_t i = tid; i < nw + 1; i += NT) st[i] = 0;
         __syncthreads();
         const uint32_t d = P.d, p = P.p;
-        if (lane == 0) {
+        if (tid == 0) {
             put_bits(st, o, d, 5);
             for (uint32_t t = 0; t < p; t++) put_bits(st, o + 5 + t * d, P.masks[t], d);
             if (nseg) {
@@ -1169,7 +1225,7 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
                 put_bits(st, o + 13 + p * d, P.wz, 4);
             }
         }
-        if (nseg) {
+        if (nseg && wave == 0) {
             // pre-order tree: leaf j (canonical order) is preceded by zj
             // internal-node zeros; lane takes leaves 4 lane .. 4 lane + 3
             const uint32_t tree0 = o + 17 + p * d;
@@ -1204,7 +1260,7 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
         }
         __syncthreads();
         const uint32_t tail = ((o + hdr_bits) & 31u) ? nw - 1 : ~0u;
-        store_words(st, nw, bit0 >> 5, o != 0, tail, outw);
+        store_words(st, nw, bit0 >> 5, o != 0, tail, outw, NT);
         return;
     }
     // segment s = y-1: it starts after the header and segments 0 .. s-1
@@ -1221,13 +1277,13 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
     const uint32_t o = (uint32_t)(abit & 31u);
     const uint64_t w0 = abit >> 5;
 #pragma unroll
-    for (uint32_t k = 0; k < 4; k++) {
-        const uint32_t sy = lane + 64 * k, lv = P.len[sy];
+    for (uint32_t k = 0; k < 256 / NT; k++) {
+        const uint32_t sy = tid + NT * k, lv = P.len[sy];
         S.code[sy] = P.code[sy];
         S.len[sy] = (uint8_t)lv;
         S.cost[sy] = (uint8_t)(lv + (sy == czr ? wz : 0u));
     }
-    for (uint32_t i = lane; i < kPackStage; i += 64) st[i] = 0;
+    for (uint32_t i = tid; i < pack_stage(NW); i += NT) st[i] = 0;
     const uint8_t *syms = ws + B.sym_off + (uint64_t)P.seg_plane[s] * plane_stride(P.p * P.n);
     __syncthreads();
     const uint32_t Bb = (1u << wz) - 1u;
@@ -1250,8 +1306,8 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
     int32_t cur = -1;     // position of the last non-zero symbol before the round
     uint32_t bp = o;      // bit position of the round's first token in the staging
     uint64_t wdone = 0;   // stream words stored so far (staging word 0 = stream word w0 + wdone)
-    for (uint32_t r0 = 0; r0 < M; r0 += kPackRound) {
-        const uint32_t lo = r0 + kPackK * lane;
+    for (uint32_t r0 = 0; r0 < M; r0 += kPackRound * NW) {
+        const uint32_t lo = r0 + kPackK * tid;
         const uint32_t hi = min(lo + kPackK, M);
         // 8 symbols of the lane (the plane stride is a multiple of 16 bytes,
         // so the 8-byte load stays in the plane); symbols >= hi read as 0
@@ -1267,7 +1323,7 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
         if (q.y) lastnz = (int32_t)(lo + 4 + (31u - (uint32_t)__builtin_clz(q.y)) / 8u);
         else if (q.x) lastnz = (int32_t)(lo + (31u - (uint32_t)__builtin_clz(q.x)) / 8u);
         int32_t mx;
-        const int32_t prev = max(cur, wave_excl_max(lastnz, mx));
+        const int32_t prev = max(cur, group_excl_max<NW>(lastnz, mx, S.wmax));
 #define LOC(i) ((((i) < 4 ? q.x : q.y) >> (8 * ((i) & 3))) & 0xffu)
         // token bits: a symbol that ends a zero run (non-zero, or the
         // segment's last) emits the run (one zero literal for length 1, else
@@ -1297,7 +1353,7 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
             }
         }
         uint32_t rbits;
-        const uint32_t off = wave_excl_sum(bits, rbits);
+        const uint32_t off = group_excl_sum<NW>(bits, rbits, S.wsum);
         {
             uint32_t b = bp + off;
             int32_t c = prev;
@@ -1333,20 +1389,20 @@ __global__ void __launch_bounds__(64) k_enc_pack(PlanHdr H, const uint8_t *__res
         // the round's complete words go out; the partial one is carried
         const uint32_t end = bp + rbits;
         const uint32_t nfull = end >> 5;
-        store_words(st, nfull, w0 + wdone, wdone == 0 && o != 0, ~0u, outw);
+        store_words(st, nfull, w0 + wdone, wdone == 0 && o != 0, ~0u, outw, NT);
         __syncthreads();
         const uint32_t carry = st[nfull];
         const uint32_t used = (end + 63) >> 5;  // words the round may have touched
-        for (uint32_t i = lane; i < used; i += 64) st[i] = 0;
+        for (uint32_t i = tid; i < used; i += NT) st[i] = 0;
         __syncthreads();
-        if (lane == 0) st[0] = carry;
+        if (tid == 0) st[0] = carry;
         __syncthreads();
         bp = end & 31u;
         wdone += nfull;
         cur = max(cur, mx);
     }
     // the segment's last, partial word is shared with what follows it
-    if (bp && lane == 0 && st[0]) atomicOr(&outw[w0 + wdone], __builtin_bswap32(st[0]));
+    if (bp && tid == 0 && st[0]) atomicOr(&outw[w0 + wdone], __builtin_bswap32(st[0]));
 }
 
 // ---------------------------------------------------------------- launch
@@ -1397,8 +1453,11 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
                                d_plan, d_ws, d_out);
         } else if (st == ENC_PACK) {
             // item y = 0 is the header, y = 1 .. nseg the segments; nseg <= d <= the tile's plane bound
-            if (H.total_blocks)
-                hipLaunchKernelGGL(k_enc_pack, dim3(H.total_blocks, H.max_dmax + 1), dim3(64), 0, stream, H, d_ws,
+            if (H.total_blocks && H.pack_nw == 4)
+                hipLaunchKernelGGL(k_enc_pack<4>, dim3(H.total_blocks, H.max_dmax + 1), dim3(256), 0, stream, H, d_ws,
+                                   d_out);
+            else if (H.total_blocks)
+                hipLaunchKernelGGL(k_enc_pack<1>, dim3(H.total_blocks, H.max_dmax + 1), dim3(64), 0, stream, H, d_ws,
                                    d_out);
         }
     }
