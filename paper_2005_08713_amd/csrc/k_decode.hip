@@ -1456,16 +1456,23 @@ hipError_t launch_decode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
                                        dim3(64), 0, stream, H, d_encoded, d_ws, d_status);
             }
         } else if (st == DEC_REASM) {
-            if (H.n_big) {
-                const uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(H.n_big, H.num_cus * H.blocks_per_cu) : H.n_big;
-                hipLaunchKernelGGL(k_dec_reasm<1024>, dim3(g), dim3(1024), 0, stream, H, d_plan, d_ws, d_status, 0u,
-                                   H.n_big);
-            }
-            if (H.n_small) {
-                const uint32_t g =
-                    H.blocks_per_cu ? std::min<uint32_t>(H.n_small, H.num_cus * H.blocks_per_cu * 4) : H.n_small;
-                hipLaunchKernelGGL(k_dec_reasm<256>, dim3(g), dim3(256), 0, stream, H, d_plan, d_ws, d_status, H.n_big,
-                                   H.n_small);
+            if (H.seg_nw == 4 && H.n_big + H.n_small) {
+                // a plan of few blocks: all of them in one launch
+                hipLaunchKernelGGL(k_dec_reasm<1024>, dim3(H.n_big + H.n_small), dim3(1024), 0, stream, H, d_plan, d_ws,
+                                   d_status, 0u, H.n_big + H.n_small);
+            } else {
+                if (H.n_big) {
+                    const uint32_t g =
+                        H.blocks_per_cu ? std::min<uint32_t>(H.n_big, H.num_cus * H.blocks_per_cu) : H.n_big;
+                    hipLaunchKernelGGL(k_dec_reasm<1024>, dim3(g), dim3(1024), 0, stream, H, d_plan, d_ws, d_status,
+                                       0u, H.n_big);
+                }
+                if (H.n_small) {
+                    const uint32_t g =
+                        H.blocks_per_cu ? std::min<uint32_t>(H.n_small, H.num_cus * H.blocks_per_cu * 4) : H.n_small;
+                    hipLaunchKernelGGL(k_dec_reasm<256>, dim3(g), dim3(256), 0, stream, H, d_plan, d_ws, d_status,
+                                       H.n_big, H.n_small);
+                }
             }
         } else if (st >= DEC_INV15 && st <= DEC_FINAL) {
             int level = DEC_FINAL - st;  // 15..1, then 0 = final stage

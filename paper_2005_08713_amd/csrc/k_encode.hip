@@ -1433,13 +1433,23 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
             hipError_t e = launch_forward_level(H, d_plan, d_pixels, d_ws, st - ENC_FWD0, stream);
             if (e != hipSuccess) return e;
         } else if (st == ENC_SYM) {
-            if (H.n_big) {
-                uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(H.n_big, H.num_cus * H.blocks_per_cu) : H.n_big;
-                hipLaunchKernelGGL(k_enc_symbols<1024>, dim3(g), dim3(1024), 0, stream, H, d_plan, d_ws, 0u, H.n_big);
-            }
-            if (H.n_small) {
-                uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(H.n_small, H.num_cus * H.blocks_per_cu * 4) : H.n_small;
-                hipLaunchKernelGGL(k_enc_symbols<256>, dim3(g), dim3(256), 0, stream, H, d_plan, d_ws, H.n_big, H.n_small);
+            if (H.pack_nw == 4 && H.n_big + H.n_small) {
+                // a plan of few blocks: all of them in one launch (a second
+                // launch for the small blocks would add its whole latency)
+                hipLaunchKernelGGL(k_enc_symbols<1024>, dim3(H.n_big + H.n_small), dim3(1024), 0, stream, H, d_plan,
+                                   d_ws, 0u, H.n_big + H.n_small);
+            } else {
+                if (H.n_big) {
+                    uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(H.n_big, H.num_cus * H.blocks_per_cu) : H.n_big;
+                    hipLaunchKernelGGL(k_enc_symbols<1024>, dim3(g), dim3(1024), 0, stream, H, d_plan, d_ws, 0u,
+                                       H.n_big);
+                }
+                if (H.n_small) {
+                    uint32_t g =
+                        H.blocks_per_cu ? std::min<uint32_t>(H.n_small, H.num_cus * H.blocks_per_cu * 4) : H.n_small;
+                    hipLaunchKernelGGL(k_enc_symbols<256>, dim3(g), dim3(256), 0, stream, H, d_plan, d_ws, H.n_big,
+                                       H.n_small);
+                }
             }
         } else if (st == ENC_CODE) {
             if (H.total_blocks) hipLaunchKernelGGL(k_enc_code, dim3(H.blk_grid), dim3(64), 0, stream, H, d_ws);
