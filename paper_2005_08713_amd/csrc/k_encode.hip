@@ -786,7 +786,38 @@ __device__ void seg_lengths(CodeShared &C, const uint16_t *seghist, uint32_t slo
         cost[j] = C.len[s] + (s == czr ? wz : 0u);
     }
     const uint32_t zcost = C.len[czr] + wz;
-    for (uint32_t sg = 0; sg < nseg; sg++) {
+    uint32_t sg = 0;
+    // four segments at a time: their 16 histogram loads in flight together,
+    // their four wave sums interleaved
+    for (; sg + 4 <= nseg; sg += 4) {
+        uint32_t cnt[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint16_t *h = seghist + (uint64_t)(slot + C.plane[sg + u]) * 256;
+#pragma unroll
+            for (int j = 0; j < 4; j++) cnt[u][j] = h[j * 64 + lane];
+        }
+        uint32_t add[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            add[u] = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                uint32_t c = cnt[u][j];
+                if (j == 0 && lane == 0) c -= C.zir[sg + u];
+                add[u] += c * cost[j];
+            }
+            if (lane == 0) add[u] += C.dig[sg + u][wz - 2] * zcost;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+            for (int u = 0; u < 4; u++) add[u] += __shfl_xor(add[u], o, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int u = 0; u < 4; u++) C.segbits[sg + u] = add[u];
+    }
+    for (; sg < nseg; sg++) {
         const uint16_t *h = seghist + (uint64_t)(slot + C.plane[sg]) * 256;
         uint32_t add = 0;
 #pragma unroll
@@ -840,10 +871,27 @@ __global__ void __launch_bounds__(64) k_enc_code(PlanHdr H, uint8_t *__restrict_
     }
     // block histogram
     uint32_t h[4] = {0, 0, 0, 0};
-    for (uint32_t sg = 0; sg < nseg; sg++) {
-        const uint16_t *hs = seghist + (uint64_t)(slot + C.plane[sg]) * 256;
+    {
+        // four segments' loads in flight at a time
+        uint32_t sg = 0;
+        for (; sg + 4 <= nseg; sg += 4) {
+            uint32_t v[4][4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) h[j] += hs[j * 64 + lane];
+            for (int u = 0; u < 4; u++) {
+                const uint16_t *hs = seghist + (uint64_t)(slot + C.plane[sg + u]) * 256;
+#pragma unroll
+                for (int j = 0; j < 4; j++) v[u][j] = hs[j * 64 + lane];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) h[j] += v[u][j];
+        }
+        for (; sg < nseg; sg++) {
+            const uint16_t *hs = seghist + (uint64_t)(slot + C.plane[sg]) * 256;
+#pragma unroll
+            for (int j = 0; j < 4; j++) h[j] += hs[j * 64 + lane];
+        }
     }
     wave_sync();
     uint32_t Z = 0;
