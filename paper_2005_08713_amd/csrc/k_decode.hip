@@ -764,10 +764,9 @@ constexpr uint32_t kSyncWin = 128, kSyncWin2 = 384;
 // lanes gives each lane its output position and pending run; phase 3 decodes
 // again and writes the non-zero symbols into a zeroed copy of the plane in
 // LDS (runs write nothing), which the workgroup then stores to the plane
-// with whole-line 16-byte stores.  One wave (NW = 1) is the throughput form;
-// more waves per segment shorten a lone segment's decode (the latency form):
-// the lanes' chunks halve, and the waves exchange their edge values through
-// LDS at barriers.
+// with whole-line 16-byte stores.  More waves per segment (NW = 2 or 4)
+// shorten a segment's decode: the lanes' chunks halve or quarter, and the
+// waves exchange their edge values through LDS at barriers.
 
 // workgroup-wide hand-over between lanes: a wave's own LDS order, or a barrier
 template <int NW>
@@ -1087,13 +1086,13 @@ __device__ __forceinline__ void dec_item(const PlanHdr &H, const uint8_t *__rest
 }
 
 // Persistent workgroups of NW waves taking (block, segment) items from the
-// two lists (large segments first).  One wave (NW = 1) is the throughput form
-// for plans of many small segments: 14.5 KB of LDS per wave, eleven waves per
-// CU.  Two waves share 14.5 KB for a large segment and decode it together;
-// once the large list is drained each of them takes small items on its own
-// in half of the workgroup's LDS (20 KB per workgroup: eight per CU, sixteen
-// waves, as many as their registers allow).  Four waves decode every item
-// together (the latency form for plans of few segments).
+// two lists (large segments first).  The default form (NW = 2): two waves
+// share 14.5 KB for a large segment and decode it together; once the large
+// list is drained each of them takes small items on its own in half of the
+// workgroup's LDS (20 KB per workgroup: eight per CU, sixteen waves, as many
+// as their registers allow).  NW = 4: four waves decode every item together
+// (the latency form for plans of few segments).  NW = 1: one wave per item,
+// 14.5 KB of LDS each, eleven per CU (selectable by the launch tuning).
 template <int NW>
 __global__ void __launch_bounds__(64 * NW, NW == 2 ? 4 : 1) k_dec_segments(PlanHdr H, const uint8_t *__restrict__ enc,
                                                           uint8_t *__restrict__ ws,
