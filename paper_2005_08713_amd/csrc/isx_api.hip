@@ -31,6 +31,19 @@ int validate_desc(const isx_tile_desc &d)
     return ISX_OK;
 }
 
+// Magnitude bound of level l's high-pass outputs (the recursion below).
+double highpass_bound(uint32_t bits, uint32_t level)
+{
+    const double M0 = (double)((1u << bits) - 1);
+    double A = M0, e = 0.0, h = 0.0;
+    for (uint32_t l = 1; l <= level; l++) {
+        h = 4.0 * A + 2.0;
+        e = 2.25 * e + 2.5;
+        A = 2.9584 * M0 + e;
+    }
+    return h;
+}
+
 // Upper bound of the number of bitplanes d of any block (1 + bit length of
 // the largest coefficient magnitude).  With M0 = 2^bits - 1 bounding every
 // colour-transformed sample: the integer LL of level l stays within
@@ -380,16 +393,21 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
     H.ws_tileout = o; o = al(o + (uint64_t)n * sizeof(TileOut));
     for (int32_t i = 0; i < n; i++) {
         TileGeo &T = tb[i].g;
-        // The level-1 LH, HL and HH bands (three quarters of the coefficients)
-        // are held as int16 by the strip kernels when every value fits: an
-        // encode's quantised level-1 outputs are at most 4 (2^bits - 1) + 2 in
-        // magnitude (the high-pass step of the bit-depth bound), and a decode's
-        // dequantised ones at most (2^(dmax-1) - 1) step + step/2, since the
-        // decoder rejects a block deeper than dmax planes.
+        // The LH, HL and HH bands of levels 1 and 2 (fifteen sixteenths of the
+        // coefficients) are held as int16 by the strip kernels when every
+        // value fits (bit l-1 of coef16 for level l): an encode's quantised
+        // level-l outputs are within the high-pass bound of the bit-depth
+        // recursion (level 1: 4 (2^bits - 1) + 2), and a decode's
+        // dequantised ones within (2^(dmax-1) - 1) step + step/2 at every
+        // level, since the decoder rejects a block deeper than dmax planes.
         T.coef16 = 0;
         if (H.tq == 32 && !P.wide_coeffs) {
-            if (mode == MODE_ENCODE) T.coef16 = T.bits <= 13;
-            else T.coef16 = ((1ull << (T.dmax - 1)) - 1) * T.qstep + T.qstep / 2 <= 32767u;
+            for (uint32_t l = 1; l <= 2 && l <= T.levels; l++) {
+                const bool fits = mode == MODE_ENCODE
+                                      ? highpass_bound(T.bits, l) <= 32767.0
+                                      : ((1ull << (T.dmax - 1)) - 1) * T.qstep + T.qstep / 2 <= 32767u;
+                if (fits) T.coef16 |= (uint8_t)(1u << (l - 1));
+            }
         }
         uint64_t base = o / 4;  // int32 elements
         T.ll_off += base;

@@ -40,7 +40,7 @@ struct TileGeo {
     uint32_t width, height;
     uint8_t channels, bps, bits, levels;
     uint8_t ct, target_level, dmax, first_level;  // first_level: lowest level reconstructed
-    uint8_t coef16;        // level-1 LH, HL, HH held as int16 in their (int32-sized) arena regions
+    uint8_t coef16;        // bit l-1: level l's LH, HL, HH held as int16 in their (int32-sized) arena regions (l <= 2)
     uint8_t pad8[3];
     uint32_t qstep;
     uint32_t qmul, qsh;    // n / qstep = (t + ((n - t) >> 1)) >> qsh, t = mulhi(qmul, n), for qstep > 1
@@ -248,15 +248,16 @@ __host__ __device__ inline void block_geometry(const TileGeo &T, uint32_t local,
     B.wb = (uint16_t)round4(cw); B.hb = (uint16_t)round4(ch);
     uint32_t tw[3] = {cw, (uint32_t)hwc, (uint32_t)hwc};
     uint32_t th[3] = {(uint32_t)hhc, ch, (uint32_t)hhc};
+    const bool c16 = l <= 2 && ((T.coef16 >> (l - 1)) & 1u);  // the level's bands held as int16
     for (int t = 0; t < 3; t++) {
         B.tw[t] = (uint8_t)(tw[t] >= 128 ? 128 : tw[t]);
         B.th[t] = (uint8_t)(th[t] >= 128 ? 128 : th[t]);
         B.pitch[t] = G.pitch[t];
         const uint64_t band = G.off[t] + (uint64_t)c * T.chan_elems;  // int32 elements
         const uint64_t org = (uint64_t)(by * kBlock - G.wy0) * G.pitch[t] + (bx * kBlock - G.wx0);
-        B.off[t] = (l == 1 && T.coef16) ? 2 * band + org : band + org;
+        B.off[t] = c16 ? 2 * band + org : band + org;
     }
-    B.c16 = (l == 1 && T.coef16) ? 1 : 0;
+    B.c16 = c16 ? 1 : 0;
 }
 
 // The 8 XCDs of the chip receive a launch's workgroups round-robin, and each

@@ -958,7 +958,7 @@ __global__ void __launch_bounds__(256) k_fwd_strips(PlanHdr H, const uint8_t *__
                                   wsi + G.off[2] + (uint64_t)c * T.chan_elems};
         const uint32_t bpitch[4] = {llpitch, G.pitch[1], G.pitch[0], G.pitch[2]};
         const int bw[4] = {llw, hw, llw, hw}, bh[4] = {llh, llh, hh, hh};
-        const bool b16 = level == 1 && T.coef16;  // the H bands of level 1 as int16
+        const bool b16 = level <= 2 && ((T.coef16 >> (level - 1)) & 1u);  // the level's H bands as int16
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const int b = k;  // band of this pass: thread t stores row t >> 3, piece t & 7
@@ -1199,7 +1199,7 @@ __global__ void __launch_bounds__(256) k_inv_level_strips(PlanHdr H, const uint8
     int32_t o[16];
     {
         InvLoad L;
-        inv_strips_load(T, level, c, rmap, cmap, wsi, lane, wv, false, L);
+        inv_strips_load(T, level, c, rmap, cmap, wsi, lane, wv, level <= 2 && ((T.coef16 >> (level - 1)) & 1u), L);
         inv_strips_cols(L, win, lane, wv, G.h > 1);
     }
     __syncthreads();
@@ -1286,7 +1286,7 @@ __global__ void __launch_bounds__(256) k_inv_final_strips(PlanHdr H, const uint8
     const int xs = 2 * qx0 + 16 * wv;  // its first output column
     int32_t v[3][16];
     InvLoad L;  // the coefficients of the channel the window takes next
-    const bool b16 = z == 0 && T.coef16;
+    const bool b16 = z < 2 && ((T.coef16 >> z) & 1u);  // level z + 1's H bands as int16
     if (fused) inv_strips_load(T, z + 1, c0, rmap, cmap, wsi, lane, wv, b16, L);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
