@@ -114,8 +114,9 @@ def random_image(width: int, height: int, channels: int, bits: int,
     """Adversarial / generic test images of any bit depth.
 
     kind: 'uniform' (iid uniform over [0, 2^bits)), 'const', 'max'
-    (all samples 2^bits-1), 'checker' (alternating 0 / max), 'ramp',
-    'sparse' (mostly zero with a few random samples).
+    (all samples 2^bits-1), 'checker' (alternating 0 / max), 'checker2'
+    (2x2 squares alternating 0 / max, channel k shifted by k squares),
+    'ramp', 'sparse' (mostly zero with a few random samples).
     Returns uint8 for bits <= 8, uint16 for bits <= 16, else uint32; shape (h, w, c).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -131,6 +132,9 @@ def random_image(width: int, height: int, channels: int, bits: int,
     elif kind == "checker":
         yy, xx = np.mgrid[0:height, 0:width]
         a = np.repeat((((yy + xx) & 1) * top)[..., None], channels, axis=2)
+    elif kind == "checker2":
+        yy, xx = np.mgrid[0:height, 0:width]
+        a = np.stack([(((yy >> 1) + (xx >> 1) + k) & 1) * top for k in range(channels)], axis=2)
     elif kind == "ramp":
         yy, xx = np.mgrid[0:height, 0:width]
         a = np.repeat(((yy * 7 + xx * 3) % (top + 1))[..., None], channels, axis=2)

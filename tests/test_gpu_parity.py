@@ -325,15 +325,20 @@ def _check_everything(case):
     # encode side: level-1 bands are held as int16 up to 13 significant bits
     (96, 80, 3, 13, 2, 1, "checker"), (96, 80, 1, 13, 3, 1, "max"), (96, 80, 3, 14, 2, 1, "checker"),
     (70, 66, 1, 14, 3, 1, "max"),
+    # level-2 bands: int16 up to 11 significant bits (2x2 checkers give the
+    # largest level-2 coefficients), int32 from 12
+    (96, 80, 3, 11, 3, 1, "checker2"), (96, 80, 1, 11, 3, 1, "checker2"), (96, 80, 3, 12, 3, 1, "checker2"),
+    (70, 66, 1, 12, 3, 1, "checker2"),
     # decode side: 8-bit, 5 levels (plane bound 13): int16 up to step 8, int32 from step 9
     (160, 144, 3, 8, 5, 7, "checker"), (160, 144, 3, 8, 5, 8, "checker"), (160, 144, 3, 8, 5, 9, "checker"),
     (150, 130, 3, 8, 5, 8, "uniform"),
 ], ids=lambda c: "x".join(map(str, c)))
 def test_int16_band_bounds_match_oracle(case):
-    """Both sides of the int16 level-1 band rule: images with the largest
-    level-1 coefficients the bit depth allows (checkerboards, alternating
-    extremes) and steps on both sides of the decoder's dequantisation bound,
-    encoded and decoded at every level against the oracle."""
+    """Both sides of the int16 band rules of levels 1 and 2: images with the
+    largest level-1 or level-2 coefficients the bit depth allows
+    (checkerboards, alternating extremes) and steps on both sides of the
+    decoder's dequantisation bound, encoded and decoded at every level
+    against the oracle."""
     w, h, c, bits, lv, q, kind = case
     img = _img(case, 3)
     print("int16 bound", case, flush=True)
