@@ -476,27 +476,17 @@ int build_plan(int mode, const isx_tile_desc *descs, const isx_decode_job *jobs,
         H.fin_count = (uint32_t)items.size() - H.fin_first;
         H.fin_wgs = wg;
     }
-    // block lists by size class (symbol kernel launch shape); an encode
-    // lists the level-1 blocks of each class first, so that their symbols can
-    // be gathered while the upper forward levels run
+    // block lists by size class (symbol kernel launch shape)
     std::vector<uint32_t> &big = tls_big, &small = tls_small;
     big.clear();
     small.clear();
-    const int npass = mode == MODE_ENCODE ? 2 : 1;
-    for (int pass = 0; pass < npass; pass++) {
-        for (int32_t i = 0; i < n; i++) {
-            const TileGeo &T = tb[i].g;
-            for (uint32_t b = 0; b < T.nblocks; b++) {
-                BlockDesc B;
-                block_geometry(T, tb[i].sel.empty() ? b : tb[i].sel[b].local, B);
-                if (npass == 2 && (B.level == 1) != (pass == 0)) continue;
-                uint32_t cells = (uint32_t)B.p * B.wb * B.hb / 16;
-                (cells > 768 ? big : small).push_back(T.block_base + b);
-            }
-        }
-        if (pass == 0 && npass == 2) {
-            H.n_big_l1 = (uint32_t)big.size();
-            H.n_small_l1 = (uint32_t)small.size();
+    for (int32_t i = 0; i < n; i++) {
+        const TileGeo &T = tb[i].g;
+        for (uint32_t b = 0; b < T.nblocks; b++) {
+            BlockDesc B;
+            block_geometry(T, tb[i].sel.empty() ? b : tb[i].sel[b].local, B);
+            uint32_t cells = (uint32_t)B.p * B.wb * B.hb / 16;
+            (cells > 768 ? big : small).push_back(T.block_base + b);
         }
     }
     H.n_big = (uint32_t)big.size();

@@ -107,7 +107,6 @@ struct PlanHdr {
     uint32_t pack_nw;           // packer: waves per item (1, or 4 for plans of few segments)
     uint64_t list_off;      // plan offset of the block list (u32): large blocks, then small ones
     uint32_t n_big, n_small;  // blocks with > 768 4x4 cells / with <= 768
-    uint32_t n_big_l1, n_small_l1;  // encode: level-1 blocks, listed first in each class
 };
 
 struct BlockDesc {

@@ -19,7 +19,6 @@
 //                 an LDS window, written once to the final position in HBM.
 // Per tile: block offsets (scan), tile offsets (scan), tile header.
 #include <algorithm>
-#include <mutex>
 
 #include "isx_common.h"
 
@@ -1465,60 +1464,6 @@ hipError_t launch_forward_only(const PlanHdr &H, const uint8_t *d_plan, const ui
                          ENC_PREP, ENC_FWD0 + kMaxLevels);
 }
 
-// The symbol kernel over list ranges of the two block classes: [b0, b1) of
-// the large blocks, [s0, s1) of the small ones (indices into each class).
-static void launch_symbols(const PlanHdr &H, const uint8_t *d_plan, uint8_t *d_ws, hipStream_t stream, uint32_t b0,
-                           uint32_t b1, uint32_t s0, uint32_t s1)
-{
-    if (b1 > b0) {
-        const uint32_t n = b1 - b0;
-        const uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(n, H.num_cus * H.blocks_per_cu) : n;
-        hipLaunchKernelGGL(k_enc_symbols<1024>, dim3(g), dim3(1024), 0, stream, H, d_plan, d_ws, b0, n);
-    }
-    if (s1 > s0) {
-        const uint32_t n = s1 - s0;
-        const uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(n, H.num_cus * H.blocks_per_cu * 4) : n;
-        hipLaunchKernelGGL(k_enc_symbols<256>, dim3(g), dim3(256), 0, stream, H, d_plan, d_ws, H.n_big + s0, n);
-    }
-}
-
-// A whole encode gathers the level-1 blocks' symbols on a helper stream as
-// soon as forward level 1 is done, while the upper levels (small, bound by
-// one workgroup's latency) run on the caller's stream; the caller's stream
-// waits for it before the code kernel.  One helper stream and two events per
-// device, created outside any stream capture at the default priority and
-// kept until the process ends; a fork enqueues its record / wait / launch /
-// record sequence under a lock, so that concurrent callers cannot interleave
-// the events (they share the helper stream, which only orders their forks).
-struct ForkRes {
-    hipStream_t s;
-    hipEvent_t e1, e2;
-    bool ok;
-};
-static ForkRes g_fork[64];
-static std::mutex g_fork_mu;
-
-static ForkRes *fork_level1_symbols(const PlanHdr &H, const uint8_t *d_plan, uint8_t *d_ws, hipStream_t stream)
-{
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    std::lock_guard<std::mutex> lock(g_fork_mu);
-    ForkRes &F = g_fork[dev];
-    if (!F.ok) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
-        if (hipStreamCreateWithFlags(&F.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        if (hipEventCreateWithFlags(&F.e1, hipEventDisableTiming) != hipSuccess) return nullptr;
-        if (hipEventCreateWithFlags(&F.e2, hipEventDisableTiming) != hipSuccess) return nullptr;
-        F.ok = true;
-    }
-    if (hipEventRecord(F.e1, stream) != hipSuccess) return nullptr;
-    if (hipStreamWaitEvent(F.s, F.e1, 0) != hipSuccess) return nullptr;
-    launch_symbols(H, d_plan, d_ws, F.s, 0, H.n_big_l1, 0, H.n_small_l1);
-    if (hipEventRecord(F.e2, F.s) != hipSuccess) return nullptr;
-    return &F;
-}
-
 // Stages (in order): prep, forward levels 0..15, symbols, code, block
 // offsets, tile offsets, tile finish, pack.  Stages without work launch nothing.
 hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t *d_pixels,
@@ -1526,9 +1471,6 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
                          uint64_t *d_tile_sizes, int32_t *d_status, uint8_t *d_ws,
                          hipStream_t stream, int first, int last)
 {
-    const bool want_fork = first <= ENC_FWD0 + 1 && last >= ENC_SYM && H.pack_nw == 1 && H.max_levels >= 2 &&
-                           H.n_big_l1 + H.n_small_l1 > 0;
-    ForkRes *fork = nullptr;
     for (int st = first; st <= last; st++) {
         if (st == ENC_PREP) {
             if (H.max_nblocks > 512)
@@ -1538,19 +1480,24 @@ hipError_t launch_encode(const PlanHdr &H, const uint8_t *d_plan, const uint8_t 
         } else if (st >= ENC_FWD0 && st <= ENC_FWD0 + kMaxLevels) {
             hipError_t e = launch_forward_level(H, d_plan, d_pixels, d_ws, st - ENC_FWD0, stream);
             if (e != hipSuccess) return e;
-            if (want_fork && st == ENC_FWD0 + 1) fork = fork_level1_symbols(H, d_plan, d_ws, stream);
         } else if (st == ENC_SYM) {
             if (H.pack_nw == 4 && H.n_big + H.n_small) {
                 // a plan of few blocks: all of them in one launch (a second
                 // launch for the small blocks would add its whole latency)
                 hipLaunchKernelGGL(k_enc_symbols<1024>, dim3(H.n_big + H.n_small), dim3(1024), 0, stream, H, d_plan,
                                    d_ws, 0u, H.n_big + H.n_small);
-            } else if (fork) {
-                launch_symbols(H, d_plan, d_ws, stream, H.n_big_l1, H.n_big, H.n_small_l1, H.n_small);
-                const hipError_t e = hipStreamWaitEvent(stream, fork->e2, 0);
-                if (e != hipSuccess) return e;
             } else {
-                launch_symbols(H, d_plan, d_ws, stream, 0, H.n_big, 0, H.n_small);
+                if (H.n_big) {
+                    uint32_t g = H.blocks_per_cu ? std::min<uint32_t>(H.n_big, H.num_cus * H.blocks_per_cu) : H.n_big;
+                    hipLaunchKernelGGL(k_enc_symbols<1024>, dim3(g), dim3(1024), 0, stream, H, d_plan, d_ws, 0u,
+                                       H.n_big);
+                }
+                if (H.n_small) {
+                    uint32_t g =
+                        H.blocks_per_cu ? std::min<uint32_t>(H.n_small, H.num_cus * H.blocks_per_cu * 4) : H.n_small;
+                    hipLaunchKernelGGL(k_enc_symbols<256>, dim3(g), dim3(256), 0, stream, H, d_plan, d_ws, H.n_big,
+                                       H.n_small);
+                }
             }
         } else if (st == ENC_CODE) {
             if (H.total_blocks) hipLaunchKernelGGL(k_enc_code, dim3(H.blk_grid), dim3(64), 0, stream, H, d_ws);
